@@ -1,0 +1,528 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test names what fixes the expected value: a library routine computed
+independently (scipy's spherical harmonics and rotations), a closed form, an
+invariant of Eq. 2, a dense autograd formulation, central finite differences,
+or published known-answer vectors.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import brute
+from paper_2507_20239_amd import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+# --------------------------------------------------------------------------
+# Spherical harmonics: scipy.special.sph_harm_y (complex, Condon-Shortley)
+# --------------------------------------------------------------------------
+def test_sh_matches_scipy_real_combinations():
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(0)
+    for _ in range(25):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        Y, _ = oracle.sh_basis(3, d)
+        th = math.acos(d[2])
+        ph = math.atan2(d[1], d[0])
+        for l in range(4):
+            for m in range(-l, l + 1):
+                k = l * l + l + m
+                z = complex(sph_harm_y(l, abs(m), th, ph))
+                ref = z.real if m == 0 else (math.sqrt(2) * (z.real if m > 0 else z.imag))
+                assert Y[k] == pytest.approx(ref, abs=1e-13), (l, m)
+
+
+def test_sh_gradient_matches_tangent_finite_difference():
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        u = rng.standard_normal(3)
+        u -= d * (u @ d)
+        u /= np.linalg.norm(u)
+        _, dY = oracle.sh_basis(3, d)
+        h = 1e-6
+        dp = (d + h * u) / np.linalg.norm(d + h * u)
+        dm = (d - h * u) / np.linalg.norm(d - h * u)
+        fd = (oracle.sh_basis(3, dp)[0] - oracle.sh_basis(3, dm)[0]) / (2 * h)
+        np.testing.assert_allclose(dY @ u, fd, atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# Covariance (Eq. 1): scipy's rotation from the quaternion
+# --------------------------------------------------------------------------
+def test_covariance_matches_scipy_rotation():
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        q = rng.standard_normal(4) * 3.0
+        ls = rng.normal(-2, 1, 3)
+        Rs = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()  # scalar-last
+        ref = Rs @ np.diag(np.exp(2 * ls)) @ Rs.T
+        np.testing.assert_allclose(oracle.covariance3d(q, ls), ref, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(oracle.covariance3d(-q, ls), ref, rtol=1e-12, atol=1e-15)
+        ev = np.linalg.eigvalsh(oracle.covariance3d(q, ls))
+        np.testing.assert_allclose(np.sort(ev), np.sort(np.exp(2 * ls)), rtol=1e-10)
+
+
+def _one_gaussian(mean, log_scale, quat, logit, rgb, deg=0):
+    Y00 = 0.5 / math.sqrt(math.pi)
+    K = (deg + 1) ** 2
+    sh = np.zeros((K, 3, 1), np.float32)
+    sh[0, :, 0] = (np.asarray(rgb) - 0.5) / Y00
+    return synth.Scene(np.asarray(mean, np.float32).reshape(3, 1),
+                       np.asarray(log_scale, np.float32).reshape(3, 1),
+                       np.asarray(quat, np.float32).reshape(4, 1),
+                       np.asarray([logit], np.float32), sh, deg, [], [], np.zeros(3, np.float32))
+
+
+def _cam(W, H, f, cx=None, cy=None, R=None, t=None):
+    return synth.Camera(np.eye(3) if R is None else R, np.zeros(3) if t is None else t, f, f,
+                        W / 2.0 if cx is None else cx, H / 2.0 if cy is None else cy, W, H)
+
+
+# --------------------------------------------------------------------------
+# Projection (Sigma' = J W Sigma W^T J^T): closed forms and finite differences
+# --------------------------------------------------------------------------
+def test_projection_isotropic_on_axis_closed_form():
+    rng = np.random.default_rng(3)
+    for z, ls in [(2.0, -3.0), (5.0, -2.0), (0.7, -4.5)]:
+        q = rng.standard_normal(4)
+        sc = _one_gaussian([0, 0, z], [ls] * 3, q, 0.3, [0.5, 0.5, 0.5])
+        cam = _cam(200, 150, 180.0)
+        p = oracle.project(sc, cam)
+        zf, s = float(np.float32(z)), math.exp(float(np.float32(ls)))
+        var = (180.0 * s / zf) ** 2 + float(np.float32(0.3))
+        np.testing.assert_allclose(p["cov2d"][0], [var, 0, var], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(p["conic"][0], [1 / var, 0, 1 / var], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(p["mean2d"][0], [100.0, 75.0], rtol=1e-14)
+        assert p["depth"][0] == zf
+
+
+def test_projection_covariance_matches_finite_difference_jacobian():
+    rng = np.random.default_rng(4)
+    R, t = synth.look_at((0.3, -0.2, -0.5), (0.1, 0.05, 3.0), up=(0, -1, 0))
+    cam = _cam(160, 120, 140.0, cx=81.3, cy=58.9, R=R, t=t)
+    for _ in range(10):
+        mu = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-0.3, 0.3), rng.uniform(2, 4)])
+        ls = rng.normal(-2.5, 0.4, 3)
+        q = rng.standard_normal(4)
+        sc = _one_gaussian(mu, ls, q, 0.0, [0.5] * 3)
+        p = oracle.project(sc, cam)
+        muf = sc.means[:, 0].astype(np.float64)
+
+        def u(m):
+            tt = R @ m + t
+            return np.array([cam.fx * tt[0] / tt[2] + cam.cx, cam.fy * tt[1] / tt[2] + cam.cy])
+
+        h = 1e-6
+        Jfd = np.stack([(u(muf + h * e) - u(muf - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        Sig = oracle.covariance3d(sc.quats[:, 0].astype(np.float64),
+                                  sc.log_scales[:, 0].astype(np.float64))
+        ref = Jfd @ Sig @ Jfd.T + float(np.float32(0.3)) * np.eye(2)
+        got = np.array([[p["cov2d"][0, 0], p["cov2d"][0, 1]], [p["cov2d"][0, 1], p["cov2d"][0, 2]]])
+        np.testing.assert_allclose(got, ref, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(p["mean2d"][0], u(muf), rtol=1e-13)
+
+
+def test_projection_culls_behind_near_plane():
+    sc = _one_gaussian([0, 0, 0.19], [-3] * 3, [1, 0, 0, 0], 2.0, [0.5] * 3)
+    p = oracle.project(sc, _cam(64, 64, 64.0))
+    assert p["visible"][0] == 0
+    sc = _one_gaussian([0, 0, 0.25], [-3] * 3, [1, 0, 0, 0], 2.0, [0.5] * 3)
+    assert oracle.project(sc, _cam(64, 64, 64.0))["visible"][0] == 1
+
+
+# --------------------------------------------------------------------------
+# Compositing (Eq. 2): closed form of one Gaussian and invariants
+# --------------------------------------------------------------------------
+def test_single_isotropic_gaussian_closed_form_image():
+    W = H = 64
+    f = 64.0
+    bg = np.array([0.1, 0.2, 0.3])
+    rgb = np.array([0.9, 0.5, 0.2])
+    for mean, ls, logit in [([0.05, -0.02, 3.0], -2.3, 1.0), ([0.0, 0.0, 2.0], -1.5, 6.0),
+                            ([-0.3, 0.2, 4.0], -2.0, -3.0)]:
+        sc = _one_gaussian(mean, [ls] * 3, [0.3, 0.1, -0.5, 0.7], logit, rgb)
+        cam = _cam(W, H, f)
+        p = oracle.project(sc, cam)
+        img, T, nc, _ = oracle.render_image(p, bg)
+        x, y, z = sc.means[:, 0].astype(np.float64)
+        s2 = math.exp(2 * float(np.float32(ls)))
+        JJt = np.array([[(f / z) ** 2 + (f * x / z ** 2) ** 2, (f * x / z ** 2) * (f * y / z ** 2)],
+                        [(f * x / z ** 2) * (f * y / z ** 2), (f / z) ** 2 + (f * y / z ** 2) ** 2]])
+        cov = s2 * JJt + float(np.float32(0.3)) * np.eye(2)
+        Q = np.linalg.inv(cov)
+        o = 1 / (1 + math.exp(-float(np.float32(logit))))
+        c_rgb = p["rgb"][0]
+        np.testing.assert_allclose(c_rgb, rgb, atol=1e-6)
+        mx, my = f * x / z + W / 2, f * y / z + H / 2
+        for py in range(H):
+            for px in range(W):
+                d = np.array([px + 0.5 - mx, py + 0.5 - my])
+                a = o * math.exp(-0.5 * d @ Q @ d)
+                if a >= float(np.float32(1 / 255)):
+                    a = min(a, float(np.float32(0.99)))
+                    ref = c_rgb * a + (1 - a) * bg
+                else:
+                    ref = bg
+                np.testing.assert_allclose(img[:, py, px], ref, rtol=1e-11, atol=1e-13)
+
+
+def test_partition_of_unity_constant_colour():
+    sc = synth.random_scene(5, 400, 40, 32, sh_degree=0, logit=(2.0, 1.0), log_scale=(-2.5, 0.4))
+    sc.sh[0] = np.float32(math.sqrt(math.pi) * 0.8)
+    bg = np.array([0.25, 0.5, 0.75])
+    p = oracle.project(sc, sc.cameras[0])
+    img, T, nc, _ = oracle.render_image(p, bg)
+    c = p["rgb"][0]
+    assert np.allclose(p["rgb"][p["visible"] > 0], c)
+    for ch in range(3):
+        np.testing.assert_allclose(img[ch], c[ch] * (1 - T) + T * bg[ch], rtol=1e-12, atol=1e-14)
+    assert T.min() >= float(np.float32(1e-4))
+    assert (nc > 0).mean() > 0.5
+
+
+def test_stop_rule_and_clamp_are_exercised_and_match_dense_reference():
+    sc = synth.random_scene(6, 60, 24, 20, sh_degree=3, logit=(4.0, 1.0), log_scale=(-1.6, 0.3),
+                            spread=0.5)
+    cam = sc.cameras[0]
+    p = oracle.project(sc, cam)
+    bg = (0.2, 0.1, 0.4)
+    img, T, nc, _ = oracle.render_image(p, bg)
+    t = brute.scene_tensors(sc)
+    ref, Tref = brute.render_dense(t["means"], t["log_scales"], t["quats"], t["opacity_logits"],
+                                   t["sh"], 3, cam, bg, depth_key=p["depth_key"])
+    np.testing.assert_allclose(img, ref.detach().numpy(), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(T, Tref.detach().numpy(), rtol=1e-10, atol=1e-14)
+    # the stop rule fired somewhere (T stays just above 1e-4) and some alpha was clamped
+    assert (T < 1e-3).any()
+    assert (p["opacity"] > 0.99).any()
+
+
+# --------------------------------------------------------------------------
+# Adjoint: torch autograd of the dense formulation and central differences
+# --------------------------------------------------------------------------
+def _oracle_grads(sc, cam, dL, bg):
+    p = oracle.project(sc, cam)
+    gproj, _ = oracle.render_backward_image(p, dL, bg)
+    return oracle.project_backward(sc, cam, p["visible"], gproj), p
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_adjoint_matches_torch_autograd(seed):
+    sc = synth.random_scene(seed, 40, 24, 20, sh_degree=3, logit=(1.0, 1.5), log_scale=(-2.0, 0.4),
+                            spread=0.9)
+    cam = sc.cameras[0]
+    bg = (0.3, 0.2, 0.1)
+    rng = np.random.default_rng(seed)
+    dL = rng.standard_normal((3, cam.height, cam.width))
+    g, p = _oracle_grads(sc, cam, dL, bg)
+    t = brute.scene_tensors(sc)
+    img, _ = brute.render_dense(t["means"], t["log_scales"], t["quats"], t["opacity_logits"],
+                                t["sh"], 3, cam, bg, depth_key=p["depth_key"])
+    (img * torch.tensor(dL)).sum().backward()
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        ref = t[name].grad.numpy()
+        scale = np.abs(ref).max()
+        np.testing.assert_allclose(g[name], ref, rtol=1e-7, atol=1e-9 * scale, err_msg=name)
+
+
+def test_adjoint_with_fov_clamp_matches_torch_autograd():
+    # Gaussians far outside the view frustum edge: x/z beyond 1.3 tan(fov/2)
+    sc = synth.random_scene(9, 30, 24, 20, sh_degree=1, logit=(1.0, 1.0), log_scale=(-0.8, 0.2),
+                            spread=2.5, depth=(1.0, 2.0))
+    cam = sc.cameras[0]
+    p = oracle.project(sc, cam)
+    limx = 1.3 * 0.5 * cam.width / cam.fx
+    xr = (sc.means[0] / sc.means[2])
+    clamped_visible = (np.abs(xr) > limx) & (p["visible"] > 0)
+    assert clamped_visible.any()
+    bg = (0.0, 0.0, 0.0)
+    dL = np.random.default_rng(9).standard_normal((3, cam.height, cam.width))
+    g, _ = _oracle_grads(sc, cam, dL, bg)
+    t = brute.scene_tensors(sc)
+    img, _ = brute.render_dense(t["means"], t["log_scales"], t["quats"], t["opacity_logits"],
+                                t["sh"], 1, cam, bg, depth_key=p["depth_key"])
+    (img * torch.tensor(dL)).sum().backward()
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        ref = t[name].grad.numpy()
+        np.testing.assert_allclose(g[name], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max(),
+                                   err_msg=name)
+
+
+def test_adjoint_matches_central_differences():
+    sc = synth.random_scene(10, 25, 20, 16, sh_degree=2, logit=(0.5, 1.0), log_scale=(-1.8, 0.3),
+                            spread=0.8)
+    cam = sc.cameras[0]
+    bg = (0.1, 0.1, 0.1)
+    rng = np.random.default_rng(10)
+    wts = rng.standard_normal((3, cam.height, cam.width))
+    g, p = _oracle_grads(sc, cam, wts, bg)
+
+    def loss(s):
+        pp = oracle.project(s, cam)
+        # the order and the discrete decisions must not flip inside +-h
+        assert np.array_equal(pp["depth_key"].argsort(kind="stable"),
+                              p["depth_key"].argsort(kind="stable"))
+        img, _, _, mg = oracle.render_image(pp, bg)
+        return float((img * wts).sum()), mg.min()
+
+    _, mg0 = loss(sc)
+    vis = np.nonzero(p["visible"])[0][:6]
+    checked = 0
+    for name in ["means", "log_scales", "quats", "opacity_logits", "sh"]:
+        arr = getattr(sc, name)
+        for i in vis:
+            for idx in np.ndindex(arr.shape[:-1]):
+                full = idx + (i,)
+                base = np.float64(arr[full])
+                h = 1e-4 * max(1.0, abs(base))
+                # FD in double on a double copy of the parameters
+                vals = []
+                for sgn in (1, -1):
+                    s2 = _double_scene(sc)
+                    getattr(s2, name)[full] = base + sgn * h
+                    vals.append(_loss_double(s2, cam, bg, wts, p))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                an = g[name][full]
+                assert fd == pytest.approx(an, rel=2e-5, abs=1e-7), (name, full)
+                checked += 1
+    assert checked > 100
+
+
+def _double_scene(sc):
+    return synth.Scene(sc.means.astype(np.float64), sc.log_scales.astype(np.float64),
+                       sc.quats.astype(np.float64), sc.opacity_logits.astype(np.float64),
+                       sc.sh.astype(np.float64), sc.sh_degree, sc.cameras, sc.targets, sc.bg)
+
+
+def _loss_double(s, cam, bg, wts, p0):
+    # evaluate the dense float64 reference (exact in double) with the fixed depth order
+    t = {k: torch.tensor(np.asarray(getattr(s, k), np.float64))
+         for k in ["means", "log_scales", "quats", "opacity_logits", "sh"]}
+    img, _ = brute.render_dense(t["means"], t["log_scales"], t["quats"], t["opacity_logits"],
+                                t["sh"], s.sh_degree, cam, bg, depth_key=p0["depth_key"])
+    return float((img.numpy() * wts).sum())
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10: published known-answer vectors and rocRAND's implementation
+# --------------------------------------------------------------------------
+def _load_kat():
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = []
+    for ln in open(path):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        w = [int(x, 16) for x in ln.split()]
+        rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+PHILOX_KAT = _load_kat()
+
+
+@pytest.mark.parametrize("ctr,key,out", PHILOX_KAT)
+def test_philox_known_answers(ctr, key, out):
+    got = oracle.philox4x32_10(ctr, key)
+    assert [int(x) for x in got] == out
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="needs hipcc for the host build")
+def test_philox_matches_rocrand_host_implementation(tmp_path):
+    src = tmp_path / "p.cpp"
+    src.write_text(r"""
+#include <cstdio>
+#include <rocrand/rocrand_philox4x32_10.h>
+struct Engine : rocrand_device::philox4x32_10_engine {
+  uint4 rounds(uint4 c, uint2 k) { return ten_rounds(c, k); }
+};
+int main() {
+  Engine e;
+  unsigned s = 12345u;
+  for (int i = 0; i < 64; ++i) {
+    s = s * 1664525u + 1013904223u; unsigned a = s;
+    s = s * 1664525u + 1013904223u; unsigned b = s;
+    s = s * 1664525u + 1013904223u; unsigned c = s;
+    s = s * 1664525u + 1013904223u; unsigned d = s;
+    s = s * 1664525u + 1013904223u; unsigned k0 = s;
+    s = s * 1664525u + 1013904223u; unsigned k1 = s;
+    uint4 r = e.rounds(uint4{a, b, c, d}, uint2{k0, k1});
+    printf("%u %u %u %u %u %u %u %u %u %u\n", a, b, c, d, k0, k1, r.x, r.y, r.z, r.w);
+  }
+  return 0;
+}
+""")
+    exe = tmp_path / "p"
+    subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-O1", "-o", str(exe), str(src)],
+                          stderr=subprocess.DEVNULL)
+    out = subprocess.check_output([str(exe)], text=True)
+    rows = [list(map(int, ln.split())) for ln in out.strip().splitlines()]
+    assert len(rows) == 64
+    for r in rows:
+        got = oracle.philox4x32_10(r[0:4], r[4:6])
+        assert [int(x) for x in got] == r[6:10]
+
+
+def test_split_normals_are_standard_normal():
+    from scipy import stats
+    zs = np.array([oracle.split_normals(0x5EED, 7, i, c)[0] for i in range(6000) for c in (0, 1)])
+    for a in range(3):
+        assert stats.kstest(zs[:, a], "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(zs[:, 0], zs[:, 1])[0, 1]) < 0.03
+    # uniforms in (0, 1]: the log is finite for the extreme word values
+    assert np.all(np.isfinite(zs))
+
+
+def test_split_offsets_follow_the_parent_covariance():
+    # 10,000 identical parents, two children each: child - parent ~ N(0, Sigma)
+    n = 10000
+    q = np.tile(np.array([[0.8], [0.2], [-0.4], [0.3]], np.float32), (1, n))
+    ls = np.tile(np.array([[-2.0], [-3.0], [-1.5]], np.float32), (1, n))
+    mu = np.tile(np.array([[1.0], [2.0], [3.0]], np.float32), (1, n))
+    par = np.repeat(np.arange(n, dtype=np.int64), 2)
+    ch = np.tile(np.array([0, 1], np.int32), n)
+    out = oracle.split_means(mu, ls, q, par, ch, 0xABC, 0)
+    d = out - mu[:, 0].astype(np.float64)
+    Sig = oracle.covariance3d(q[:, 0].astype(np.float64), ls[:, 0].astype(np.float64))
+    emp = d.T @ d / d.shape[0]
+    np.testing.assert_allclose(emp, Sig, atol=0.05 * np.abs(Sig).max())
+    assert np.abs(d.mean(0)).max() < 0.01
+
+
+# --------------------------------------------------------------------------
+# Densification: hand-computed cases and closed-form counts
+# --------------------------------------------------------------------------
+def test_stats_hand_computed():
+    # two Gaussians, three views of 100x50 (NDC scale 50, 25)
+    g = np.zeros((3, 2, 2), np.float32)
+    g[0, :, 0] = [3e-3, 4e-3]     # NDC (0.15, 0.1)
+    g[1, :, 0] = [0.0, 2e-3]      # NDC (0, 0.05)
+    g[2, :, 0] = [1.0, 1.0]       # not visible
+    g[0, :, 1] = [-2e-2, 0.0]     # NDC (-1, 0)
+    vis = np.array([[1, 1], [1, 0], [0, 0]], np.int32)
+    wh = np.array([[100, 50]] * 3, np.int32)
+    acc, den = oracle.stats_f32(g, vis, wh)
+    assert den.tolist() == [2.0, 1.0]
+    assert acc[0] == pytest.approx(math.hypot(0.15, 0.1) + 0.05, rel=1e-6)
+    assert acc[1] == pytest.approx(1.0, rel=1e-6)
+
+
+def test_select_rule_and_global_phase():
+    tau_g, lthr, pthr = oracle.thresholds(2e-4, 0.01, 4.4, 0.005)
+    assert lthr == np.float32(math.log(0.044))
+    acc = np.array([3e-4, 3e-4, 1e-4, 0.0, 2e-4 * 4], np.float32)
+    den = np.array([1, 1, 1, 0, 4], np.float32)
+    ls = np.full((3, 5), -5.0, np.float32)
+    ls[1, 0] = -2.0          # max scale exp(-2) = 0.135 > 0.044  -> split
+    ls[2, 4] = float(lthr)   # exactly at the threshold -> not split (strict) -> clone
+    lg = np.array([0.0, -6.0, 0.0, -5.2, 1.0], np.float32)
+    s, c, p = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, allow_clone=True)
+    assert s.tolist() == [1, 0, 0, 0, 0]
+    assert c.tolist() == [0, 1, 0, 0, 1]
+    assert p.tolist() == [0, 1, 0, 0, 0]   # sigmoid(-6) = 0.0025 < 0.005; sigmoid(-5.2) = 0.0055
+    s2, c2, _ = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, allow_clone=False)
+    assert s2.tolist() == s.tolist() and c2.sum() == 0
+
+
+def test_densify_plan_brute_force_and_counts():
+    rng = np.random.default_rng(11)
+    n = 500
+    split = rng.random(n) < 0.1
+    clone = (rng.random(n) < 0.2) & ~split
+    prune = rng.random(n) < 0.1
+    src, kind = oracle.densify_plan(split, clone, prune)
+    # brute force, one parent at a time
+    bs, bk = [], []
+    for i in range(n):
+        if prune[i]:
+            continue
+        if split[i]:
+            bs += [i, i]; bk += [oracle.SPLIT0, oracle.SPLIT1]
+        elif clone[i]:
+            bs += [i, i]; bk += [oracle.KEEP, oracle.CLONE]
+        else:
+            bs += [i]; bk += [oracle.KEEP]
+    assert src.tolist() == bs and kind.tolist() == bk
+    P, S, C = prune, split, clone
+    assert src.size == n - P.sum() + (C & ~P).sum() + (S & ~P).sum()
+
+
+def test_densify_apply_split_and_clone_rows():
+    sc = synth.random_scene(12, 50, 16, 16, sh_degree=1)
+    params = dict(means=sc.means, log_scales=sc.log_scales, quats=sc.quats,
+                  opacity_logits=sc.opacity_logits)
+    split = np.zeros(50, bool); split[[3, 7]] = True
+    clone = np.zeros(50, bool); clone[[4]] = True
+    prune = np.zeros(50, bool); prune[[5, 7]] = True
+    src, kind = oracle.densify_plan(split, clone, prune)
+    out = oracle.densify_apply(params, src, kind, seed=99, step=1)
+    assert out["means"].shape[1] == 50 - 2 + 1 + 1
+    j = np.nonzero(src == 3)[0]
+    assert kind[j].tolist() == [oracle.SPLIT0, oracle.SPLIT1]
+    np.testing.assert_allclose(out["log_scales"][:, j],
+                               sc.log_scales[:, [3, 3]].astype(np.float64) - math.log(1.6))
+    assert not np.allclose(out["means"][:, j[0]], out["means"][:, j[1]])
+    j = np.nonzero(src == 4)[0]
+    np.testing.assert_array_equal(out["means"][:, j[0]], out["means"][:, j[1]])
+    np.testing.assert_array_equal(out["quats"][:, j], sc.quats[:, [4, 4]])
+
+
+def test_adaptive_threshold_order_statistic():
+    rng = np.random.default_rng(13)
+    lg = rng.normal(0, 2, 1001).astype(np.float32)
+    thr, k = oracle.adaptive_prune_logit(lg, p=0.03, tau_u=0.9)
+    assert k == 30
+    assert thr == np.sort(lg)[30]
+    assert (lg < thr).sum() == 30                 # exactly k pruned (no ties)
+    thr2, _ = oracle.adaptive_prune_logit(lg, p=0.03, tau_u=1e-6)
+    assert thr2 == np.float32(math.log(1e-6 / (1 - 1e-6)))
+
+
+# --------------------------------------------------------------------------
+# Binning by definition: the footprint is conservative and tight
+# --------------------------------------------------------------------------
+def test_footprint_rect_covers_every_contributing_pixel():
+    sc = synth.random_scene(14, 120, 50, 40, sh_degree=0, log_scale=(-2.2, 0.6), spread=1.2)
+    cam = sc.cameras[0]
+    p = oracle.project(sc, cam)
+    tiles, gids, ranges = oracle.tile_lists(p)
+    tx_n = (cam.width + 15) // 16
+    per_tile = {t: set(gids[ranges[t, 0]:ranges[t, 1]].tolist()) for t in range(ranges.shape[0])}
+    touched = np.zeros((120, 4), np.int64)
+    touched[:, 0] = 10**9; touched[:, 2] = 10**9; touched[:, 1] = -1; touched[:, 3] = -1
+    for py in range(cam.height):
+        for px in range(cam.width):
+            d = np.array([px + 0.5, py + 0.5]) - p["mean2d"]
+            a, b, c = p["conic"].T
+            G = np.exp(-0.5 * (a * d[:, 0] ** 2 + c * d[:, 1] ** 2) - b * d[:, 0] * d[:, 1])
+            contrib = np.nonzero((p["opacity"] * G >= 1 / 255.0) & (p["visible"] > 0))[0]
+            t = (py // 16) * tx_n + px // 16
+            assert set(contrib.tolist()) <= per_tile[t]
+            for i in contrib:
+                touched[i] = [min(touched[i, 0], px), max(touched[i, 1], px),
+                              min(touched[i, 2], py), max(touched[i, 3], py)]
+    # tight up to the 2^-10 inflation: the rect is the tile box of the touched pixels
+    # except where a bound lands within one pixel of a tile edge
+    for i in np.nonzero(p["visible"])[0]:
+        if touched[i, 1] < 0:
+            continue
+        want = [touched[i, 0] // 16, touched[i, 1] // 16, touched[i, 2] // 16, touched[i, 3] // 16]
+        got = p["rect"][i].tolist()
+        assert got[0] <= want[0] and got[1] >= want[1] and got[2] <= want[2] and got[3] >= want[3]
+        assert got[0] >= (touched[i, 0] - 1) // 16 and got[1] <= (touched[i, 1] + 1) // 16
+    # lists are depth ordered with ties by index
+    for t in range(ranges.shape[0]):
+        g = gids[ranges[t, 0]:ranges[t, 1]]
+        k = p["depth_key"][g]
+        assert np.all((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (g[1:] > g[:-1])))
