@@ -1,0 +1,314 @@
+/*
+ * gsmi.h -- C ABI of the MI355X (gfx950) Gaussian-splatting hot path.
+ *
+ * Implements, as hand-written HIP kernels, the differentiable tile rasterizer
+ * and the densification step of 3D Gaussian Splatting training as scheduled
+ * in "Decomposing Densification in Gaussian Splatting for Faster 3D Scene
+ * Reconstruction" (arXiv 2507.20239):
+ *   - projection of anisotropic Gaussians (Eq. 1; Sigma = R S S^T R^T and
+ *     Sigma' = J W Sigma W^T J^T, Preliminary) with spherical-harmonic colour;
+ *   - depth-ordered front-to-back alpha compositing per 16x16 tile (Eq. 2)
+ *     and its adjoint;
+ *   - the densification statistic (norm of the view-space position gradient)
+ *     and the split / clone / prune rule (Preliminary, last paragraph),
+ *     including the clone suppression of the global phase (Methodology,
+ *     Global-to-local framework);
+ *   - the adaptive opacity threshold (Methodology, Adaptive Opacity Pruning).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers unless the comment says "host".
+ *     The caller owns every buffer it passes; the library never frees or
+ *     keeps caller pointers after the call returns (a captured step graph,
+ *     gs_step_graph_*, is the one exception and says so).
+ *   - `stream` is a hipStream_t passed as void*; all work is enqueued on it
+ *     asynchronously.  Entry points that must read a device value on the host
+ *     say "synchronises".
+ *   - Every call returns a gs_status.  Argument validation happens on the
+ *     host before any launch; on error nothing is enqueued and
+ *     gs_last_error() returns a description (thread-local).
+ *   - Gaussian parameters are structure-of-arrays FP32 with the Gaussian
+ *     index fastest: means[3][n], log_scales[3][n], quats[4][n] (w, x, y, z,
+ *     any norm), opacity_logits[n], sh[K][3][n] with K = (sh_degree+1)^2,
+ *     real spherical harmonics with the Condon-Shortley phase,
+ *     colour = max(0, sum_k Y_k f_k + 1/2).
+ *   - Cameras are world->camera rigid transforms in OpenCV axes (x right,
+ *     y down, z forward); pixel (px, py) is sampled at (px+0.5, py+0.5).
+ *   - Images are planar FP32 [3][H][W]; a frame with several views stores
+ *     them one after the other in view order.
+ *   - Rendering constants: alpha = min(0.99, o G); Gaussians with
+ *     alpha < 1/255 are skipped at that pixel; a pixel stops before
+ *     compositing a Gaussian that would take its transmittance below 1e-4;
+ *     Sigma' gets +0.3 px^2 on its diagonal; x/z and y/z are clamped to
+ *     +-1.3 tan(half field of view) inside J.
+ */
+#ifndef GSMI_H
+#define GSMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_INVALID = 1,     /* bad argument; nothing was enqueued */
+    GS_ERR_CAPACITY = 2,    /* a device-side capacity was exceeded (see gs_frame_status) */
+    GS_ERR_HIP = 3,         /* a HIP runtime call failed */
+    GS_ERR_UNSUPPORTED = 4  /* valid but not supported by this build */
+} gs_status;
+
+/* Text of the last non-OK status on the calling thread (never NULL). */
+const char* gs_last_error(void);
+/* Library version string. */
+const char* gs_version(void);
+
+#define GS_MAX_VIEWS 32
+#define GS_TILE 16
+
+/* One camera (72 bytes).  R: world->camera rotation, row-major; t: translation
+ * (x_cam = R x_world + t); fx, fy, cx, cy: pinhole intrinsics in pixels for the
+ * resolution being rendered (a coarse level 1/r divides all four by r);
+ * width, height: image size in pixels.  Passed to kernels as a device array. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} gs_camera;
+
+/* Gaussian parameters (device, FP32 SoA as described above). */
+typedef struct {
+    const float* means;          /* [3][n] */
+    const float* log_scales;     /* [3][n] */
+    const float* quats;          /* [4][n] */
+    const float* opacity_logits; /* [n]    */
+    const float* sh;             /* [K][3][n] */
+    int64_t n;
+    int32_t sh_degree;           /* 0..3 */
+    int32_t reserved;
+} gs_gaussians;
+
+/* Gradients w.r.t. the raw parameters (device, same layouts; overwritten). */
+typedef struct {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} gs_gaussian_grads;
+
+/* Rasterisation options. */
+typedef struct {
+    float bg[3];                 /* background colour composited behind every pixel */
+    float near_plane;            /* Gaussians with camera depth <= near are culled (default 0.2) */
+    int32_t raster_batch;        /* Gaussians staged in LDS per batch: 64, 128 or 256; 0 = 256 */
+    int32_t persistent_blocks;   /* 0: one workgroup per (view, tile);  > 0: a persistent grid of
+                                    this many workgroups takes (view, tile) items from a queue,
+                                    heaviest tile lists first */
+    int32_t reserved[2];
+} gs_raster_opts;
+
+/* ------------------------------------------------------------------------ */
+/* Frame: the device state of one rendering step for a fixed set of view     */
+/* shapes (projected splats, sort buffers, tile ranges, per-pixel state,     */
+/* per-splat gradients).  Its memory is a caller-owned device workspace.     */
+/* ------------------------------------------------------------------------ */
+typedef struct gs_frame gs_frame;
+
+/* Bytes of device workspace a frame needs (host call, no device work).
+ * n: Gaussians; n_views <= GS_MAX_VIEWS; widths/heights: host arrays of the
+ * view sizes; max_instances: capacity for (view, tile, Gaussian) instances
+ * (<= 2^31 - 1). */
+gs_status gs_frame_workspace_size(int64_t n, int32_t n_views, const int32_t* widths,
+                                  const int32_t* heights, int64_t max_instances, uint64_t* bytes);
+
+/* Create a frame over `workspace` (device, at least the queried size, 256-byte
+ * aligned).  Copies a small view table to the device (synchronises). */
+gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
+                          const int32_t* heights, int64_t max_instances, void* workspace,
+                          uint64_t workspace_bytes, gs_frame** out);
+gs_status gs_frame_destroy(gs_frame* frame);
+
+/* Buffers inside the frame, for inspection (device pointer and element count). */
+enum {
+    GS_BUF_DEPTH_KEY = 0,     /* u32 [V*n]   FP32 bits of the camera depth of entry v*n+i */
+    GS_BUF_TILES_TOUCHED = 1, /* u32 [V*n]   tiles covered by the footprint (0 = not rendered) */
+    GS_BUF_RECT = 2,          /* u32 [V*n][2] tile rect: x0 | x1 << 16, y0 | y1 << 16 */
+    GS_BUF_SPLAT = 3,         /* f32 [V*n][12] mean hi (2), mean lo (2), conic a b c, opacity, rgb, pad */
+    GS_BUF_SORTED_ENTRIES = 4,/* u32 [V*n]   visible entries in (depth key, entry) order */
+    GS_BUF_INST_TILE = 5,     /* u32 [cap]   tile id of each sorted instance */
+    GS_BUF_INST_ENTRY = 6,    /* u32 [cap]   entry id of each sorted instance */
+    GS_BUF_RANGES = 7,        /* u32 [T][2]  [start, end) of each tile's instance list */
+    GS_BUF_T_FINAL = 8,       /* f32 [P]     final transmittance per pixel */
+    GS_BUF_N_CONTRIB = 9,     /* u32 [P]     instances walked per pixel (last composited + 1) */
+    GS_BUF_SPLAT_GRAD = 10,   /* f32 [V*n][9] dL/d(mean2d x, y, conic a, b, c, opacity, r, g, b) */
+    GS_BUF_COUNTERS = 11      /* u32 [16]    [0] visible entries, [1] instances, [2] overflow flag */
+};
+gs_status gs_frame_buffer(const gs_frame* frame, int32_t which, void** ptr, int64_t* count);
+
+/* Visible entries, instances and the overflow flag of the last render
+ * (synchronises the stream).  overflow != 0 means max_instances was too small:
+ * the images are incomplete; grow the frame and render again. */
+gs_status gs_frame_status(gs_frame* frame, void* stream, int64_t* n_visible,
+                          int64_t* n_instances, int32_t* overflow);
+
+/* ------------------------------------------------------------------------ */
+/* Rendering and its adjoint                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* project(means, scales, quats, opacities, SH, camera): for every view v and
+ * Gaussian i, the camera depth, the EWA screen-space Gaussian (mean, conic =
+ * Sigma'^-1, opacity), its SH colour for the direction from the camera
+ * centre, and its footprint rectangle in tiles.  cameras: device gs_camera[V]
+ * whose width/height must equal the frame's view sizes.  g->n must equal the
+ * frame's n. */
+gs_status gs_project(gs_frame* frame, const gs_gaussians* g, const gs_camera* cameras,
+                     const gs_raster_opts* opts, void* stream);
+
+/* render(view, resolution): sort the projected footprints into per-tile,
+ * depth-ordered lists (prefix sums and LSD radix sorts) and composite every
+ * pixel of every view front to back (Eq. 2).  images: device FP32, the views'
+ * planar images one after the other (sum_v 3 H_v W_v floats).  Also keeps the
+ * per-pixel final transmittance and walk length for the backward. */
+gs_status gs_render(gs_frame* frame, const gs_raster_opts* opts, float* images, void* stream);
+
+/* Adjoint of gs_render: from dL/dimages (same layout as images) to the
+ * per-splat gradients GS_BUF_SPLAT_GRAD (overwritten).  Walks each pixel's
+ * list back to front, recovering transmittance from the saved final value. */
+gs_status gs_render_backward(gs_frame* frame, const gs_raster_opts* opts,
+                             const float* dL_dimages, void* stream);
+
+/* Adjoint of gs_project: from the per-splat gradients to the raw parameters,
+ * summed over the frame's views (grads are overwritten, every Gaussian gets a
+ * value).  When accum and denom are not NULL, also accumulates the
+ * densification statistic: for each view where entry (v, i) was rendered,
+ * accum[i] += ||(dL/dmean2d_x W_v/2, dL/dmean2d_y H_v/2)|| and denom[i] += 1. */
+gs_status gs_project_backward(gs_frame* frame, const gs_gaussians* g, const gs_camera* cameras,
+                              const gs_raster_opts* opts, const gs_gaussian_grads* grads,
+                              float* accum, float* denom, void* stream);
+
+/* L1 term of Eq. 3: loss[0] += scale * sum |image - target| and
+ * dL_dimage = scale * sign(image - target) (sign(0) = 0). */
+gs_status gs_l1_loss_grad(const float* image, const float* target, int64_t numel, float scale,
+                          float* loss, float* dL_dimage, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Densification                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* accumulate_densify_stats: for v in 0..n_views-1 in order, for every i with
+ * visible[v][i] != 0: gx = dmean2d[v][0][i] * W_v/2, gy = dmean2d[v][1][i] * H_v/2
+ * (FP32), accum[i] += sqrt(fma(gx, gx, gy*gy)) (correctly rounded), denom[i] += 1.
+ * dmean2d: device [V][2][n] pixel-space gradients; visible: device int32 [V][n];
+ * view_wh: HOST int32 [V][2].  Deterministic. */
+gs_status gs_accumulate_densify_stats(const float* dmean2d, const int32_t* visible,
+                                      const int32_t* view_wh, int32_t n_views, int64_t n,
+                                      float* accum, float* denom, void* stream);
+
+/* Split / clone / prune masks (u8, 0 or 1):
+ *   avg = accum/denom (0 where denom == 0), FP32 correctly rounded;
+ *   split = avg >= grad_threshold and max_k log_scales[k][i] > log_scale_threshold;
+ *   clone = avg >= grad_threshold and not (max log-scale > threshold) and allow_clone;
+ *   prune = opacity_logits[i] < logit_threshold.
+ * Thresholds are in raw-parameter space: log_scale_threshold = ln(rho * extent),
+ * logit_threshold = ln(tau_o / (1 - tau_o)).  allow_clone = 0 is the global
+ * (split-only) phase. */
+gs_status gs_densify_select(const float* accum, const float* denom, const float* log_scales,
+                            const float* opacity_logits, int64_t n, float grad_threshold,
+                            float log_scale_threshold, float logit_threshold, int32_t allow_clone,
+                            uint8_t* split, uint8_t* clone, uint8_t* prune, void* stream);
+
+enum { GS_KIND_KEEP = 0, GS_KIND_CLONE = 1, GS_KIND_SPLIT0 = 2, GS_KIND_SPLIT1 = 3 };
+
+/* Device workspace bytes for gs_densify_plan over n parents. */
+gs_status gs_densify_plan_workspace_size(int64_t n, uint64_t* bytes);
+
+/* densify(split_mask, clone_mask, prune_mask), step 1: the compaction map.
+ * Parent i emits nothing if prune[i]; else [SPLIT0, SPLIT1] if split[i];
+ * else [KEEP, CLONE] if clone[i]; else [KEEP].  Outputs follow parent order:
+ * src[j] = parent of output row j, kind[j] = GS_KIND_*.  n_out (device int64)
+ * receives the number of rows; rows beyond `capacity` are not written (then
+ * n_out > capacity tells the caller to grow and call again). */
+gs_status gs_densify_plan(const uint8_t* split, const uint8_t* clone, const uint8_t* prune,
+                          int64_t n, int32_t* src, uint8_t* kind, int64_t capacity,
+                          int64_t* n_out, void* workspace, uint64_t workspace_bytes,
+                          void* stream);
+
+/* How an attribute row is produced from its parent row. */
+enum {
+    GS_ATTR_COPY = 0,      /* every output row copies its parent's row */
+    GS_ATTR_MEAN = 1,      /* SPLITk rows: mu + R(q) (s * z_k), z_k ~ N(0, I3) from Philox; else copy */
+    GS_ATTR_LOGSCALE = 2,  /* SPLITk rows: parent - ln(1.6); else copy */
+    GS_ATTR_ZERO_NEW = 3,  /* KEEP rows copy, CLONE/SPLIT rows are zero (optimizer moments) */
+    GS_ATTR_ZERO = 4       /* every output row is zero (densification statistics) */
+};
+
+/* One attribute: in [rows][n_in] -> out [rows][n_out] (device FP32). */
+typedef struct {
+    const float* in;
+    float* out;
+    int32_t rows;
+    int32_t policy;
+} gs_attr;
+
+/* densify step 2: produce every attribute's new rows.  n_out: host value (the
+ * caller read it to allocate).  parent_means/parent_log_scales/parent_quats are
+ * the inputs [3|3|4][n_in] that GS_ATTR_MEAN needs.  The split normals for
+ * child k of parent i come from Philox4x32-10 with counter
+ * (i lo, i hi, k, step) and key (seed lo, seed hi): u1 = ((x0 >> 8) + 1) 2^-24,
+ * u2 = (x1 >> 8) 2^-24, z0/z1 = Box-Muller cos/sin, z2 = Box-Muller cos of
+ * (x2, x3).  attrs: HOST array of n_attrs <= 16. */
+gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_out, int64_t n_in,
+                           const gs_attr* attrs, int32_t n_attrs, const float* parent_means,
+                           const float* parent_log_scales, const float* parent_quats,
+                           uint64_t seed, uint64_t step, void* stream);
+
+/* The split normals of (parent, child) pairs as the apply step draws them:
+ * words [m][4] (raw Philox output) and z [m][3]. */
+gs_status gs_split_normals(const int64_t* parents, const int32_t* children, int64_t m,
+                           uint64_t seed, uint64_t step, uint32_t* words, float* z, void* stream);
+
+/* Adaptive opacity threshold in logit space: thr[0] = min(logits_sorted[k],
+ * upper_logit) where logits_sorted is the ascending order of opacity_logits
+ * and k = floor(n p) is given by the caller (radix select, exact).  Then
+ * prune = logit < thr.  workspace: gs_radix_select_workspace_size(n). */
+gs_status gs_radix_select_workspace_size(int64_t n, uint64_t* bytes);
+gs_status gs_adaptive_prune_threshold(const float* opacity_logits, int64_t n, int64_t k,
+                                      float upper_logit, float* thr, void* workspace,
+                                      uint64_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Primitives exposed for testing                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Stable LSD radix sort of (key, value) u32 pairs on the low key_bits bits
+ * (1..32).  Result in keys/vals.  n <= 2^31-1.  workspace: gs_sort_workspace_size(n). */
+gs_status gs_sort_workspace_size(int64_t n, uint64_t* bytes);
+gs_status gs_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
+                        void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Captured training step (hipGraph)                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct gs_graph gs_graph;
+
+/* Capture project -> render -> L1 loss/gradient -> render backward -> project
+ * backward (+ statistics) for the frame's views into a hipGraph.  The graph
+ * keeps every pointer given here; the caller must keep those buffers alive and
+ * unchanged in size until gs_graph_destroy.  Camera contents (device) may be
+ * rewritten between launches.  loss: device float, zeroed by the graph.
+ * targets/images/dL_dimages: the frame's image layout.  l1_scale multiplies
+ * the L1 sum. */
+gs_status gs_step_graph_create(gs_frame* frame, const gs_gaussians* g, const gs_camera* cameras,
+                               const gs_raster_opts* opts, float* images, const float* targets,
+                               float l1_scale, float* loss, float* dL_dimages,
+                               const gs_gaussian_grads* grads, float* accum, float* denom,
+                               void* stream, gs_graph** out);
+gs_status gs_graph_launch(gs_graph* graph, void* stream);
+gs_status gs_graph_destroy(gs_graph* graph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSMI_H */

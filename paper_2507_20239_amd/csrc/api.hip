@@ -1,0 +1,407 @@
+// Host side of the C ABI declared in gsmi.h: argument validation, the frame
+// workspace layout, and the entry points that enqueue the kernels.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "gs_internal.h"
+
+static thread_local char g_err[512] = "no error";
+
+gs_status gs_fail(gs_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+gs_status gs_check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return gs_fail(GS_ERR_HIP, "%s launch failed: %s", what, hipGetErrorString(e));
+    return GS_OK;
+}
+
+namespace {
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+struct Layout {
+    uint64_t off[40];
+    int count = 0;
+    uint64_t total = 0;
+    uint64_t add(uint64_t bytes) {
+        const uint64_t o = total;
+        off[count++] = o;
+        total += align256(bytes > 0 ? bytes : 1);
+        return o;
+    }
+};
+
+gs_status check_views(int64_t n, int32_t V, const int32_t* widths, const int32_t* heights,
+                      int64_t cap) {
+    if (n < 0) return gs_fail(GS_ERR_INVALID, "n must be >= 0");
+    if (V < 1 || V > GS_MAX_VIEWS) return gs_fail(GS_ERR_INVALID, "n_views must be in [1, %d]", GS_MAX_VIEWS);
+    if (!widths || !heights) return gs_fail(GS_ERR_INVALID, "widths/heights are null");
+    if ((int64_t)V * n >= ((int64_t)1 << 31)) return gs_fail(GS_ERR_INVALID, "n_views * n must be < 2^31");
+    if (cap < 1 || cap >= ((int64_t)1 << 31) - 1) return gs_fail(GS_ERR_INVALID, "max_instances must be in [1, 2^31-1)");
+    int64_t tiles = 0;
+    for (int v = 0; v < V; ++v) {
+        if (widths[v] <= 0 || heights[v] <= 0 || widths[v] > 16384 || heights[v] > 16384)
+            return gs_fail(GS_ERR_INVALID, "view %d: size %dx%d out of range", v, widths[v], heights[v]);
+        tiles += (int64_t)((widths[v] + GS_TILE - 1) / GS_TILE) * ((heights[v] + GS_TILE - 1) / GS_TILE);
+    }
+    if (tiles >= ((int64_t)1 << 24)) return gs_fail(GS_ERR_INVALID, "too many tiles");
+    return GS_OK;
+}
+
+void fill_views(gs_frame* f, const int32_t* widths, const int32_t* heights) {
+    int32_t tb = 0;
+    int64_t pb = 0;
+    for (int v = 0; v < f->V; ++v) {
+        gs_view_info& vi = f->views[v];
+        vi.width = widths[v];
+        vi.height = heights[v];
+        vi.tiles_x = (widths[v] + GS_TILE - 1) / GS_TILE;
+        vi.tiles_y = (heights[v] + GS_TILE - 1) / GS_TILE;
+        vi.tile_base = tb;
+        vi.pad = 0;
+        vi.pix_base = pb;
+        tb += vi.tiles_x * vi.tiles_y;
+        pb += (int64_t)widths[v] * heights[v];
+    }
+    f->T = tb;
+    f->P = pb;
+    int bits = 1;
+    while (((int64_t)1 << bits) < (int64_t)tb) ++bits;
+    f->tile_bits = bits;
+}
+
+Layout layout_for(gs_frame* f) {
+    const uint64_t E = (uint64_t)f->E, cap = (uint64_t)f->cap, T = (uint64_t)f->T, P = (uint64_t)f->P;
+    f->G_vis = gs_radix_partitions(f->E);
+    f->G_inst = gs_radix_partitions(f->cap);
+    f->G_tile = gs_radix_partitions(f->T);
+    int G = f->G_vis;
+    if (f->G_inst > G) G = f->G_inst;
+    if (f->G_tile > G) G = f->G_tile;
+    Layout L;
+    L.add(4 * E);        // 0 depth_key
+    L.add(4 * E);        // 1 tiles_touched
+    L.add(8 * E);        // 2 rect
+    L.add(48 * E);       // 3 splat
+    L.add(4 * E);        // 4 flags
+    L.add(4 * E);        // 5 vkeys0
+    L.add(4 * E);        // 6 vkeys1
+    L.add(4 * E);        // 7 vvals0
+    L.add(4 * E);        // 8 vvals1
+    L.add(4 * E);        // 9 inst_off
+    L.add(4 * cap);      // 10 ikeys0
+    L.add(4 * cap);      // 11 ikeys1
+    L.add(4 * cap);      // 12 ivals0
+    L.add(4 * cap);      // 13 ivals1
+    L.add(8 * T);        // 14 ranges
+    L.add(4 * T);        // 15 tkeys0
+    L.add(4 * T);        // 16 tkeys1
+    L.add(4 * T);        // 17 tvals0
+    L.add(4 * T);        // 18 tvals1
+    L.add(4 * P);        // 19 T_final
+    L.add(4 * P);        // 20 n_contrib
+    L.add(36 * E);       // 21 splat_grad
+    L.add(64);           // 22 counters
+    L.add(4 * 256 * (uint64_t)G);  // 23 radix_hist
+    L.add(4 * (GS_SCAN_PARTS + 8));  // 24 scan_part
+    L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 25 views
+    return L;
+}
+
+gs_status check_frame(const gs_frame* f) {
+    if (!f) return gs_fail(GS_ERR_INVALID, "frame is null");
+    return GS_OK;
+}
+
+gs_status check_gaussians(const gs_frame* f, const gs_gaussians* g) {
+    if (!g) return gs_fail(GS_ERR_INVALID, "gaussians is null");
+    if (g->n != f->n) return gs_fail(GS_ERR_INVALID, "gaussians n=%lld but the frame was made for n=%lld",
+                                     (long long)g->n, (long long)f->n);
+    if (g->sh_degree < 0 || g->sh_degree > 3) return gs_fail(GS_ERR_INVALID, "sh_degree must be in [0, 3]");
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+        return gs_fail(GS_ERR_INVALID, "a Gaussian parameter pointer is null");
+    return GS_OK;
+}
+
+gs_status check_opts(const gs_raster_opts* o) {
+    if (!o) return gs_fail(GS_ERR_INVALID, "opts is null");
+    if (o->raster_batch != 0 && o->raster_batch != 64 && o->raster_batch != 128 && o->raster_batch != 256)
+        return gs_fail(GS_ERR_INVALID, "raster_batch must be 0, 64, 128 or 256");
+    if (o->persistent_blocks < 0 || o->persistent_blocks > 65536)
+        return gs_fail(GS_ERR_INVALID, "persistent_blocks must be in [0, 65536]");
+    if (!(o->near_plane > 0.f)) return gs_fail(GS_ERR_INVALID, "near_plane must be > 0");
+    return GS_OK;
+}
+
+}  // namespace
+
+struct gs_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+const char* gs_last_error(void) { return g_err; }
+const char* gs_version(void) { return "gsmi 0.1 (gfx950)"; }
+
+gs_status gs_frame_workspace_size(int64_t n, int32_t n_views, const int32_t* widths,
+                                  const int32_t* heights, int64_t max_instances, uint64_t* bytes) {
+    GS_TRY(check_views(n, n_views, widths, heights, max_instances));
+    if (!bytes) return gs_fail(GS_ERR_INVALID, "bytes is null");
+    gs_frame f;
+    memset(&f, 0, sizeof f);
+    f.n = n;
+    f.V = n_views;
+    f.E = n * n_views;
+    f.cap = max_instances;
+    fill_views(&f, widths, heights);
+    *bytes = layout_for(&f).total;
+    return GS_OK;
+}
+
+gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
+                          const int32_t* heights, int64_t max_instances, void* workspace,
+                          uint64_t workspace_bytes, gs_frame** out) {
+    GS_TRY(check_views(n, n_views, widths, heights, max_instances));
+    if (!out || !workspace) return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (((uintptr_t)workspace & 255) != 0) return gs_fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
+    gs_frame* f = (gs_frame*)calloc(1, sizeof(gs_frame));
+    if (!f) return gs_fail(GS_ERR_INVALID, "out of host memory");
+    f->n = n;
+    f->V = n_views;
+    f->E = n * n_views;
+    f->cap = max_instances;
+    fill_views(f, widths, heights);
+    Layout L = layout_for(f);
+    if (workspace_bytes < L.total) {
+        free(f);
+        return gs_fail(GS_ERR_INVALID, "workspace too small (%llu < %llu)",
+                       (unsigned long long)workspace_bytes, (unsigned long long)L.total);
+    }
+    char* b = (char*)workspace;
+    f->depth_key = (u32*)(b + L.off[0]);
+    f->tiles_touched = (u32*)(b + L.off[1]);
+    f->rect = (uint2*)(b + L.off[2]);
+    f->splat = (float4*)(b + L.off[3]);
+    f->flags = (u32*)(b + L.off[4]);
+    f->vkeys[0] = (u32*)(b + L.off[5]);
+    f->vkeys[1] = (u32*)(b + L.off[6]);
+    f->vvals[0] = (u32*)(b + L.off[7]);
+    f->vvals[1] = (u32*)(b + L.off[8]);
+    f->inst_off = (u32*)(b + L.off[9]);
+    f->ikeys[0] = (u32*)(b + L.off[10]);
+    f->ikeys[1] = (u32*)(b + L.off[11]);
+    f->ivals[0] = (u32*)(b + L.off[12]);
+    f->ivals[1] = (u32*)(b + L.off[13]);
+    f->ranges = (uint2*)(b + L.off[14]);
+    f->tkeys[0] = (u32*)(b + L.off[15]);
+    f->tkeys[1] = (u32*)(b + L.off[16]);
+    f->tvals[0] = (u32*)(b + L.off[17]);
+    f->tvals[1] = (u32*)(b + L.off[18]);
+    f->T_final = (float*)(b + L.off[19]);
+    f->n_contrib = (u32*)(b + L.off[20]);
+    f->splat_grad = (float*)(b + L.off[21]);
+    f->counters = (u32*)(b + L.off[22]);
+    f->radix_hist = (u32*)(b + L.off[23]);
+    f->scan_part = (u32*)(b + L.off[24]);
+    f->d_views = (gs_view_info*)(b + L.off[25]);
+    // the slots holding sorted results depend only on the pass counts
+    f->vsorted = (((31 + 7) / 8) & 1);
+    f->isorted = (((f->tile_bits + 7) / 8) & 1);
+    f->tsorted = (((24 + 7) / 8) & 1);
+    hipError_t e = hipMemcpy(f->d_views, f->views, sizeof(gs_view_info) * n_views, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(f->counters, 0, 64);
+    if (e != hipSuccess) {
+        free(f);
+        return gs_fail(GS_ERR_HIP, "frame upload failed: %s", hipGetErrorString(e));
+    }
+    *out = f;
+    return GS_OK;
+}
+
+gs_status gs_frame_destroy(gs_frame* frame) {
+    free(frame);
+    return GS_OK;
+}
+
+gs_status gs_frame_buffer(const gs_frame* f, int32_t which, void** ptr, int64_t* count) {
+    GS_TRY(check_frame(f));
+    if (!ptr || !count) return gs_fail(GS_ERR_INVALID, "null pointer");
+    switch (which) {
+        case GS_BUF_DEPTH_KEY: *ptr = f->depth_key; *count = f->E; break;
+        case GS_BUF_TILES_TOUCHED: *ptr = f->tiles_touched; *count = f->E; break;
+        case GS_BUF_RECT: *ptr = f->rect; *count = 2 * f->E; break;
+        case GS_BUF_SPLAT: *ptr = f->splat; *count = 12 * f->E; break;
+        case GS_BUF_SORTED_ENTRIES: *ptr = f->vvals[f->vsorted]; *count = f->E; break;
+        case GS_BUF_INST_TILE: *ptr = f->ikeys[f->isorted]; *count = f->cap; break;
+        case GS_BUF_INST_ENTRY: *ptr = f->ivals[f->isorted]; *count = f->cap; break;
+        case GS_BUF_RANGES: *ptr = f->ranges; *count = 2 * (int64_t)f->T; break;
+        case GS_BUF_T_FINAL: *ptr = f->T_final; *count = f->P; break;
+        case GS_BUF_N_CONTRIB: *ptr = f->n_contrib; *count = f->P; break;
+        case GS_BUF_SPLAT_GRAD: *ptr = f->splat_grad; *count = 9 * f->E; break;
+        case GS_BUF_COUNTERS: *ptr = f->counters; *count = 16; break;
+        default: return gs_fail(GS_ERR_INVALID, "unknown buffer id %d", which);
+    }
+    return GS_OK;
+}
+
+gs_status gs_frame_status(gs_frame* f, void* stream, int64_t* n_visible, int64_t* n_instances,
+                          int32_t* overflow) {
+    GS_TRY(check_frame(f));
+    u32 h[8];
+    GS_HIP(hipStreamSynchronize((hipStream_t)stream));
+    GS_HIP(hipMemcpy(h, f->counters, sizeof h, hipMemcpyDeviceToHost));
+    if (n_visible) *n_visible = h[0];
+    if (n_instances) *n_instances = h[1];
+    if (overflow) *overflow = (int32_t)h[2];
+    return h[2] ? gs_fail(GS_ERR_CAPACITY, "instance capacity %lld exceeded (%u needed)",
+                          (long long)f->cap, h[1])
+                : GS_OK;
+}
+
+gs_status gs_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,
+                     const gs_raster_opts* opts, void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_gaussians(f, g));
+    GS_TRY(check_opts(opts));
+    if (!cameras) return gs_fail(GS_ERR_INVALID, "cameras is null");
+    return gs_launch_project(f, g, cameras, opts->near_plane, (hipStream_t)stream);
+}
+
+gs_status gs_render(gs_frame* f, const gs_raster_opts* opts, float* images, void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_opts(opts));
+    if (!images) return gs_fail(GS_ERR_INVALID, "images is null");
+    hipStream_t s = (hipStream_t)stream;
+    GS_TRY(gs_launch_bin(f, s, opts->persistent_blocks > 0));
+    return gs_launch_raster_fwd(f, opts, images, s);
+}
+
+gs_status gs_render_backward(gs_frame* f, const gs_raster_opts* opts, const float* dL_dimages,
+                             void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_opts(opts));
+    if (!dL_dimages) return gs_fail(GS_ERR_INVALID, "dL_dimages is null");
+    hipStream_t s = (hipStream_t)stream;
+    GS_TRY(gs_fill_u32((u32*)f->splat_grad, 0u, 9 * f->E, s));
+    return gs_launch_raster_bwd(f, opts, dL_dimages, s);
+}
+
+gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,
+                              const gs_raster_opts* opts, const gs_gaussian_grads* grads,
+                              float* accum, float* denom, void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_gaussians(f, g));
+    GS_TRY(check_opts(opts));
+    if (!cameras || !grads) return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (f->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
+        return gs_fail(GS_ERR_INVALID, "a gradient pointer is null");
+    if ((accum == nullptr) != (denom == nullptr))
+        return gs_fail(GS_ERR_INVALID, "accum and denom must both be set or both be null");
+    return gs_launch_project_bwd(f, g, cameras, opts->near_plane, grads, accum, denom,
+                                 (hipStream_t)stream);
+}
+
+gs_status gs_sort_workspace_size(int64_t n, uint64_t* bytes) {
+    if (n < 0 || n >= ((int64_t)1 << 31) - 1 || !bytes) return gs_fail(GS_ERR_INVALID, "bad argument");
+    const int G = gs_radix_partitions(n);
+    *bytes = 2 * align256(4 * (uint64_t)(n > 0 ? n : 1)) + align256(4 * 256 * (uint64_t)G) +
+             align256(4 * (GS_SCAN_PARTS + 8));
+    return GS_OK;
+}
+
+gs_status gs_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int32_t key_bits,
+                        void* workspace, uint64_t workspace_bytes, void* stream) {
+    if (key_bits < 1 || key_bits > 32) return gs_fail(GS_ERR_INVALID, "key_bits must be in [1, 32]");
+    uint64_t need;
+    GS_TRY(gs_sort_workspace_size(n, &need));
+    if (n == 0) return GS_OK;
+    if (!keys || !vals || !workspace) return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (workspace_bytes < need) return gs_fail(GS_ERR_INVALID, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* b = (char*)workspace;
+    const uint64_t nb = align256(4 * (uint64_t)n);
+    const int G = gs_radix_partitions(n);
+    u32* k[2] = {keys, (u32*)b};
+    u32* v[2] = {vals, (u32*)(b + nb)};
+    u32* hist = (u32*)(b + 2 * nb);
+    u32* part = (u32*)(b + 2 * nb + align256(4 * 256 * (uint64_t)G));
+    int slot = 0;
+    GS_TRY(gs_radix_sort(k, v, nullptr, (u32)n, key_bits, G, hist, part, &slot, s));
+    if (slot == 1) {
+        GS_HIP(hipMemcpyAsync(keys, k[1], 4 * n, hipMemcpyDeviceToDevice, s));
+        GS_HIP(hipMemcpyAsync(vals, v[1], 4 * n, hipMemcpyDeviceToDevice, s));
+    }
+    return GS_OK;
+}
+
+gs_status gs_step_graph_create(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,
+                               const gs_raster_opts* opts, float* images, const float* targets,
+                               float l1_scale, float* loss, float* dL_dimages,
+                               const gs_gaussian_grads* grads, float* accum, float* denom,
+                               void* stream, gs_graph** out) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_gaussians(f, g));
+    GS_TRY(check_opts(opts));
+    if (!cameras || !images || !targets || !loss || !dL_dimages || !grads || !out)
+        return gs_fail(GS_ERR_INVALID, "null pointer");
+    hipStream_t cs;
+    GS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    gs_status st = GS_OK;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return gs_fail(GS_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+    }
+    const int64_t numel = 3 * f->P;
+    st = gs_project(f, g, cameras, opts, cs);
+    if (st == GS_OK) st = gs_render(f, opts, images, cs);
+    if (st == GS_OK) st = gs_fill_u32((u32*)loss, 0u, 1, cs);
+    if (st == GS_OK) st = gs_l1_loss_grad(images, targets, numel, l1_scale, loss, dL_dimages, cs);
+    if (st == GS_OK) st = gs_render_backward(f, opts, dL_dimages, cs);
+    if (st == GS_OK) st = gs_project_backward(f, g, cameras, opts, grads, accum, denom, cs);
+    e = hipStreamEndCapture(cs, &graph);
+    if (st == GS_OK && e != hipSuccess) st = gs_fail(GS_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    if (st == GS_OK) {
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = gs_fail(GS_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != GS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    gs_graph* gr = (gs_graph*)calloc(1, sizeof(gs_graph));
+    gr->graph = graph;
+    gr->exec = exec;
+    *out = gr;
+    (void)stream;
+    return GS_OK;
+}
+
+gs_status gs_graph_launch(gs_graph* graph, void* stream) {
+    if (!graph) return gs_fail(GS_ERR_INVALID, "graph is null");
+    GS_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return GS_OK;
+}
+
+gs_status gs_graph_destroy(gs_graph* graph) {
+    if (!graph) return GS_OK;
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    free(graph);
+    return GS_OK;
+}
+
+}  // extern "C"

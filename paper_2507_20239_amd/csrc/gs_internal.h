@@ -1,0 +1,174 @@
+// Internal declarations shared by the HIP translation units of libgsmi.
+// Target: gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsmi.h"
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+// Rendering constants (FP32 values; the CPU reference uses the same values).
+#define GS_ALPHA_MAX 0.99f
+#define GS_ALPHA_MIN (1.0f / 255.0f)
+#define GS_T_MIN 1e-4f
+#define GS_DILATION 0.3f
+#define GS_FOV_CLAMP 1.3f
+#define GS_FOOTPRINT_INFLATE (1.0 + 1.0 / 1024.0)
+
+#define GS_WAVE 64
+#define GS_BLOCK 256
+
+// Per-view constants kept in device memory (32 bytes).
+struct gs_view_info {
+    int32_t width, height, tiles_x, tiles_y;
+    int32_t tile_base;   // first global tile id of the view
+    int32_t pad;
+    int64_t pix_base;    // first pixel of the view in the per-pixel arrays
+};
+
+struct gs_frame {
+    int64_t n;           // Gaussians
+    int32_t V;           // views
+    int64_t E;           // entries = V * n
+    int64_t cap;         // instance capacity
+    int32_t T;           // tiles over all views
+    int64_t P;           // pixels over all views
+    gs_view_info views[GS_MAX_VIEWS];
+    gs_view_info* d_views;
+
+    // projection
+    u32* depth_key;      // [E]
+    u32* tiles_touched;  // [E]
+    uint2* rect;         // [E]
+    float4* splat;       // [E][3]
+    // visible-entry compaction + depth sort (ping-pong)
+    u32* flags;          // [E] scan input / output
+    u32* vkeys[2];       // [E]
+    u32* vvals[2];       // [E]
+    u32* inst_off;       // [E] instance offsets in depth order
+    int vsorted;         // ping-pong slot holding the sorted entries
+    // instances (ping-pong)
+    u32* ikeys[2];       // [cap]
+    u32* ivals[2];       // [cap]
+    int isorted;
+    uint2* ranges;       // [T]
+    // heavy-first tile order for persistent launches
+    u32* tkeys[2];       // [T]
+    u32* tvals[2];       // [T]
+    int tsorted;
+    int32_t tile_bits;   // bits needed for a global tile id
+    // per pixel
+    float* T_final;      // [P]
+    u32* n_contrib;      // [P]
+    // per splat gradient
+    float* splat_grad;   // [E][9]
+    // counters: [0] visible, [1] instances, [2] overflow, [3] fwd queue, [4] bwd queue
+    u32* counters;
+    // sort scratch
+    u32* radix_hist;     // [256 * G]
+    u32* scan_part;      // [GS_SCAN_PARTS + 1]
+    int G_vis, G_inst, G_tile;
+};
+
+#define GS_SCAN_PARTS 1024
+
+// ------------------------------------------------------------------------
+// Status
+// ------------------------------------------------------------------------
+gs_status gs_fail(gs_status s, const char* fmt, ...);
+gs_status gs_check_launch(const char* what);
+
+#define GS_HIP(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return gs_fail(GS_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GS_TRY(x)                        \
+    do {                                 \
+        gs_status s_ = (x);              \
+        if (s_ != GS_OK) return s_;      \
+    } while (0)
+
+// ------------------------------------------------------------------------
+// Launch helpers implemented in the .hip files
+// ------------------------------------------------------------------------
+// fill a u32 array with a value (graph-capture safe replacement for memset)
+gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s);
+
+// exclusive scan of u32 values; the length is n_dev[0] when n_dev != NULL,
+// else n_host.  total (device, may be NULL) receives the sum.  `part` needs
+// GS_SCAN_PARTS + 1 u32.
+gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
+                            u32* part, hipStream_t s);
+
+// stable LSD radix sort on the low `bits` bits.  Buffers k[0]/v[0] hold the input;
+// returns in *slot the buffer index (0 or 1) that holds the result.
+// hist needs 256 * G u32.
+gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int bits, int G,
+                        u32* hist, u32* part, int* slot, hipStream_t s);
+
+int gs_radix_partitions(int64_t capacity);
+
+gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
+                            float near_plane, hipStream_t s);
+gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first);
+gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* images,
+                               hipStream_t s);
+gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float* dL,
+                               hipStream_t s);
+gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
+                                float near_plane, const gs_gaussian_grads* gr, float* accum,
+                                float* denom, hipStream_t s);
+
+// ------------------------------------------------------------------------
+// Device helpers
+// ------------------------------------------------------------------------
+#ifdef __HIPCC__
+__device__ __forceinline__ int lane_id() {
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of `mask` in lanes below the calling lane
+__device__ __forceinline__ u32 popc_below(u64 mask) {
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+}
+
+// DPP move with a compile-time control word; lanes whose source is outside
+// the row (or whose row is masked off) read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_mov_zero(float x) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK, 0xF, true));
+}
+
+// Sum over the 64 lanes of a wave; the total lands in lane 63.  Must be
+// called with all 64 lanes active.  row_shr 1/2/4/8 builds each row's
+// inclusive prefix, row_bcast15 and row_bcast31 carry it across rows.
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+    x += dpp_mov_zero<0x111, 0xF>(x);  // row_shr:1
+    x += dpp_mov_zero<0x112, 0xF>(x);  // row_shr:2
+    x += dpp_mov_zero<0x114, 0xF>(x);  // row_shr:4
+    x += dpp_mov_zero<0x118, 0xF>(x);  // row_shr:8
+    x += dpp_mov_zero<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_mov_zero<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// Alpha of one splat at a pixel centre, shared by the forward and the
+// adjoint so both evaluate bit-identical values.  p0 = (mean hi x, y, mean lo x, y),
+// p1 = (conic a, b, c, opacity).  Returns o G (before the 0.99 clamp).
+__device__ __forceinline__ float splat_raw_alpha(float4 p0, float4 p1, float pxc, float pyc,
+                                                 float& G, float& dx, float& dy) {
+    dx = (pxc - p0.x) - p0.z;
+    dy = (pyc - p0.y) - p0.w;
+    const float q = fmaf(p1.x * dx, dx, p1.z * dy * dy);      // a dx^2 + c dy^2
+    const float power = fmaf(-0.5f, q, -(p1.y * dx) * dy);    // -(q/2) - b dx dy
+    G = __expf(power);
+    return p1.w * G;
+}
+#endif

@@ -1,0 +1,573 @@
+// Projection of 3D Gaussians into one or more views, and its adjoint.
+//
+// Forward (Preliminary of the paper: Sigma = R S S^T R^T, Sigma' = J W Sigma
+// W^T J^T; Eq. 2's colour c_i from spherical harmonics): one thread per
+// Gaussian, looping over the views so the parameters are read from HBM once
+// (structure-of-arrays, coalesced).  The camera-space position and the
+// screen-space mean are evaluated in FP64 (cheap on CDNA4 for this
+// HBM-bound kernel) and the mean is stored as an FP32 hi/lo pair, which keeps
+// the pixel offset exact to ~1e-7 px on 1600-pixel images.  The depth used
+// for ordering is the FP32 rounding of the FP64 depth evaluated as a fused
+// multiply-add chain.
+//
+// Adjoint: one thread per Gaussian again; it recomputes the projection
+// (instead of storing intermediates), applies the chain rule to the raw
+// parameters, sums over views in registers (deterministic, no atomics) and
+// accumulates the densification statistic: the norm of the position
+// gradient in NDC units (Preliminary, last paragraph), one term per view in
+// which the Gaussian was rendered.
+#include "gs_internal.h"
+
+namespace {
+
+// Real spherical-harmonic constants, Condon-Shortley phase:
+// Y00 = 1/(2 sqrt(pi)); C1 = sqrt(3/(4 pi)); C2a = sqrt(15/(4 pi)); C2b = sqrt(5/(16 pi));
+// C2c = sqrt(15/(16 pi)); C3a = sqrt(35/(32 pi)); C3b = sqrt(105/(4 pi));
+// C3c = sqrt(21/(32 pi)); C3d = sqrt(7/(16 pi)); C3e = sqrt(105/(16 pi)).
+constexpr float SH_Y00 = 0.28209479177387814f;
+constexpr float SH_C1 = 0.4886025119029199f;
+constexpr float SH_C2a = 1.0925484305920792f;
+constexpr float SH_C2b = 0.31539156525252005f;
+constexpr float SH_C2c = 0.5462742152960396f;
+constexpr float SH_C3a = 0.5900435899266435f;
+constexpr float SH_C3b = 2.890611442640554f;
+constexpr float SH_C3c = 0.4570457994644658f;
+constexpr float SH_C3d = 0.3731763325901154f;
+constexpr float SH_C3e = 1.445305721320277f;
+
+template <int DEG>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
+    Y[0] = SH_Y00;
+    if (DEG >= 1) {
+        Y[1] = -SH_C1 * y;
+        Y[2] = SH_C1 * z;
+        Y[3] = -SH_C1 * x;
+    }
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = SH_C2a * x * y;
+        Y[5] = -SH_C2a * y * z;
+        Y[6] = SH_C2b * (2.f * zz - xx - yy);
+        Y[7] = -SH_C2a * x * z;
+        Y[8] = SH_C2c * (xx - yy);
+        if (DEG >= 3) {
+            Y[9] = -SH_C3a * y * (3.f * xx - yy);
+            Y[10] = SH_C3b * x * y * z;
+            Y[11] = -SH_C3c * y * (4.f * zz - xx - yy);
+            Y[12] = SH_C3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+            Y[13] = -SH_C3c * x * (4.f * zz - xx - yy);
+            Y[14] = SH_C3e * z * (xx - yy);
+            Y[15] = -SH_C3a * x * (xx - 3.f * yy);
+        }
+    }
+}
+
+// Gradient of each polynomial Y_k w.r.t. (x, y, z), contracted with w_k:
+// out = sum_k w_k grad Y_k.
+template <int DEG>
+__device__ __forceinline__ void sh_grad_contract(float x, float y, float z, const float* w,
+                                                 float& gx, float& gy, float& gz) {
+    gx = gy = gz = 0.f;
+    if (DEG >= 1) {
+        gy -= SH_C1 * w[1];
+        gz += SH_C1 * w[2];
+        gx -= SH_C1 * w[3];
+    }
+    if (DEG >= 2) {
+        gx += SH_C2a * y * w[4];
+        gy += SH_C2a * x * w[4];
+        gy -= SH_C2a * z * w[5];
+        gz -= SH_C2a * y * w[5];
+        gx -= 2.f * SH_C2b * x * w[6];
+        gy -= 2.f * SH_C2b * y * w[6];
+        gz += 4.f * SH_C2b * z * w[6];
+        gx -= SH_C2a * z * w[7];
+        gz -= SH_C2a * x * w[7];
+        gx += 2.f * SH_C2c * x * w[8];
+        gy -= 2.f * SH_C2c * y * w[8];
+        if (DEG >= 3) {
+            const float xx = x * x, yy = y * y, zz = z * z;
+            gx -= SH_C3a * 6.f * x * y * w[9];
+            gy -= SH_C3a * 3.f * (xx - yy) * w[9];
+            gx += SH_C3b * y * z * w[10];
+            gy += SH_C3b * x * z * w[10];
+            gz += SH_C3b * x * y * w[10];
+            gx += 2.f * SH_C3c * x * y * w[11];
+            gy -= SH_C3c * (4.f * zz - xx - 3.f * yy) * w[11];
+            gz -= 8.f * SH_C3c * y * z * w[11];
+            gx -= 6.f * SH_C3d * x * z * w[12];
+            gy -= 6.f * SH_C3d * y * z * w[12];
+            gz += SH_C3d * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
+            gx -= SH_C3c * (4.f * zz - 3.f * xx - yy) * w[13];
+            gy += 2.f * SH_C3c * x * y * w[13];
+            gz -= 8.f * SH_C3c * x * z * w[13];
+            gx += 2.f * SH_C3e * x * z * w[14];
+            gy -= 2.f * SH_C3e * y * z * w[14];
+            gz += SH_C3e * (xx - yy) * w[14];
+            gx -= SH_C3a * 3.f * (xx - yy) * w[15];
+            gy += SH_C3a * 6.f * x * y * w[15];
+        }
+    }
+}
+
+struct ProjArgs {
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* logits;
+    const float* sh;
+    int64_t n;
+    int V;
+    float near_plane;
+    const gs_camera* cams;
+    const gs_view_info* views;
+    u32* depth_key;
+    u32* tiles_touched;
+    uint2* rect;
+    float4* splat;
+};
+
+// Per-Gaussian activated parameters.
+struct Activated {
+    float s[3];        // scales
+    float q[4];        // unit quaternion (w, x, y, z)
+    float qnorm;
+    float o;           // opacity
+    float R[9];        // rotation, row-major
+    float Sig[6];      // Sigma: 00 01 02 11 12 22
+};
+
+__device__ __forceinline__ void activate(const ProjArgs& a, int64_t i, float mu[3], Activated& g) {
+    const int64_t n = a.n;
+    mu[0] = a.means[i];
+    mu[1] = a.means[n + i];
+    mu[2] = a.means[2 * n + i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.s[k] = expf(a.log_scales[k * n + i]);
+    float q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
+    g.qnorm = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const float inv = 1.0f / g.qnorm;
+    const float w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
+    g.q[0] = w; g.q[1] = x; g.q[2] = y; g.q[3] = z;
+    g.o = 1.0f / (1.0f + expf(-a.logits[i]));
+    g.R[0] = 1.f - 2.f * (y * y + z * z); g.R[1] = 2.f * (x * y - w * z); g.R[2] = 2.f * (x * z + w * y);
+    g.R[3] = 2.f * (x * y + w * z); g.R[4] = 1.f - 2.f * (x * x + z * z); g.R[5] = 2.f * (y * z - w * x);
+    g.R[6] = 2.f * (x * z - w * y); g.R[7] = 2.f * (y * z + w * x); g.R[8] = 1.f - 2.f * (x * x + y * y);
+    const float s0 = g.s[0] * g.s[0], s1 = g.s[1] * g.s[1], s2 = g.s[2] * g.s[2];
+    const float* R = g.R;
+    g.Sig[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
+    g.Sig[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
+    g.Sig[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
+    g.Sig[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
+    g.Sig[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
+    g.Sig[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+}
+
+// Camera-space quantities of one Gaussian in one view.
+struct ViewProj {
+    double tx, ty, tz;     // FP64 camera-space position
+    float t[3];            // the same in FP32
+    float xt, yt;          // clamped x/z, y/z
+    bool clx, cly;         // clamp active
+    float T[6];            // J W, 2x3 row-major
+    float TS[6];           // T Sigma
+    float cov[3];          // Sigma' 00 01 11 (with dilation)
+    float conic[3];
+};
+
+__device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_info& vi,
+                                             float near_plane, const float mu[3],
+                                             const Activated& g, ViewProj& p) {
+    const double x = mu[0], y = mu[1], z = mu[2];
+    p.tx = fma((double)c.R[0], x, fma((double)c.R[1], y, fma((double)c.R[2], z, (double)c.t[0])));
+    p.ty = fma((double)c.R[3], x, fma((double)c.R[4], y, fma((double)c.R[5], z, (double)c.t[1])));
+    p.tz = fma((double)c.R[6], x, fma((double)c.R[7], y, fma((double)c.R[8], z, (double)c.t[2])));
+    if (!(p.tz > (double)near_plane) || !isfinite(p.tx) || !isfinite(p.ty)) return false;
+    p.t[0] = (float)p.tx;
+    p.t[1] = (float)p.ty;
+    p.t[2] = (float)p.tz;
+    const double limx = (double)GS_FOV_CLAMP * (0.5 * vi.width / (double)c.fx);
+    const double limy = (double)GS_FOV_CLAMP * (0.5 * vi.height / (double)c.fy);
+    double xr = p.tx / p.tz, yr = p.ty / p.tz;
+    p.clx = xr < -limx || xr > limx;
+    p.cly = yr < -limy || yr > limy;
+    xr = xr < -limx ? -limx : (xr > limx ? limx : xr);
+    yr = yr < -limy ? -limy : (yr > limy ? limy : yr);
+    p.xt = (float)xr;
+    p.yt = (float)yr;
+    const float iz = 1.0f / p.t[2];
+    const float J00 = c.fx * iz, J02 = -c.fx * p.xt * iz;
+    const float J11 = c.fy * iz, J12 = -c.fy * p.yt * iz;
+    // T = J W
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        p.T[b] = J00 * c.R[b] + J02 * c.R[6 + b];
+        p.T[3 + b] = J11 * c.R[3 + b] + J12 * c.R[6 + b];
+    }
+    const float* S = g.Sig;
+    // T Sigma (Sigma symmetric: rows 00 01 02 / 01 11 12 / 02 12 22)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const float* Tr = p.T + 3 * u;
+        p.TS[3 * u + 0] = Tr[0] * S[0] + Tr[1] * S[1] + Tr[2] * S[2];
+        p.TS[3 * u + 1] = Tr[0] * S[1] + Tr[1] * S[3] + Tr[2] * S[4];
+        p.TS[3 * u + 2] = Tr[0] * S[2] + Tr[1] * S[4] + Tr[2] * S[5];
+    }
+    p.cov[0] = p.TS[0] * p.T[0] + p.TS[1] * p.T[1] + p.TS[2] * p.T[2] + GS_DILATION;
+    p.cov[1] = p.TS[0] * p.T[3] + p.TS[1] * p.T[4] + p.TS[2] * p.T[5];
+    p.cov[2] = p.TS[3] * p.T[3] + p.TS[4] * p.T[4] + p.TS[5] * p.T[5] + GS_DILATION;
+    const float det = p.cov[0] * p.cov[2] - p.cov[1] * p.cov[1];
+    const float idet = 1.0f / det;
+    p.conic[0] = p.cov[2] * idet;
+    p.conic[1] = -p.cov[1] * idet;
+    p.conic[2] = p.cov[0] * idet;
+    return true;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    float mu[3];
+    Activated g;
+    activate(a, i, mu, g);
+    float f[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) f[k][ch] = a.sh[((int64_t)k * 3 + ch) * n + i];
+
+    for (int v = 0; v < a.V; ++v) {
+        const gs_camera c = a.cams[v];
+        const gs_view_info vi = a.views[v];
+        const int64_t e = (int64_t)v * n + i;
+        ViewProj p;
+        const bool ok = view_project(c, vi, a.near_plane, mu, g, p);
+        const float tzf = (float)p.tz;
+        a.depth_key[e] = __float_as_uint(tzf);
+        u32 tt = 0;
+        uint2 rc = make_uint2(0u, 0u);
+        if (ok && g.o >= GS_ALPHA_MIN) {
+            const double u = (double)c.fx * p.tx / p.tz + (double)c.cx;
+            const double w = (double)c.fy * p.ty / p.tz + (double)c.cy;
+            // footprint: bounding box of { o G >= 1/255 }, inflated by 2^-10
+            const float L = 2.0f * logf(255.0f * g.o);
+            const double ex = (double)(sqrtf(L * p.cov[0]) * (float)GS_FOOTPRINT_INFLATE);
+            const double ey = (double)(sqrtf(L * p.cov[2]) * (float)GS_FOOTPRINT_INFLATE);
+            double x0 = ceil(u - ex - 0.5), x1 = floor(u + ex - 0.5);
+            double y0 = ceil(w - ey - 0.5), y1 = floor(w + ey - 0.5);
+            x0 = x0 < 0.0 ? 0.0 : x0;
+            y0 = y0 < 0.0 ? 0.0 : y0;
+            x1 = x1 > vi.width - 1 ? (double)(vi.width - 1) : x1;
+            y1 = y1 > vi.height - 1 ? (double)(vi.height - 1) : y1;
+            if (x0 <= x1 && y0 <= y1) {
+                const u32 tx0 = (u32)x0 / GS_TILE, tx1 = (u32)x1 / GS_TILE;
+                const u32 ty0 = (u32)y0 / GS_TILE, ty1 = (u32)y1 / GS_TILE;
+                tt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                // colour for the direction from the camera centre C = -R^T t
+                const float cx = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
+                const float cy = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
+                const float cz = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
+                float dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
+                const float idist = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                dx *= idist; dy *= idist; dz *= idist;
+                float Y[16];
+                sh_eval<DEG>(dx, dy, dz, Y);
+                float rgb[3];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    float acc = 0.5f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) acc = fmaf(Y[k], f[k][ch], acc);
+                    rgb[ch] = acc > 0.f ? acc : 0.f;
+                }
+                const float uh = (float)u, wh = (float)w;
+                const float ul = (float)(u - (double)uh), wl = (float)(w - (double)wh);
+                a.splat[3 * e + 0] = make_float4(uh, wh, ul, wl);
+                a.splat[3 * e + 1] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o);
+                a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
+            }
+        }
+        a.tiles_touched[e] = tt;
+        a.rect[e] = rc;
+    }
+}
+
+struct ProjBwdArgs {
+    ProjArgs p;
+    const u32* tiles_touched;
+    const float* splat_grad;
+    float* d_means;
+    float* d_log_scales;
+    float* d_quats;
+    float* d_logits;
+    float* d_sh;
+    float* accum;
+    float* denom;
+};
+
+template <int DEG>
+__global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const ProjArgs& a = b.p;
+    const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    float mu[3];
+    Activated g;
+    activate(a, i, mu, g);
+    float f[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) f[k][ch] = a.sh[((int64_t)k * 3 + ch) * n + i];
+
+    float dmu[3] = {0.f, 0.f, 0.f};
+    float dls[3] = {0.f, 0.f, 0.f};
+    float dq[4] = {0.f, 0.f, 0.f, 0.f};
+    float dlogit = 0.f;
+    float dsh[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) dsh[k][0] = dsh[k][1] = dsh[k][2] = 0.f;
+    float st_acc = 0.f, st_den = 0.f;
+    // gradient w.r.t. Sigma (symmetric, 6 entries), summed over views
+    float GSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    for (int v = 0; v < a.V; ++v) {
+        const int64_t e = (int64_t)v * n + i;
+        if (b.tiles_touched[e] == 0) continue;
+        const gs_camera c = a.cams[v];
+        const gs_view_info vi = a.views[v];
+        ViewProj p;
+        if (!view_project(c, vi, a.near_plane, mu, g, p)) continue;
+        float gr[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gr[k] = b.splat_grad[9 * e + k];
+
+        // densification statistic: position gradient in NDC units
+        {
+            const float gx = gr[0] * (0.5f * (float)vi.width);
+            const float gy = gr[1] * (0.5f * (float)vi.height);
+            st_acc += sqrtf(gx * gx + gy * gy);
+            st_den += 1.f;
+        }
+        // opacity = sigmoid(logit)
+        dlogit += gr[5] * g.o * (1.f - g.o);
+
+        // colour = max(0, sum_k Y_k f_k + 1/2), direction from the camera centre
+        {
+            const float cx = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
+            const float cy = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
+            const float cz = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
+            float dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
+            const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
+            const float idist = 1.0f / dist;
+            dx *= idist; dy *= idist; dz *= idist;
+            float Y[16];
+            sh_eval<DEG>(dx, dy, dz, Y);
+            float wk[16];
+#pragma unroll
+            for (int k = 0; k < K; ++k) wk[k] = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.5f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc = fmaf(Y[k], f[k][ch], acc);
+                const float gc = acc < 0.f ? 0.f : gr[6 + ch];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    dsh[k][ch] += Y[k] * gc;
+                    wk[k] += f[k][ch] * gc;
+                }
+            }
+            if (DEG > 0) {
+                float gdx, gdy, gdz;
+                sh_grad_contract<DEG>(dx, dy, dz, wk, gdx, gdy, gdz);
+                const float dd = dx * gdx + dy * gdy + dz * gdz;
+                dmu[0] += (gdx - dx * dd) * idist;
+                dmu[1] += (gdy - dy * dd) * idist;
+                dmu[2] += (gdz - dz * dd) * idist;
+            }
+        }
+
+        // conic -> Sigma': G_Sigma' = -Q G_Q Q with G_Q = [[ga, gb/2], [gb/2, gc]]
+        const float qa = p.conic[0], qb = p.conic[1], qc = p.conic[2];
+        const float ga = gr[2], gb = 0.5f * gr[3], gc = gr[4];
+        const float P00 = qa * ga + qb * gb, P01 = qa * gb + qb * gc;
+        const float P10 = qb * ga + qc * gb, P11 = qb * gb + qc * gc;
+        const float S00 = -(P00 * qa + P01 * qb);
+        const float S01 = -0.5f * ((P00 * qb + P01 * qc) + (P10 * qa + P11 * qb));
+        const float S11 = -(P10 * qb + P11 * qc);
+        // Sigma' = T Sigma T^T + 0.3 I: G_Sigma += T^T S T, G_T = 2 S T Sigma
+        const float* T = p.T;
+        {
+            // U = S T (2x3)
+            float U[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                U[k] = S00 * T[k] + S01 * T[3 + k];
+                U[3 + k] = S01 * T[k] + S11 * T[3 + k];
+            }
+            // T^T U (3x3 symmetric)
+            GSig[0] += T[0] * U[0] + T[3] * U[3];
+            GSig[1] += T[0] * U[1] + T[3] * U[4];
+            GSig[2] += T[0] * U[2] + T[3] * U[5];
+            GSig[3] += T[1] * U[1] + T[4] * U[4];
+            GSig[4] += T[1] * U[2] + T[4] * U[5];
+            GSig[5] += T[2] * U[2] + T[5] * U[5];
+        }
+        float GT[6];
+        {
+            const float* TS = p.TS;  // (T Sigma)
+            GT[0] = 2.f * (S00 * TS[0] + S01 * TS[3]);
+            GT[1] = 2.f * (S00 * TS[1] + S01 * TS[4]);
+            GT[2] = 2.f * (S00 * TS[2] + S01 * TS[5]);
+            GT[3] = 2.f * (S01 * TS[0] + S11 * TS[3]);
+            GT[4] = 2.f * (S01 * TS[1] + S11 * TS[4]);
+            GT[5] = 2.f * (S01 * TS[2] + S11 * TS[5]);
+        }
+        // T = J W:  G_J = G_T W^T (only J00, J02, J11, J12 vary)
+        const float* W = c.R;
+        const float GJ00 = GT[0] * W[0] + GT[1] * W[1] + GT[2] * W[2];
+        const float GJ02 = GT[0] * W[6] + GT[1] * W[7] + GT[2] * W[8];
+        const float GJ11 = GT[3] * W[3] + GT[4] * W[4] + GT[5] * W[5];
+        const float GJ12 = GT[3] * W[6] + GT[4] * W[7] + GT[5] * W[8];
+        const float tz = p.t[2], iz = 1.0f / tz, iz2 = iz * iz;
+        float gt0 = 0.f, gt1 = 0.f, gt2 = 0.f;
+        gt2 -= (GJ00 * c.fx + GJ11 * c.fy) * iz2;
+        if (!p.clx) {
+            gt0 -= GJ02 * c.fx * iz2;
+            gt2 += GJ02 * 2.f * c.fx * p.t[0] * iz2 * iz;
+        } else {
+            gt2 += GJ02 * c.fx * p.xt * iz2;
+        }
+        if (!p.cly) {
+            gt1 -= GJ12 * c.fy * iz2;
+            gt2 += GJ12 * 2.f * c.fy * p.t[1] * iz2 * iz;
+        } else {
+            gt2 += GJ12 * c.fy * p.yt * iz2;
+        }
+        // mean2d = (fx tx/tz + cx, fy ty/tz + cy)
+        gt0 += gr[0] * c.fx * iz;
+        gt1 += gr[1] * c.fy * iz;
+        gt2 -= (gr[0] * c.fx * p.t[0] + gr[1] * c.fy * p.t[1]) * iz2;
+        // t = W mu + t_w
+        dmu[0] += W[0] * gt0 + W[3] * gt1 + W[6] * gt2;
+        dmu[1] += W[1] * gt0 + W[4] * gt1 + W[7] * gt2;
+        dmu[2] += W[2] * gt0 + W[5] * gt1 + W[8] * gt2;
+    }
+
+    // Sigma = M M^T, M = R diag(s):  G_M = 2 G_Sigma M, then scales and rotation
+    {
+        const float G[9] = {GSig[0], GSig[1], GSig[2], GSig[1], GSig[3], GSig[4],
+                            GSig[2], GSig[4], GSig[5]};
+        float GR[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float Mk0 = g.R[k] * g.s[k];          // M[0][k]
+                const float Mk1 = g.R[3 + k] * g.s[k];      // M[1][k]
+                const float Mk2 = g.R[6 + k] * g.s[k];      // M[2][k]
+                const float GM = 2.f * (G[3 * r] * Mk0 + G[3 * r + 1] * Mk1 + G[3 * r + 2] * Mk2);
+                GR[3 * r + k] = GM * g.s[k];
+                dls[k] += GM * g.R[3 * r + k];              // dL/ds_k, scaled below
+            }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dls[k] *= g.s[k];
+        const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+        const float gw = 2.f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+        const float gx = 2.f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.f * x * GR[4] - w * GR[5] +
+                                z * GR[6] + w * GR[7] - 2.f * x * GR[8]);
+        const float gy = 2.f * (-2.f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] -
+                                w * GR[6] + z * GR[7] - 2.f * y * GR[8]);
+        const float gz = 2.f * (-2.f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] -
+                                2.f * z * GR[4] + y * GR[5] + x * GR[6] + y * GR[7]);
+        const float dot = w * gw + x * gx + y * gy + z * gz;
+        const float iq = 1.0f / g.qnorm;
+        dq[0] = (gw - w * dot) * iq;
+        dq[1] = (gx - x * dot) * iq;
+        dq[2] = (gy - y * dot) * iq;
+        dq[3] = (gz - z * dot) * iq;
+    }
+
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        b.d_means[k * n + i] = dmu[k];
+        b.d_log_scales[k * n + i] = dls[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b.d_quats[k * n + i] = dq[k];
+    b.d_logits[i] = dlogit;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) b.d_sh[((int64_t)k * 3 + ch) * n + i] = dsh[k][ch];
+    if (b.accum) {
+        b.accum[i] += st_acc;
+        b.denom[i] += st_den;
+    }
+}
+
+ProjArgs make_args(gs_frame* f, const gs_gaussians* g, const gs_camera* cams, float near_plane) {
+    ProjArgs a;
+    a.means = g->means;
+    a.log_scales = g->log_scales;
+    a.quats = g->quats;
+    a.logits = g->opacity_logits;
+    a.sh = g->sh;
+    a.n = g->n;
+    a.V = f->V;
+    a.near_plane = near_plane;
+    a.cams = cams;
+    a.views = f->d_views;
+    a.depth_key = f->depth_key;
+    a.tiles_touched = f->tiles_touched;
+    a.rect = f->rect;
+    a.splat = f->splat;
+    return a;
+}
+
+}  // namespace
+
+gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
+                            float near_plane, hipStream_t s) {
+    if (f->n == 0) return GS_OK;
+    ProjArgs a = make_args(f, g, cams, near_plane);
+    const unsigned blocks = (unsigned)((f->n + GS_BLOCK - 1) / GS_BLOCK);
+    switch (g->sh_degree) {
+        case 0: project_fwd_kernel<0><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+        case 1: project_fwd_kernel<1><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+        case 2: project_fwd_kernel<2><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+        default: project_fwd_kernel<3><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+    }
+    return gs_check_launch("project_fwd");
+}
+
+gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
+                                float near_plane, const gs_gaussian_grads* gr, float* accum,
+                                float* denom, hipStream_t s) {
+    if (f->n == 0) return GS_OK;
+    ProjBwdArgs b;
+    b.p = make_args(f, g, cams, near_plane);
+    b.tiles_touched = f->tiles_touched;
+    b.splat_grad = f->splat_grad;
+    b.d_means = gr->means;
+    b.d_log_scales = gr->log_scales;
+    b.d_quats = gr->quats;
+    b.d_logits = gr->opacity_logits;
+    b.d_sh = gr->sh;
+    b.accum = accum;
+    b.denom = denom;
+    const unsigned blocks = (unsigned)((f->n + GS_BLOCK - 1) / GS_BLOCK);
+    switch (g->sh_degree) {
+        case 0: project_bwd_kernel<0><<<blocks, GS_BLOCK, 0, s>>>(b); break;
+        case 1: project_bwd_kernel<1><<<blocks, GS_BLOCK, 0, s>>>(b); break;
+        case 2: project_bwd_kernel<2><<<blocks, GS_BLOCK, 0, s>>>(b); break;
+        default: project_bwd_kernel<3><<<blocks, GS_BLOCK, 0, s>>>(b); break;
+    }
+    return gs_check_launch("project_bwd");
+}

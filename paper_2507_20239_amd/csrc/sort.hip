@@ -1,0 +1,236 @@
+// Prefix sums and stable LSD radix sort for wave64 (gfx950).
+//
+// Both work on a length that may live in device memory, so a step can be
+// enqueued (or captured into a graph) without reading counts on the host:
+// the grid is a fixed number of partitions and every workgroup derives its
+// chunk from the device length.
+//
+// Radix pass = per-partition digit histogram -> exclusive scan of the
+// digit-major [256][G] count matrix -> stable scatter.  The scatter ranks
+// keys inside a workgroup with a wave-level multi-split: eight ballots give
+// each lane the mask of lanes holding the same digit, the popcount below the
+// lane is its rank within the item, and per-wave running counters in LDS
+// order successive items; a 4-wave exclusive scan orders the waves.
+#include "gs_internal.h"
+
+namespace {
+
+constexpr int RADIX_ITEMS = 8;                       // keys per lane per sub-batch
+constexpr int RADIX_SUB = GS_BLOCK * RADIX_ITEMS;    // 2048 keys per sub-batch
+
+__device__ __forceinline__ u32 dev_len(const u32* n_dev, u32 n_host) {
+    return n_dev ? *n_dev : n_host;
+}
+
+__device__ __forceinline__ void chunk_of(u32 n, u32 parts, u32 b, u32& beg, u32& end) {
+    u32 chunk = (n + parts - 1) / parts;
+    chunk = (chunk + 63u) & ~63u;
+    const u64 b0 = (u64)b * chunk;
+    beg = b0 < n ? (u32)b0 : n;
+    const u64 e0 = (u64)beg + chunk;
+    end = e0 < n ? (u32)e0 : n;
+}
+
+// Exclusive scan of one value per thread over a 256-thread workgroup.
+__device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* lds4, u32& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u32 x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        u32 y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds4[w] = x;
+    __syncthreads();
+    u32 wbase = 0;
+    for (int j = 0; j < w; ++j) wbase += lds4[j];
+    total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    __syncthreads();
+    return wbase + x - v;
+}
+
+__global__ void fill_u32_kernel(u32* p, u32 value, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) scan_reduce_kernel(const u32* in, const u32* n_dev,
+                                                               u32 n_host, u32* part) {
+    __shared__ u32 lds4[4];
+    u32 beg, end;
+    chunk_of(dev_len(n_dev, n_host), GS_SCAN_PARTS, blockIdx.x, beg, end);
+    u32 s = 0;
+    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) s += in[i];
+    u32 total;
+    block_exclusive_scan(s, lds4, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(GS_SCAN_PARTS) scan_parts_kernel(u32* part, u32* total) {
+    __shared__ u32 lds[GS_SCAN_PARTS / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const u32 v = part[t];
+    u32 x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        u32 y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    u32 base = 0, all = 0;
+    for (int j = 0; j < GS_SCAN_PARTS / 64; ++j) {
+        if (j < w) base += lds[j];
+        all += lds[j];
+    }
+    part[t] = base + x - v;
+    if (t == 0) {
+        part[GS_SCAN_PARTS] = all;
+        if (total) *total = all;
+    }
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, u32* out,
+                                                             const u32* n_dev, u32 n_host,
+                                                             const u32* part) {
+    __shared__ u32 lds4[4];
+    u32 beg, end;
+    chunk_of(dev_len(n_dev, n_host), GS_SCAN_PARTS, blockIdx.x, beg, end);
+    u32 carry = part[blockIdx.x];
+    for (u32 base = beg; base < end; base += GS_BLOCK * 4) {
+        u32 v[4];
+        u32 s = 0;
+        const u32 i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = (i0 + j < end) ? in[i0 + j] : 0u;
+            s += v[j];
+        }
+        u32 total;
+        u32 ex = block_exclusive_scan(s, lds4, total) + carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < end) out[i0 + j] = ex;
+            ex += v[j];
+        }
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) radix_hist_kernel(const u32* keys, const u32* n_dev,
+                                                              u32 n_host, int shift, int bits,
+                                                              u32* hist, int G) {
+    __shared__ u32 h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    u32 beg, end;
+    chunk_of(dev_len(n_dev, n_host), (u32)G, blockIdx.x, beg, end);
+    const u32 mask = (1u << bits) - 1u;
+    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    hist[(u64)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) radix_scatter_kernel(
+    const u32* __restrict__ kin, const u32* __restrict__ vin, u32* __restrict__ kout,
+    u32* __restrict__ vout, const u32* n_dev, u32 n_host, int shift, int bits,
+    const u32* __restrict__ offs, int G) {
+    __shared__ u32 whist[4][256];
+    __shared__ u32 base[256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const u32 n = dev_len(n_dev, n_host);
+    u32 beg, end;
+    chunk_of(n, (u32)G, blockIdx.x, beg, end);
+    base[tid] = offs[(u64)tid * G + blockIdx.x];
+    const u32 mask = (1u << bits) - 1u;
+    for (u32 sub = beg; sub < end; sub += RADIX_SUB) {
+        u32 k[RADIX_ITEMS], v[RADIX_ITEMS], d[RADIX_ITEMS], r[RADIX_ITEMS];
+        for (int j = lane; j < 256; j += 64) whist[w][j] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RADIX_ITEMS; ++i) {
+            const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
+            const bool valid = idx < end;
+            k[i] = valid ? kin[idx] : 0u;
+            v[i] = valid ? vin[idx] : 0u;
+            d[i] = (k[i] >> shift) & mask;
+            u64 peers = __ballot(valid);
+            for (int b = 0; b < bits; ++b) {
+                const bool bit = (d[i] >> b) & 1u;
+                const u64 bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            const u32 below = popc_below(peers);
+            const u32 cnt = (u32)__popcll(peers);
+            u32 prior = 0;
+            if (valid) prior = whist[w][d[i]];
+            r[i] = prior + below;
+            // the highest lane of each digit group advances the wave counter
+            if (valid && below == cnt - 1u) whist[w][d[i]] = prior + cnt;
+        }
+        __syncthreads();
+        const u32 c0 = whist[0][tid], c1 = whist[1][tid], c2 = whist[2][tid], c3 = whist[3][tid];
+        whist[0][tid] = 0;
+        whist[1][tid] = c0;
+        whist[2][tid] = c0 + c1;
+        whist[3][tid] = c0 + c1 + c2;
+        const u32 tot = c0 + c1 + c2 + c3;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RADIX_ITEMS; ++i) {
+            const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
+            if (idx < end) {
+                const u32 pos = base[d[i]] + whist[w][d[i]] + r[i];
+                if (pos < n) {
+                    kout[pos] = k[i];
+                    vout[pos] = v[i];
+                }
+            }
+        }
+        __syncthreads();
+        base[tid] += tot;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int gs_radix_partitions(int64_t capacity) {
+    int64_t g = (capacity + 4095) / 4096;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    return (int)g;
+}
+
+gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s) {
+    if (count <= 0) return GS_OK;
+    int64_t blocks = (count + GS_BLOCK - 1) / GS_BLOCK;
+    if (blocks > 4096) blocks = 4096;
+    fill_u32_kernel<<<(unsigned)blocks, GS_BLOCK, 0, s>>>(p, value, count);
+    return gs_check_launch("fill_u32");
+}
+
+gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
+                            u32* part, hipStream_t s) {
+    scan_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, n_dev, n_host, part);
+    scan_parts_kernel<<<1, GS_SCAN_PARTS, 0, s>>>(part, total);
+    scan_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, out, n_dev, n_host, part);
+    return gs_check_launch("scan_exclusive");
+}
+
+gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int bits, int G,
+                        u32* hist, u32* part, int* slot, hipStream_t s) {
+    int cur = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        const int b = (bits - shift) < 8 ? (bits - shift) : 8;
+        radix_hist_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], n_dev, n_host, shift, b, hist, G);
+        GS_TRY(gs_check_launch("radix_hist"));
+        GS_TRY(gs_scan_exclusive(hist, hist, nullptr, (u32)(256 * G), nullptr, part, s));
+        radix_scatter_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n_dev,
+                                                    n_host, shift, b, hist, G);
+        GS_TRY(gs_check_launch("radix_scatter"));
+        cur ^= 1;
+    }
+    *slot = cur;
+    return GS_OK;
+}

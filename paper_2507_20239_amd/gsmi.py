@@ -1,0 +1,426 @@
+"""ctypes binding of libgsmi (the C ABI in include/gsmi.h).
+
+Argument marshalling only: every step of the rendering / densification path
+runs in the HIP kernels of libgsmi.so.  PyTorch provides device memory and the
+current stream.  There is no CPU fallback: when the library is missing the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsmi.so")
+_lock = threading.Lock()
+_lib = None
+
+GS_OK, GS_ERR_INVALID, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(5)
+MAX_VIEWS = 32
+TILE = 16
+
+BUF_DEPTH_KEY, BUF_TILES_TOUCHED, BUF_RECT, BUF_SPLAT, BUF_SORTED_ENTRIES, BUF_INST_TILE, \
+    BUF_INST_ENTRY, BUF_RANGES, BUF_T_FINAL, BUF_N_CONTRIB, BUF_SPLAT_GRAD, BUF_COUNTERS = range(12)
+KIND_KEEP, KIND_CLONE, KIND_SPLIT0, KIND_SPLIT1 = range(4)
+ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO = range(5)
+
+
+class GsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("gsmi status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p), ("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class GaussianGrads(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
+class RasterOpts(ctypes.Structure):
+    _fields_ = [("bg", ctypes.c_float * 3), ("near_plane", ctypes.c_float),
+                ("raster_batch", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class Attr(ctypes.Structure):
+    _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("rows", ctypes.c_int32),
+                ("policy", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_U64 = ctypes.c_uint64
+_F = ctypes.c_float
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+# name -> argument types (every function returns gs_status unless listed in _RET)
+_SIGS = {
+    "gs_last_error": [],
+    "gs_version": [],
+    "gs_frame_workspace_size": [_I64, _I32, _P, _P, _I64, ctypes.POINTER(_U64)],
+    "gs_frame_create": [_I64, _I32, _P, _P, _I64, _P, _U64, _PP],
+    "gs_frame_destroy": [_P],
+    "gs_frame_buffer": [_P, _I32, _PP, ctypes.POINTER(_I64)],
+    "gs_frame_status": [_P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
+    "gs_project": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts), _P],
+    "gs_render": [_P, ctypes.POINTER(RasterOpts), _P, _P],
+    "gs_render_backward": [_P, ctypes.POINTER(RasterOpts), _P, _P],
+    "gs_project_backward": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts),
+                            ctypes.POINTER(GaussianGrads), _P, _P, _P],
+    "gs_l1_loss_grad": [_P, _P, _I64, _F, _P, _P, _P],
+    "gs_accumulate_densify_stats": [_P, _P, _P, _I32, _I64, _P, _P, _P],
+    "gs_densify_select": [_P, _P, _P, _P, _I64, _F, _F, _F, _I32, _P, _P, _P, _P],
+    "gs_densify_plan_workspace_size": [_I64, ctypes.POINTER(_U64)],
+    "gs_densify_plan": [_P, _P, _P, _I64, _P, _P, _I64, _P, _P, _U64, _P],
+    "gs_densify_apply": [_P, _P, _I64, _I64, ctypes.POINTER(Attr), _I32, _P, _P, _P, _U64, _U64,
+                         _P],
+    "gs_split_normals": [_P, _P, _I64, _U64, _U64, _P, _P, _P],
+    "gs_radix_select_workspace_size": [_I64, ctypes.POINTER(_U64)],
+    "gs_adaptive_prune_threshold": [_P, _I64, _I64, _F, _P, _P, _U64, _P],
+    "gs_sort_workspace_size": [_I64, ctypes.POINTER(_U64)],
+    "gs_sort_pairs": [_P, _P, _I64, _I32, _P, _U64, _P],
+    "gs_step_graph_create": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts), _P, _P,
+                             _F, _P, _P, ctypes.POINTER(GaussianGrads), _P, _P, _P, _PP],
+    "gs_graph_launch": [_P, _P],
+    "gs_graph_destroy": [_P],
+}
+_RET = {"gs_last_error": ctypes.c_char_p, "gs_version": ctypes.c_char_p}
+
+
+def exported_names():
+    return list(_SIGS.keys())
+
+
+def lib():
+    """Load libgsmi.so (built in-tree).  Raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libgsmi.so is not built (%s); run __graft_entry__.build()"
+                                   % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, args in _SIGS.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = _RET.get(name, ctypes.c_int)
+            _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != GS_OK:
+        raise GsError(status, lib().gs_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def version():
+    return lib().gs_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# Parameters, cameras, options
+# ----------------------------------------------------------------------------
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def gaussians_struct(params: dict, sh_degree: int) -> Gaussians:
+    for k in PARAM_NAMES:
+        t = params[k]
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("%s must be a contiguous float32 CUDA tensor" % k)
+    n = params["means"].shape[-1]
+    return Gaussians(params["means"].data_ptr(), params["log_scales"].data_ptr(),
+                     params["quats"].data_ptr(), params["opacity_logits"].data_ptr(),
+                     params["sh"].data_ptr(), n, sh_degree, 0)
+
+
+def grads_struct(grads: dict) -> GaussianGrads:
+    return GaussianGrads(*(grads[k].data_ptr() for k in PARAM_NAMES))
+
+
+def camera_array(cams) -> np.ndarray:
+    """Pack synth.Camera objects into gs_camera structs (host bytes)."""
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].R[:] = [float(x) for x in np.asarray(c.R, np.float64).reshape(9)]
+        arr[i].t[:] = [float(x) for x in np.asarray(c.t, np.float64).reshape(3)]
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = c.fx, c.fy, c.cx, c.cy
+        arr[i].width, arr[i].height = c.width, c.height
+    return np.frombuffer(bytes(arr), np.uint8)
+
+
+def cameras_to_device(cams, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(camera_array(cams).copy()).to(device)
+
+
+def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0):
+    o = RasterOpts()
+    o.bg[:] = [float(x) for x in bg]
+    o.near_plane = float(np.float32(near_plane))
+    o.raster_batch = int(raster_batch)
+    o.persistent_blocks = int(persistent_blocks)
+    return o
+
+
+# ----------------------------------------------------------------------------
+# Frame
+# ----------------------------------------------------------------------------
+class Frame:
+    """Device state of one rendering step for fixed view sizes (C ABI gs_frame)."""
+
+    def __init__(self, n: int, sizes, max_instances: int, device="cuda"):
+        self.n = int(n)
+        self.sizes = [(int(w), int(h)) for w, h in sizes]
+        self.V = len(self.sizes)
+        self.cap = int(max_instances)
+        self.device = torch.device(device)
+        W = np.array([w for w, _ in self.sizes], np.int32)
+        H = np.array([h for _, h in self.sizes], np.int32)
+        self._W, self._H = W, H
+        nbytes = ctypes.c_uint64()
+        _check(lib().gs_frame_workspace_size(self.n, self.V, W.ctypes.data_as(_P),
+                                             H.ctypes.data_as(_P), self.cap,
+                                             ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(lib().gs_frame_create(self.n, self.V, W.ctypes.data_as(_P), H.ctypes.data_as(_P),
+                                     self.cap, _ptr(self.workspace), int(nbytes.value),
+                                     ctypes.byref(h)))
+        self.handle = h
+        self.tiles = [((w + TILE - 1) // TILE) * ((h + TILE - 1) // TILE) for w, h in self.sizes]
+        self.pixels = [w * h for w, h in self.sizes]
+        self.T = sum(self.tiles)
+        self.P = sum(self.pixels)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and _lib is not None:
+                _lib.gs_frame_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def buffer(self, which: int, dtype=torch.int32) -> torch.Tensor:
+        """A view of one frame buffer (no copy)."""
+        p = ctypes.c_void_p()
+        cnt = ctypes.c_int64()
+        _check(lib().gs_frame_buffer(self.handle, which, ctypes.byref(p), ctypes.byref(cnt)))
+        elem = torch.empty(0, dtype=dtype).element_size()
+        off = p.value - self.workspace.data_ptr()
+        return self.workspace[off:off + cnt.value * elem].view(dtype)
+
+    def status(self, stream=None, raise_on_overflow=True):
+        nv, ni, ov = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        st = lib().gs_frame_status(self.handle, _stream(stream), ctypes.byref(nv), ctypes.byref(ni),
+                                   ctypes.byref(ov))
+        if st not in (GS_OK, GS_ERR_CAPACITY) or (st == GS_ERR_CAPACITY and raise_on_overflow):
+            _check(st)
+        return int(nv.value), int(ni.value), int(ov.value)
+
+    def image_numel(self):
+        return 3 * self.P
+
+    def split_images(self, flat: torch.Tensor):
+        out, o = [], 0
+        for (w, h) in self.sizes:
+            out.append(flat[o:o + 3 * w * h].view(3, h, w))
+            o += 3 * w * h
+        return out
+
+    def project(self, params, sh_degree, cams_dev, opts, stream=None):
+        g = gaussians_struct(params, sh_degree)
+        _check(lib().gs_project(self.handle, ctypes.byref(g), _ptr(cams_dev), ctypes.byref(opts),
+                                _stream(stream)))
+
+    def render(self, opts, images=None, stream=None):
+        if images is None:
+            images = torch.empty(self.image_numel(), dtype=torch.float32, device=self.device)
+        _check(lib().gs_render(self.handle, ctypes.byref(opts), _ptr(images), _stream(stream)))
+        return images
+
+    def render_backward(self, opts, dL_dimages, stream=None):
+        _check(lib().gs_render_backward(self.handle, ctypes.byref(opts), _ptr(dL_dimages),
+                                        _stream(stream)))
+
+    def project_backward(self, params, sh_degree, cams_dev, opts, grads, accum=None, denom=None,
+                         stream=None):
+        g = gaussians_struct(params, sh_degree)
+        gr = grads_struct(grads)
+        _check(lib().gs_project_backward(self.handle, ctypes.byref(g), _ptr(cams_dev),
+                                         ctypes.byref(opts), ctypes.byref(gr), _ptr(accum),
+                                         _ptr(denom), _stream(stream)))
+
+
+def empty_grads(params: dict) -> dict:
+    return {k: torch.empty_like(params[k]) for k in PARAM_NAMES}
+
+
+# ----------------------------------------------------------------------------
+# Loss
+# ----------------------------------------------------------------------------
+def l1_loss_grad(image, target, scale, loss=None, grad=None, stream=None):
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=image.device)
+    if grad is None:
+        grad = torch.empty_like(image)
+    _check(lib().gs_l1_loss_grad(_ptr(image), _ptr(target), image.numel(), float(scale),
+                                 _ptr(loss), _ptr(grad), _stream(stream)))
+    return loss, grad
+
+
+# ----------------------------------------------------------------------------
+# Densification
+# ----------------------------------------------------------------------------
+def accumulate_densify_stats(dmean2d, visible, view_wh, accum, denom, stream=None):
+    V, _, n = dmean2d.shape
+    wh = np.ascontiguousarray(np.asarray(view_wh, np.int32).reshape(V, 2))
+    _check(lib().gs_accumulate_densify_stats(_ptr(dmean2d), _ptr(visible), wh.ctypes.data_as(_P),
+                                             V, n, _ptr(accum), _ptr(denom), _stream(stream)))
+
+
+def densify_select(accum, denom, log_scales, logits, grad_threshold, log_scale_threshold,
+                   logit_threshold, allow_clone=True, stream=None):
+    n = accum.numel()
+    dev = accum.device
+    split = torch.empty(n, dtype=torch.uint8, device=dev)
+    clone = torch.empty(n, dtype=torch.uint8, device=dev)
+    prune = torch.empty(n, dtype=torch.uint8, device=dev)
+    _check(lib().gs_densify_select(_ptr(accum), _ptr(denom), _ptr(log_scales), _ptr(logits), n,
+                                   float(grad_threshold), float(log_scale_threshold),
+                                   float(logit_threshold), int(bool(allow_clone)), _ptr(split),
+                                   _ptr(clone), _ptr(prune), _stream(stream)))
+    return split, clone, prune
+
+
+def densify_plan(split, clone, prune, capacity=None, stream=None):
+    """Returns (src, kind, n_out) -- n_out read back from the device (synchronises)."""
+    n = split.numel()
+    dev = split.device
+    if capacity is None:
+        capacity = 2 * n
+    nb = ctypes.c_uint64()
+    _check(lib().gs_densify_plan_workspace_size(n, ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    src = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    kind = torch.empty(max(capacity, 1), dtype=torch.uint8, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().gs_densify_plan(_ptr(split), _ptr(clone), _ptr(prune), n, _ptr(src), _ptr(kind),
+                                 capacity, _ptr(n_out), _ptr(ws), int(nb.value), _stream(stream)))
+    m = int(n_out.item())
+    return src[:m], kind[:m], m
+
+
+def densify_apply(src, kind, n_in, attrs, parent_means, parent_log_scales, parent_quats, seed,
+                  step, stream=None):
+    """attrs: list of (input tensor [rows, n_in] or None, rows, policy); returns outputs."""
+    n_out = src.numel()
+    dev = src.device
+    outs = []
+    arr = (Attr * len(attrs))()
+    for i, (inp, rows, policy) in enumerate(attrs):
+        out = torch.empty((rows, n_out), dtype=torch.float32, device=dev)
+        outs.append(out)
+        arr[i].inp = inp.data_ptr() if inp is not None else None
+        arr[i].out = out.data_ptr()
+        arr[i].rows = rows
+        arr[i].policy = policy
+    _check(lib().gs_densify_apply(_ptr(src), _ptr(kind), n_out, n_in, arr, len(attrs),
+                                  _ptr(parent_means), _ptr(parent_log_scales), _ptr(parent_quats),
+                                  int(seed), int(step), _stream(stream)))
+    return outs
+
+
+def split_normals(parents, children, seed, step, stream=None):
+    m = parents.numel()
+    words = torch.empty((m, 4), dtype=torch.int32, device=parents.device)
+    z = torch.empty((m, 3), dtype=torch.float32, device=parents.device)
+    _check(lib().gs_split_normals(_ptr(parents), _ptr(children), m, int(seed), int(step),
+                                  _ptr(words), _ptr(z), _stream(stream)))
+    return words, z
+
+
+def adaptive_prune_threshold(logits, p=0.03, tau_u=0.05, stream=None):
+    """tau = min(alpha_sorted[floor(N p)], tau_u) in logit space (radix select on the GPU)."""
+    n = logits.numel()
+    k = min(int(math.floor(n * p)), n - 1)
+    upper = float(np.float32(math.log(tau_u / (1.0 - tau_u))))
+    nb = ctypes.c_uint64()
+    _check(lib().gs_radix_select_workspace_size(n, ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=logits.device)
+    thr = torch.empty(1, dtype=torch.float32, device=logits.device)
+    _check(lib().gs_adaptive_prune_threshold(_ptr(logits), n, k, upper, _ptr(thr), _ptr(ws),
+                                             int(nb.value), _stream(stream)))
+    return thr, k
+
+
+def sort_pairs(keys, vals, key_bits=32, stream=None):
+    """In-place stable radix sort of int32-viewed u32 keys/values on the GPU."""
+    n = keys.numel()
+    nb = ctypes.c_uint64()
+    _check(lib().gs_sort_workspace_size(n, ctypes.byref(nb)))
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=keys.device)
+    _check(lib().gs_sort_pairs(_ptr(keys), _ptr(vals), n, int(key_bits), _ptr(ws), int(nb.value),
+                               _stream(stream)))
+
+
+# ----------------------------------------------------------------------------
+# Captured step
+# ----------------------------------------------------------------------------
+class StepGraph:
+    """hipGraph of project -> render -> L1 -> render backward -> project backward."""
+
+    def __init__(self, frame: Frame, params, sh_degree, cams_dev, opts, images, targets, l1_scale,
+                 loss, dL, grads, accum=None, denom=None, stream=None):
+        self._keep = (frame, params, cams_dev, images, targets, loss, dL, grads, accum, denom)
+        g = gaussians_struct(params, sh_degree)
+        gr = grads_struct(grads)
+        h = ctypes.c_void_p()
+        _check(lib().gs_step_graph_create(frame.handle, ctypes.byref(g), _ptr(cams_dev),
+                                          ctypes.byref(opts), _ptr(images), _ptr(targets),
+                                          float(l1_scale), _ptr(loss), _ptr(dL), ctypes.byref(gr),
+                                          _ptr(accum), _ptr(denom), _stream(stream),
+                                          ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().gs_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and _lib is not None:
+                _lib.gs_graph_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

@@ -41,6 +41,14 @@ class Camera:
     width: int
     height: int
 
+    def __post_init__(self):
+        # cameras travel to the GPU as FP32: keep exactly the FP32 values here too
+        self.R = np.asarray(self.R, np.float32).astype(np.float64)
+        self.t = np.asarray(self.t, np.float32).astype(np.float64)
+        self.fx, self.fy = float(np.float32(self.fx)), float(np.float32(self.fy))
+        self.cx, self.cy = float(np.float32(self.cx)), float(np.float32(self.cy))
+        self.width, self.height = int(self.width), int(self.height)
+
     def scaled(self, r: int) -> "Camera":
         """The same pose rendered at 1/r resolution (coarse-to-fine level r)."""
         w = int(round(self.width / r))

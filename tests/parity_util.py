@@ -1,0 +1,74 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and the FP64 oracle on the same seeded inputs, and compare."""
+import numpy as np
+import torch
+
+import oracle
+from paper_2507_20239_amd import gsmi
+
+MARGIN = 1e-5      # decisions closer than this (relative) to a threshold are excluded
+RTOL = 1e-4        # FP32 vs FP64 bound for images and gradients
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def params_of(sc, device=None):
+    device = device or dev()
+    return {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(device)
+            for k in gsmi.PARAM_NAMES}
+
+
+def gpu_forward(sc, cams, opts=None, cap=1 << 22, frame=None):
+    """Project + render every camera in one frame.  Returns (frame, images list)."""
+    opts = opts or gsmi.raster_opts(bg=tuple(float(x) for x in sc.bg))
+    params = params_of(sc)
+    cams_dev = gsmi.cameras_to_device(cams, dev())
+    if frame is None:
+        frame = gsmi.Frame(sc.n, [(c.width, c.height) for c in cams], cap, dev())
+    frame.project(params, sc.sh_degree, cams_dev, opts)
+    flat = frame.render(opts)
+    torch.cuda.synchronize()
+    return frame, flat, params, cams_dev, opts
+
+
+def splat_view(frame):
+    """(E, 12) float32 numpy copy of the projected splats."""
+    return frame.buffer(gsmi.BUF_SPLAT, torch.float32).view(-1, 12).cpu().numpy()
+
+
+def gpu_mean2d(sp):
+    return sp[:, 0:2].astype(np.float64) + sp[:, 2:4].astype(np.float64)
+
+
+def raw_grad_scale(sc, cam, p, gabs):
+    """Upper bound of sum_p |per-pixel raw-parameter gradient term| per element:
+    |J_i| applied to the oracle's per-splat absolute term sums (J_i = Jacobian of
+    the nine projected quantities w.r.t. the raw parameters of Gaussian i)."""
+    n = sc.n
+    K = (sc.sh_degree + 1) ** 2
+    out = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+               opacity_logits=np.zeros(n), sh=np.zeros((K, 3, n)))
+    for k in range(9):
+        g = np.zeros((n, 9))
+        g[:, k] = 1.0
+        J = oracle.project_backward(sc, cam, p["visible"], g)
+        for name in out:
+            out[name] += np.abs(J[name]) * gabs[:, k]
+    return out
+
+
+def assert_close_scaled(got, ref, scale, rtol=RTOL, what=""):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    tol = rtol * np.maximum(np.abs(ref), scale) + 1e-30
+    bad = np.abs(got - ref) > tol
+    if bad.any():
+        idx = np.argwhere(bad)[:5]
+        raise AssertionError("%s: %d/%d elements outside tolerance, e.g. %s got %s ref %s scale %s"
+                             % (what, int(bad.sum()), bad.size, idx.tolist(),
+                                got[bad][:5], ref[bad][:5], np.broadcast_to(scale, ref.shape)[bad][:5]))
+    nrm = np.linalg.norm(ref)
+    if nrm > 0:
+        assert np.linalg.norm(got - ref) <= rtol * max(nrm, np.linalg.norm(scale)), what

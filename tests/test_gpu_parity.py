@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: integer / index outputs bit-exact; FP32 images and gradients within
+1e-4 of the FP64 values, relative to the value or to the sum of absolute terms
+that formed it (the scale FP32 summation error is proportional to).  Pixels
+where a discrete decision of the compositing (alpha cutoff 1/255, clamp 0.99,
+transmittance stop 1e-4) lies within 1e-5 (relative) of its threshold are
+excluded from the image comparison, and their loss gradient is set to zero for
+the gradient comparison, on both sides.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2507_20239_amd import gsmi, synth
+from parity_util import (MARGIN, RTOL, assert_close_scaled, dev, gpu_forward, gpu_mean2d,
+                         params_of, raw_grad_scale, splat_view)
+
+pytestmark = pytest.mark.gpu
+
+
+def _scenes():
+    c1 = synth.tiny_scene(seed=0, n=2000)
+    rag = synth.random_scene(21, 300, 37, 29, sh_degree=3, log_scale=(-2.6, 0.5), spread=1.0)
+    rag.bg = np.array([0.2, 0.4, 0.1], np.float32)
+    deg1 = synth.random_scene(22, 500, 70, 45, sh_degree=1, logit=(1.5, 1.0), log_scale=(-2.2, 0.5))
+    return {"c1_2000_128x128_sh0": c1, "ragged_300_37x29_sh3": rag, "sh1_500_70x45": deg1}
+
+
+SCENES = _scenes()
+
+
+def _norm_ranges(r):
+    """Ranges with empty tiles written as [0, 0] (the GPU leaves them zero)."""
+    r = np.asarray(r, np.int64).copy()
+    r[r[:, 0] == r[:, 1]] = 0
+    return r
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_project_matches_oracle(name):
+    sc = SCENES[name]
+    cam = sc.cameras[0]
+    frame, *_ = gpu_forward(sc, [cam])
+    p = oracle.project(sc, cam)
+    tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy().view(np.uint32).astype(np.int64)
+    key = frame.buffer(gsmi.BUF_DEPTH_KEY).cpu().numpy().view(np.uint32)
+    rect = frame.buffer(gsmi.BUF_RECT).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    sp = splat_view(frame)
+    ok = p["flags"] == 0
+    assert ok.mean() > 0.99
+    vis = p["visible"] > 0
+    # bit-exact: depth keys (all), visibility and rectangles (unflagged)
+    np.testing.assert_array_equal(key[p["depth"] > 0], p["depth_key"][p["depth"] > 0])
+    np.testing.assert_array_equal((tt > 0)[ok], vis[ok])
+    np.testing.assert_array_equal(tt[ok], p["tiles_touched"][ok])
+    r = p["rect"]
+    gx0, gx1 = rect[:, 0] & 0xFFFF, rect[:, 0] >> 16
+    gy0, gy1 = rect[:, 1] & 0xFFFF, rect[:, 1] >> 16
+    m = ok & vis
+    np.testing.assert_array_equal(np.stack([gx0, gx1, gy0, gy1], 1)[m], r[m])
+    # FP32 values of visible splats
+    m = vis & (tt > 0)
+    np.testing.assert_allclose(gpu_mean2d(sp)[m], p["mean2d"][m], rtol=1e-7, atol=1e-5)
+    assert_close_scaled(sp[m, 4:7], p["conic"][m], np.abs(p["conic"][m]).max(1, keepdims=True),
+                        what="conic")
+    np.testing.assert_allclose(sp[m, 7], p["opacity"][m], rtol=1e-6)
+    np.testing.assert_allclose(sp[m, 8:11], p["rgb"][m], rtol=1e-5, atol=1e-6)
+
+
+def _check_ranges_partition(gr, gt):
+    """Ranges are the runs of equal tile ids of the sorted instance list."""
+    n = gt.size
+    starts = np.flatnonzero(np.r_[True, gt[1:] != gt[:-1]]) if n else np.zeros(0, np.int64)
+    ends = np.r_[starts[1:], n] if n else starts
+    want = np.zeros_like(gr, dtype=np.int64)
+    want[gt[starts], 0] = starts
+    want[gt[starts], 1] = ends
+    np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(want))
+
+
+def _compare_lists(p, gt, ge, tiles, gids, entry_base=0):
+    """Bit-exact (tile, Gaussian) order, leaving out the Gaussians whose footprint
+    rectangle lies within 1e-3 px of a tile-edge decision (reported by the oracle)."""
+    flagged = np.flatnonzero(p["flags"] & 1)
+    assert flagged.size <= max(2, p["n"] // 500)
+    kg = ~np.isin(ge - entry_base, flagged)
+    ko = ~np.isin(gids, flagged)
+    np.testing.assert_array_equal(gt[kg], tiles[ko])
+    np.testing.assert_array_equal(ge[kg] - entry_base, gids[ko])
+    return flagged.size
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_binning_lists_match_oracle_exactly(name):
+    sc = SCENES[name]
+    cam = sc.cameras[0]
+    frame, *_ = gpu_forward(sc, [cam])
+    p = oracle.project(sc, cam)
+    tiles, gids, ranges = oracle.tile_lists(p)
+    nv, ni, ovf = frame.status()
+    assert ovf == 0
+    gt = frame.buffer(gsmi.BUF_INST_TILE).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    ge = frame.buffer(gsmi.BUF_INST_ENTRY).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    gr = frame.buffer(gsmi.BUF_RANGES).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    nflag = _compare_lists(p, gt, ge, tiles, gids)
+    _check_ranges_partition(gr, gt)
+    if nflag == 0:
+        assert ni == tiles.size and nv == int((p["visible"] > 0).sum())
+        np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(ranges))
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_render_matches_oracle(name):
+    sc = SCENES[name]
+    cam = sc.cameras[0]
+    frame, flat, *_ = gpu_forward(sc, [cam])
+    p = oracle.project(sc, cam)
+    ref, Tref, nref, margin = oracle.render_image(p, sc.bg)
+    img = flat.view(3, cam.height, cam.width).cpu().numpy()
+    T = frame.buffer(gsmi.BUF_T_FINAL, torch.float32).cpu().numpy().reshape(cam.height, cam.width)
+    good = margin > MARGIN
+    assert good.mean() > 0.99
+    scale = np.abs(ref) + np.abs(np.asarray(sc.bg, np.float64))[:, None, None]
+    assert_close_scaled(img[:, good], ref[:, good], scale[:, good], what="image")
+    assert_close_scaled(T[good], Tref[good], np.abs(Tref[good]), what="T_final")
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_backward_matches_oracle(name):
+    sc = SCENES[name]
+    cam = sc.cameras[0]
+    frame, flat, params, cams_dev, opts = gpu_forward(sc, [cam])
+    p = oracle.project(sc, cam)
+    _, _, _, margin = oracle.render_image(p, sc.bg)
+    rng = np.random.default_rng(5)
+    dL = rng.standard_normal((3, cam.height, cam.width)) * 1e-3
+    dL[:, margin <= MARGIN] = 0.0
+    dL = dL.astype(np.float32)
+    frame.render_backward(opts, torch.from_numpy(dL).to(dev()).reshape(-1))
+    grads = gsmi.empty_grads(params)
+    acc = torch.zeros(sc.n, device=dev())
+    den = torch.zeros(sc.n, device=dev())
+    frame.project_backward(params, sc.sh_degree, cams_dev, opts, grads, acc, den)
+    torch.cuda.synchronize()
+    gproj, gabs = oracle.render_backward_image(p, dL.astype(np.float64), sc.bg)
+    sg = frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).view(-1, 9).cpu().numpy()
+    assert_close_scaled(sg, gproj, gabs, what="splat gradients")
+    racc, rden = np.zeros(sc.n), np.zeros(sc.n)
+    gref = oracle.project_backward(sc, cam, p["visible"], gproj, stats=(racc, rden))
+    scales = raw_grad_scale(sc, cam, p, gabs)
+    for k in gsmi.PARAM_NAMES:
+        assert_close_scaled(grads[k].cpu().numpy(), gref[k], scales[k], what=k)
+    np.testing.assert_array_equal(den.cpu().numpy(), rden)
+    gn = np.hypot(gabs[:, 0] * cam.width / 2, gabs[:, 1] * cam.height / 2)
+    assert_close_scaled(acc.cpu().numpy(), racc, gn, what="densify statistic")
+
+
+def test_multiview_frame_matches_per_view_oracle():
+    sc = synth.random_scene(23, 400, 48, 40, sh_degree=2, n_views=3, log_scale=(-2.5, 0.5))
+    cams = [sc.cameras[0], sc.cameras[1].scaled(2), sc.cameras[2]]
+    cams[2] = synth.Camera(cams[2].R, cams[2].t, cams[2].fx, cams[2].fy, 20.5, 17.0, 41, 35)
+    frame, flat, params, cams_dev, opts = gpu_forward(sc, cams)
+    imgs = frame.split_images(flat)
+    ranges = frame.buffer(gsmi.BUF_RANGES).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    nv, ni, _ = frame.status()
+    gt = frame.buffer(gsmi.BUF_INST_TILE).cpu().numpy()[:ni].view(np.uint32)
+    ge = frame.buffer(gsmi.BUF_INST_ENTRY).cpu().numpy()[:ni].view(np.uint32)
+    base = 0
+    for v, cam in enumerate(cams):
+        p = oracle.project(sc, cam)
+        ref, _, _, margin = oracle.render_image(p)
+        good = margin > MARGIN
+        got = imgs[v].cpu().numpy()
+        assert_close_scaled(got[:, good], ref[:, good], np.abs(ref[:, good]), what="view %d" % v)
+        tiles, gids, rr = oracle.tile_lists(p, tile_base=base)
+        T = rr.shape[0]
+        sel = (gt >= base) & (gt < base + T)
+        _compare_lists(p, gt[sel].astype(np.int64), ge[sel].astype(np.int64), tiles, gids,
+                       entry_base=v * sc.n)
+        base += T
+    _check_ranges_partition(ranges, gt.astype(np.int64))
+    assert base == frame.T
+
+
+def test_empty_and_culled_scene_renders_background():
+    sc = synth.random_scene(24, 64, 33, 17, sh_degree=0)
+    sc.means[2] = -1.0          # every Gaussian behind the camera
+    sc.bg = np.array([0.3, 0.6, 0.9], np.float32)
+    frame, flat, params, cams_dev, opts = gpu_forward(sc, sc.cameras)
+    nv, ni, ovf = frame.status()
+    assert nv == 0 and ni == 0 and ovf == 0
+    img = flat.view(3, 17, 33).cpu().numpy()
+    for c in range(3):
+        assert np.all(img[c] == sc.bg[c])
+    dL = torch.ones(flat.numel(), device=dev())
+    frame.render_backward(opts, dL)
+    grads = gsmi.empty_grads(params)
+    frame.project_backward(params, 0, cams_dev, opts, grads)
+    for k in gsmi.PARAM_NAMES:
+        assert torch.count_nonzero(grads[k]).item() == 0
+
+
+def test_capacity_overflow_is_reported_and_bounded():
+    sc = SCENES["c1_2000_128x128_sh0"]
+    cam = sc.cameras[0]
+    frame, flat, *_ = gpu_forward(sc, [cam], cap=1000)
+    nv, ni, ovf = frame.status(raise_on_overflow=False)
+    assert ovf == 1 and ni > 1000
+    with pytest.raises(gsmi.GsError):
+        frame.status()
+
+
+def test_persistent_queue_gives_identical_images():
+    sc = SCENES["ragged_300_37x29_sh3"]
+    cam = sc.cameras[0]
+    o1 = gsmi.raster_opts(bg=tuple(sc.bg))
+    o2 = gsmi.raster_opts(bg=tuple(sc.bg), persistent_blocks=7, raster_batch=64)
+    _, a, *_ = gpu_forward(sc, [cam], o1)
+    _, b, *_ = gpu_forward(sc, [cam], o2)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n,bits", [(0, 32), (1, 32), (100, 7), (4097, 16), (70001, 32),
+                                    (1_000_003, 24)])
+def test_radix_sort_is_stable_and_exact(n, bits):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 2 ** bits, n, dtype=np.uint64).astype(np.uint32)
+    if n > 10:
+        keys[: n // 3] = keys[n // 2]     # many ties
+    vals = np.arange(n, dtype=np.uint32)
+    kt = torch.from_numpy(keys.view(np.int32).copy()).to(dev())
+    vt = torch.from_numpy(vals.view(np.int32).copy()).to(dev())
+    gsmi.sort_pairs(kt, vt, bits)
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint32), keys[order])
+    np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
+
+
+def test_l1_loss_grad():
+    rng = np.random.default_rng(3)
+    a = rng.random(100_003).astype(np.float32)
+    b = rng.random(100_003).astype(np.float32)
+    b[:10] = a[:10]
+    loss, g = gsmi.l1_loss_grad(torch.from_numpy(a).to(dev()), torch.from_numpy(b).to(dev()),
+                                1.0 / a.size)
+    ref_loss, ref_g = oracle.l1_loss_grad(a, b)
+    assert float(loss.item()) == pytest.approx(ref_loss, rel=1e-5)
+    np.testing.assert_array_equal(g.cpu().numpy(), ref_g.astype(np.float32))

@@ -121,7 +121,7 @@ def test_projection_covariance_matches_finite_difference_jacobian():
         muf = sc.means[:, 0].astype(np.float64)
 
         def u(m):
-            tt = R @ m + t
+            tt = cam.R @ m + cam.t
             return np.array([cam.fx * tt[0] / tt[2] + cam.cx, cam.fy * tt[1] / tt[2] + cam.cy])
 
         h = 1e-6
