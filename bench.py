@@ -1,0 +1,327 @@
+#!/usr/bin/env python3
+"""Benchmark of the Gaussian-splatting hot path on one MI355X (gfx950).
+
+Metric: milliseconds per training iteration's forward + backward at
+1,000,000 Gaussians, one 1600x1040 view, SH degree 3, FP32: projection ->
+tile binning (prefix sums + radix sorts) -> front-to-back compositing -> L1
+loss and its gradient -> compositing adjoint -> chain rule to the raw
+parameters with the densification statistic fused.  All inputs are resident
+in HBM before the timed region; the step is a captured hipGraph replayed K
+times between two synchronisations.
+
+Also reported: the batched coarse-to-fine step (8 views at 400x260, 800x520
+and 1600x1040 in one frame, 500,000 Gaussians) against the same 8 views
+stepped one at a time, the roofline position of the dominant kernel (timed
+live with HIP events on the stream it runs on), and the FP64 CPU oracle timed
+on a bounded sample on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batched]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak: 256 CUs x 128 FP32 lanes (dual-issue / packed) x 2 flop (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3
+# per evaluated (pixel, splat) pair of the adjoint: alpha re-evaluation 16 flop for every pair
+# walked, plus 40 flop of gradient arithmetic for every composited pair (FMA = 2 flop)
+BWD_FLOP_WALKED = 16
+BWD_FLOP_COMPOSITED = 40
+FWD_FLOP_WALKED = 16
+FWD_FLOP_COMPOSITED = 10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--profile", action="store_true",
+                    help="minimal run for a profiler: metric workload only, no CPU leg")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def to_dev(sc, dev, torch, gsmi):
+    return {k: torch.from_numpy(getattr(sc, k)).to(dev).contiguous() for k in gsmi.PARAM_NAMES}
+
+
+class Step:
+    """One training step's buffers and its captured graph for a set of views."""
+
+    def __init__(self, sc, cams, params, opts, cap, torch, gsmi, dev):
+        self.torch, self.gsmi = torch, gsmi
+        self.sc, self.cams, self.params, self.opts = sc, cams, params, opts
+        self.frame = gsmi.Frame(sc.n, [(c.width, c.height) for c in cams], cap, dev)
+        self.cams_dev = gsmi.cameras_to_device(cams, dev)
+        self.images = torch.empty(self.frame.image_numel(), device=dev)
+        if sc.targets:
+            self.targets = torch.cat([torch.from_numpy(t).reshape(-1) for t in sc.targets]).to(dev)
+        else:
+            self.targets = torch.rand(self.frame.image_numel(), device=dev)
+        self.loss = torch.zeros(1, device=dev)
+        self.dL = torch.empty_like(self.images)
+        self.grads = gsmi.empty_grads(params)
+        self.acc = torch.zeros(sc.n, device=dev)
+        self.den = torch.zeros(sc.n, device=dev)
+        self.l1_scale = 1.0 / self.images.numel()
+        self.graph = None
+
+    def eager(self, events=None):
+        f, g = self.frame, self.gsmi
+        ev = events
+        if ev: ev[0].record()
+        f.project(self.params, self.sc.sh_degree, self.cams_dev, self.opts)
+        if ev: ev[1].record()
+        f.render(self.opts, self.images)
+        if ev: ev[2].record()
+        self.loss.zero_()
+        g.l1_loss_grad(self.images, self.targets, self.l1_scale, self.loss, self.dL)
+        if ev: ev[3].record()
+        f.render_backward(self.opts, self.dL)
+        if ev: ev[4].record()
+        f.project_backward(self.params, self.sc.sh_degree, self.cams_dev, self.opts, self.grads,
+                           self.acc, self.den)
+        if ev: ev[5].record()
+
+    def capture(self):
+        self.graph = self.gsmi.StepGraph(self.frame, self.params, self.sc.sh_degree, self.cams_dev,
+                                         self.opts, self.images, self.targets, self.l1_scale,
+                                         self.loss, self.dL, self.grads, self.acc, self.den)
+
+    def launch(self):
+        self.graph.launch()
+
+
+def time_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def breakdown(torch, step, reps):
+    names = ["project", "render(bin+composite)", "l1", "render_backward", "project_backward"]
+    acc = [0.0] * 5
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        step.eager(ev)
+        torch.cuda.synchronize()
+        for i in range(5):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    return {n: a / reps for n, a in zip(names, acc)}
+
+
+def source_hash(*files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel_src_hash):
+    """HBM bytes per launch of the adjoint kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "raster_bwd_1m_1600x1040_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for ln in open(path):
+        if "=" in ln and not ln.startswith("#"):
+            k, v = ln.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(sc, dL_img, seconds):
+    """The FP64 oracle, untuned, on a bounded sample of the same workload:
+    full projection and chain rule of all Gaussians, compositing and its
+    adjoint on a random sample of pixels; scaled to ms per full iteration."""
+    import numpy as np
+    import oracle
+    cam = sc.cameras[0]
+    P = cam.width * cam.height
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    p = oracle.project(sc, cam)
+    t_proj = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    # size the pixel samples from a short probe so the leg stays near `seconds`
+    nprobe = 4 * threads
+    probe = np.stack([rng.integers(0, cam.width, nprobe), rng.integers(0, cam.height, nprobe)], 1)
+    t0 = time.perf_counter()
+    oracle.render_pixels(p, probe)
+    t_probe = (time.perf_counter() - t0) / nprobe * threads     # serial cost per pixel
+    n_fwd = int(max(16, min(65536, 0.4 * seconds * threads / max(t_probe, 1e-6))))
+    n_bwd = int(max(4, min(8192, 0.4 * seconds / max(t_probe * 1.5, 1e-6))))
+    pix = np.stack([rng.integers(0, cam.width, n_fwd), rng.integers(0, cam.height, n_fwd)], 1)
+    t0 = time.perf_counter()
+    oracle.render_pixels(p, pix)
+    t_fwd = time.perf_counter() - t0
+    pb = pix[:n_bwd]
+    g = dL_img.reshape(3, -1)[:, pb[:, 1] * cam.width + pb[:, 0]].T.astype(np.float64)
+    t0 = time.perf_counter()
+    gproj, _ = oracle.render_backward_pixels(p, pb, g)
+    t_bwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.project_backward(sc, cam, p["visible"], gproj,
+                            stats=(np.zeros(sc.n), np.zeros(sc.n)))
+    t_pbwd = time.perf_counter() - t0
+    est_s = t_proj + t_pbwd + t_fwd / n_fwd * P + t_bwd / n_bwd * P
+    return {"value": est_s * 1e3, "unit": "ms per fwd+bwd iter (estimated from sample)",
+            "cores": threads, "kind": "oracle",
+            "sample": ("FP64 oracle: projection + chain rule of all %d Gaussians (%.2f s + %.2f s, "
+                       "%d threads), per-pixel compositing on %d random pixels (%.2f s, %d threads) "
+                       "and its adjoint on %d pixels (%.2f s, 1 thread), scaled to %d pixels"
+                       % (sc.n, t_proj, t_pbwd, threads, n_fwd, t_fwd, threads, n_bwd, t_bwd, P)),
+            "sample_seconds": round(t_proj + t_pbwd + t_fwd + t_bwd + t_probe / threads * 8, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the view-parallel "
+              "sharding is a design only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2507_20239_amd import gsmi, synth
+
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+
+    # ---------------- metric workload: 1M Gaussians, 1600x1040, SH3 ----------------
+    log("generating 1M-Gaussian scene")
+    sc = synth.single_view_1m()
+    params = to_dev(sc, dev, torch, gsmi)
+    opts = gsmi.raster_opts()
+    st = Step(sc, sc.cameras, params, opts, 16 << 20, torch, gsmi, dev)
+    st.eager()
+    torch.cuda.synchronize()
+    nvis, ninst, ovf = st.frame.status()
+    log("visible %d instances %d overflow %d" % (nvis, ninst, ovf))
+    st.capture()
+    ms_graph = time_loop(torch, st.launch, K, W)
+    ms_eager = time_loop(torch, st.eager, K, W)
+    log("C2 graph %.3f ms eager %.3f ms" % (ms_graph, ms_eager))
+    parts = breakdown(torch, st, max(3, K // 2))
+    log("breakdown", json.dumps({k: round(v, 4) for k, v in parts.items()}))
+
+    # dominant kernel: the compositing adjoint (one kernel per gs_render_backward call)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    for i in range(K):
+        st.frame.project(params, sc.sh_degree, st.cams_dev, opts)
+        st.frame.render(opts, st.images)
+        ev[i][0].record()
+        st.frame.render_backward(opts, st.dL)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    bwd_ms = sum(a.elapsed_time(b) for a, b in ev) / K
+    n_contrib = st.frame.buffer(gsmi.BUF_N_CONTRIB).to(torch.int64).sum().item()
+    n_comp = st.frame.buffer(gsmi.BUF_N_COMPOSITED).to(torch.int64).sum().item()
+    flop = BWD_FLOP_WALKED * n_contrib + BWD_FLOP_COMPOSITED * n_comp
+    achieved = flop / (bwd_ms * 1e-3) / 1e12
+    src_hash = source_hash("paper_2507_20239_amd/csrc/raster.hip",
+                           "paper_2507_20239_amd/csrc/gs_internal.h")
+    roofline = {"kernel": "raster_bwd_kernel (compositing adjoint)", "bound": "alu",
+                "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": counter_traffic(src_hash),
+                "launch_ms": round(bwd_ms, 4), "pairs_walked": int(n_contrib),
+                "pairs_composited": int(n_comp), "source_hash": src_hash}
+
+    result = {
+        "metric": "ms per fwd+bwd iter at 1M Gaussians 1600x1040; batched vs plain speedup",
+        "value": round(ms_graph, 4), "unit": "ms", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms_graph, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single view 1600x1040, 1,000,000 Gaussians, SH degree 3, "
+                               "fwd+bwd+densify statistic, hipGraph-captured step",
+                   "gaussians": sc.n, "width": 1600, "height": 1040, "sh_degree": 3,
+                   "visible": nvis, "instances": ninst},
+        "eager_ms": round(ms_eager, 4),
+        "breakdown_ms": {k: round(v, 4) for k, v in parts.items()},
+        "roofline": roofline,
+    }
+
+    # ---------------- batched coarse-to-fine vs per-view plain ----------------
+    if not args.no_batched and not args.profile:
+        log("generating batched coarse-to-fine scene (500K, 8 views)")
+        sb = synth.batched_c2f()
+        pb = to_dev(sb, dev, torch, gsmi)
+        from paper_2507_20239_amd import autotune
+        best = autotune.tune_batched(sb, sb.cameras, pb, dev, cap=32 << 20)
+        bopts = gsmi.raster_opts(raster_batch=best["raster_batch"],
+                                 persistent_blocks=best["persistent_blocks"])
+        bst = Step(sb, sb.cameras, pb, bopts, 32 << 20, torch, gsmi, dev)
+        bst.eager()
+        bst.capture()
+        ms_b = time_loop(torch, bst.launch, K, W)
+        ms_b_eager = time_loop(torch, bst.eager, K, W)
+        plain = []
+        popts = gsmi.raster_opts()
+        for v, cam in enumerate(sb.cameras):
+            one = synth.Scene(sb.means, sb.log_scales, sb.quats, sb.opacity_logits, sb.sh,
+                              sb.sh_degree, [cam], [sb.targets[v]], sb.bg)
+            s1 = Step(one, [cam], pb, popts, 16 << 20, torch, gsmi, dev)
+            s1.eager()
+            s1.capture()
+            plain.append(s1)
+
+        def plain_graph():
+            for s1 in plain:
+                s1.launch()
+
+        def plain_eager():
+            for s1 in plain:
+                s1.eager()
+
+        ms_p = time_loop(torch, plain_graph, K, W)
+        ms_p_eager = time_loop(torch, plain_eager, K, W)
+        best_plain = min(ms_p, ms_p_eager)
+        result["batched"] = {
+            "workload": "8 views (2x400x260, 3x800x520, 3x1600x1040), 500,000 Gaussians, SH3",
+            "batched_graph_ms": round(ms_b, 4), "batched_eager_ms": round(ms_b_eager, 4),
+            "plain_graph_ms": round(ms_p, 4), "plain_eager_ms": round(ms_p_eager, 4),
+            "speedup": round(best_plain / ms_b, 3), "tuned": best}
+        log("batched %.3f ms, plain %.3f ms (graph) %.3f ms (eager)" % (ms_b, ms_p, ms_p_eager))
+        del plain, bst
+
+    # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
+    if not args.no_cpu and not args.profile:
+        log("timing the FP64 oracle on a sample")
+        dL_img = st.dL.view(3, 1040, 1600).cpu().numpy()
+        result["cpu_baseline"] = cpu_baseline(sc, dL_img, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

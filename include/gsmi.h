@@ -143,7 +143,8 @@ enum {
     GS_BUF_T_FINAL = 8,       /* f32 [P]     final transmittance per pixel */
     GS_BUF_N_CONTRIB = 9,     /* u32 [P]     instances walked per pixel (last composited + 1) */
     GS_BUF_SPLAT_GRAD = 10,   /* f32 [V*n][9] dL/d(mean2d x, y, conic a, b, c, opacity, r, g, b) */
-    GS_BUF_COUNTERS = 11      /* u32 [16]    [0] visible entries, [1] instances, [2] overflow flag */
+    GS_BUF_COUNTERS = 11,     /* u32 [16]    [0] visible entries, [1] instances, [2] overflow flag */
+    GS_BUF_N_COMPOSITED = 12  /* u32 [P]     splats composited per pixel */
 };
 gs_status gs_frame_buffer(const gs_frame* frame, int32_t which, void** ptr, int64_t* count);
 
@@ -174,8 +175,10 @@ gs_status gs_project(gs_frame* frame, const gs_gaussians* g, const gs_camera* ca
 gs_status gs_render(gs_frame* frame, const gs_raster_opts* opts, float* images, void* stream);
 
 /* Adjoint of gs_render: from dL/dimages (same layout as images) to the
- * per-splat gradients GS_BUF_SPLAT_GRAD (overwritten).  Walks each pixel's
- * list back to front, recovering transmittance from the saved final value. */
+ * per-splat gradients GS_BUF_SPLAT_GRAD, which gs_project cleared; call it
+ * once per gs_project/gs_render.  Walks each pixel's list back to front,
+ * recovering transmittance from the saved final value.  One kernel launch
+ * (plus a one-word queue reset when persistent_blocks > 0). */
 gs_status gs_render_backward(gs_frame* frame, const gs_raster_opts* opts,
                              const float* dL_dimages, void* stream);
 

@@ -1,0 +1,97 @@
+"""Autotuner for the rasterizer launch shape.
+
+Searches the LDS batch size (splats staged per batch: 64, 128, 256) and the
+work distribution (one workgroup per (view, tile), or a persistent grid of
+1024 / 2048 workgroups pulling tiles heaviest-first from a queue) by timing
+the captured training step of the given views, and caches the winner per
+(device, workload signature) in a JSON file ($GSMI_AUTOTUNE_CACHE, default
+~/.cache/gsmi_autotune.json).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import gsmi
+
+BATCHES = (64, 128, 256)
+PERSISTENT = (0, 1024, 2048)
+
+
+def _cache_path():
+    return os.environ.get("GSMI_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "gsmi_autotune.json"))
+
+
+def _signature(n, cams, sh_degree):
+    dev = torch.cuda.get_device_name(0)
+    sizes = ",".join("%dx%d" % (c.width, c.height) for c in cams)
+    return "%s|n=%d|sh=%d|%s" % (dev, n, sh_degree, sizes)
+
+
+def _load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time_step(frame, params, sh_degree, cams_dev, opts, images, targets, scale, loss, dL, grads,
+               reps=5):
+    g = gsmi.StepGraph(frame, params, sh_degree, cams_dev, opts, images, targets, scale, loss, dL,
+                       grads)
+    for _ in range(2):
+        g.launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_batched(scene, cams, params, device, cap=32 << 20, use_cache=True):
+    """Best {raster_batch, persistent_blocks, ms} for a step over `cams`."""
+    sig = _signature(scene.n, cams, scene.sh_degree)
+    cache = _load() if use_cache else {}
+    if sig in cache:
+        return cache[sig]
+    frame = gsmi.Frame(scene.n, [(c.width, c.height) for c in cams], cap, device)
+    cams_dev = gsmi.cameras_to_device(cams, device)
+    images = torch.empty(frame.image_numel(), device=device)
+    targets = torch.rand(frame.image_numel(), device=device)
+    loss = torch.zeros(1, device=device)
+    dL = torch.empty_like(images)
+    grads = gsmi.empty_grads(params)
+    scale = 1.0 / images.numel()
+    results = []
+    for b in BATCHES:
+        for pb in PERSISTENT:
+            opts = gsmi.raster_opts(raster_batch=b, persistent_blocks=pb)
+            ms = _time_step(frame, params, scene.sh_degree, cams_dev, opts, images, targets, scale,
+                            loss, dL, grads)
+            results.append({"raster_batch": b, "persistent_blocks": pb, "ms": round(ms, 4)})
+    best = dict(min(results, key=lambda r: r["ms"]))
+    best["candidates"] = len(results)
+    cache[sig] = best
+    if use_cache:
+        _store(cache)
+    return best

@@ -113,6 +113,7 @@ Layout layout_for(gs_frame* f) {
     L.add(4 * 256 * (uint64_t)G);  // 23 radix_hist
     L.add(4 * (GS_SCAN_PARTS + 8));  // 24 scan_part
     L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 25 views
+    L.add(4 * P);        // 26 n_comp
     return L;
 }
 
@@ -214,6 +215,7 @@ gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
     f->radix_hist = (u32*)(b + L.off[23]);
     f->scan_part = (u32*)(b + L.off[24]);
     f->d_views = (gs_view_info*)(b + L.off[25]);
+    f->n_comp = (u32*)(b + L.off[26]);
     // the slots holding sorted results depend only on the pass counts
     f->vsorted = (((31 + 7) / 8) & 1);
     f->isorted = (((f->tile_bits + 7) / 8) & 1);
@@ -249,6 +251,7 @@ gs_status gs_frame_buffer(const gs_frame* f, int32_t which, void** ptr, int64_t*
         case GS_BUF_N_CONTRIB: *ptr = f->n_contrib; *count = f->P; break;
         case GS_BUF_SPLAT_GRAD: *ptr = f->splat_grad; *count = 9 * f->E; break;
         case GS_BUF_COUNTERS: *ptr = f->counters; *count = 16; break;
+        case GS_BUF_N_COMPOSITED: *ptr = f->n_comp; *count = f->P; break;
         default: return gs_fail(GS_ERR_INVALID, "unknown buffer id %d", which);
     }
     return GS_OK;
@@ -291,9 +294,7 @@ gs_status gs_render_backward(gs_frame* f, const gs_raster_opts* opts, const floa
     GS_TRY(check_frame(f));
     GS_TRY(check_opts(opts));
     if (!dL_dimages) return gs_fail(GS_ERR_INVALID, "dL_dimages is null");
-    hipStream_t s = (hipStream_t)stream;
-    GS_TRY(gs_fill_u32((u32*)f->splat_grad, 0u, 9 * f->E, s));
-    return gs_launch_raster_bwd(f, opts, dL_dimages, s);
+    return gs_launch_raster_bwd(f, opts, dL_dimages, (hipStream_t)stream);
 }
 
 gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,

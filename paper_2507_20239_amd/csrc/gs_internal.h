@@ -63,6 +63,7 @@ struct gs_frame {
     // per pixel
     float* T_final;      // [P]
     u32* n_contrib;      // [P]
+    u32* n_comp;         // [P] splats composited per pixel
     // per splat gradient
     float* splat_grad;   // [E][9]
     // counters: [0] visible, [1] instances, [2] overflow, [3] fwd queue, [4] bwd queue

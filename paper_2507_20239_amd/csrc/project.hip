@@ -125,6 +125,7 @@ struct ProjArgs {
     u32* tiles_touched;
     uint2* rect;
     float4* splat;
+    float* splat_grad;     // [E][9], cleared here for the adjoint of this step
 };
 
 // Per-Gaussian activated parameters.
@@ -293,6 +294,10 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
         }
         a.tiles_touched[e] = tt;
         a.rect[e] = rc;
+        if (a.splat_grad) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) a.splat_grad[9 * e + k] = 0.f;
+        }
     }
 }
 
@@ -528,6 +533,7 @@ ProjArgs make_args(gs_frame* f, const gs_gaussians* g, const gs_camera* cams, fl
     a.tiles_touched = f->tiles_touched;
     a.rect = f->rect;
     a.splat = f->splat;
+    a.splat_grad = f->splat_grad;
     return a;
 }
 

@@ -38,6 +38,7 @@ struct RasterArgs {
     float* images;
     float* T_final;
     u32* n_contrib;
+    u32* n_comp;
     // backward
     const float* dL;
     float* splat_grad;
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(GS_BLOCK) raster_fwd_kernel(RasterArgs a) {
         const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
 
         float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-        u32 last = 0;
+        u32 last = 0, ncomp = 0;
         bool done = !inside;
         for (u32 b0 = rg.x; b0 < rg.y; b0 += BATCH) {
             if (__syncthreads_count(done) == GS_BLOCK) break;
@@ -106,6 +107,7 @@ __global__ void __launch_bounds__(GS_BLOCK) raster_fwd_kernel(RasterArgs a) {
                     C2 = fmaf(c.z, wgt, C2);
                     T = Tn;
                     last = b0 - rg.x + k + 1;
+                    ++ncomp;
                 }
             }
         }
@@ -118,6 +120,7 @@ __global__ void __launch_bounds__(GS_BLOCK) raster_fwd_kernel(RasterArgs a) {
             img[2 * hw] = fmaf(T, a.bg2, C2);
             a.T_final[pix] = T;
             a.n_contrib[pix] = last;
+            a.n_comp[pix] = ncomp;
         }
         if (!a.queue) break;
     }
@@ -265,6 +268,7 @@ RasterArgs make_args(gs_frame* f, const gs_raster_opts* o) {
     a.images = nullptr;
     a.T_final = f->T_final;
     a.n_contrib = f->n_contrib;
+    a.n_comp = f->n_comp;
     a.dL = nullptr;
     a.splat_grad = f->splat_grad;
     return a;

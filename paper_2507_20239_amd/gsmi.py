@@ -25,7 +25,8 @@ MAX_VIEWS = 32
 TILE = 16
 
 BUF_DEPTH_KEY, BUF_TILES_TOUCHED, BUF_RECT, BUF_SPLAT, BUF_SORTED_ENTRIES, BUF_INST_TILE, \
-    BUF_INST_ENTRY, BUF_RANGES, BUF_T_FINAL, BUF_N_CONTRIB, BUF_SPLAT_GRAD, BUF_COUNTERS = range(12)
+    BUF_INST_ENTRY, BUF_RANGES, BUF_T_FINAL, BUF_N_CONTRIB, BUF_SPLAT_GRAD, BUF_COUNTERS, \
+    BUF_N_COMPOSITED = range(13)
 KIND_KEEP, KIND_CLONE, KIND_SPLIT0, KIND_SPLIT1 = range(4)
 ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO = range(5)
 
