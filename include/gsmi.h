@@ -102,10 +102,10 @@ typedef struct {
 typedef struct {
     float bg[3];                 /* background colour composited behind every pixel */
     float near_plane;            /* Gaussians with camera depth <= near are culled (default 0.2) */
-    int32_t raster_batch;        /* Gaussians staged in LDS per batch: 64, 128 or 256; 0 = 256 */
-    int32_t persistent_blocks;   /* 0: one workgroup per (view, tile);  > 0: a persistent grid of
-                                    this many workgroups takes (view, tile) items from a queue,
-                                    heaviest tile lists first */
+    int32_t raster_batch;        /* Gaussians staged in LDS per batch: 64, 128 or 256; 0 = 128 */
+    int32_t persistent_blocks;   /* 0: one wave64 workgroup per (view, tile);  > 0: a persistent
+                                    grid of this many wave64 workgroups takes (view, tile) items
+                                    from a queue, heaviest tile lists first */
     int32_t reserved[2];
 } gs_raster_opts;
 
@@ -142,7 +142,8 @@ enum {
     GS_BUF_RANGES = 7,        /* u32 [T][2]  [start, end) of each tile's instance list */
     GS_BUF_T_FINAL = 8,       /* f32 [P]     final transmittance per pixel */
     GS_BUF_N_CONTRIB = 9,     /* u32 [P]     instances walked per pixel (last composited + 1) */
-    GS_BUF_SPLAT_GRAD = 10,   /* f32 [V*n][9] dL/d(mean2d x, y, conic a, b, c, opacity, r, g, b) */
+    GS_BUF_SPLAT_GRAD = 10,   /* f32 [V*n][9] dL/d(mean2d x, y, conic a, b, c, opacity, r, g, b);
+                                 defined for rendered entries (tiles_touched > 0) only */
     GS_BUF_COUNTERS = 11,     /* u32 [16]    [0] visible entries, [1] instances, [2] overflow flag */
     GS_BUF_N_COMPOSITED = 12  /* u32 [P]     splats composited per pixel */
 };

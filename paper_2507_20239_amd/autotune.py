@@ -1,8 +1,8 @@
 """Autotuner for the rasterizer launch shape.
 
 Searches the LDS batch size (splats staged per batch: 64, 128, 256) and the
-work distribution (one workgroup per (view, tile), or a persistent grid of
-1024 / 2048 workgroups pulling tiles heaviest-first from a queue) by timing
+work distribution (one wave64 workgroup per (view, tile), or a persistent grid
+of 2048 / 4096 / 8192 waves pulling tiles heaviest-first from a queue) by timing
 the captured training step of the given views, and caches the winner per
 (device, workload signature) in a JSON file ($GSMI_AUTOTUNE_CACHE, default
 ~/.cache/gsmi_autotune.json).
@@ -17,7 +17,7 @@ import torch
 from . import gsmi
 
 BATCHES = (64, 128, 256)
-PERSISTENT = (0, 1024, 2048)
+PERSISTENT = (0, 2048, 4096, 8192)
 
 
 def _cache_path():

@@ -44,8 +44,8 @@ gs_status check_views(int64_t n, int32_t V, const int32_t* widths, const int32_t
     if (n < 0) return gs_fail(GS_ERR_INVALID, "n must be >= 0");
     if (V < 1 || V > GS_MAX_VIEWS) return gs_fail(GS_ERR_INVALID, "n_views must be in [1, %d]", GS_MAX_VIEWS);
     if (!widths || !heights) return gs_fail(GS_ERR_INVALID, "widths/heights are null");
-    if ((int64_t)V * n >= ((int64_t)1 << 31)) return gs_fail(GS_ERR_INVALID, "n_views * n must be < 2^31");
-    if (cap < 1 || cap >= ((int64_t)1 << 31) - 1) return gs_fail(GS_ERR_INVALID, "max_instances must be in [1, 2^31-1)");
+    if ((int64_t)V * n >= ((int64_t)1 << 30)) return gs_fail(GS_ERR_INVALID, "n_views * n must be < 2^30");
+    if (cap < 1 || cap >= ((int64_t)1 << 30)) return gs_fail(GS_ERR_INVALID, "max_instances must be in [1, 2^30)");
     int64_t tiles = 0;
     for (int v = 0; v < V; ++v) {
         if (widths[v] <= 0 || heights[v] <= 0 || widths[v] > 16384 || heights[v] > 16384)
@@ -80,12 +80,11 @@ void fill_views(gs_frame* f, const int32_t* widths, const int32_t* heights) {
 
 Layout layout_for(gs_frame* f) {
     const uint64_t E = (uint64_t)f->E, cap = (uint64_t)f->cap, T = (uint64_t)f->T, P = (uint64_t)f->P;
-    f->G_vis = gs_radix_partitions(f->E);
-    f->G_inst = gs_radix_partitions(f->cap);
-    f->G_tile = gs_radix_partitions(f->T);
-    int G = f->G_vis;
-    if (f->G_inst > G) G = f->G_inst;
-    if (f->G_tile > G) G = f->G_tile;
+    uint64_t sort_bytes = gs_radix_scratch_bytes(f->E, 31);
+    const uint64_t si = gs_radix_scratch_bytes(f->cap, f->tile_bits);
+    const uint64_t st = gs_radix_scratch_bytes(f->T, 24);
+    if (si > sort_bytes) sort_bytes = si;
+    if (st > sort_bytes) sort_bytes = st;
     Layout L;
     L.add(4 * E);        // 0 depth_key
     L.add(4 * E);        // 1 tiles_touched
@@ -110,10 +109,11 @@ Layout layout_for(gs_frame* f) {
     L.add(4 * P);        // 20 n_contrib
     L.add(36 * E);       // 21 splat_grad
     L.add(64);           // 22 counters
-    L.add(4 * 256 * (uint64_t)G);  // 23 radix_hist
+    L.add(sort_bytes);   // 23 sort scratch
     L.add(4 * (GS_SCAN_PARTS + 8));  // 24 scan_part
     L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 25 views
     L.add(4 * P);        // 26 n_comp
+    L.add(4 * (cap / 256 + 2));  // 27 chunk_start
     return L;
 }
 
@@ -212,10 +212,11 @@ gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
     f->n_contrib = (u32*)(b + L.off[20]);
     f->splat_grad = (float*)(b + L.off[21]);
     f->counters = (u32*)(b + L.off[22]);
-    f->radix_hist = (u32*)(b + L.off[23]);
+    f->sort_scratch = (void*)(b + L.off[23]);
     f->scan_part = (u32*)(b + L.off[24]);
     f->d_views = (gs_view_info*)(b + L.off[25]);
     f->n_comp = (u32*)(b + L.off[26]);
+    f->chunk_start = (u32*)(b + L.off[27]);
     // the slots holding sorted results depend only on the pass counts
     f->vsorted = (((31 + 7) / 8) & 1);
     f->isorted = (((f->tile_bits + 7) / 8) & 1);
@@ -266,6 +267,7 @@ gs_status gs_frame_status(gs_frame* f, void* stream, int64_t* n_visible, int64_t
     if (n_visible) *n_visible = h[0];
     if (n_instances) *n_instances = h[1];
     if (overflow) *overflow = (int32_t)h[2];
+    if (h[6]) return gs_fail(GS_ERR_HIP, "a sort look-back wait gave up; results are invalid");
     return h[2] ? gs_fail(GS_ERR_CAPACITY, "instance capacity %lld exceeded (%u needed)",
                           (long long)f->cap, h[1])
                 : GS_OK;
@@ -313,10 +315,9 @@ gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camer
 }
 
 gs_status gs_sort_workspace_size(int64_t n, uint64_t* bytes) {
-    if (n < 0 || n >= ((int64_t)1 << 31) - 1 || !bytes) return gs_fail(GS_ERR_INVALID, "bad argument");
-    const int G = gs_radix_partitions(n);
-    *bytes = 2 * align256(4 * (uint64_t)(n > 0 ? n : 1)) + align256(4 * 256 * (uint64_t)G) +
-             align256(4 * (GS_SCAN_PARTS + 8));
+    if (n < 0 || n >= ((int64_t)1 << 30) || !bytes) return gs_fail(GS_ERR_INVALID, "bad argument");
+    *bytes = 2 * align256(4 * (uint64_t)(n > 0 ? n : 1)) + align256(gs_radix_scratch_bytes(n, 32)) +
+             256;
     return GS_OK;
 }
 
@@ -331,13 +332,13 @@ gs_status gs_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int32_t key_b
     hipStream_t s = (hipStream_t)stream;
     char* b = (char*)workspace;
     const uint64_t nb = align256(4 * (uint64_t)n);
-    const int G = gs_radix_partitions(n);
     u32* k[2] = {keys, (u32*)b};
     u32* v[2] = {vals, (u32*)(b + nb)};
-    u32* hist = (u32*)(b + 2 * nb);
-    u32* part = (u32*)(b + 2 * nb + align256(4 * 256 * (uint64_t)G));
+    void* scratch = (void*)(b + 2 * nb);
+    u32* err = (u32*)(b + 2 * nb + align256(gs_radix_scratch_bytes(n, 32)));
     int slot = 0;
-    GS_TRY(gs_radix_sort(k, v, nullptr, (u32)n, key_bits, G, hist, part, &slot, s));
+    GS_TRY(gs_fill_u32(err, 0u, 1, s));
+    GS_TRY(gs_radix_sort(k, v, nullptr, (u32)n, n, key_bits, scratch, err, &slot, s));
     if (slot == 1) {
         GS_HIP(hipMemcpyAsync(keys, k[1], 4 * n, hipMemcpyDeviceToDevice, s));
         GS_HIP(hipMemcpyAsync(vals, v[1], 4 * n, hipMemcpyDeviceToDevice, s));

@@ -19,11 +19,6 @@
 
 namespace {
 
-__global__ void flag_visible_kernel(const u32* tiles_touched, u32* flags, int64_t E) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < E) flags[i] = tiles_touched[i] > 0 ? 1u : 0u;
-}
-
 __global__ void compact_kernel(const u32* tiles_touched, const u32* offs, const u32* depth_key,
                                u32* keys, u32* vals, int64_t E) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,45 +36,94 @@ __global__ void gather_counts_kernel(const u32* vals, const u32* tiles_touched, 
     cnt[j] = e < (u64)E ? tiles_touched[e] : 0u;
 }
 
-// counters[5] = min(instances, capacity): the length the tile sort works on
-__global__ void clamp_count_kernel(u32* counters, u32 cap) {
-    const u32 n = counters[1];
-    counters[5] = n < cap ? n : cap;
-    counters[2] = n > cap ? 1u : 0u;
+// Instance emission, balanced per 256 instances.  Pass 1 records, for every
+// chunk of 256 consecutive instance slots, the depth-sorted entry whose tiles
+// start the chunk.  Pass 2 gives each workgroup whole chunks: it stages the
+// (at most 256) entries a chunk can touch in LDS, and each thread finds the
+// entry of its slot by binary search over their offsets (strictly
+// increasing: every visible entry has at least one tile), then writes
+// (tile, entry) for the k-th tile of the rectangle, row-major.  Depth order
+// puts the largest footprints (nearest Gaussians) together, so balancing on
+// instances rather than on entries is what keeps the workgroups even.
+constexpr u32 EMIT_CHUNK = 256;
+
+// Also publishes counters[5] = min(instances, capacity) (the length the tile
+// sort works on) and the overflow flag counters[2].
+__global__ void chunk_start_kernel(const u32* vals, const u32* offs, const u32* tiles_touched,
+                                   u32* counters, u32 cap, u32* chunk_start, int64_t E) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const u32 total = counters[1];
+    const u32 kept = total < cap ? total : cap;
+    if (j == 0) {
+        counters[5] = kept;
+        counters[2] = total > cap ? 1u : 0u;
+    }
+    if (j >= E || j >= (int64_t)counters[0]) return;
+    const u32 e = vals[j];
+    const u32 tt = e < (u64)E ? tiles_touched[e] : 0u;
+    const u32 off = offs[j];
+    if (tt == 0 || off >= kept) return;
+    const u32 last = (off + tt - 1) < kept ? off + tt - 1 : kept - 1;
+    for (u32 c = (off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK <= last; ++c) chunk_start[c] = (u32)j;
 }
 
-__global__ void emit_kernel(const u32* vals, const u32* offs, const uint2* rect,
-                            const gs_view_info* views, int64_t n, const u32* n_vis, u32 cap,
-                            u32* tile_keys, u32* entries, int64_t E) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= E || j >= (int64_t)*n_vis) return;
-    const u32 e = vals[j];
-    if (e >= (u64)E) return;
-    const int v = (int)(e / (u64)n);
-    const gs_view_info vi = views[v];
-    const uint2 r = rect[e];
-    const u32 x0 = r.x & 0xffffu, x1 = r.x >> 16, y0 = r.y & 0xffffu, y1 = r.y >> 16;
-    u32 o = offs[j];
-    for (u32 ty = y0; ty <= y1; ++ty) {
-        const u32 row = (u32)vi.tile_base + ty * (u32)vi.tiles_x;
-        for (u32 tx = x0; tx <= x1; ++tx) {
-            if (o < cap) {
-                tile_keys[o] = row + tx;
-                entries[o] = e;
+__global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u32* offs,
+                                                        const uint2* rect,
+                                                        const gs_view_info* views, int64_t n,
+                                                        const u32* n_vis, const u32* n_kept,
+                                                        const u32* chunk_start, u32* tile_keys,
+                                                        u32* entries, int64_t E) {
+    __shared__ u32 s_off[EMIT_CHUNK], s_e[EMIT_CHUNK], s_rx[EMIT_CHUNK], s_ry[EMIT_CHUNK];
+    __shared__ u32 s_tb[EMIT_CHUNK], s_tw[EMIT_CHUNK];
+    const int t = threadIdx.x;
+    const u32 nv = *n_vis, kept = *n_kept;
+    const u32 chunks = (kept + EMIT_CHUNK - 1) / EMIT_CHUNK;
+    for (u32 c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const u32 j0 = chunk_start[c];
+        const int m = (nv - j0) < EMIT_CHUNK ? (int)(nv - j0) : (int)EMIT_CHUNK;
+        __syncthreads();
+        if (t < m) {
+            u32 e = vals[j0 + t];
+            if (e >= (u64)E) e = 0;
+            const uint2 r = rect[e];
+            int v = 0;
+            while ((u64)(v + 1) * (u64)n <= (u64)e) ++v;   // view of the entry (V <= 32)
+            s_off[t] = offs[j0 + t];
+            s_e[t] = e;
+            s_rx[t] = r.x;
+            s_ry[t] = r.y;
+            s_tb[t] = (u32)views[v].tile_base;
+            s_tw[t] = (u32)views[v].tiles_x;
+        }
+        __syncthreads();
+        const u32 o = c * EMIT_CHUNK + (u32)t;
+        if (o < kept) {
+            int lo = 0, hi = m - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= o) lo = mid;
+                else hi = mid - 1;
             }
-            ++o;
+            const u32 k = o - s_off[lo];
+            const u32 rx = s_rx[lo], ry = s_ry[lo];
+            const u32 x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu;
+            const u32 w = x1 - x0 + 1;
+            const u32 dy = k / w, dx = k - dy * w;
+            tile_keys[o] = s_tb[lo] + (y0 + dy) * s_tw[lo] + x0 + dx;
+            entries[o] = s_e[lo];
         }
     }
 }
 
 __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, u32 T) {
     const u32 n = *n_ptr;
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const u32 k = keys[i];
-    if (k >= T) return;
-    if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-    if (i == n - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+    const u32 stride = gridDim.x * blockDim.x;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const u32 k = keys[i];
+        if (k >= T) continue;
+        if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
+        if (i == n - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+    }
 }
 
 // heavy-first order key: longer lists first, ties by tile id (stable sort)
@@ -100,41 +144,40 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     const int64_t E = f->E;
     u32* cnt = f->counters;
     if (E > 0) {
-        flag_visible_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(f->tiles_touched, f->flags, E);
-        GS_TRY(gs_check_launch("flag_visible"));
+        // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection
         GS_TRY(gs_scan_exclusive(f->flags, f->flags, nullptr, (u32)E, cnt + 0, f->scan_part, s));
         compact_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(f->tiles_touched, f->flags, f->depth_key,
                                                           f->vkeys[0], f->vvals[0], E);
         GS_TRY(gs_check_launch("compact"));
         // depths are positive, so the sign bit is zero: 31 key bits
-        GS_TRY(gs_radix_sort(f->vkeys, f->vvals, cnt + 0, 0, 31, f->G_vis, f->radix_hist,
-                             f->scan_part, &f->vsorted, s));
+        GS_TRY(gs_radix_sort(f->vkeys, f->vvals, cnt + 0, 0, E, 31, f->sort_scratch, cnt + 6,
+                             &f->vsorted, s));
         const u32* sv = f->vvals[f->vsorted];
         gather_counts_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->tiles_touched, f->inst_off,
                                                                 cnt + 0, E);
         GS_TRY(gs_check_launch("gather_counts"));
         GS_TRY(gs_scan_exclusive(f->inst_off, f->inst_off, cnt + 0, 0, cnt + 1, f->scan_part, s));
-        clamp_count_kernel<<<1, 1, 0, s>>>(cnt, (u32)f->cap);
-        GS_TRY(gs_check_launch("clamp_count"));
-        emit_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->inst_off, f->rect, f->d_views, f->n,
-                                                       cnt + 0, (u32)f->cap, f->ikeys[0],
-                                                       f->ivals[0], E);
+        chunk_start_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->inst_off, f->tiles_touched,
+                                                              cnt, (u32)f->cap, f->chunk_start, E);
+        GS_TRY(gs_check_launch("chunk_start"));
+        emit_kernel<<<2048, GS_BLOCK, 0, s>>>(sv, f->inst_off, f->rect, f->d_views, f->n, cnt + 0,
+                                              cnt + 5, f->chunk_start, f->ikeys[0], f->ivals[0], E);
         GS_TRY(gs_check_launch("emit"));
-        GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->tile_bits, f->G_inst,
-                             f->radix_hist, f->scan_part, &f->isorted, s));
+        GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->cap, f->tile_bits, f->sort_scratch,
+                             cnt + 6, &f->isorted, s));
     } else {
         GS_TRY(gs_fill_u32(cnt, 0u, 8, s));
     }
     GS_TRY(gs_fill_u32((u32*)f->ranges, 0u, 2 * (int64_t)f->T, s));
-    ranges_kernel<<<blocks_for(f->cap), GS_BLOCK, 0, s>>>(f->ikeys[f->isorted], cnt + 5, f->ranges,
+    ranges_kernel<<<1024, GS_BLOCK, 0, s>>>(f->ikeys[f->isorted], cnt + 5, f->ranges,
                                                               (u32)f->T);
     GS_TRY(gs_check_launch("ranges"));
     if (heavy_first) {
         tile_weight_kernel<<<blocks_for(f->T), GS_BLOCK, 0, s>>>(f->ranges, f->tkeys[0], f->tvals[0],
                                                                  f->T);
         GS_TRY(gs_check_launch("tile_weight"));
-        GS_TRY(gs_radix_sort(f->tkeys, f->tvals, nullptr, (u32)f->T, 24, f->G_tile, f->radix_hist,
-                             f->scan_part, &f->tsorted, s));
+        GS_TRY(gs_radix_sort(f->tkeys, f->tvals, nullptr, (u32)f->T, f->T, 24, f->sort_scratch,
+                             cnt + 6, &f->tsorted, s));
     }
     return GS_OK;
 }

@@ -53,6 +53,7 @@ struct gs_frame {
     // instances (ping-pong)
     u32* ikeys[2];       // [cap]
     u32* ivals[2];       // [cap]
+    u32* chunk_start;    // [cap / 256 + 1] first entry of each 256-instance chunk
     int isorted;
     uint2* ranges;       // [T]
     // heavy-first tile order for persistent launches
@@ -66,12 +67,12 @@ struct gs_frame {
     u32* n_comp;         // [P] splats composited per pixel
     // per splat gradient
     float* splat_grad;   // [E][9]
-    // counters: [0] visible, [1] instances, [2] overflow, [3] fwd queue, [4] bwd queue
+    // counters: [0] visible, [1] instances, [2] overflow, [3] fwd queue, [4] bwd queue,
+    // [5] instances kept (min(instances, capacity)), [6] sort look-back error
     u32* counters;
-    // sort scratch
-    u32* radix_hist;     // [256 * G]
+    // sort and scan scratch
+    void* sort_scratch;
     u32* scan_part;      // [GS_SCAN_PARTS + 1]
-    int G_vis, G_inst, G_tile;
 };
 
 #define GS_SCAN_PARTS 1024
@@ -107,13 +108,15 @@ gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s);
 gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
                             u32* part, hipStream_t s);
 
-// stable LSD radix sort on the low `bits` bits.  Buffers k[0]/v[0] hold the input;
-// returns in *slot the buffer index (0 or 1) that holds the result.
-// hist needs 256 * G u32.
-gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int bits, int G,
-                        u32* hist, u32* part, int* slot, hipStream_t s);
-
-int gs_radix_partitions(int64_t capacity);
+// stable LSD radix sort on the low `bits` bits (8-bit digits, one kernel per
+// pass).  Buffers k[0]/v[0] hold the input; *slot receives the buffer index
+// (0 or 1) that holds the result.  The length is n_dev[0] when n_dev != NULL,
+// else n_host, and never exceeds `capacity` (< 2^30).  `scratch` needs
+// gs_radix_scratch_bytes(capacity, bits); `err` (device) is or-ed with 1 if a
+// look-back wait gave up (the output is then invalid).
+gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
+                        int bits, void* scratch, u32* err, int* slot, hipStream_t s);
+uint64_t gs_radix_scratch_bytes(int64_t capacity, int bits);
 
 gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                             float near_plane, hipStream_t s);

@@ -126,6 +126,8 @@ struct ProjArgs {
     uint2* rect;
     float4* splat;
     float* splat_grad;     // [E][9], cleared here for the adjoint of this step
+    u32* flags;            // [E] 1 if rendered (input of the visible-entry compaction)
+    u32* counters;         // frame counters; [6] (sort error) is cleared here
 };
 
 // Per-Gaussian activated parameters.
@@ -138,19 +140,26 @@ struct Activated {
     float Sig[6];      // Sigma: 00 01 02 11 12 22
 };
 
-__device__ __forceinline__ void activate(const ProjArgs& a, int64_t i, float mu[3], Activated& g) {
+// Position, scales and opacity: all the culling test needs.
+__device__ __forceinline__ void activate_light(const ProjArgs& a, int64_t i, float mu[3],
+                                              Activated& g) {
     const int64_t n = a.n;
     mu[0] = a.means[i];
     mu[1] = a.means[n + i];
     mu[2] = a.means[2 * n + i];
 #pragma unroll
     for (int k = 0; k < 3; ++k) g.s[k] = expf(a.log_scales[k * n + i]);
+    g.o = 1.0f / (1.0f + expf(-a.logits[i]));
+}
+
+// Rotation and covariance (Eq. 1: Sigma = R S S^T R^T).
+__device__ __forceinline__ void activate_rot(const ProjArgs& a, int64_t i, Activated& g) {
+    const int64_t n = a.n;
     float q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
     g.qnorm = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     const float inv = 1.0f / g.qnorm;
     const float w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
     g.q[0] = w; g.q[1] = x; g.q[2] = y; g.q[3] = z;
-    g.o = 1.0f / (1.0f + expf(-a.logits[i]));
     g.R[0] = 1.f - 2.f * (y * y + z * z); g.R[1] = 2.f * (x * y - w * z); g.R[2] = 2.f * (x * z + w * y);
     g.R[3] = 2.f * (x * y + w * z); g.R[4] = 1.f - 2.f * (x * x + z * z); g.R[5] = 2.f * (y * z - w * x);
     g.R[6] = 2.f * (x * z - w * y); g.R[7] = 2.f * (y * z + w * x); g.R[8] = 1.f - 2.f * (x * x + y * y);
@@ -229,11 +238,13 @@ template <int DEG>
 __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+    if (i == 0) a.counters[6] = 0;   // sort look-back error flag of this step
     if (i >= a.n) return;
     const int64_t n = a.n;
     float mu[3];
     Activated g;
-    activate(a, i, mu, g);
+    activate_light(a, i, mu, g);
+    activate_rot(a, i, g);
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -246,8 +257,7 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
         const int64_t e = (int64_t)v * n + i;
         ViewProj p;
         const bool ok = view_project(c, vi, a.near_plane, mu, g, p);
-        const float tzf = (float)p.tz;
-        a.depth_key[e] = __float_as_uint(tzf);
+        a.depth_key[e] = __float_as_uint((float)p.tz);
         u32 tt = 0;
         uint2 rc = make_uint2(0u, 0u);
         if (ok && g.o >= GS_ALPHA_MIN) {
@@ -293,8 +303,10 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
             }
         }
         a.tiles_touched[e] = tt;
-        a.rect[e] = rc;
-        if (a.splat_grad) {
+        a.flags[e] = tt ? 1u : 0u;
+        if (tt) {
+            a.rect[e] = rc;
+            // the adjoint of this step accumulates into these
 #pragma unroll
             for (int k = 0; k < 9; ++k) a.splat_grad[9 * e + k] = 0.f;
         }
@@ -321,9 +333,14 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
+    // Every lane takes the same path (a Gaussian no view rendered just gets
+    // zeros): with visibility scattered over the index order every 128-byte
+    // line of the SoA arrays is fetched anyway, and a divergent early exit
+    // would split each store into partial-line writes.
     float mu[3];
     Activated g;
-    activate(a, i, mu, g);
+    activate_light(a, i, mu, g);
+    activate_rot(a, i, g);
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -534,6 +551,8 @@ ProjArgs make_args(gs_frame* f, const gs_gaussians* g, const gs_camera* cams, fl
     a.rect = f->rect;
     a.splat = f->splat;
     a.splat_grad = f->splat_grad;
+    a.flags = f->flags;
+    a.counters = f->counters;
     return a;
 }
 

@@ -1,27 +1,32 @@
 // Tile rasterizer: front-to-back compositing of depth-sorted splats (Eq. 2
 // of the paper) and its adjoint.
 //
-// One 256-lane workgroup (4 wave64) owns a 16x16 tile; each wave owns an 8x8
-// quadrant (more compact than 16x4 rows, so a wave's pixels agree more often
-// on early termination).  The tile's depth-ordered splat list is streamed
-// through LDS in batches; every lane composites its own pixel.  A pixel stops
-// before the splat that would take its transmittance below 1e-4; a wave leaves
-// the batch loop when its execution mask empties, and the workgroup stops
-// loading batches once a block-wide count says every pixel is done.
+// One wave64 owns a 16x16 tile and each lane a 2x2 pixel quad (lanes form an
+// 8x8 grid of quads).  The tile's depth-ordered splat list is streamed
+// through LDS in batches (the lanes load one splat each, then every lane reads
+// the batch back with uniform, broadcast LDS loads) and each lane composites
+// its four pixels.  A pixel stops before the splat that would take its
+// transmittance below 1e-4; the wave leaves the list as soon as a ballot over
+// its lanes finds no live pixel.
 //
 // The adjoint replays the same lists back to front from each pixel's last
 // composited splat, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved
-// final transmittance instead of storing per-splat state.  Per-splat partial
-// derivatives are summed over the wave with DPP row shifts/broadcasts and the
-// 9 totals go to HBM with hardware FP32 atomics (one set per wave and splat).
+// final transmittance instead of storing per-splat state.  Each lane sums
+// the partial derivatives of its four pixels, the wave reduces the nine sums
+// with DPP row shifts and broadcasts, and one lane adds them to HBM with
+// hardware FP32 atomics: one set of atomics per (splat, tile).  Owning a whole
+// tile with one wave is what keeps both the reductions and the atomics at one
+// per (splat, tile) instead of one per (splat, wave).
 //
 // Work items are (view, tile) pairs over every view of the frame.  With
-// persistent > 0 a fixed grid takes items from an atomic queue in
+// persistent > 0 a fixed grid of waves takes items from an atomic queue in
 // heaviest-list-first order (coarse-to-fine batches mix tiny and full-size
 // views, so the tail is what limits a plain launch).
 #include "gs_internal.h"
 
 namespace {
+
+constexpr int PIX = 4;   // pixels per lane (2x2 quad)
 
 struct RasterArgs {
     const float4* splat;       // [E][3]
@@ -50,204 +55,239 @@ __device__ __forceinline__ int find_view(const gs_view_info* views, int V, u32 t
     return v;
 }
 
-template <int BATCH>
-__global__ void __launch_bounds__(GS_BLOCK) raster_fwd_kernel(RasterArgs a) {
-    __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
-    __shared__ u32 s_item;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
-    u32 item = blockIdx.x;
-    for (;;) {
-        if (a.queue) {
-            __syncthreads();
-            if (tid == 0) s_item = atomicAdd(a.queue, 1u);
-            __syncthreads();
-            item = s_item;
-        }
-        if (item >= (u32)a.T) break;
-        const u32 t = a.order ? a.order[item] : item;
-        const int v = find_view(a.views, a.V, t);
-        const gs_view_info vi = a.views[v];
-        const int lt = (int)t - vi.tile_base;
-        const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
-        const int px = tx * GS_TILE + lx, py = ty * GS_TILE + ly;
-        const bool inside = px < vi.width && py < vi.height;
-        const uint2 rg = a.ranges[t];
-        const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+// Next work item of this wave: the block index, or a queue ticket.
+__device__ __forceinline__ u32 next_item(const RasterArgs& a, u32 item, bool first) {
+    if (!a.queue) return first ? blockIdx.x : (u32)a.T;
+    u32 t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(a.queue, 1u);
+    return __shfl(t, 0, 64);
+}
 
-        float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-        u32 last = 0, ncomp = 0;
-        bool done = !inside;
-        for (u32 b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-            if (__syncthreads_count(done) == GS_BLOCK) break;
-            const u32 cnt = min((u32)BATCH, rg.y - b0);
-            if ((u32)tid < cnt) {
-                u32 e = a.inst_entry[b0 + tid];
-                if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
-                sp0[tid] = a.splat[3 * (u64)e + 0];
-                sp1[tid] = a.splat[3 * (u64)e + 1];
-                sp2[tid] = a.splat[3 * (u64)e + 2];
-            }
-            __syncthreads();
-            if (!done) {
-                for (u32 k = 0; k < cnt; ++k) {
-                    float G, dx, dy;
-                    const float raw = splat_raw_alpha(sp0[k], sp1[k], pxc, pyc, G, dx, dy);
-                    const float alpha = fminf(raw, GS_ALPHA_MAX);
-                    if (alpha < GS_ALPHA_MIN) continue;
-                    const float Tn = T * (1.f - alpha);
-                    if (Tn < GS_T_MIN) {
-                        done = true;
-                        break;
-                    }
-                    const float4 c = sp2[k];
-                    const float wgt = alpha * T;
-                    C0 = fmaf(c.x, wgt, C0);
-                    C1 = fmaf(c.y, wgt, C1);
-                    C2 = fmaf(c.z, wgt, C2);
-                    T = Tn;
-                    last = b0 - rg.x + k + 1;
-                    ++ncomp;
-                }
-            }
-        }
-        if (inside) {
-            const int64_t pix = vi.pix_base + (int64_t)py * vi.width + px;
-            const int64_t hw = (int64_t)vi.width * vi.height;
-            float* img = a.images + 3 * vi.pix_base + (int64_t)py * vi.width + px;
-            img[0] = fmaf(T, a.bg0, C0);
-            img[hw] = fmaf(T, a.bg1, C1);
-            img[2 * hw] = fmaf(T, a.bg2, C2);
-            a.T_final[pix] = T;
-            a.n_contrib[pix] = last;
-            a.n_comp[pix] = ncomp;
-        }
-        if (!a.queue) break;
+struct TileCoords {
+    gs_view_info vi;
+    uint2 rg;
+    int px0, py0;   // top-left pixel of this lane's quad
+};
+
+__device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t) {
+    TileCoords c;
+    const int v = find_view(a.views, a.V, t);
+    c.vi = a.views[v];
+    const int lt = (int)t - c.vi.tile_base;
+    const int tx = lt % c.vi.tiles_x, ty = lt / c.vi.tiles_x;
+    const int lane = threadIdx.x;
+    c.px0 = tx * GS_TILE + 2 * (lane & 7);
+    c.py0 = ty * GS_TILE + 2 * (lane >> 3);
+    c.rg = a.ranges[t];
+    return c;
+}
+
+template <int BATCH>
+__device__ __forceinline__ void load_batch(const RasterArgs& a, u32 b0, u32 cnt, float4* sp0,
+                                           float4* sp1, float4* sp2, u32* se) {
+    for (u32 j = threadIdx.x; j < cnt; j += 64) {
+        u32 e = a.inst_entry[b0 + j];
+        if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
+        sp0[j] = a.splat[3 * (u64)e + 0];
+        sp1[j] = a.splat[3 * (u64)e + 1];
+        sp2[j] = a.splat[3 * (u64)e + 2];
+        if (se) se[j] = e;
     }
 }
 
 template <int BATCH>
-__global__ void __launch_bounds__(GS_BLOCK) raster_bwd_kernel(RasterArgs a) {
+__global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
+    __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
+    for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
+        const u32 t = a.order ? a.order[item] : item;
+        const TileCoords tc = tile_coords(a, t);
+        float pxc[PIX], pyc[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
+        u32 last[PIX], ncomp[PIX];
+        bool done[PIX];
+#pragma unroll
+        for (int i = 0; i < PIX; ++i) {
+            const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
+            pxc[i] = (float)px + 0.5f;
+            pyc[i] = (float)py + 0.5f;
+            T[i] = 1.f;
+            C0[i] = C1[i] = C2[i] = 0.f;
+            last[i] = 0;
+            ncomp[i] = 0;
+            done[i] = !(px < tc.vi.width && py < tc.vi.height);
+        }
+        for (u32 b0 = tc.rg.x; b0 < tc.rg.y; b0 += BATCH) {
+            if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0) break;
+            const u32 cnt = min((u32)BATCH, tc.rg.y - b0);
+            __syncthreads();
+            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2, nullptr);
+            __syncthreads();
+            for (u32 k = 0; k < cnt; ++k) {
+                const float4 p0 = sp0[k], p1 = sp1[k];
+                bool live = false;
+#pragma unroll
+                for (int i = 0; i < PIX; ++i) {
+                    float G, dx, dy;
+                    const float raw = splat_raw_alpha(p0, p1, pxc[i], pyc[i], G, dx, dy);
+                    const float alpha = fminf(raw, GS_ALPHA_MAX);
+                    bool take = !done[i] && alpha >= GS_ALPHA_MIN;
+                    const float Tn = T[i] * (1.f - alpha);
+                    const bool stop = take && Tn < GS_T_MIN;
+                    done[i] = done[i] || stop;
+                    take = take && !stop;
+                    if (take) {
+                        const float4 c = sp2[k];
+                        const float wgt = alpha * T[i];
+                        C0[i] = fmaf(c.x, wgt, C0[i]);
+                        C1[i] = fmaf(c.y, wgt, C1[i]);
+                        C2[i] = fmaf(c.z, wgt, C2[i]);
+                        T[i] = Tn;
+                        last[i] = b0 - tc.rg.x + k + 1;
+                        ++ncomp[i];
+                    }
+                    live = live || !done[i];
+                }
+                if (__ballot(live) == 0) break;
+            }
+        }
+        const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
+#pragma unroll
+        for (int i = 0; i < PIX; ++i) {
+            const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
+            if (px < tc.vi.width && py < tc.vi.height) {
+                const int64_t off = (int64_t)py * tc.vi.width + px;
+                float* img = a.images + 3 * tc.vi.pix_base + off;
+                img[0] = fmaf(T[i], a.bg0, C0[i]);
+                img[hw] = fmaf(T[i], a.bg1, C1[i]);
+                img[2 * hw] = fmaf(T[i], a.bg2, C2[i]);
+                a.T_final[tc.vi.pix_base + off] = T[i];
+                a.n_contrib[tc.vi.pix_base + off] = last[i];
+                a.n_comp[tc.vi.pix_base + off] = ncomp[i];
+            }
+        }
+    }
+}
+
+template <int BATCH>
+__global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
     __shared__ u32 se[BATCH];
-    __shared__ u32 s_item, s_max;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
-    u32 item = blockIdx.x;
-    for (;;) {
-        if (a.queue) {
-            __syncthreads();
-            if (tid == 0) s_item = atomicAdd(a.queue, 1u);
-            __syncthreads();
-            item = s_item;
-        }
-        if (item >= (u32)a.T) break;
+    const int lane = threadIdx.x;
+    for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
         const u32 t = a.order ? a.order[item] : item;
-        const int v = find_view(a.views, a.V, t);
-        const gs_view_info vi = a.views[v];
-        const int lt = (int)t - vi.tile_base;
-        const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
-        const int px = tx * GS_TILE + lx, py = ty * GS_TILE + ly;
-        const bool inside = px < vi.width && py < vi.height;
-        const uint2 rg = a.ranges[t];
-        const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-
-        float T = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-        u32 last = 0;
-        if (inside) {
-            const int64_t pix = vi.pix_base + (int64_t)py * vi.width + px;
-            const int64_t hw = (int64_t)vi.width * vi.height;
-            const float* d = a.dL + 3 * vi.pix_base + (int64_t)py * vi.width + px;
-            T = a.T_final[pix];
-            last = a.n_contrib[pix];
-            g0 = d[0];
-            g1 = d[hw];
-            g2 = d[2 * hw];
-        }
-        // colour behind the current splat, background included
-        float S0 = T * a.bg0, S1 = T * a.bg1, S2 = T * a.bg2;
-        __syncthreads();
-        if (tid == 0) s_max = 0;
-        __syncthreads();
-        if (last) atomicMax(&s_max, last);
-        __syncthreads();
-        const u32 maxlast = s_max;
-
-        for (int bi = (int)((maxlast + BATCH - 1) / BATCH) - 1; bi >= 0; --bi) {
-            const u32 b0 = rg.x + (u32)bi * BATCH;
-            const u32 cnt = min((u32)BATCH, maxlast - (u32)bi * BATCH);
-            __syncthreads();
-            if ((u32)tid < cnt) {
-                u32 e = a.inst_entry[b0 + tid];
-                if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
-                se[tid] = e;
-                sp0[tid] = a.splat[3 * (u64)e + 0];
-                sp1[tid] = a.splat[3 * (u64)e + 1];
-                sp2[tid] = a.splat[3 * (u64)e + 2];
+        const TileCoords tc = tile_coords(a, t);
+        const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
+        float pxc[PIX], pyc[PIX], T[PIX], g0[PIX], g1[PIX], g2[PIX], S0[PIX], S1[PIX], S2[PIX];
+        u32 last[PIX];
+        u32 mlast = 0;
+#pragma unroll
+        for (int i = 0; i < PIX; ++i) {
+            const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
+            pxc[i] = (float)px + 0.5f;
+            pyc[i] = (float)py + 0.5f;
+            T[i] = g0[i] = g1[i] = g2[i] = 0.f;
+            last[i] = 0;
+            if (px < tc.vi.width && py < tc.vi.height) {
+                const int64_t off = (int64_t)py * tc.vi.width + px;
+                const float* d = a.dL + 3 * tc.vi.pix_base + off;
+                T[i] = a.T_final[tc.vi.pix_base + off];
+                last[i] = a.n_contrib[tc.vi.pix_base + off];
+                g0[i] = d[0];
+                g1[i] = d[hw];
+                g2[i] = d[2 * hw];
             }
+            // colour behind the current splat, background included
+            S0[i] = T[i] * a.bg0;
+            S1[i] = T[i] * a.bg1;
+            S2[i] = T[i] * a.bg2;
+            mlast = max(mlast, last[i]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mlast = max(mlast, (u32)__shfl_xor((int)mlast, off, 64));
+
+        for (int bi = (int)((mlast + BATCH - 1) / BATCH) - 1; bi >= 0; --bi) {
+            const u32 b0 = tc.rg.x + (u32)bi * BATCH;
+            const u32 cnt = min((u32)BATCH, mlast - (u32)bi * BATCH);
+            __syncthreads();
+            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2, se);
             __syncthreads();
             for (int k = (int)cnt - 1; k >= 0; --k) {
                 const u32 rel = (u32)bi * BATCH + (u32)k;
-                float gm0 = 0.f, gm1 = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, gop = 0.f;
+                const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
+                // per-lane moments of w = dL/dG * G over the lane's pixels:
+                // sum w dx, sum w dy, sum w dx^2, sum w dx dy, sum w dy^2; the
+                // conic is applied once per splat after the wave reduction
+                float sx = 0.f, sy = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, gop = 0.f;
                 float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
                 bool contrib = false;
-                if (rel < last) {
-                    const float4 p1 = sp1[k];
+#pragma unroll
+                for (int i = 0; i < PIX; ++i) {
+                    if (rel >= last[i]) continue;
                     float G, dx, dy;
-                    const float raw = splat_raw_alpha(sp0[k], p1, pxc, pyc, G, dx, dy);
+                    const float raw = splat_raw_alpha(p0, p1, pxc[i], pyc[i], G, dx, dy);
                     const float alpha = fminf(raw, GS_ALPHA_MAX);
-                    if (alpha >= GS_ALPHA_MIN) {
-                        contrib = true;
-                        const float4 c = sp2[k];
-                        const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-                        const float Ti = T * inv;
-                        const float wgt = alpha * Ti;
-                        gr0 = wgt * g0;
-                        gr1 = wgt * g1;
-                        gr2 = wgt * g2;
-                        const float cd = fmaf(c.x, g0, fmaf(c.y, g1, c.z * g2));
-                        const float sd = fmaf(S0, g0, fmaf(S1, g1, S2 * g2));
-                        const float dalpha = cd * Ti - sd * inv;
-                        S0 = fmaf(c.x, wgt, S0);
-                        S1 = fmaf(c.y, wgt, S1);
-                        S2 = fmaf(c.z, wgt, S2);
-                        T = Ti;
-                        if (raw <= GS_ALPHA_MAX) {
-                            gop = dalpha * G;
-                            const float gG = gop * p1.w;   // dL/dG * G
-                            gm0 = gG * fmaf(p1.x, dx, p1.y * dy);
-                            gm1 = gG * fmaf(p1.y, dx, p1.z * dy);
-                            ga = -0.5f * gG * dx * dx;
-                            gb = -gG * dx * dy;
-                            gc = -0.5f * gG * dy * dy;
-                        }
+                    if (alpha < GS_ALPHA_MIN) continue;
+                    contrib = true;
+                    const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+                    const float Ti = T[i] * inv;
+                    const float wgt = alpha * Ti;
+                    gr0 = fmaf(wgt, g0[i], gr0);
+                    gr1 = fmaf(wgt, g1[i], gr1);
+                    gr2 = fmaf(wgt, g2[i], gr2);
+                    const float cd = fmaf(c.x, g0[i], fmaf(c.y, g1[i], c.z * g2[i]));
+                    const float sd = fmaf(S0[i], g0[i], fmaf(S1[i], g1[i], S2[i] * g2[i]));
+                    const float dalpha = cd * Ti - sd * inv;
+                    S0[i] = fmaf(c.x, wgt, S0[i]);
+                    S1[i] = fmaf(c.y, wgt, S1[i]);
+                    S2[i] = fmaf(c.z, wgt, S2[i]);
+                    T[i] = Ti;
+                    if (raw <= GS_ALPHA_MAX) {
+                        const float go = dalpha * G;
+                        const float gG = go * p1.w;   // dL/dG * G
+                        const float wx = gG * dx, wy = gG * dy;
+                        gop += go;
+                        sx += wx;
+                        sy += wy;
+                        sxx = fmaf(wx, dx, sxx);
+                        sxy = fmaf(wx, dy, sxy);
+                        syy = fmaf(wy, dy, syy);
                     }
                 }
                 if (__ballot(contrib) == 0) continue;
-                gm0 = wave_sum_lane63(gm0);
-                gm1 = wave_sum_lane63(gm1);
-                ga = wave_sum_lane63(ga);
-                gb = wave_sum_lane63(gb);
-                gc = wave_sum_lane63(gc);
+                sx = wave_sum_lane63(sx);
+                sy = wave_sum_lane63(sy);
+                sxx = wave_sum_lane63(sxx);
+                sxy = wave_sum_lane63(sxy);
+                syy = wave_sum_lane63(syy);
                 gop = wave_sum_lane63(gop);
                 gr0 = wave_sum_lane63(gr0);
                 gr1 = wave_sum_lane63(gr1);
                 gr2 = wave_sum_lane63(gr2);
-                if (lane == 63) {
-                    float* dst = a.splat_grad + 9 * (u64)se[k];
-                    unsafeAtomicAdd(dst + 0, gm0);
-                    unsafeAtomicAdd(dst + 1, gm1);
-                    unsafeAtomicAdd(dst + 2, ga);
-                    unsafeAtomicAdd(dst + 3, gb);
-                    unsafeAtomicAdd(dst + 4, gc);
-                    unsafeAtomicAdd(dst + 5, gop);
-                    unsafeAtomicAdd(dst + 6, gr0);
-                    unsafeAtomicAdd(dst + 7, gr1);
-                    unsafeAtomicAdd(dst + 8, gr2);
-                }
+                // The nine totals sit in lane 63.  Broadcast them and let lanes
+                // 0..8 add one each: a single 9-lane atomic instruction, which
+                // the memory system coalesces into one request per cache line
+                // (nine single-lane atomics cost nine requests).
+                // dG/dmean = G Q d, dG/d(a, b, c) = -G (dx^2/2, dx dy, dy^2/2)
+                const float t_sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), 63));
+                const float t_sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), 63));
+                const float t_sxx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sxx), 63));
+                const float t_sxy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sxy), 63));
+                const float t_syy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(syy), 63));
+                const float t_op = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gop), 63));
+                const float t_r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr0), 63));
+                const float t_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr1), 63));
+                const float t_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr2), 63));
+                float val = fmaf(p1.x, t_sx, p1.y * t_sy);
+                val = lane == 1 ? fmaf(p1.y, t_sx, p1.z * t_sy) : val;
+                val = lane == 2 ? -0.5f * t_sxx : val;
+                val = lane == 3 ? -t_sxy : val;
+                val = lane == 4 ? -0.5f * t_syy : val;
+                val = lane == 5 ? t_op : val;
+                val = lane == 6 ? t_r0 : val;
+                val = lane == 7 ? t_r1 : val;
+                val = lane == 8 ? t_r2 : val;
+                if (lane < 9) unsafeAtomicAdd(a.splat_grad + 9 * (u64)se[k] + lane, val);
             }
         }
-        if (!a.queue) break;
     }
 }
 
@@ -297,9 +337,9 @@ gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* imag
     unsigned grid;
     GS_TRY(grid_for(f, o, a, 3, s, grid));
     switch (o->raster_batch) {
-        case 64: raster_fwd_kernel<64><<<grid, GS_BLOCK, 0, s>>>(a); break;
-        case 128: raster_fwd_kernel<128><<<grid, GS_BLOCK, 0, s>>>(a); break;
-        default: raster_fwd_kernel<256><<<grid, GS_BLOCK, 0, s>>>(a); break;
+        case 64: raster_fwd_kernel<64><<<grid, 64, 0, s>>>(a); break;
+        case 256: raster_fwd_kernel<256><<<grid, 64, 0, s>>>(a); break;
+        default: raster_fwd_kernel<128><<<grid, 64, 0, s>>>(a); break;
     }
     return gs_check_launch("raster_fwd");
 }
@@ -312,9 +352,9 @@ gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float
     unsigned grid;
     GS_TRY(grid_for(f, o, a, 4, s, grid));
     switch (o->raster_batch) {
-        case 64: raster_bwd_kernel<64><<<grid, GS_BLOCK, 0, s>>>(a); break;
-        case 128: raster_bwd_kernel<128><<<grid, GS_BLOCK, 0, s>>>(a); break;
-        default: raster_bwd_kernel<256><<<grid, GS_BLOCK, 0, s>>>(a); break;
+        case 64: raster_bwd_kernel<64><<<grid, 64, 0, s>>>(a); break;
+        case 256: raster_bwd_kernel<256><<<grid, 64, 0, s>>>(a); break;
+        default: raster_bwd_kernel<128><<<grid, 64, 0, s>>>(a); break;
     }
     return gs_check_launch("raster_bwd");
 }

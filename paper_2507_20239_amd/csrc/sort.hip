@@ -5,12 +5,12 @@
 // the grid is a fixed number of partitions and every workgroup derives its
 // chunk from the device length.
 //
-// Radix pass = per-partition digit histogram -> exclusive scan of the
-// digit-major [256][G] count matrix -> stable scatter.  The scatter ranks
-// keys inside a workgroup with a wave-level multi-split: eight ballots give
-// each lane the mask of lanes holding the same digit, the popcount below the
-// lane is its rank within the item, and per-wave running counters in LDS
-// order successive items; a 4-wave exclusive scan orders the waves.
+// Radix sort: 8-bit digits; per pass, per-workgroup digit counts, an
+// exclusive scan of the count matrix and a stable scatter.  Keys are ranked
+// inside a workgroup with a wave-level multi-split: eight ballots
+// give each lane the mask of lanes holding the same digit, the popcount below
+// the lane is its rank within the item, per-wave running counters in LDS
+// order successive items, and a 4-wave exclusive scan orders the waves.
 #include "gs_internal.h"
 
 namespace {
@@ -117,36 +117,61 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, u32*
     }
 }
 
-__global__ void __launch_bounds__(GS_BLOCK) radix_hist_kernel(const u32* keys, const u32* n_dev,
-                                                              u32 n_host, int shift, int bits,
-                                                              u32* hist, int G) {
+// ---- Radix pass: per-workgroup digit counts (digit-major matrix [256][G]),
+// an exclusive scan of that matrix over the whole GPU (which gives every
+// workgroup the start of each of its digit runs), and a stable scatter.
+// Workgroup counts could also be combined by a chained (decoupled look-back)
+// scan or by each workgroup summing the rows before it; both were measured
+// to be latency-bound on this part (device-scope loads cross the XCDs), so
+// the three-launch form is used.  The scatter reorders each 2048-key
+// sub-batch by digit in LDS first, so consecutive lanes write consecutive
+// addresses of a digit run (coalesced) instead of scattering 4-byte stores.
+
+__global__ void __launch_bounds__(GS_BLOCK) sort_count_kernel(const u32* __restrict__ keys,
+                                                              const u32* n_dev, u32 n_host,
+                                                              int shift, int bits, u32* counts) {
     __shared__ u32 h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     u32 beg, end;
-    chunk_of(dev_len(n_dev, n_host), (u32)G, blockIdx.x, beg, end);
+    chunk_of(dev_len(n_dev, n_host), gridDim.x, blockIdx.x, beg, end);
     const u32 mask = (1u << bits) - 1u;
-    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    for (u32 base = beg; base < end; base += GS_BLOCK) {
+        const u32 i = base + threadIdx.x;
+        const bool valid = i < end;
+        const u32 d = valid ? (keys[i] >> shift) & mask : 0u;
+        // one LDS add per group of equal digits in the wave
+        u64 peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const u64 bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        if (valid && popc_below(peers) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
+    }
     __syncthreads();
-    hist[(u64)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+    counts[(u64)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(GS_BLOCK) radix_scatter_kernel(
+__global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
     const u32* __restrict__ kin, const u32* __restrict__ vin, u32* __restrict__ kout,
     u32* __restrict__ vout, const u32* n_dev, u32 n_host, int shift, int bits,
-    const u32* __restrict__ offs, int G) {
+    const u32* __restrict__ offs) {
     __shared__ u32 whist[4][256];
-    __shared__ u32 base[256];
+    __shared__ u32 s_base[256];    // global start of each digit's run for the next sub-batch
+    __shared__ u32 s_local[256];   // start of each digit inside the sub-batch
+    __shared__ u32 s_key[RADIX_SUB], s_val[RADIX_SUB];
+    __shared__ u32 lds4[4];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const u32 n = dev_len(n_dev, n_host);
+    s_base[tid] = offs[(u64)tid * gridDim.x + blockIdx.x];
     u32 beg, end;
-    chunk_of(n, (u32)G, blockIdx.x, beg, end);
-    base[tid] = offs[(u64)tid * G + blockIdx.x];
+    chunk_of(n, gridDim.x, blockIdx.x, beg, end);
     const u32 mask = (1u << bits) - 1u;
     for (u32 sub = beg; sub < end; sub += RADIX_SUB) {
-        u32 k[RADIX_ITEMS], v[RADIX_ITEMS], d[RADIX_ITEMS], r[RADIX_ITEMS];
         for (int j = lane; j < 256; j += 64) whist[w][j] = 0;
         __syncthreads();
+        u32 k[RADIX_ITEMS], v[RADIX_ITEMS], d[RADIX_ITEMS], r[RADIX_ITEMS];
 #pragma unroll
         for (int i = 0; i < RADIX_ITEMS; ++i) {
             const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
@@ -160,46 +185,63 @@ __global__ void __launch_bounds__(GS_BLOCK) radix_scatter_kernel(
                 const u64 bal = __ballot(bit);
                 peers &= bit ? bal : ~bal;
             }
-            const u32 below = popc_below(peers);
+            const u32 lo = popc_below(peers);
             const u32 cnt = (u32)__popcll(peers);
             u32 prior = 0;
             if (valid) prior = whist[w][d[i]];
-            r[i] = prior + below;
+            r[i] = prior + lo;
             // the highest lane of each digit group advances the wave counter
-            if (valid && below == cnt - 1u) whist[w][d[i]] = prior + cnt;
+            if (valid && lo == cnt - 1u) whist[w][d[i]] = prior + cnt;
         }
         __syncthreads();
         const u32 c0 = whist[0][tid], c1 = whist[1][tid], c2 = whist[2][tid], c3 = whist[3][tid];
-        whist[0][tid] = 0;
-        whist[1][tid] = c0;
-        whist[2][tid] = c0 + c1;
-        whist[3][tid] = c0 + c1 + c2;
         const u32 tot = c0 + c1 + c2 + c3;
+        u32 subtotal;
+        const u32 loc = block_exclusive_scan(tot, lds4, subtotal);
+        s_local[tid] = loc;
+        whist[0][tid] = loc;
+        whist[1][tid] = loc + c0;
+        whist[2][tid] = loc + c0 + c1;
+        whist[3][tid] = loc + c0 + c1 + c2;
         __syncthreads();
+        // place the sub-batch in LDS in (digit, original order) order
 #pragma unroll
         for (int i = 0; i < RADIX_ITEMS; ++i) {
             const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
             if (idx < end) {
-                const u32 pos = base[d[i]] + whist[w][d[i]] + r[i];
-                if (pos < n) {
-                    kout[pos] = k[i];
-                    vout[pos] = v[i];
-                }
+                const u32 pos = whist[w][d[i]] + r[i];
+                s_key[pos] = k[i];
+                s_val[pos] = v[i];
             }
         }
         __syncthreads();
-        base[tid] += tot;
+        // write out: position i of the reordered sub-batch goes to its digit run
+        for (u32 i = (u32)tid; i < subtotal; i += GS_BLOCK) {
+            const u32 key = s_key[i];
+            const u32 dd = (key >> shift) & mask;
+            const u32 pos = s_base[dd] + (i - s_local[dd]);
+            if (pos < n) {
+                kout[pos] = key;
+                vout[pos] = s_val[i];
+            }
+        }
         __syncthreads();
+        s_base[tid] += tot;
     }
+}
+
+unsigned sort_blocks(int64_t capacity) {
+    int64_t g = (capacity + 4095) / 4096;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    return (unsigned)g;
 }
 
 }  // namespace
 
-int gs_radix_partitions(int64_t capacity) {
-    int64_t g = (capacity + 4095) / 4096;
-    if (g < 1) g = 1;
-    if (g > 1024) g = 1024;
-    return (int)g;
+uint64_t gs_radix_scratch_bytes(int64_t capacity, int bits) {
+    (void)bits;
+    return 4 * 256 * (uint64_t)sort_blocks(capacity) + 4 * (GS_SCAN_PARTS + 8);
 }
 
 gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s) {
@@ -218,17 +260,21 @@ gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_hos
     return gs_check_launch("scan_exclusive");
 }
 
-gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int bits, int G,
-                        u32* hist, u32* part, int* slot, hipStream_t s) {
+gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
+                        int bits, void* scratch, u32* err, int* slot, hipStream_t s) {
+    (void)err;
+    const unsigned G = sort_blocks(capacity);
+    u32* counts = (u32*)scratch;
+    u32* part = counts + 256 * (uint64_t)G;
     int cur = 0;
     for (int shift = 0; shift < bits; shift += 8) {
         const int b = (bits - shift) < 8 ? (bits - shift) : 8;
-        radix_hist_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], n_dev, n_host, shift, b, hist, G);
-        GS_TRY(gs_check_launch("radix_hist"));
-        GS_TRY(gs_scan_exclusive(hist, hist, nullptr, (u32)(256 * G), nullptr, part, s));
-        radix_scatter_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n_dev,
-                                                    n_host, shift, b, hist, G);
-        GS_TRY(gs_check_launch("radix_scatter"));
+        sort_count_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], n_dev, n_host, shift, b, counts);
+        GS_TRY(gs_check_launch("sort_count"));
+        GS_TRY(gs_scan_exclusive(counts, counts, nullptr, 256 * G, nullptr, part, s));
+        sort_scatter_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n_dev,
+                                                   n_host, shift, b, counts);
+        GS_TRY(gs_check_launch("sort_scatter"));
         cur ^= 1;
     }
     *slot = cur;

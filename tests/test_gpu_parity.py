@@ -148,7 +148,9 @@ def test_backward_matches_oracle(name):
     torch.cuda.synchronize()
     gproj, gabs = oracle.render_backward_image(p, dL.astype(np.float64), sc.bg)
     sg = frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).view(-1, 9).cpu().numpy()
-    assert_close_scaled(sg, gproj, gabs, what="splat gradients")
+    rendered = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy() > 0
+    assert np.all(gabs[~rendered] == 0)
+    assert_close_scaled(sg[rendered], gproj[rendered], gabs[rendered], what="splat gradients")
     racc, rden = np.zeros(sc.n), np.zeros(sc.n)
     gref = oracle.project_backward(sc, cam, p["visible"], gproj, stats=(racc, rden))
     scales = raw_grad_scale(sc, cam, p, gabs)
