@@ -173,25 +173,36 @@ def cpu_baseline(sc, dL_img, seconds):
     p = oracle.project(sc, cam)
     t_proj = time.perf_counter() - t0
     rng = np.random.default_rng(0)
-    # size the pixel samples from a short probe so the leg stays near `seconds`
-    nprobe = 4 * threads
-    probe = np.stack([rng.integers(0, cam.width, nprobe), rng.integers(0, cam.height, nprobe)], 1)
+
+    def timed_sample(run, budget, first):
+        """Run growing batches of random pixels until about `budget` seconds
+        are spent; returns (pixels done, seconds)."""
+        done, spent, batch = 0, 0.0, first
+        while spent < budget:
+            pix = np.stack([rng.integers(0, cam.width, batch),
+                            rng.integers(0, cam.height, batch)], 1)
+            t0 = time.perf_counter()
+            run(pix)
+            spent += time.perf_counter() - t0
+            done += batch
+            per_px = spent / done
+            batch = int(max(1, min(2 * batch, (budget - spent) / per_px)))
+        return done, spent
+
+    # 45% of the leg on the threaded compositing sample, 35% on the serial adjoint sample
+    n_fwd, t_fwd = timed_sample(lambda pix: oracle.render_pixels(p, pix), 0.45 * seconds,
+                                8 * threads)
+    g_img = dL_img.reshape(3, -1)
+
+    last = {}
+
+    def bwd(pix):
+        g = g_img[:, pix[:, 1] * cam.width + pix[:, 0]].T.astype(np.float64)
+        last["gproj"], _ = oracle.render_backward_pixels(p, pix, g)
+
+    n_bwd, t_bwd = timed_sample(bwd, 0.35 * seconds, 4)
     t0 = time.perf_counter()
-    oracle.render_pixels(p, probe)
-    t_probe = (time.perf_counter() - t0) / nprobe * threads     # serial cost per pixel
-    n_fwd = int(max(16, min(65536, 0.4 * seconds * threads / max(t_probe, 1e-6))))
-    n_bwd = int(max(4, min(8192, 0.4 * seconds / max(t_probe * 1.5, 1e-6))))
-    pix = np.stack([rng.integers(0, cam.width, n_fwd), rng.integers(0, cam.height, n_fwd)], 1)
-    t0 = time.perf_counter()
-    oracle.render_pixels(p, pix)
-    t_fwd = time.perf_counter() - t0
-    pb = pix[:n_bwd]
-    g = dL_img.reshape(3, -1)[:, pb[:, 1] * cam.width + pb[:, 0]].T.astype(np.float64)
-    t0 = time.perf_counter()
-    gproj, _ = oracle.render_backward_pixels(p, pb, g)
-    t_bwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.project_backward(sc, cam, p["visible"], gproj,
+    oracle.project_backward(sc, cam, p["visible"], last["gproj"],
                             stats=(np.zeros(sc.n), np.zeros(sc.n)))
     t_pbwd = time.perf_counter() - t0
     est_s = t_proj + t_pbwd + t_fwd / n_fwd * P + t_bwd / n_bwd * P
@@ -201,7 +212,7 @@ def cpu_baseline(sc, dL_img, seconds):
                        "%d threads), per-pixel compositing on %d random pixels (%.2f s, %d threads) "
                        "and its adjoint on %d pixels (%.2f s, 1 thread), scaled to %d pixels"
                        % (sc.n, t_proj, t_pbwd, threads, n_fwd, t_fwd, threads, n_bwd, t_bwd, P)),
-            "sample_seconds": round(t_proj + t_pbwd + t_fwd + t_bwd + t_probe / threads * 8, 2)}
+            "sample_seconds": round(t_proj + t_pbwd + t_fwd + t_bwd, 2)}
 
 
 def main():
@@ -257,6 +268,16 @@ def main():
                 "traffic": counter_traffic(src_hash),
                 "launch_ms": round(bwd_ms, 4), "pairs_walked": int(n_contrib),
                 "pairs_composited": int(n_comp), "source_hash": src_hash}
+
+    if args.profile:
+        # a plain device copy of known size (256 MiB read + 256 MiB written): the
+        # reference that scales rocprofv3's HBM byte counters
+        src = torch.ones(64 << 20, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     result = {
         "metric": "ms per fwd+bwd iter at 1M Gaussians 1600x1040; batched vs plain speedup",
