@@ -457,8 +457,10 @@ void oracle_render_pixels(int64_t n, const double* mean2d, const double* conic,
  * loss gradient of pixel k.  Accumulates into per-Gaussian arrays (n x 9):
  *   [0..1] dL/dmean2d, [2..4] dL/d(conic a, b, c) with b the off-diagonal
  *   entry taken once, [5] dL/dopacity, [6..8] dL/drgb,
- * and g_abs (n x 9) receives the sum of |term| over pixels (the scale that
- * FP32 summation error is measured against).
+ * and g_abs (n x 9) receives, for every element, the sum over pixels of the
+ * magnitudes of the terms that make it up, with dL/dalpha and Q d expanded into
+ * their terms: the scale that the rounding error of an FP32 evaluation in any
+ * order is proportional to.
  * Derivation (Eq. 2 with T_k = prod_{j<k}(1 - alpha_j), w_k = alpha_k T_k):
  *   dC/drgb_k = w_k;
  *   dC/dalpha_k = rgb_k T_k - (sum_{j>k} rgb_j w_j + T_final bg) / (1 - alpha_k);
@@ -497,31 +499,38 @@ void oracle_render_backward_pixels(int64_t n, const double* mean2d, const double
                 const int32_t ih = cand[h].idx;
                 for (int c = 0; c < 3; ++c) behind[c] += rgb[3 * ih + c] * cand[h].alpha * Tk[h];
             }
-            double dal = 0.0;
+            /* dal: dL/dalpha; dal_abs: the sum of the magnitudes of its terms (the
+             * scale of the rounding error of any evaluation of it) */
+            double dal = 0.0, dal_abs = 0.0;
             for (int c = 0; c < 3; ++c) {
-                const double t = rgb[3 * i + c] * Tk[j] - behind[c] / (1.0 - al);
-                dal += g[c] * t;
+                const double front = rgb[3 * i + c] * Tk[j], back = behind[c] / (1.0 - al);
+                dal += g[c] * (front - back);
+                dal_abs += fabs(g[c]) * (fabs(front) + fabs(back));
                 const double dr = g[c] * al * Tk[j];
                 grad[9 * i + 6 + c] += dr;
                 g_abs[9 * i + 6 + c] += fabs(dr);
             }
             if (cand[j].clamped) continue;
             const double G = cand[j].G, o = opacity[i];
-            const double dG = dal * o;
+            const double dG = dal * o, dG_abs = dal_abs * o;
             const double dop = dal * G;
             grad[9 * i + 5] += dop;
-            g_abs[9 * i + 5] += fabs(dop);
+            g_abs[9 * i + 5] += dal_abs * G;
             const double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
             const double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
             const double gm[2] = {dG * G * (a * dx + b * dy), dG * G * (b * dx + c * dy)};
+            const double gm_abs[2] = {dG_abs * G * (fabs(a * dx) + fabs(b * dy)),
+                                      dG_abs * G * (fabs(b * dx) + fabs(c * dy))};
             const double gc[3] = {-0.5 * dG * G * dx * dx, -dG * G * dx * dy, -0.5 * dG * G * dy * dy};
+            const double gc_abs[3] = {0.5 * dG_abs * G * dx * dx, dG_abs * G * fabs(dx * dy),
+                                      0.5 * dG_abs * G * dy * dy};
             for (int u = 0; u < 2; ++u) {
                 grad[9 * i + u] += gm[u];
-                g_abs[9 * i + u] += fabs(gm[u]);
+                g_abs[9 * i + u] += gm_abs[u];
             }
             for (int u = 0; u < 3; ++u) {
                 grad[9 * i + 2 + u] += gc[u];
-                g_abs[9 * i + 2 + u] += fabs(gc[u]);
+                g_abs[9 * i + 2 + u] += gc_abs[u];
             }
         }
     }
