@@ -135,7 +135,10 @@ enum {
     GS_BUF_DEPTH_KEY = 0,     /* u32 [V*n]   FP32 bits of the camera depth of entry v*n+i */
     GS_BUF_TILES_TOUCHED = 1, /* u32 [V*n]   tiles covered by the footprint (0 = not rendered) */
     GS_BUF_RECT = 2,          /* u32 [V*n][2] tile rect: x0 | x1 << 16, y0 | y1 << 16 */
-    GS_BUF_SPLAT = 3,         /* f32 [V*n][12] mean hi (2), mean lo (2), conic a b c, opacity, rgb, pad */
+    GS_BUF_SPLAT = 3,         /* f32 [V*n][12] mean hi (2), mean lo (2), l11 l21 l22, opacity, rgb, pad;
+                                 mean = hi + lo; [l11 0; l21 l22] is the Cholesky factor of
+                                 kappa Q, Q = Sigma'^-1 the conic, kappa = log2(e)/2, so that
+                                 G(d) = 2^-((l11 dx + l21 dy)^2 + (l22 dy)^2) */
     GS_BUF_SORTED_ENTRIES = 4,/* u32 [V*n]   visible entries in (depth key, entry) order */
     GS_BUF_INST_TILE = 5,     /* u32 [cap]   tile id of each sorted instance */
     GS_BUF_INST_ENTRY = 6,    /* u32 [cap]   entry id of each sorted instance */

@@ -29,7 +29,9 @@ __global__ void __launch_bounds__(GS_BLOCK) stats_kernel(const float* __restrict
         if (!vis[v * n + i]) continue;
         const float gx = g[(2 * v) * n + i] * sc.sx[k];
         const float gy = g[(2 * v + 1) * n + i] * sc.sy[k];
-        const float nrm = __fsqrt_rn(fmaf(gx, gx, gy * gy));
+        // sqrtf is correctly rounded under the default HIP flags (the _rn
+        // intrinsic is a bare v_sqrt_f32 on gfx950, up to 1 ulp off)
+        const float nrm = sqrtf(fmaf(gx, gx, gy * gy));
         a = a + nrm;
         d = d + 1.0f;
     }

@@ -166,13 +166,38 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 // Alpha of one splat at a pixel centre, shared by the forward and the
 // adjoint so both evaluate bit-identical values.  p0 = (mean hi x, y, mean lo x, y),
 // p1 = (conic a, b, c, opacity).  Returns o G (before the 0.99 clamp).
-__device__ __forceinline__ float splat_raw_alpha(float4 p0, float4 p1, float pxc, float pyc,
-                                                 float& G, float& dx, float& dy) {
-    dx = (pxc - p0.x) - p0.z;
-    dy = (pyc - p0.y) - p0.w;
-    const float q = fmaf(p1.x * dx, dx, p1.z * dy * dy);      // a dx^2 + c dy^2
-    const float power = fmaf(-0.5f, q, -(p1.y * dx) * dy);    // -(q/2) - b dx dy
-    G = __expf(power);
-    return p1.w * G;
+// A projected splat is three float4: (mean hi x, y, mean lo x, y), (l11, l21,
+// l22, opacity), (r, g, b, pad).  L = [l11 0; l21 l22] is the Cholesky factor
+// of kappa Q, Q the conic (inverse screen-space covariance) and kappa =
+// log2(e)/2, so G = exp(-d^T Q d / 2) = 2^-(u^2 + v^2) with u = l11 dx + l21 dy
+// and v = l22 dy: a sum of squares, free of the cancellation that a dx^2 +
+// 2 b dx dy + c dy^2 suffers for elongated splats, and two FMAs per pixel.
+#define GS_KAPPA_D 0.72134752044448170
+#define GS_KAPPA ((float)GS_KAPPA_D)
+
+// One lane's 2x2 pixel quad relative to a splat: column offsets dx0, dx1 =
+// dx0 + 1, row offsets dy0, dy1 = dy0 + 1, and the per-row terms l21 dy and
+// (l22 dy)^2.  Pixel i of the quad is column i & 1, row i >> 1.
+struct Quad {
+    float dx[2], dy[2], t[2], vv[2];
+};
+
+__device__ __forceinline__ void quad_setup(float4 p0, float4 p1, float pxc0, float pyc0, Quad& q) {
+    q.dx[0] = (pxc0 - p0.x) - p0.z;
+    q.dx[1] = q.dx[0] + 1.f;
+    q.dy[0] = (pyc0 - p0.y) - p0.w;
+    q.dy[1] = q.dy[0] + 1.f;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        q.t[r] = p1.y * q.dy[r];
+        const float v = p1.z * q.dy[r];
+        q.vv[r] = v * v;
+    }
+}
+
+// G of pixel i of the quad
+__device__ __forceinline__ float quad_G(float l11, const Quad& q, int i) {
+    const float u = fmaf(l11, q.dx[i & 1], q.t[i >> 1]);
+    return __builtin_amdgcn_exp2f(-fmaf(u, u, q.vv[i >> 1]));
 }
 #endif

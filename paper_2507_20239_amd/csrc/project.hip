@@ -138,6 +138,7 @@ struct Activated {
     float o;           // opacity
     float R[9];        // rotation, row-major
     float Sig[6];      // Sigma: 00 01 02 11 12 22
+    double SigD[6];    // the same in FP64 (input of the screen-space covariance)
 };
 
 // Position, scales and opacity: all the culling test needs.
@@ -152,25 +153,36 @@ __device__ __forceinline__ void activate_light(const ProjArgs& a, int64_t i, flo
     g.o = 1.0f / (1.0f + expf(-a.logits[i]));
 }
 
-// Rotation and covariance (Eq. 1: Sigma = R S S^T R^T).
+// Rotation and covariance (Eq. 1: Sigma = R S S^T R^T).  Evaluated in FP64:
+// an elongated Gaussian seen edge-on has a screen-space covariance whose
+// determinant cancels to a few 1e-4 of its terms, so FP32 products here would
+// leave the conic with relative errors far above FP32 rounding.
 __device__ __forceinline__ void activate_rot(const ProjArgs& a, int64_t i, Activated& g) {
     const int64_t n = a.n;
-    float q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
-    g.qnorm = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    const float inv = 1.0f / g.qnorm;
-    const float w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
-    g.q[0] = w; g.q[1] = x; g.q[2] = y; g.q[3] = z;
-    g.R[0] = 1.f - 2.f * (y * y + z * z); g.R[1] = 2.f * (x * y - w * z); g.R[2] = 2.f * (x * z + w * y);
-    g.R[3] = 2.f * (x * y + w * z); g.R[4] = 1.f - 2.f * (x * x + z * z); g.R[5] = 2.f * (y * z - w * x);
-    g.R[6] = 2.f * (x * z - w * y); g.R[7] = 2.f * (y * z + w * x); g.R[8] = 1.f - 2.f * (x * x + y * y);
-    const float s0 = g.s[0] * g.s[0], s1 = g.s[1] * g.s[1], s2 = g.s[2] * g.s[2];
-    const float* R = g.R;
-    g.Sig[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
-    g.Sig[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
-    g.Sig[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
-    g.Sig[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
-    g.Sig[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
-    g.Sig[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+    const double q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i],
+                 q3 = a.quats[3 * n + i];
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    g.qnorm = (float)qn;
+    const double inv = 1.0 / qn;
+    const double w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
+    g.q[0] = (float)w; g.q[1] = (float)x; g.q[2] = (float)y; g.q[3] = (float)z;
+    double R[9];
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g.R[k] = (float)R[k];
+    const double s0 = (double)g.s[0] * g.s[0], s1 = (double)g.s[1] * g.s[1],
+                 s2 = (double)g.s[2] * g.s[2];
+    double* S = g.SigD;
+    S[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
+    S[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
+    S[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
+    S[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
+    S[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
+    S[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g.Sig[k] = (float)S[k];
 }
 
 // Camera-space quantities of one Gaussian in one view.
@@ -183,6 +195,7 @@ struct ViewProj {
     float TS[6];           // T Sigma
     float cov[3];          // Sigma' 00 01 11 (with dilation)
     float conic[3];
+    float chol[3];         // Cholesky factor of kappa * conic: l11, l21, l22
 };
 
 __device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_info& vi,
@@ -205,32 +218,47 @@ __device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_i
     yr = yr < -limy ? -limy : (yr > limy ? limy : yr);
     p.xt = (float)xr;
     p.yt = (float)yr;
-    const float iz = 1.0f / p.t[2];
-    const float J00 = c.fx * iz, J02 = -c.fx * p.xt * iz;
-    const float J11 = c.fy * iz, J12 = -c.fy * p.yt * iz;
-    // T = J W
+    // J W, T Sigma, Sigma' and its inverse in FP64 (see activate_rot), stored as FP32
+    const double iz = 1.0 / p.tz;
+    const double J00 = c.fx * iz, J02 = -(double)c.fx * xr * iz;
+    const double J11 = c.fy * iz, J12 = -(double)c.fy * yr * iz;
+    double T[6];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        p.T[b] = J00 * c.R[b] + J02 * c.R[6 + b];
-        p.T[3 + b] = J11 * c.R[3 + b] + J12 * c.R[6 + b];
+        T[b] = J00 * c.R[b] + J02 * c.R[6 + b];
+        T[3 + b] = J11 * c.R[3 + b] + J12 * c.R[6 + b];
     }
-    const float* S = g.Sig;
-    // T Sigma (Sigma symmetric: rows 00 01 02 / 01 11 12 / 02 12 22)
+    const double* S = g.SigD;
+    double TS[6];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-        const float* Tr = p.T + 3 * u;
-        p.TS[3 * u + 0] = Tr[0] * S[0] + Tr[1] * S[1] + Tr[2] * S[2];
-        p.TS[3 * u + 1] = Tr[0] * S[1] + Tr[1] * S[3] + Tr[2] * S[4];
-        p.TS[3 * u + 2] = Tr[0] * S[2] + Tr[1] * S[4] + Tr[2] * S[5];
+        const double* Tr = T + 3 * u;
+        TS[3 * u + 0] = Tr[0] * S[0] + Tr[1] * S[1] + Tr[2] * S[2];
+        TS[3 * u + 1] = Tr[0] * S[1] + Tr[1] * S[3] + Tr[2] * S[4];
+        TS[3 * u + 2] = Tr[0] * S[2] + Tr[1] * S[4] + Tr[2] * S[5];
     }
-    p.cov[0] = p.TS[0] * p.T[0] + p.TS[1] * p.T[1] + p.TS[2] * p.T[2] + GS_DILATION;
-    p.cov[1] = p.TS[0] * p.T[3] + p.TS[1] * p.T[4] + p.TS[2] * p.T[5];
-    p.cov[2] = p.TS[3] * p.T[3] + p.TS[4] * p.T[4] + p.TS[5] * p.T[5] + GS_DILATION;
-    const float det = p.cov[0] * p.cov[2] - p.cov[1] * p.cov[1];
-    const float idet = 1.0f / det;
-    p.conic[0] = p.cov[2] * idet;
-    p.conic[1] = -p.cov[1] * idet;
-    p.conic[2] = p.cov[0] * idet;
+    const double c0 = TS[0] * T[0] + TS[1] * T[1] + TS[2] * T[2] + (double)GS_DILATION;
+    const double c1 = TS[0] * T[3] + TS[1] * T[4] + TS[2] * T[5];
+    const double c2 = TS[3] * T[3] + TS[4] * T[4] + TS[5] * T[5] + (double)GS_DILATION;
+    const double idet = 1.0 / (c0 * c2 - c1 * c1);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        p.T[k] = (float)T[k];
+        p.TS[k] = (float)TS[k];
+    }
+    p.cov[0] = (float)c0;
+    p.cov[1] = (float)c1;
+    p.cov[2] = (float)c2;
+    p.conic[0] = (float)(c2 * idet);
+    p.conic[1] = (float)(-c1 * idet);
+    p.conic[2] = (float)(c0 * idet);
+    // kappa Q = L L^T: l11 = sqrt(kappa a), l21 = kappa b / l11, l22^2 = kappa det(Q) / a
+    // = kappa / Sigma'_yy
+    const double kappa = GS_KAPPA_D;
+    const double l11 = sqrt(kappa * c2 * idet);
+    p.chol[0] = (float)l11;
+    p.chol[1] = (float)(-kappa * c1 * idet / l11);
+    p.chol[2] = (float)sqrt(kappa / c2);
     return true;
 }
 
@@ -298,7 +326,7 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
                 const float uh = (float)u, wh = (float)w;
                 const float ul = (float)(u - (double)uh), wl = (float)(w - (double)wh);
                 a.splat[3 * e + 0] = make_float4(uh, wh, ul, wl);
-                a.splat[3 * e + 1] = make_float4(p.conic[0], p.conic[1], p.conic[2], g.o);
+                a.splat[3 * e + 1] = make_float4(p.chol[0], p.chol[1], p.chol[2], g.o);
                 a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
             }
         }

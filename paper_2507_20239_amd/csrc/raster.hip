@@ -122,28 +122,26 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
             load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2, nullptr);
             __syncthreads();
             for (u32 k = 0; k < cnt; ++k) {
-                const float4 p0 = sp0[k], p1 = sp1[k];
+                const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
+                const u32 idx = b0 - tc.rg.x + k + 1;
+                Quad q;
+                quad_setup(p0, p1, pxc[0], pyc[0], q);
                 bool live = false;
 #pragma unroll
                 for (int i = 0; i < PIX; ++i) {
-                    float G, dx, dy;
-                    const float raw = splat_raw_alpha(p0, p1, pxc[i], pyc[i], G, dx, dy);
-                    const float alpha = fminf(raw, GS_ALPHA_MAX);
+                    const float alpha = fminf(p1.w * quad_G(p1.x, q, i), GS_ALPHA_MAX);
                     bool take = !done[i] && alpha >= GS_ALPHA_MIN;
                     const float Tn = T[i] * (1.f - alpha);
                     const bool stop = take && Tn < GS_T_MIN;
                     done[i] = done[i] || stop;
                     take = take && !stop;
-                    if (take) {
-                        const float4 c = sp2[k];
-                        const float wgt = alpha * T[i];
-                        C0[i] = fmaf(c.x, wgt, C0[i]);
-                        C1[i] = fmaf(c.y, wgt, C1[i]);
-                        C2[i] = fmaf(c.z, wgt, C2[i]);
-                        T[i] = Tn;
-                        last[i] = b0 - tc.rg.x + k + 1;
-                        ++ncomp[i];
-                    }
+                    const float wgt = take ? alpha * T[i] : 0.f;
+                    C0[i] = fmaf(c.x, wgt, C0[i]);
+                    C1[i] = fmaf(c.y, wgt, C1[i]);
+                    C2[i] = fmaf(c.z, wgt, C2[i]);
+                    T[i] = take ? Tn : T[i];
+                    last[i] = take ? idx : last[i];
+                    ncomp[i] += take ? 1u : 0u;
                     live = live || !done[i];
                 }
                 if (__ballot(live) == 0) break;
@@ -176,7 +174,7 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
         const u32 t = a.order ? a.order[item] : item;
         const TileCoords tc = tile_coords(a, t);
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
-        float pxc[PIX], pyc[PIX], T[PIX], g0[PIX], g1[PIX], g2[PIX], S0[PIX], S1[PIX], S2[PIX];
+        float pxc[PIX], pyc[PIX], T[PIX], g0[PIX], g1[PIX], g2[PIX], sd[PIX];
         u32 last[PIX];
         u32 mlast = 0;
 #pragma unroll
@@ -195,10 +193,8 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                 g1[i] = d[hw];
                 g2[i] = d[2 * hw];
             }
-            // colour behind the current splat, background included
-            S0[i] = T[i] * a.bg0;
-            S1[i] = T[i] * a.bg1;
-            S2[i] = T[i] * a.bg2;
+            // dL/dC . (colour behind the current splat), background included
+            sd[i] = T[i] * fmaf(a.bg0, g0[i], fmaf(a.bg1, g1[i], a.bg2 * g2[i]));
             mlast = max(mlast, last[i]);
         }
 #pragma unroll
@@ -213,46 +209,51 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
             for (int k = (int)cnt - 1; k >= 0; --k) {
                 const u32 rel = (u32)bi * BATCH + (u32)k;
                 const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
-                // per-lane moments of w = dL/dG * G over the lane's pixels:
-                // sum w dx, sum w dy, sum w dx^2, sum w dx dy, sum w dy^2; the
-                // conic is applied once per splat after the wave reduction
-                float sx = 0.f, sy = 0.f, sxx = 0.f, sxy = 0.f, syy = 0.f, gop = 0.f;
+                Quad q;
+                quad_setup(p0, p1, pxc[0], pyc[0], q);
+                // per pixel: go = dL/dalpha * G (zero where the splat did not
+                // contribute or alpha was clamped); per lane: colour gradient sums
+                float go[PIX];
                 float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
                 bool contrib = false;
 #pragma unroll
                 for (int i = 0; i < PIX; ++i) {
-                    if (rel >= last[i]) continue;
-                    float G, dx, dy;
-                    const float raw = splat_raw_alpha(p0, p1, pxc[i], pyc[i], G, dx, dy);
+                    const float G = quad_G(p1.x, q, i);
+                    const float raw = p1.w * G;
                     const float alpha = fminf(raw, GS_ALPHA_MAX);
-                    if (alpha < GS_ALPHA_MIN) continue;
-                    contrib = true;
-                    const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+                    const bool use = rel < last[i] && alpha >= GS_ALPHA_MIN;
+                    contrib = contrib || use;
+                    // T_i = T_{i+1} / (1 - alpha_i).  The hardware reciprocal is
+                    // within 1 ulp but biased, and the bias compounds over a long
+                    // back-to-front walk; one Newton step leaves an unbiased error
+                    // of about half an ulp.
+                    const float om = 1.f - alpha;
+                    float inv = __builtin_amdgcn_rcpf(om);
+                    inv = fmaf(fmaf(-om, inv, 1.f), inv, inv);
                     const float Ti = T[i] * inv;
-                    const float wgt = alpha * Ti;
+                    const float wgt = use ? alpha * Ti : 0.f;
+                    const float cd = fmaf(c.x, g0[i], fmaf(c.y, g1[i], c.z * g2[i]));
+                    // dL/dalpha = (c . g) T_i - (g . colour behind) / (1 - alpha)
+                    const float dalpha = fmaf(cd, Ti, -sd[i] * inv);
+                    sd[i] = fmaf(cd, wgt, sd[i]);
+                    T[i] = use ? Ti : T[i];
                     gr0 = fmaf(wgt, g0[i], gr0);
                     gr1 = fmaf(wgt, g1[i], gr1);
                     gr2 = fmaf(wgt, g2[i], gr2);
-                    const float cd = fmaf(c.x, g0[i], fmaf(c.y, g1[i], c.z * g2[i]));
-                    const float sd = fmaf(S0[i], g0[i], fmaf(S1[i], g1[i], S2[i] * g2[i]));
-                    const float dalpha = cd * Ti - sd * inv;
-                    S0[i] = fmaf(c.x, wgt, S0[i]);
-                    S1[i] = fmaf(c.y, wgt, S1[i]);
-                    S2[i] = fmaf(c.z, wgt, S2[i]);
-                    T[i] = Ti;
-                    if (raw <= GS_ALPHA_MAX) {
-                        const float go = dalpha * G;
-                        const float gG = go * p1.w;   // dL/dG * G
-                        const float wx = gG * dx, wy = gG * dy;
-                        gop += go;
-                        sx += wx;
-                        sy += wy;
-                        sxx = fmaf(wx, dx, sxx);
-                        sxy = fmaf(wx, dy, sxy);
-                        syy = fmaf(wy, dy, syy);
-                    }
+                    go[i] = (use && raw <= GS_ALPHA_MAX) ? dalpha * G : 0.f;
                 }
                 if (__ballot(contrib) == 0) continue;
+                // lane moments of go over the quad: sum go (1, dx, dy, dx^2, dx dy, dy^2),
+                // factored by column (pixels 0, 2 | 1, 3) and row (0, 1 | 2, 3)
+                const float A0 = go[0] + go[2], A1 = go[1] + go[3];
+                const float B0 = go[0] + go[1], B1 = go[2] + go[3];
+                float gop = A0 + A1;
+                float sx = fmaf(q.dx[0], A0, q.dx[1] * A1);
+                float sy = fmaf(q.dy[0], B0, q.dy[1] * B1);
+                float sxx = fmaf(q.dx[0] * q.dx[0], A0, (q.dx[1] * q.dx[1]) * A1);
+                float syy = fmaf(q.dy[0] * q.dy[0], B0, (q.dy[1] * q.dy[1]) * B1);
+                float sxy = fmaf(q.dx[0], fmaf(go[0], q.dy[0], go[2] * q.dy[1]),
+                                 q.dx[1] * fmaf(go[1], q.dy[0], go[3] * q.dy[1]));
                 sx = wave_sum_lane63(sx);
                 sy = wave_sum_lane63(sy);
                 sxx = wave_sum_lane63(sxx);
@@ -266,7 +267,9 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                 // 0..8 add one each: a single 9-lane atomic instruction, which
                 // the memory system coalesces into one request per cache line
                 // (nine single-lane atomics cost nine requests).
-                // dG/dmean = G Q d, dG/d(a, b, c) = -G (dx^2/2, dx dy, dy^2/2)
+                // With w = dL/dalpha o G:  dL/dmean = sum w Q d,
+                // dL/d(a, b, c) = -sum w (dx^2/2, dx dy, dy^2/2), dL/do = sum dL/dalpha G;
+                // Q = L L^T / kappa from the stored Cholesky factor.
                 const float t_sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), 63));
                 const float t_sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), 63));
                 const float t_sxx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sxx), 63));
@@ -276,11 +279,13 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                 const float t_r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr0), 63));
                 const float t_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr1), 63));
                 const float t_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr2), 63));
-                float val = fmaf(p1.x, t_sx, p1.y * t_sy);
-                val = lane == 1 ? fmaf(p1.y, t_sx, p1.z * t_sy) : val;
-                val = lane == 2 ? -0.5f * t_sxx : val;
-                val = lane == 3 ? -t_sxy : val;
-                val = lane == 4 ? -0.5f * t_syy : val;
+                const float ok = p1.w * (1.f / GS_KAPPA);
+                const float qa = p1.x * p1.x, qb = p1.x * p1.y, qc = fmaf(p1.y, p1.y, p1.z * p1.z);
+                float val = ok * fmaf(qa, t_sx, qb * t_sy);
+                val = lane == 1 ? ok * fmaf(qb, t_sx, qc * t_sy) : val;
+                val = lane == 2 ? -0.5f * p1.w * t_sxx : val;
+                val = lane == 3 ? -p1.w * t_sxy : val;
+                val = lane == 4 ? -0.5f * p1.w * t_syy : val;
                 val = lane == 5 ? t_op : val;
                 val = lane == 6 ? t_r0 : val;
                 val = lane == 7 ? t_r1 : val;

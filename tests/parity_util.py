@@ -1,5 +1,7 @@
 """Helpers shared by the GPU parity tests: run the HIP path through the C ABI
 and the FP64 oracle on the same seeded inputs, and compare."""
+import math
+
 import numpy as np
 import torch
 
@@ -38,6 +40,25 @@ def splat_view(frame):
     return frame.buffer(gsmi.BUF_SPLAT, torch.float32).view(-1, 12).cpu().numpy()
 
 
+KAPPA = math.log2(math.e) / 2
+
+
+def oracle_chol(conic):
+    """Cholesky factor (l11, l21, l22) of kappa * conic, the form the splat
+    record stores (kappa = log2(e)/2), from the oracle's FP64 conic."""
+    a, b, c = np.asarray(conic, np.float64).T
+    l11 = np.sqrt(KAPPA * a)
+    return np.stack([l11, KAPPA * b / l11, np.sqrt(KAPPA * (c - b * b / a))], 1)
+
+
+def check_chol(got, conic, rtol=1e-5, what="conic factor"):
+    """The stored factor against the oracle's; l21 is measured against
+    sqrt(l21^2 + l22^2) = sqrt(kappa c), the scale its rounding error has."""
+    ref = oracle_chol(conic)
+    scale = np.stack([ref[:, 0], np.hypot(ref[:, 1], ref[:, 2]), ref[:, 2]], 1)
+    assert_close_scaled(got, ref, scale, rtol=rtol, what=what)
+
+
 def gpu_mean2d(sp):
     return sp[:, 0:2].astype(np.float64) + sp[:, 2:4].astype(np.float64)
 
@@ -72,3 +93,33 @@ def assert_close_scaled(got, ref, scale, rtol=RTOL, what=""):
     nrm = np.linalg.norm(ref)
     if nrm > 0:
         assert np.linalg.norm(got - ref) <= rtol * max(nrm, np.linalg.norm(scale)), what
+
+
+def _norm_ranges(r):
+    """Ranges with empty tiles written as [0, 0] (the GPU leaves them zero)."""
+    r = np.asarray(r, np.int64).copy()
+    r[r[:, 0] == r[:, 1]] = 0
+    return r
+
+
+def _check_ranges_partition(gr, gt):
+    """Ranges are the runs of equal tile ids of the sorted instance list."""
+    n = gt.size
+    starts = np.flatnonzero(np.r_[True, gt[1:] != gt[:-1]]) if n else np.zeros(0, np.int64)
+    ends = np.r_[starts[1:], n] if n else starts
+    want = np.zeros_like(gr, dtype=np.int64)
+    want[gt[starts], 0] = starts
+    want[gt[starts], 1] = ends
+    np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(want))
+
+
+def _compare_lists(p, gt, ge, tiles, gids, entry_base=0):
+    """Bit-exact (tile, Gaussian) order, leaving out the Gaussians whose footprint
+    rectangle lies within 1e-3 px of a tile-edge decision (reported by the oracle)."""
+    flagged = np.flatnonzero(p["flags"] & 1)
+    assert flagged.size <= max(2, p["n"] // 500)
+    kg = ~np.isin(ge - entry_base, flagged)
+    ko = ~np.isin(gids, flagged)
+    np.testing.assert_array_equal(gt[kg], tiles[ko])
+    np.testing.assert_array_equal(ge[kg] - entry_base, gids[ko])
+    return flagged.size

@@ -16,7 +16,8 @@ import torch
 
 import oracle
 from paper_2507_20239_amd import gsmi, synth
-from parity_util import (MARGIN, RTOL, assert_close_scaled, dev, gpu_forward, gpu_mean2d,
+from parity_util import (MARGIN, RTOL, _check_ranges_partition, _compare_lists, _norm_ranges,
+                         assert_close_scaled, check_chol, dev, gpu_forward, gpu_mean2d,
                          params_of, raw_grad_scale, splat_view)
 
 pytestmark = pytest.mark.gpu
@@ -31,13 +32,6 @@ def _scenes():
 
 
 SCENES = _scenes()
-
-
-def _norm_ranges(r):
-    """Ranges with empty tiles written as [0, 0] (the GPU leaves them zero)."""
-    r = np.asarray(r, np.int64).copy()
-    r[r[:, 0] == r[:, 1]] = 0
-    return r
 
 
 @pytest.mark.parametrize("name", list(SCENES))
@@ -65,33 +59,9 @@ def test_project_matches_oracle(name):
     # FP32 values of visible splats
     m = vis & (tt > 0)
     np.testing.assert_allclose(gpu_mean2d(sp)[m], p["mean2d"][m], rtol=1e-7, atol=1e-5)
-    assert_close_scaled(sp[m, 4:7], p["conic"][m], np.abs(p["conic"][m]).max(1, keepdims=True),
-                        what="conic")
+    check_chol(sp[m, 4:7], p["conic"][m])
     np.testing.assert_allclose(sp[m, 7], p["opacity"][m], rtol=1e-6)
     np.testing.assert_allclose(sp[m, 8:11], p["rgb"][m], rtol=1e-5, atol=1e-6)
-
-
-def _check_ranges_partition(gr, gt):
-    """Ranges are the runs of equal tile ids of the sorted instance list."""
-    n = gt.size
-    starts = np.flatnonzero(np.r_[True, gt[1:] != gt[:-1]]) if n else np.zeros(0, np.int64)
-    ends = np.r_[starts[1:], n] if n else starts
-    want = np.zeros_like(gr, dtype=np.int64)
-    want[gt[starts], 0] = starts
-    want[gt[starts], 1] = ends
-    np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(want))
-
-
-def _compare_lists(p, gt, ge, tiles, gids, entry_base=0):
-    """Bit-exact (tile, Gaussian) order, leaving out the Gaussians whose footprint
-    rectangle lies within 1e-3 px of a tile-edge decision (reported by the oracle)."""
-    flagged = np.flatnonzero(p["flags"] & 1)
-    assert flagged.size <= max(2, p["n"] // 500)
-    kg = ~np.isin(ge - entry_base, flagged)
-    ko = ~np.isin(gids, flagged)
-    np.testing.assert_array_equal(gt[kg], tiles[ko])
-    np.testing.assert_array_equal(ge[kg] - entry_base, gids[ko])
-    return flagged.size
 
 
 @pytest.mark.parametrize("name", list(SCENES))
