@@ -1,0 +1,107 @@
+"""torch.autograd wrapper of the rasterizer (projection + binning +
+compositing forward, compositing adjoint + projection adjoint backward).
+
+The forward keeps no per-(pixel, splat) state: what the backward needs is the
+frame's projected splats, sorted tile lists, tile ranges and per-pixel final
+transmittance and walk length, all inside the frame workspace; the adjoint
+kernel recomputes every alpha and transmittance from them (back-to-front replay).
+The densification statistic (mean over views of the view-space position
+gradient norm, Preliminary, last paragraph of the paper) accumulates into the
+rasterizer's `accum` / `denom` as a side effect of the backward.
+
+Every step of the computation runs in libgsmi.so; this module only moves
+pointers.  A frame holds the state of one forward at a time: calling the
+rasterizer again before the backward of an earlier call invalidates that
+backward, which then raises instead of returning wrong gradients.
+"""
+import torch
+
+from . import gsmi
+
+
+class GaussianRasterizer:
+    """Renders N Gaussians into a fixed list of views.
+
+    cameras: list of objects with R (3x3), t (3), fx, fy, cx, cy, width, height
+    (see synth.Camera); their sizes fix the frame.  The instance capacity
+    grows (and the step re-runs) when a render overflows it.
+    """
+
+    def __init__(self, n, cameras, sh_degree, device="cuda", bg=(0.0, 0.0, 0.0),
+                 raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2):
+        self.n = int(n)
+        self.sh_degree = int(sh_degree)
+        self.device = torch.device(device)
+        self.opts = gsmi.raster_opts(bg=bg, near_plane=near_plane, raster_batch=raster_batch,
+                                     persistent_blocks=persistent_blocks)
+        self.set_cameras(cameras)
+        sizes = [(c.width, c.height) for c in cameras]
+        if capacity is None:
+            tiles = sum(((w + 15) // 16) * ((h + 15) // 16) for w, h in sizes)
+            capacity = max(1 << 20, 64 * tiles)
+        self.frame = gsmi.Frame(self.n, sizes, capacity, self.device)
+        self.accum = torch.zeros(self.n, device=self.device)
+        self.denom = torch.zeros(self.n, device=self.device)
+        self.generation = 0
+
+    def set_cameras(self, cameras):
+        """New poses / intrinsics for views of the same sizes."""
+        if hasattr(self, "frame"):
+            sizes = [(c.width, c.height) for c in cameras]
+            if sizes != self.frame.sizes:
+                raise ValueError("view sizes differ from the frame's; build a new rasterizer")
+        self.cameras = list(cameras)
+        self.cams_dev = gsmi.cameras_to_device(self.cameras, self.device)
+
+    def reset_stats(self):
+        self.accum.zero_()
+        self.denom.zero_()
+
+    def _grow(self, needed):
+        cap = self.frame.cap
+        while cap < needed:
+            cap *= 2
+        self.frame = gsmi.Frame(self.n, self.frame.sizes, cap, self.device)
+
+    def __call__(self, means, log_scales, quats, opacity_logits, sh):
+        """Images of every view, as a list of [3, H, W] tensors (differentiable
+        w.r.t. all five parameter tensors)."""
+        flat = _Rasterize.apply(means, log_scales, quats, opacity_logits, sh, self)
+        return self.frame.split_images(flat)
+
+
+class _Rasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, r):
+        params = {"means": means.detach().contiguous(), "log_scales": log_scales.detach().contiguous(),
+                  "quats": quats.detach().contiguous(),
+                  "opacity_logits": opacity_logits.detach().contiguous(),
+                  "sh": sh.detach().contiguous()}
+        for k, t in params.items():
+            if t.dtype != torch.float32 or t.device != r.device:
+                raise TypeError("%s must be float32 on %s" % (k, r.device))
+        while True:
+            r.frame.project(params, r.sh_degree, r.cams_dev, r.opts)
+            images = r.frame.render(r.opts)
+            nv, ni, ovf = r.frame.status(raise_on_overflow=False)
+            if not ovf:
+                break
+            r._grow(ni)
+        r.generation += 1
+        ctx.r = r
+        ctx.generation = r.generation
+        ctx.params = params
+        return images
+
+    @staticmethod
+    def backward(ctx, dL_dimages):
+        r = ctx.r
+        if r.generation != ctx.generation:
+            raise RuntimeError("the rasterizer rendered again before this backward; its frame no "
+                               "longer holds this forward's state")
+        r.frame.render_backward(r.opts, dL_dimages.contiguous())
+        grads = gsmi.empty_grads(ctx.params)
+        r.frame.project_backward(ctx.params, r.sh_degree, r.cams_dev, r.opts, grads, r.accum,
+                                 r.denom)
+        return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"],
+                grads["sh"], None)

@@ -1,0 +1,343 @@
+"""The torch.autograd path (GaussianRasterizer): gradients against the
+oracle's analytic adjoint on small multi-view scenes, against central finite
+differences of the FP64 oracle on a 64-Gaussian slice of the 6,000,000-Gaussian
+procedural scene (4 views of 1920x1080), the densification statistic as a side
+effect of the backward, instance-capacity growth, and the guard against a
+backward whose frame was overwritten."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2507_20239_amd import gsmi, synth
+from paper_2507_20239_amd.autograd import GaussianRasterizer
+from parity_util import MARGIN, assert_close_scaled, dev, raw_grad_scale
+
+pytestmark = pytest.mark.gpu
+
+
+def _leaf_params(sc):
+    return {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(dev()).requires_grad_()
+            for k in gsmi.PARAM_NAMES}
+
+
+def _call(r, P):
+    return r(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"])
+
+
+def _subscene(sc, idx):
+    idx = np.sort(np.asarray(idx))
+    return synth.Scene(sc.means[:, idx].copy(), sc.log_scales[:, idx].copy(),
+                       sc.quats[:, idx].copy(), sc.opacity_logits[idx].copy(),
+                       sc.sh[:, :, idx].copy(), sc.sh_degree, [], [], sc.bg), idx
+
+
+def test_autograd_gradients_match_oracle_adjoint():
+    sc = synth.random_scene(51, 800, 96, 80, sh_degree=3, n_views=2, log_scale=(-2.5, 0.5))
+    cams = [sc.cameras[0], sc.cameras[1].scaled(2)]
+    r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev())
+    P = _leaf_params(sc)
+    imgs = _call(r, P)
+    rng = np.random.default_rng(3)
+    Ws, projs = [], []
+    for cam in cams:
+        p = oracle.project(sc, cam)
+        _, _, _, margin = oracle.render_image(p)
+        w = rng.standard_normal((3, cam.height, cam.width)) * 1e-2
+        w[:, margin <= MARGIN] = 0.0
+        Ws.append(w.astype(np.float32))
+        projs.append(p)
+    loss = sum((img * torch.from_numpy(w).to(dev())).sum() for img, w in zip(imgs, Ws))
+    loss.backward()
+    want = {k: 0.0 for k in gsmi.PARAM_NAMES}
+    scale = {k: 0.0 for k in gsmi.PARAM_NAMES}
+    den = np.zeros(sc.n)
+    for cam, p, w in zip(cams, projs, Ws):
+        gproj, gabs = oracle.render_backward_image(p, w.astype(np.float64))
+        acc, dn = np.zeros(sc.n), np.zeros(sc.n)
+        g = oracle.project_backward(sc, cam, p["visible"], gproj, stats=(acc, dn))
+        s = raw_grad_scale(sc, cam, p, gabs)
+        for k in gsmi.PARAM_NAMES:
+            want[k] = want[k] + g[k]
+            scale[k] = scale[k] + s[k]
+        den += dn
+    for k in gsmi.PARAM_NAMES:
+        assert_close_scaled(P[k].grad.cpu().numpy(), want[k], scale[k], what=k)
+    # the statistic's count: views in which each Gaussian was rendered
+    np.testing.assert_array_equal(r.denom.cpu().numpy(), den)
+
+
+def test_capacity_grows_and_images_do_not_change():
+    sc = synth.random_scene(52, 1500, 128, 96, sh_degree=1, log_scale=(-2.0, 0.5))
+    P = _leaf_params(sc)
+    small = GaussianRasterizer(sc.n, sc.cameras, sc.sh_degree, device=dev(), capacity=256)
+    big = GaussianRasterizer(sc.n, sc.cameras, sc.sh_degree, device=dev(), capacity=1 << 20)
+    a = _call(small, P)[0]
+    b = _call(big, P)[0]
+    assert small.frame.cap > 256
+    assert torch.equal(a, b)
+
+
+def test_stale_backward_raises():
+    sc = synth.random_scene(53, 300, 64, 48, sh_degree=0)
+    P = _leaf_params(sc)
+    r = GaussianRasterizer(sc.n, sc.cameras, sc.sh_degree, device=dev())
+    first = _call(r, P)[0].sum()
+    _call(r, P)
+    with pytest.raises(RuntimeError, match="rendered again"):
+        first.backward()
+
+
+# ---------------------------------------------------------------------------
+# 6,000,000 Gaussians on spheres and planes, 4 views of 1920x1080
+# ---------------------------------------------------------------------------
+def _rect_pixels(rect, W, H):
+    x0, x1, y0, y1 = (int(v) for v in rect)
+    ys, xs = np.mgrid[y0 * 16:min((y1 + 1) * 16, H), x0 * 16:min((x1 + 1) * 16, W)]
+    return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+
+
+def _overlapping(p, tiles, tiles_x, tiles_y, among=None):
+    """Gaussians (among `among`, default all visible) whose footprint rectangle
+    meets any tile of `tiles` ([m, 2] of (tx, ty)): a summed-area table of the
+    tile mask, evaluated per rectangle."""
+    m = np.zeros((tiles_y + 1, tiles_x + 1), np.int64)
+    m[tiles[:, 1] + 1, tiles[:, 0] + 1] = 1
+    sat = m.cumsum(0).cumsum(1)
+    vis = np.flatnonzero(p["visible"] > 0) if among is None else among
+    x0, x1, y0, y1 = (p["rect"][vis, k] for k in range(4))
+    cnt = sat[y1 + 1, x1 + 1] - sat[y0, x1 + 1] - sat[y1 + 1, x0] + sat[y0, x0]
+    return vis[cnt > 0]
+
+
+def _support_tiles(items):
+    return sorted({tuple(t) for _, rect, _ in items for t in _tiles_of(rect)})
+
+
+def _tiles_of(rect):
+    x0, x1, y0, y1 = (int(v) for v in rect)
+    ty, tx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+    return np.stack([tx.ravel(), ty.ravel()], 1)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    sc = synth.procedural_scene()
+    cams = synth.procedural_cameras()[:4]
+    sc.cameras = cams
+    projs = [oracle.project(sc, cam) for cam in cams]
+    return sc, cams, projs
+
+
+def _tile_pixels(tx, ty, W, H):
+    return _rect_pixels((tx, tx, ty, ty), W, H)
+
+
+def c5_slice_and_weights(sc, cams, projs, seed=9, m=64):
+    """64 Gaussians rendered in view 0 inside a single tile with no flagged
+    decision, and loss weights: random on every tile they cover in any view,
+    zero on pixels where a compositing decision lies within rounding distance
+    of its threshold."""
+    rng = np.random.default_rng(seed)
+    p0 = projs[0]
+    r0 = p0["rect"]
+    single = np.flatnonzero((p0["visible"] > 0) & (p0["flags"] == 0) & (r0[:, 0] == r0[:, 1]) &
+                            (r0[:, 2] == r0[:, 3]))
+    assert single.size > 10 * m
+    slice_ids = np.sort(rng.choice(single, m, replace=False))
+    Ws = [np.zeros((3, c.height, c.width), np.float32) for c in cams]
+    support = []   # per view: list of (gaussian, rect, pixels)
+    for v, (cam, p) in enumerate(zip(cams, projs)):
+        items = []
+        for g in slice_ids:
+            if p["visible"][g] > 0:
+                items.append((g, p["rect"][g].copy(),
+                               _rect_pixels(p["rect"][g], cam.width, cam.height)))
+        support.append(items)
+        tiles = _support_tiles(items)
+        if not tiles:
+            continue
+        txy = ((cam.width + 15) // 16, (cam.height + 15) // 16)
+        cand = _overlapping(p, np.array(tiles), *txy)
+        for tx, ty in tiles:
+            pix = _tile_pixels(tx, ty, cam.width, cam.height)
+            sub, _ = _subscene(sc, _overlapping(p, np.array([[tx, ty]]), *txy, among=cand))
+            _, _, _, margin = oracle.render_pixels(oracle.project(sub, cam), pix)
+            w = rng.standard_normal((3, pix.shape[0])) * 1e-2
+            w[:, margin <= MARGIN] = 0.0
+            Ws[v][:, pix[:, 1], pix[:, 0]] = w
+    return slice_ids, Ws, support
+
+
+def oracle_slice_grads(sc, cams, projs, Ws, support, slice_ids):
+    """The oracle's analytic raw-parameter gradients of sum_v W_v . image_v for
+    the slice and their error scales, tile by tile over the weighted tiles with
+    the Gaussians that reach each tile."""
+    want = {k: np.zeros(getattr(sc, k).shape[:-1] + (slice_ids.size,)) for k in gsmi.PARAM_NAMES}
+    scale = {k: np.zeros_like(want[k]) for k in gsmi.PARAM_NAMES}
+    sl, _ = _subscene(sc, slice_ids)
+    for v, (cam, p) in enumerate(zip(cams, projs)):
+        gproj = np.zeros((slice_ids.size, 9))
+        gabs = np.zeros((slice_ids.size, 9))
+        tiles = _support_tiles(support[v])
+        if not tiles:
+            continue
+        txy = ((cam.width + 15) // 16, (cam.height + 15) // 16)
+        cand = _overlapping(p, np.array(tiles), *txy)
+        for tx, ty in tiles:
+            pix = _tile_pixels(tx, ty, cam.width, cam.height)
+            idx = _overlapping(p, np.array([[tx, ty]]), *txy, among=cand)
+            sub, idx = _subscene(sc, idx)
+            ps = oracle.project(sub, cam)
+            wv = Ws[v][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
+            gp, ga = oracle.render_backward_pixels(ps, pix, wv)
+            pos = np.searchsorted(idx, slice_ids)
+            inside = (pos < idx.size) & (idx[np.minimum(pos, idx.size - 1)] == slice_ids)
+            gproj[inside] += gp[pos[inside]]
+            gabs[inside] += ga[pos[inside]]
+        psl = oracle.project(sl, cam)
+        g = oracle.project_backward(sl, cam, psl["visible"], gproj)
+        s = raw_grad_scale(sl, cam, psl, gabs)
+        for k in gsmi.PARAM_NAMES:
+            want[k] += g[k]
+            scale[k] += s[k]
+    return want, scale
+
+
+class FiniteDifferences:
+    """Central differences of the FP64 oracle's sum_v W_v . image_v w.r.t. the 59
+    raw parameters of Gaussian gid (order: means, log-scales, quats, logit, SH).
+    Only the pixels inside the Gaussian's footprint can change, so only they are
+    rendered, with the Gaussians that reach its tiles; a step re-projects the
+    one perturbed Gaussian.  Parameters are FP32, so the step actually taken is
+    the difference of the two rounded values."""
+
+    def __init__(self, sc, cams, projs, Ws, support, gid):
+        self.views = []
+        for v, (cam, p) in enumerate(zip(cams, projs)):
+            for (g2, rect, rp) in support[v]:
+                if g2 != gid:
+                    continue
+                idx = _overlapping(p, _tiles_of(rect), (cam.width + 15) // 16,
+                                   (cam.height + 15) // 16)
+                sub, idx = _subscene(sc, idx)
+                jj = int(np.searchsorted(idx, gid))
+                ps = oracle.project(sub, cam)
+                # pixels of the footprint {o G >= 1/255}, widened by 1%
+                d = rp + 0.5 - ps["mean2d"][jj]
+                a, b, c = ps["conic"][jj]
+                q = a * d[:, 0] ** 2 + 2 * b * d[:, 0] * d[:, 1] + c * d[:, 1] ** 2
+                lim = 2.0 * np.log(255.0 * ps["opacity"][jj]) * 1.01
+                pix = rp[q <= lim]
+                w = Ws[v][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
+                if not w.any():
+                    continue
+                # keep the Gaussians whose footprint box meets these pixels' box
+                o = np.maximum(ps["opacity"], 1.0 / 255.0)
+                L = 2.0 * np.log(255.0 * o) * 1.01
+                ex = np.sqrt(L * ps["cov2d"][:, 0]) + 1.0
+                ey = np.sqrt(L * ps["cov2d"][:, 2]) + 1.0
+                m2 = ps["mean2d"]
+                lo, hi = pix.min(0) + 0.5, pix.max(0) + 0.5
+                keep = ((ps["visible"] > 0) & (m2[:, 0] + ex >= lo[0]) & (m2[:, 0] - ex <= hi[0]) &
+                        (m2[:, 1] + ey >= lo[1]) & (m2[:, 1] - ey <= hi[1]))
+                keep[jj] = True
+                sub, kept = _subscene(sub, np.flatnonzero(keep))
+                jj = int(np.searchsorted(kept, jj))
+                ps = oracle.project(sub, cam)
+                one, _ = _subscene(sub, [jj])
+                self.views.append((cam, sub, jj, ps, one, pix, w))
+        self.slots = [(name, row) for name in gsmi.PARAM_NAMES
+                      for row in range(int(np.prod(getattr(sc, name).shape[:-1])))]
+
+    def __call__(self, k, rel_step=1e-6):
+        # per-pixel differences first: summing the loss before differencing would
+        # leave its own rounding (1e-16 of the whole loss) in every derivative
+        name, row = self.slots[k]
+        total, step = 0.0, None
+        for cam, sub, jj, ps, one, pix, w in self.views:
+            if pix.shape[0] == 0:
+                continue
+            arr = getattr(one, name)
+            flat = arr.reshape(-1, 1)
+            x0 = float(flat[row, 0])
+            C, xs = [], []
+            for sign in (-1.0, 1.0):
+                x = np.float32(x0 + sign * rel_step * max(1.0, abs(x0)))
+                flat[row, 0] = x
+                q1 = oracle.project(one, cam)
+                pp = dict(ps)
+                for key in ("mean2d", "conic", "opacity", "rgb", "depth_key", "visible"):
+                    pp[key] = ps[key].copy()
+                    pp[key][jj] = q1[key][0]
+                C.append(oracle.render_pixels(pp, pix)[0])
+                xs.append(float(x))
+            flat[row, 0] = np.float32(x0)
+            total += float((w * (C[1] - C[0])).sum())
+            step = xs[1] - xs[0]
+        return total / step if step else 0.0
+
+
+GROUPS = ((0, 3), (3, 6), (6, 10), (10, 11), (11, 59))
+
+
+def check_fd(gg, fdiff, gid):
+    """GPU gradient (FP32) against central differences, per parameter group:
+    within 1e-3 of the group's largest derivative plus 1e-3 relative.  A
+    component that fails is differenced again with a 4x larger step: if the
+    two differences disagree the loss is not smooth there (the depth key is
+    the FP32 rounding of the depth, a step function, so moving a mean can swap
+    two splats of equal key) and the component is counted as skipped.
+    Returns the number skipped."""
+    fd = np.array([fdiff(k) for k in range(gg.size)])
+    skipped = 0
+    for a, b in GROUPS:
+        big = np.abs(fd[a:b]).max()
+        for k in range(a, b):
+            tol = 1e-3 * big + 1e-3 * abs(fd[k]) + 1e-11
+            if abs(gg[k] - fd[k]) <= tol:
+                continue
+            fd4 = fdiff(k, rel_step=4e-6)
+            assert abs(fd4 - fd[k]) > 1e-2 * (abs(fd[k]) + big), (gid, k, gg[k], fd[k], fd4)
+            skipped += 1
+    return skipped
+
+
+@pytest.fixture(scope="module")
+def c5_grads(c5):
+    """GPU autograd over the whole scene with the slice's loss weights."""
+    sc, cams, projs = c5
+    slice_ids, Ws, support = c5_slice_and_weights(sc, cams, projs)
+    r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev())
+    P = _leaf_params(sc)
+    imgs = _call(r, P)
+    loss = sum((img * torch.from_numpy(w).to(dev())).sum() for img, w in zip(imgs, Ws))
+    loss.backward()
+    got = {k: P[k].grad.cpu().numpy()[..., slice_ids] for k in gsmi.PARAM_NAMES}
+    assert r.frame.status()[2] == 0
+    del r, P, imgs, loss
+    return slice_ids, Ws, support, got
+
+
+def test_c5_slice_gradients_match_oracle_adjoint(c5, c5_grads):
+    sc, cams, projs = c5
+    slice_ids, Ws, support, got = c5_grads
+    want, scale = oracle_slice_grads(sc, cams, projs, Ws, support, slice_ids)
+    for k in gsmi.PARAM_NAMES:
+        assert_close_scaled(got[k], want[k], scale[k], what="C5 slice " + k)
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_c5_slice_gradients_match_finite_differences(c5, c5_grads, part):
+    """Central differences on all 64 Gaussians of the slice (16 per part), all
+    59 raw parameters each."""
+    sc, cams, projs = c5
+    slice_ids, Ws, support, got = c5_grads
+    skipped = 0
+    for j in range(16 * part, 16 * part + 16):
+        gid = slice_ids[j]
+        fdiff = FiniteDifferences(sc, cams, projs, Ws, support, gid)
+        gg = np.concatenate([got[k][..., j].reshape(-1) for k in gsmi.PARAM_NAMES])
+        skipped += check_fd(gg, fdiff, gid)
+    assert skipped <= 0.02 * 16 * 59
