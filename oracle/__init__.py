@@ -120,7 +120,9 @@ def camera_array(cam) -> np.ndarray:
 
 
 def project(scene_or_params, cam, near_plane: float = NEAR_PLANE) -> dict:
-    """Project every Gaussian into one camera (FP64)."""
+    """Project every Gaussian into one camera (FP64).  tiles_touched counts the
+    tiles footprint_tiles bins a Gaussian to; flags bit 0 also marks Gaussians
+    with a tile decision within rounding distance of flipping."""
     p = scene_or_params
     n = int(p.means.shape[1])
     deg = int(p.sh_degree)
@@ -139,9 +141,9 @@ def project(scene_or_params, cam, near_plane: float = NEAR_PLANE) -> dict:
                          _ptr(out["cov2d"]), _ptr(out["opacity"]), _ptr(out["rgb"]),
                          _ptr(out["depth"]), _ptr(out["depth_key"]), _ptr(out["visible"]),
                          _ptr(out["rect"]), _ptr(out["flags"]))
-    r = out["rect"]
-    tt = (r[:, 1] - r[:, 0] + 1) * (r[:, 3] - r[:, 2] + 1)
-    out["tiles_touched"] = np.where(out["visible"] > 0, tt, 0).astype(np.int64)
+    gid, tx, ty, hit, border = footprint_tiles(out)
+    out["tiles_touched"] = np.bincount(gid[hit], minlength=n).astype(np.int64)
+    out["flags"] |= (np.bincount(gid[border], minlength=n) > 0).astype(np.int32)
     out["n"] = n
     out["width"], out["height"] = int(cam.width), int(cam.height)
     return out
@@ -234,30 +236,62 @@ def l1_loss_grad(image, target):
 # ----------------------------------------------------------------------------
 # Tile binning by definition (the footprint rectangles, depth-ordered lists)
 # ----------------------------------------------------------------------------
+FOOTPRINT_INFLATE = 1.0 + 1.0 / 1024.0
+
+
+def footprint_tiles(proj: dict):
+    """The tiles a Gaussian is binned to: the tiles of its footprint rectangle
+    whose 16x16 square [16 tx, 16 tx + 16] x [16 ty, 16 ty + 16] meets the ellipse
+    d^T Q d <= 2 ln(255 o) (1 + 2^-10)^2 (the footprint ellipse, inflated like the
+    rectangle).  Returns, for every (Gaussian, rectangle tile) pair: Gaussian id,
+    tx, ty, whether the square meets the ellipse, and whether that decision lies
+    within 1e-5 (relative) of flipping.  The minimum of the quadratic form over a
+    square is 0 if the centre lies inside, else its minimum over the four edges
+    (on an edge the minimiser of a convex quadratic is its stationary point
+    clamped to the edge)."""
+    vis = np.flatnonzero(proj["visible"] > 0)
+    r = proj["rect"][vis].astype(np.int64)
+    w = r[:, 1] - r[:, 0] + 1
+    h = r[:, 3] - r[:, 2] + 1
+    cnt = w * h
+    j = np.repeat(np.arange(vis.size), cnt)
+    k = np.arange(int(cnt.sum())) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    tx = r[j, 0] + k % w[j]
+    ty = r[j, 2] + k // w[j]
+    m = proj["mean2d"][vis][j]
+    a, b, c = (proj["conic"][vis][j, u] for u in range(3))
+    o = proj["opacity"][vis][j]
+    x0 = TILE * tx - m[:, 0]
+    x1 = x0 + TILE
+    y0 = TILE * ty - m[:, 1]
+    y1 = y0 + TILE
+
+    def q(x, y):
+        return a * x * x + 2.0 * b * x * y + c * y * y
+
+    inside = (x0 <= 0) & (x1 >= 0) & (y0 <= 0) & (y1 >= 0)
+    qmin = np.where(inside, 0.0, np.inf)
+    for X in (x0, x1):
+        qmin = np.minimum(qmin, q(X, np.clip(-b * X / c, y0, y1)))
+    for Y in (y0, y1):
+        qmin = np.minimum(qmin, q(np.clip(-b * Y / a, x0, x1), Y))
+    lim = 2.0 * np.log(255.0 * o) * FOOTPRINT_INFLATE ** 2
+    hit = qmin <= lim
+    border = np.abs(qmin - lim) <= 1e-5 * lim + 1e-6
+    return vis[j], tx, ty, hit, border
+
+
 def tile_lists(proj: dict, tile_base: int = 0):
-    """Per tile of the view: the Gaussians whose footprint rectangle covers
-    it, ordered by (FP32 depth bits, Gaussian index).  Returns (tile ids,
+    """Per tile of the view: the Gaussians binned to it (footprint_tiles),
+    ordered by (FP32 depth bits, Gaussian index).  Returns (tile ids,
     Gaussian ids) in global order (tile, depth, index) and ranges [T, 2]."""
     W, H = proj["width"], proj["height"]
     tx_n = (W + TILE - 1) // TILE
     ty_n = (H + TILE - 1) // TILE
-    vis = np.nonzero(proj["visible"])[0]
-    tiles, gids, keys = [], [], []
-    for i in vis:
-        x0, x1, y0, y1 = proj["rect"][i]
-        ty, tx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
-        t = (ty * tx_n + tx).ravel()
-        tiles.append(t)
-        gids.append(np.full(t.size, i, np.int64))
-        keys.append(np.full(t.size, proj["depth_key"][i], np.uint32))
-    if tiles:
-        tiles = np.concatenate(tiles)
-        gids = np.concatenate(gids)
-        keys = np.concatenate(keys)
-    else:
-        tiles = np.zeros(0, np.int64)
-        gids = np.zeros(0, np.int64)
-        keys = np.zeros(0, np.uint32)
+    gid, tx, ty, hit, _ = footprint_tiles(proj)
+    gids = gid[hit]
+    tiles = (ty * tx_n + tx)[hit]
+    keys = proj["depth_key"][gids]
     order = np.lexsort((gids, keys, tiles))
     tiles = tiles[order] + tile_base
     gids = gids[order]

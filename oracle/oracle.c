@@ -23,7 +23,8 @@
  *   pixel (px,py) is sampled at (px+0.5, py+0.5); Sigma' gets +0.3 px^2 on its
  *   diagonal; x/z and y/z are clamped to +-1.3 tan(half fov) inside J only;
  *   Gaussians with camera depth <= near (0.2) are culled; the footprint of a
- *   Gaussian is the bounding box of the ellipse o G >= 1/255 inflated by 2^-10;
+ *   Gaussian is the bounding box of the ellipse o G >= 1/255 inflated by 2^-10,
+ *   and it is binned to the tiles of that box whose square meets the ellipse;
  *   depth order uses the FP32 rounding of the camera depth (computed as a
  *   fused multiply-add chain in double), ties broken by Gaussian index;
  *   real spherical harmonics with the Condon-Shortley phase, rgb = max(0, sum + 1/2).

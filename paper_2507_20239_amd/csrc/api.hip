@@ -73,8 +73,9 @@ void fill_views(gs_frame* f, const int32_t* widths, const int32_t* heights) {
     }
     f->T = tb;
     f->P = pb;
+    // tile keys hold 0..T, T being the never-taken 'no tile' value of the emission
     int bits = 1;
-    while (((int64_t)1 << bits) < (int64_t)tb) ++bits;
+    while (((int64_t)1 << bits) <= (int64_t)tb) ++bits;
     f->tile_bits = bits;
 }
 

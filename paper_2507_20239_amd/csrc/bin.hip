@@ -68,13 +68,14 @@ __global__ void chunk_start_kernel(const u32* vals, const u32* offs, const u32* 
 }
 
 __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u32* offs,
-                                                        const uint2* rect,
+                                                        const uint2* rect, const float4* splat,
                                                         const gs_view_info* views, int64_t n,
                                                         const u32* n_vis, const u32* n_kept,
                                                         const u32* chunk_start, u32* tile_keys,
-                                                        u32* entries, int64_t E) {
+                                                        u32* entries, int64_t E, u32 T) {
     __shared__ u32 s_off[EMIT_CHUNK], s_e[EMIT_CHUNK], s_rx[EMIT_CHUNK], s_ry[EMIT_CHUNK];
     __shared__ u32 s_tb[EMIT_CHUNK], s_tw[EMIT_CHUNK];
+    __shared__ float4 s_p0[EMIT_CHUNK], s_p1[EMIT_CHUNK];
     const int t = threadIdx.x;
     const u32 nv = *n_vis, kept = *n_kept;
     const u32 chunks = (kept + EMIT_CHUNK - 1) / EMIT_CHUNK;
@@ -94,6 +95,8 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u
             s_ry[t] = r.y;
             s_tb[t] = (u32)views[v].tile_base;
             s_tw[t] = (u32)views[v].tiles_x;
+            s_p0[t] = splat[3 * (u64)e];
+            s_p1[t] = splat[3 * (u64)e + 1];
         }
         __syncthreads();
         const u32 o = c * EMIT_CHUNK + (u32)t;
@@ -104,12 +107,25 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u
                 if (s_off[mid] <= o) lo = mid;
                 else hi = mid - 1;
             }
-            const u32 k = o - s_off[lo];
+            // the k-th tile of the entry, rows top to bottom, columns left to right,
+            // counted exactly as the projection counted them
+            u32 k = o - s_off[lo];
             const u32 rx = s_rx[lo], ry = s_ry[lo];
-            const u32 x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu;
-            const u32 w = x1 - x0 + 1;
-            const u32 dy = k / w, dx = k - dy * w;
-            tile_keys[o] = s_tb[lo] + (y0 + dy) * s_tw[lo] + x0 + dx;
+            const int x0 = (int)(rx & 0xffffu), x1 = (int)(rx >> 16);
+            const int y0 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
+            const float4 p0 = s_p0[lo], p1 = s_p1[lo];
+            const float r2 = footprint_r2(p1.w);
+            u32 tile = T;   // not reached: the rows hold exactly the counted tiles
+            for (int ty = y0; ty <= y1; ++ty) {
+                int first = 0;
+                const u32 cnt = footprint_row_count(p0, p1, r2, ty, x0, x1, &first);
+                if (k < cnt) {
+                    tile = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first + k;
+                    break;
+                }
+                k -= cnt;
+            }
+            tile_keys[o] = tile;
             entries[o] = s_e[lo];
         }
     }
@@ -160,8 +176,9 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         chunk_start_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->inst_off, f->tiles_touched,
                                                               cnt, (u32)f->cap, f->chunk_start, E);
         GS_TRY(gs_check_launch("chunk_start"));
-        emit_kernel<<<2048, GS_BLOCK, 0, s>>>(sv, f->inst_off, f->rect, f->d_views, f->n, cnt + 0,
-                                              cnt + 5, f->chunk_start, f->ikeys[0], f->ivals[0], E);
+        emit_kernel<<<2048, GS_BLOCK, 0, s>>>(sv, f->inst_off, f->rect, f->splat, f->d_views, f->n, cnt + 0,
+                                              cnt + 5, f->chunk_start, f->ikeys[0], f->ivals[0], E,
+                                              (u32)f->T);
         GS_TRY(gs_check_launch("emit"));
         GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->cap, f->tile_bits, f->sort_scratch,
                              cnt + 6, &f->isorted, s));

@@ -200,4 +200,53 @@ __device__ __forceinline__ float quad_G(float l11, const Quad& q, int i) {
     const float u = fmaf(l11, q.dx[i & 1], q.t[i >> 1]);
     return __builtin_amdgcn_exp2f(-fmaf(u, u, q.vv[i >> 1]));
 }
+
+// Squared radius of a splat's footprint ellipse in (u, v) coordinates:
+// o G >= 1/255  <=>  u^2 + v^2 <= log2(255 o), inflated like the footprint
+// rectangle.  Negative when o < 1/255 (empty footprint).
+__device__ __forceinline__ float footprint_r2(float o) {
+    const float k = (float)GS_FOOTPRINT_INFLATE;
+    return log2f(255.0f * o) * (k * k);
+}
+
+// Tile columns [c0, c1] of tile row ty whose 16x16 squares the footprint
+// ellipse of a splat meets (before clamping to the footprint rectangle).  The
+// ellipse cut by the row band 16 ty <= y <= 16 ty + 16 spans, in x, from its
+// leftmost to its rightmost point inside the band: the boundary's extreme
+// points clamped to the band.  Returns false when the band misses the ellipse.
+// Counting (projection) and enumeration (instance emission) both call this
+// with the same stored FP32 splat, so they agree bit for bit.
+__device__ __forceinline__ bool footprint_row(float4 p0, float4 p1, float r2, int ty, int& c0,
+                                              int& c1) {
+    const float l11 = p1.x, l21 = p1.y, l22 = p1.z;
+    const float R = sqrtf(r2);
+    const float ry = R / l22;                       // dy half-extent of the ellipse
+    float dya = ((float)(GS_TILE * ty) - p0.y) - p0.w;
+    float dyb = dya + (float)GS_TILE;
+    if (dya > ry || dyb < -ry) return false;
+    dya = fmaxf(dya, -ry);
+    dyb = fminf(dyb, ry);
+    const float ds = l21 * R / (l22 * sqrtf(fmaf(l21, l21, l22 * l22)));  // dy of the leftmost point
+    const float dl = fminf(fmaxf(ds, dya), dyb);
+    const float dr = fminf(fmaxf(-ds, dya), dyb);
+    const float vl = l22 * dl, vr = l22 * dr;
+    const float xl = (-sqrtf(fmaxf(fmaf(-vl, vl, r2), 0.f)) - l21 * dl) / l11;
+    const float xr = (sqrtf(fmaxf(fmaf(-vr, vr, r2), 0.f)) - l21 * dr) / l11;
+    const float mx = p0.x + p0.z;
+    c0 = (int)ceilf((mx + xl) * (1.0f / GS_TILE)) - 1;   // 16 tx + 16 >= x_left
+    c1 = (int)floorf((mx + xr) * (1.0f / GS_TILE));      // 16 tx <= x_right
+    return true;
+}
+
+// Number of tiles of row ty inside the rectangle columns [x0, x1]; the first
+// of them in *first.
+__device__ __forceinline__ u32 footprint_row_count(float4 p0, float4 p1, float r2, int ty, int x0,
+                                                   int x1, int* first) {
+    int c0, c1;
+    if (!footprint_row(p0, p1, r2, ty, c0, c1)) return 0;
+    c0 = c0 > x0 ? c0 : x0;
+    c1 = c1 < x1 ? c1 : x1;
+    *first = c0;
+    return c1 >= c0 ? (u32)(c1 - c0 + 1) : 0u;
+}
 #endif

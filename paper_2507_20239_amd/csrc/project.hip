@@ -304,7 +304,6 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
             if (x0 <= x1 && y0 <= y1) {
                 const u32 tx0 = (u32)x0 / GS_TILE, tx1 = (u32)x1 / GS_TILE;
                 const u32 ty0 = (u32)y0 / GS_TILE, ty1 = (u32)y1 / GS_TILE;
-                tt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
                 rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
                 // colour for the direction from the camera centre C = -R^T t
                 const float cx = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
@@ -325,9 +324,16 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
                 }
                 const float uh = (float)u, wh = (float)w;
                 const float ul = (float)(u - (double)uh), wl = (float)(w - (double)wh);
-                a.splat[3 * e + 0] = make_float4(uh, wh, ul, wl);
-                a.splat[3 * e + 1] = make_float4(p.chol[0], p.chol[1], p.chol[2], g.o);
+                const float4 s0 = make_float4(uh, wh, ul, wl);
+                const float4 s1 = make_float4(p.chol[0], p.chol[1], p.chol[2], g.o);
+                a.splat[3 * e + 0] = s0;
+                a.splat[3 * e + 1] = s1;
                 a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
+                // bin to the tiles of the rectangle whose squares meet the ellipse
+                const float r2 = footprint_r2(g.o);
+                int first;
+                for (u32 ty = ty0; ty <= ty1; ++ty)
+                    tt += footprint_row_count(s0, s1, r2, (int)ty, (int)tx0, (int)tx1, &first);
             }
         }
         a.tiles_touched[e] = tt;

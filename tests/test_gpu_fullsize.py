@@ -44,7 +44,10 @@ def test_c2_projection_and_tile_lists(c2):
     sp = splat_view(frame)
     tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy().view(np.uint32)
     ok = p["flags"] == 0
-    vis = p["visible"] > 0
+    # binned: the footprint rectangle is non-empty and one of its tile squares meets
+    # the footprint ellipse (a thin ellipse near the image border can have the one
+    # without the other)
+    vis = p["tiles_touched"] > 0
     np.testing.assert_array_equal((tt > 0)[ok], vis[ok])
     m = vis & (tt > 0)
     np.testing.assert_allclose(gpu_mean2d(sp)[m], p["mean2d"][m], rtol=1e-7, atol=1e-4)

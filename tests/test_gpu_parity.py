@@ -46,7 +46,10 @@ def test_project_matches_oracle(name):
     sp = splat_view(frame)
     ok = p["flags"] == 0
     assert ok.mean() > 0.99
-    vis = p["visible"] > 0
+    # binned: the footprint rectangle is non-empty and one of its tile squares meets
+    # the footprint ellipse (a thin ellipse near the image border can have the one
+    # without the other)
+    vis = p["tiles_touched"] > 0
     # bit-exact: depth keys (all), visibility and rectangles (unflagged)
     np.testing.assert_array_equal(key[p["depth"] > 0], p["depth_key"][p["depth"] > 0])
     np.testing.assert_array_equal((tt > 0)[ok], vis[ok])

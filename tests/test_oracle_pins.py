@@ -526,3 +526,31 @@ def test_footprint_rect_covers_every_contributing_pixel():
         g = gids[ranges[t, 0]:ranges[t, 1]]
         k = p["depth_key"][g]
         assert np.all((k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (g[1:] > g[:-1])))
+
+
+def test_footprint_tiles_match_brute_force_minimum_over_the_square():
+    """The tile test (minimum of d^T Q d over a tile square against the
+    footprint limit) against a 129 x 129 sample grid of every square: the exact
+    minimum never exceeds the grid's, and exceeds it by no more than the grid
+    spacing allows."""
+    sc = synth.random_scene(15, 60, 80, 64, sh_degree=0, log_scale=(-2.0, 0.8), spread=1.2)
+    p = oracle.project(sc, sc.cameras[0])
+    gid, tx, ty, hit, border = oracle.footprint_tiles(p)
+    assert hit.sum() > 50 and (~hit).sum() > 20
+    t = np.linspace(0.0, 16.0, 129)
+    gx, gy = np.meshgrid(t, t)
+    step = 16.0 / 128
+    for g, x, y, h in zip(gid, tx, ty, hit):
+        a, b, c = p["conic"][g]
+        dx = 16 * x + gx - p["mean2d"][g, 0]
+        dy = 16 * y + gy - p["mean2d"][g, 1]
+        qg = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        lim = 2 * np.log(255 * p["opacity"][g]) * oracle.FOOTPRINT_INFLATE ** 2
+        lam = 0.5 * (a + c) + np.hypot(0.5 * (a - c), b)
+        i = np.unravel_index(np.argmin(qg), qg.shape)
+        slack = 2 * lam * (np.hypot(dx[i], dy[i]) + step) * step + lam * step * step
+        # exact min <= grid min <= exact min + slack
+        if h:
+            assert qg.min() <= lim + slack
+        else:
+            assert qg.min() > lim
