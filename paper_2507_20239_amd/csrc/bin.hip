@@ -24,6 +24,7 @@ __global__ void compact_kernel(const u32* tiles_touched, const u32* offs, const 
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E || tiles_touched[e] == 0) return;
     const u32 j = offs[e];
+    if (j >= (u64)E) return;   // never taken: offsets are a scan of 0/1 flags
     keys[j] = depth_key[e];
     vals[j] = (u32)e;
 }
@@ -160,9 +161,11 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     const int64_t E = f->E;
     u32* cnt = f->counters;
     if (E > 0) {
-        // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection
-        GS_TRY(gs_scan_exclusive(f->flags, f->flags, nullptr, (u32)E, cnt + 0, f->scan_part, s));
-        compact_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(f->tiles_touched, f->flags, f->depth_key,
+        // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection.
+        // The scan goes to inst_off (free until the gather below), leaving the
+        // projection's outputs intact: rendering again repeats the same work.
+        GS_TRY(gs_scan_exclusive(f->flags, f->inst_off, nullptr, (u32)E, cnt + 0, f->scan_part, s));
+        compact_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(f->tiles_touched, f->inst_off, f->depth_key,
                                                           f->vkeys[0], f->vvals[0], E);
         GS_TRY(gs_check_launch("compact"));
         // depths are positive, so the sign bit is zero: 31 key bits

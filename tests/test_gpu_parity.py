@@ -225,3 +225,15 @@ def test_l1_loss_grad():
     ref_loss, ref_g = oracle.l1_loss_grad(a, b)
     assert float(loss.item()) == pytest.approx(ref_loss, rel=1e-5)
     np.testing.assert_array_equal(g.cpu().numpy(), ref_g.astype(np.float32))
+
+
+def test_render_twice_after_one_projection_is_identical():
+    """Rendering reads the projection's outputs without modifying them, so a
+    second render of the same projection repeats the first exactly."""
+    sc = SCENES["sh1_500_70x45"]
+    cam = sc.cameras[0]
+    frame, a, params, cams_dev, opts = gpu_forward(sc, [cam])
+    a = a.clone()
+    b = frame.render(opts)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
