@@ -58,7 +58,9 @@
 static double legendre_coef[SH_MAXL + 1][SH_MAXL + 1]; /* P_l(x) = sum_j c[l][j] x^j */
 static int legendre_ready = 0;
 
-static void legendre_init(void) {
+/* Built once when the library loads, before any OpenMP region can reach it
+ * (a lazy first-use build raced with readers on other threads). */
+__attribute__((constructor)) static void legendre_init(void) {
     if (legendre_ready) return;
     memset(legendre_coef, 0, sizeof(legendre_coef));
     legendre_coef[0][0] = 1.0;
