@@ -170,6 +170,9 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
     __shared__ u32 se[BATCH];
     const int lane = threadIdx.x;
+    // factor of each reduced value (lane l holds value l): fa * o + fb
+    const float fa = lane < 2 ? 1.f / GS_KAPPA : (lane == 2 || lane == 4) ? -0.5f : lane == 3 ? -1.f : 0.f;
+    const float fb = (lane >= 5 && lane < 9) ? 1.f : 0.f;
     for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
         const u32 t = a.order ? a.order[item] : item;
         const TileCoords tc = tile_coords(a, t);
@@ -254,42 +257,25 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                 float syy = fmaf(q.dy[0] * q.dy[0], B0, (q.dy[1] * q.dy[1]) * B1);
                 float sxy = fmaf(q.dx[0], fmaf(go[0], q.dy[0], go[2] * q.dy[1]),
                                  q.dx[1] * fmaf(go[1], q.dy[0], go[3] * q.dy[1]));
-                sx = wave_sum_lane63(sx);
-                sy = wave_sum_lane63(sy);
-                sxx = wave_sum_lane63(sxx);
-                sxy = wave_sum_lane63(sxy);
-                syy = wave_sum_lane63(syy);
-                gop = wave_sum_lane63(gop);
-                gr0 = wave_sum_lane63(gr0);
-                gr1 = wave_sum_lane63(gr1);
-                gr2 = wave_sum_lane63(gr2);
-                // The nine totals sit in lane 63.  Broadcast them and let lanes
-                // 0..8 add one each: a single 9-lane atomic instruction, which
-                // the memory system coalesces into one request per cache line
-                // (nine single-lane atomics cost nine requests).
                 // With w = dL/dalpha o G:  dL/dmean = sum w Q d,
                 // dL/d(a, b, c) = -sum w (dx^2/2, dx dy, dy^2/2), dL/do = sum dL/dalpha G;
-                // Q = L L^T / kappa from the stored Cholesky factor.
-                const float t_sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sx), 63));
-                const float t_sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sy), 63));
-                const float t_sxx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sxx), 63));
-                const float t_sxy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sxy), 63));
-                const float t_syy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(syy), 63));
-                const float t_op = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gop), 63));
-                const float t_r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr0), 63));
-                const float t_r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr1), 63));
-                const float t_r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr2), 63));
-                const float ok = p1.w * (1.f / GS_KAPPA);
+                // Q = L L^T / kappa from the stored Cholesky factor.  Q is applied
+                // to the lane sums before the reduction (it is linear), the per-value
+                // factors of o after it, and lanes 0..8 then add the nine totals
+                // with a single 9-lane atomic instruction, which the memory system
+                // coalesces into one request per cache line.
                 const float qa = p1.x * p1.x, qb = p1.x * p1.y, qc = fmaf(p1.y, p1.y, p1.z * p1.z);
-                float val = ok * fmaf(qa, t_sx, qb * t_sy);
-                val = lane == 1 ? ok * fmaf(qb, t_sx, qc * t_sy) : val;
-                val = lane == 2 ? -0.5f * p1.w * t_sxx : val;
-                val = lane == 3 ? -p1.w * t_sxy : val;
-                val = lane == 4 ? -0.5f * p1.w * t_syy : val;
-                val = lane == 5 ? t_op : val;
-                val = lane == 6 ? t_r0 : val;
-                val = lane == 7 ? t_r1 : val;
-                val = lane == 8 ? t_r2 : val;
+                float v[9];
+                v[0] = fmaf(qa, sx, qb * sy);
+                v[1] = fmaf(qb, sx, qc * sy);
+                v[2] = sxx;
+                v[3] = sxy;
+                v[4] = syy;
+                v[5] = gop;
+                v[6] = gr0;
+                v[7] = gr1;
+                v[8] = gr2;
+                const float val = wave_reduce9(v, lane) * fmaf(p1.w, fa, fb);
                 if (lane < 9) unsafeAtomicAdd(a.splat_grad + 9 * (u64)se[k] + lane, val);
             }
         }
