@@ -29,14 +29,6 @@ __global__ void compact_kernel(const u32* tiles_touched, const u32* offs, const 
     vals[j] = (u32)e;
 }
 
-__global__ void gather_counts_kernel(const u32* vals, const u32* tiles_touched, u32* cnt,
-                                     const u32* n_vis, int64_t E) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= E || j >= (int64_t)*n_vis) return;
-    const u32 e = vals[j];
-    cnt[j] = e < (u64)E ? tiles_touched[e] : 0u;
-}
-
 // Instance emission, balanced per 256 instances.  Pass 1 records, for every
 // chunk of 256 consecutive instance slots, the depth-sorted entry whose tiles
 // start the chunk.  Pass 2 gives each workgroup whole chunks: it stages the
@@ -81,8 +73,12 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u
     const u32 nv = *n_vis, kept = *n_kept;
     const u32 chunks = (kept + EMIT_CHUNK - 1) / EMIT_CHUNK;
     for (u32 c = blockIdx.x; c < chunks; c += gridDim.x) {
+        // the entries that own instances of this chunk: from its first owner to
+        // the owner of the next chunk's first instance
         const u32 j0 = chunk_start[c];
-        const int m = (nv - j0) < EMIT_CHUNK ? (int)(nv - j0) : (int)EMIT_CHUNK;
+        const u32 j1 = c + 1 < chunks ? chunk_start[c + 1] : nv - 1;
+        const u32 span = j1 - j0 + 1;
+        const int m = span < EMIT_CHUNK ? (int)span : (int)EMIT_CHUNK;
         __syncthreads();
         if (t < m) {
             u32 e = vals[j0 + t];
@@ -114,12 +110,11 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u
             const u32 rx = s_rx[lo], ry = s_ry[lo];
             const int x0 = (int)(rx & 0xffffu), x1 = (int)(rx >> 16);
             const int y0 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
-            const float4 p0 = s_p0[lo], p1 = s_p1[lo];
-            const float r2 = footprint_r2(p1.w);
+            const FootprintRows fr = footprint_rows(s_p0[lo], s_p1[lo]);
             u32 tile = T;   // not reached: the rows hold exactly the counted tiles
             for (int ty = y0; ty <= y1; ++ty) {
                 int first = 0;
-                const u32 cnt = footprint_row_count(p0, p1, r2, ty, x0, x1, &first);
+                const u32 cnt = footprint_row_count(fr, ty, x0, x1, &first);
                 if (k < cnt) {
                     tile = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first + k;
                     break;
@@ -132,14 +127,22 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u
     }
 }
 
+// Tile ranges [start, end) from the sorted tile keys, empty tiles included
+// (as an empty range at the position where they would start), so no clearing
+// pass is needed: the thread at each boundary i (a change of key between i-1
+// and i, or the two ends) closes the previous tile, writes the tiles strictly
+// between the two keys and opens the next.  Keys >= T (never produced) count
+// as T.
 __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, u32 T) {
     const u32 n = *n_ptr;
     const u32 stride = gridDim.x * blockDim.x;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const u32 k = keys[i];
-        if (k >= T) continue;
-        if (i == 0 || keys[i - 1] != k) ranges[k].x = i;
-        if (i == n - 1 || keys[i + 1] != k) ranges[k].y = i + 1;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+        const int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] < T ? keys[i - 1] : T);
+        const int64_t cur = i == n ? (int64_t)T : (int64_t)(keys[i] < T ? keys[i] : T);
+        if (cur == prev) continue;
+        if (prev >= 0 && prev < (int64_t)T) ranges[prev].y = i;
+        for (int64_t t = prev + 1; t < cur && t < (int64_t)T; ++t) ranges[t] = make_uint2(i, i);
+        if (cur < (int64_t)T) ranges[cur].x = i;
     }
 }
 
@@ -162,7 +165,7 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     u32* cnt = f->counters;
     if (E > 0) {
         // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection.
-        // The scan goes to inst_off (free until the gather below), leaving the
+        // The scan goes to inst_off (free until the offsets scan below), leaving the
         // projection's outputs intact: rendering again repeats the same work.
         GS_TRY(gs_scan_exclusive(f->flags, f->inst_off, nullptr, (u32)E, cnt + 0, f->scan_part, s));
         compact_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(f->tiles_touched, f->inst_off, f->depth_key,
@@ -172,10 +175,9 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         GS_TRY(gs_radix_sort(f->vkeys, f->vvals, cnt + 0, 0, E, 31, f->sort_scratch, cnt + 6,
                              &f->vsorted, s));
         const u32* sv = f->vvals[f->vsorted];
-        gather_counts_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->tiles_touched, f->inst_off,
-                                                                cnt + 0, E);
-        GS_TRY(gs_check_launch("gather_counts"));
-        GS_TRY(gs_scan_exclusive(f->inst_off, f->inst_off, cnt + 0, 0, cnt + 1, f->scan_part, s));
+        // instance offsets: exclusive scan of tiles_touched in depth order
+        GS_TRY(gs_scan_exclusive(f->tiles_touched, f->inst_off, cnt + 0, 0, cnt + 1, f->scan_part,
+                                 s, sv));
         chunk_start_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->inst_off, f->tiles_touched,
                                                               cnt, (u32)f->cap, f->chunk_start, E);
         GS_TRY(gs_check_launch("chunk_start"));
@@ -188,9 +190,7 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     } else {
         GS_TRY(gs_fill_u32(cnt, 0u, 8, s));
     }
-    GS_TRY(gs_fill_u32((u32*)f->ranges, 0u, 2 * (int64_t)f->T, s));
-    ranges_kernel<<<1024, GS_BLOCK, 0, s>>>(f->ikeys[f->isorted], cnt + 5, f->ranges,
-                                                              (u32)f->T);
+    ranges_kernel<<<4096, GS_BLOCK, 0, s>>>(f->ikeys[f->isorted], cnt + 5, f->ranges, (u32)f->T);
     GS_TRY(gs_check_launch("ranges"));
     if (heavy_first) {
         tile_weight_kernel<<<blocks_for(f->T), GS_BLOCK, 0, s>>>(f->ranges, f->tkeys[0], f->tvals[0],

@@ -330,10 +330,10 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
                 a.splat[3 * e + 1] = s1;
                 a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
                 // bin to the tiles of the rectangle whose squares meet the ellipse
-                const float r2 = footprint_r2(g.o);
+                const FootprintRows fr = footprint_rows(s0, s1);
                 int first;
                 for (u32 ty = ty0; ty <= ty1; ++ty)
-                    tt += footprint_row_count(s0, s1, r2, (int)ty, (int)tx0, (int)tx1, &first);
+                    tt += footprint_row_count(fr, (int)ty, (int)tx0, (int)tx1, &first);
             }
         }
         a.tiles_touched[e] = tt;

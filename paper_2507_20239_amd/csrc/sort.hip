@@ -54,13 +54,18 @@ __global__ void fill_u32_kernel(u32* p, u32 value, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
 }
 
-__global__ void __launch_bounds__(GS_BLOCK) scan_reduce_kernel(const u32* in, const u32* n_dev,
-                                                               u32 n_host, u32* part) {
+__device__ __forceinline__ u32 scan_in(const u32* in, const u32* gather, u32 i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) scan_reduce_kernel(const u32* in, const u32* gather,
+                                                               const u32* n_dev, u32 n_host,
+                                                               u32* part) {
     __shared__ u32 lds4[4];
     u32 beg, end;
     chunk_of(dev_len(n_dev, n_host), GS_SCAN_PARTS, blockIdx.x, beg, end);
     u32 s = 0;
-    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) s += in[i];
+    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) s += scan_in(in, gather, i);
     u32 total;
     block_exclusive_scan(s, lds4, total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
@@ -90,8 +95,8 @@ __global__ void __launch_bounds__(GS_SCAN_PARTS) scan_parts_kernel(u32* part, u3
     }
 }
 
-__global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, u32* out,
-                                                             const u32* n_dev, u32 n_host,
+__global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, const u32* gather,
+                                                             u32* out, const u32* n_dev, u32 n_host,
                                                              const u32* part) {
     __shared__ u32 lds4[4];
     u32 beg, end;
@@ -103,7 +108,7 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, u32*
         const u32 i0 = base + threadIdx.x * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            v[j] = (i0 + j < end) ? in[i0 + j] : 0u;
+            v[j] = (i0 + j < end) ? scan_in(in, gather, i0 + j) : 0u;
             s += v[j];
         }
         u32 total;
@@ -253,10 +258,10 @@ gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s) {
 }
 
 gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
-                            u32* part, hipStream_t s) {
-    scan_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, n_dev, n_host, part);
+                            u32* part, hipStream_t s, const u32* gather) {
+    scan_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, gather, n_dev, n_host, part);
     scan_parts_kernel<<<1, GS_SCAN_PARTS, 0, s>>>(part, total);
-    scan_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, out, n_dev, n_host, part);
+    scan_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, gather, out, n_dev, n_host, part);
     return gs_check_launch("scan_exclusive");
 }
 
