@@ -123,12 +123,12 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, cons
 }
 
 // ---- Radix pass: per-workgroup digit counts (digit-major matrix [256][G]),
-// an exclusive scan of that matrix over the whole GPU (which gives every
-// workgroup the start of each of its digit runs), and a stable scatter.
-// Workgroup counts could also be combined by a chained (decoupled look-back)
-// scan or by each workgroup summing the rows before it; both were measured
-// to be latency-bound on this part (device-scope loads cross the XCDs), so
-// the three-launch form is used.  The scatter reorders each 2048-key
+// a scan of each digit's row over the workgroups plus the digit totals, and a
+// stable scatter that adds the digit bases (which gives every workgroup the
+// start of each of its digit runs).  Workgroup counts could also be combined
+// by a chained (decoupled look-back) scan or by each workgroup summing the
+// rows before it; both were measured to be latency-bound on this part
+// (device-scope loads cross the XCDs).  The scatter reorders each 2048-key
 // sub-batch by digit in LDS first, so consecutive lanes write consecutive
 // addresses of a digit run (coalesced) instead of scattering 4-byte stores.
 
@@ -158,10 +158,35 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_count_kernel(const u32* __restr
     counts[(u64)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
+// One workgroup per digit: exclusive scan of the digit's row of workgroup
+// counts (counts[d][0..G), G <= 1024, in place) and the digit's total.  The
+// scatter adds the digit bases (an exclusive scan of the 256 totals, which
+// every scatter workgroup computes for itself), so a pass is three launches.
+__global__ void __launch_bounds__(GS_BLOCK) sort_rowscan_kernel(u32* counts, u32 G, u32* dtot) {
+    __shared__ u32 lds4[4];
+    u32* row = counts + (u64)blockIdx.x * G;
+    const u32 i0 = threadIdx.x * 4;
+    u32 v[4];
+    u32 sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        v[j] = i0 + j < G ? row[i0 + j] : 0u;
+        sum += v[j];
+    }
+    u32 total;
+    u32 ex = block_exclusive_scan(sum, lds4, total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (i0 + j < G) row[i0 + j] = ex;
+        ex += v[j];
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = total;
+}
+
 __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
     const u32* __restrict__ kin, const u32* __restrict__ vin, u32* __restrict__ kout,
     u32* __restrict__ vout, const u32* n_dev, u32 n_host, int shift, int bits,
-    const u32* __restrict__ offs) {
+    const u32* __restrict__ offs, const u32* __restrict__ dtot) {
     __shared__ u32 whist[4][256];
     __shared__ u32 s_base[256];    // global start of each digit's run for the next sub-batch
     __shared__ u32 s_local[256];   // start of each digit inside the sub-batch
@@ -169,7 +194,11 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
     __shared__ u32 lds4[4];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const u32 n = dev_len(n_dev, n_host);
-    s_base[tid] = offs[(u64)tid * gridDim.x + blockIdx.x];
+    {
+        u32 all;
+        const u32 dbase = block_exclusive_scan(dtot[tid], lds4, all);
+        s_base[tid] = dbase + offs[(u64)tid * gridDim.x + blockIdx.x];
+    }
     u32 beg, end;
     chunk_of(n, gridDim.x, blockIdx.x, beg, end);
     const u32 mask = (1u << bits) - 1u;
@@ -276,9 +305,10 @@ gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int6
         const int b = (bits - shift) < 8 ? (bits - shift) : 8;
         sort_count_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], n_dev, n_host, shift, b, counts);
         GS_TRY(gs_check_launch("sort_count"));
-        GS_TRY(gs_scan_exclusive(counts, counts, nullptr, 256 * G, nullptr, part, s));
+        sort_rowscan_kernel<<<256, GS_BLOCK, 0, s>>>(counts, G, part);
+        GS_TRY(gs_check_launch("sort_rowscan"));
         sort_scatter_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n_dev,
-                                                   n_host, shift, b, counts);
+                                                   n_host, shift, b, counts, part);
         GS_TRY(gs_check_launch("sort_scatter"));
         cur ^= 1;
     }
