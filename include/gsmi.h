@@ -286,6 +286,33 @@ gs_status gs_adaptive_prune_threshold(const float* opacity_logits, int64_t n, in
                                       uint64_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Optimiser                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* One parameter array for gs_adam_step: param, grad, m, v are device FP32
+ * [rows][n] (structure of arrays, Gaussian index fastest); lr its step size. */
+typedef struct {
+    float* param;
+    const float* grad;
+    float* m;
+    float* v;
+    int32_t rows;
+    float lr;
+} gs_adam_param;
+
+/* Sparse Adam, the optimiser step of the accelerated 3DGS training the paper
+ * builds on (Experiments, implementation details): Gaussians that no view
+ * rendered (tiles_touched[v][i] == 0 for every v) keep their parameters and
+ * moments; the others take m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * params: HOST array of n_params <= 8 entries; tiles_touched: device u32
+ * [n_views][n] (a frame's GS_BUF_TILES_TOUCHED) or NULL to update every
+ * Gaussian; step >= 1 is the global step count used for the bias correction. */
+gs_status gs_adam_step(const gs_adam_param* params, int32_t n_params, int64_t n,
+                       const uint32_t* tiles_touched, int32_t n_views, float beta1, float beta2,
+                       float eps, int64_t step, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Primitives exposed for testing                                            */
 /* ------------------------------------------------------------------------ */
 

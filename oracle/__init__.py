@@ -417,3 +417,27 @@ def adaptive_prune_logit(logits, p=0.03, tau_u=0.05):
     k = min(k, lg.size - 1)
     upper = np.float32(math.log(tau_u / (1.0 - tau_u)))
     return np.float32(min(lg[k], upper)), k
+
+
+# ----------------------------------------------------------------------------
+# Sparse Adam (the optimiser of the accelerated training the paper builds on)
+# ----------------------------------------------------------------------------
+def adam_step(param, grad, m, v, lr, visible, beta1, beta2, eps, step):
+    """One sparse Adam step in FP64 on arrays [..., n]: the columns i with
+    visible[i] take m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2 and
+    p -= lr m_hat / (sqrt(v_hat) + eps) with m_hat = m / (1 - b1^step),
+    v_hat = v / (1 - b2^step); the other columns are returned unchanged."""
+    p = np.array(param, np.float64)
+    g = np.asarray(grad, np.float64)
+    m = np.array(m, np.float64)
+    v = np.array(v, np.float64)
+    sel = np.asarray(visible, bool)
+    m2 = beta1 * m + (1 - beta1) * g
+    v2 = beta2 * v + (1 - beta2) * g * g
+    mh = m2 / (1 - beta1 ** step)
+    vh = v2 / (1 - beta2 ** step)
+    p2 = p - lr * mh / (np.sqrt(vh) + eps)
+    p[..., sel] = p2[..., sel]
+    m[..., sel] = m2[..., sel]
+    v[..., sel] = v2[..., sel]
+    return p, m, v

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgsmi.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "sort.hip", "project.hip", "bin.hip", "raster.hip", "densify.hip"]
+SOURCES = ["api.hip", "sort.hip", "project.hip", "bin.hip", "raster.hip", "densify.hip",
+           "optim.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -67,6 +67,11 @@ class Attr(ctypes.Structure):
                 ("policy", ctypes.c_int32)]
 
 
+class AdamParam(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("m", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("rows", ctypes.c_int32), ("lr", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
@@ -96,6 +101,8 @@ _SIGS = {
     "gs_densify_apply": [_P, _P, _I64, _I64, ctypes.POINTER(Attr), _I32, _P, _P, _P, _U64, _U64,
                          _P],
     "gs_split_normals": [_P, _P, _I64, _U64, _U64, _P, _P, _P],
+    "gs_adam_step": [ctypes.POINTER(AdamParam), _I32, _I64, _P, _I32, ctypes.c_float,
+                     ctypes.c_float, ctypes.c_float, _I64, _P],
     "gs_radix_select_workspace_size": [_I64, ctypes.POINTER(_U64)],
     "gs_adaptive_prune_threshold": [_P, _I64, _I64, _F, _P, _P, _U64, _P],
     "gs_sort_workspace_size": [_I64, ctypes.POINTER(_U64)],
@@ -384,6 +391,25 @@ def adaptive_prune_threshold(logits, p=0.03, tau_u=0.05, stream=None):
     _check(lib().gs_adaptive_prune_threshold(_ptr(logits), n, k, upper, _ptr(thr), _ptr(ws),
                                              int(nb.value), _stream(stream)))
     return thr, k
+
+
+def adam_step(entries, n, step, tiles_touched=None, n_views=1, beta1=0.9, beta2=0.999, eps=1e-15,
+              stream=None):
+    """Sparse Adam step.  entries: list of (param, grad, m, v, lr), tensors of
+    shape [rows, n] (or [n]); tiles_touched: a frame's BUF_TILES_TOUCHED (only
+    Gaussians rendered in some view are updated) or None (all of them)."""
+    arr = (AdamParam * len(entries))()
+    for i, (p, g, m, v, lr) in enumerate(entries):
+        rows = p.numel() // n if n else 0
+        for t in (g, m, v):
+            if t.numel() != p.numel() or not t.is_contiguous():
+                raise ValueError("grad and moments must match the parameter's shape")
+        arr[i].param, arr[i].grad, arr[i].m, arr[i].v = (p.data_ptr(), g.data_ptr(), m.data_ptr(),
+                                                         v.data_ptr())
+        arr[i].rows = rows
+        arr[i].lr = float(lr)
+    _check(lib().gs_adam_step(arr, len(entries), int(n), _ptr(tiles_touched), int(n_views),
+                              float(beta1), float(beta2), float(eps), int(step), _stream(stream)))
 
 
 def sort_pairs(keys, vals, key_bits=32, stream=None):

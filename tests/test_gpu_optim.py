@@ -1,0 +1,69 @@
+"""Sparse Adam on the GPU (through the C ABI) against the FP64 oracle: the
+updated parameters and moments of rendered Gaussians within FP32 rounding,
+everything else bit-identical, over several steps with changing visibility."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2507_20239_amd import gsmi
+from parity_util import dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,views", [(1, 1), (1000, 2), (100_003, 3)])
+def test_sparse_adam_matches_oracle(n, views):
+    rng = np.random.default_rng(n)
+    shapes = {"means": (3, n), "log_scales": (3, n), "quats": (4, n), "logits": (1, n),
+              "sh": (48, n)}
+    lrs = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "logits": 5e-2, "sh": 2.5e-3}
+    host = {k: [rng.standard_normal(s).astype(np.float32), np.zeros(s, np.float32),
+                np.zeros(s, np.float32)] for k, s in shapes.items()}
+    gpu = {k: [torch.from_numpy(a.copy()).to(dev()) for a in v] for k, v in host.items()}
+    for step in range(1, 5):
+        tt = (rng.random((views, n)) < 0.3).astype(np.uint32) * rng.integers(1, 9, (views, n),
+                                                                            dtype=np.uint32)
+        vis = tt.any(0)
+        grads = {k: (rng.standard_normal(s) * 10.0 ** rng.uniform(-6, 0)).astype(np.float32)
+                 for k, s in shapes.items()}
+        entries = []
+        for k in shapes:
+            g = torch.from_numpy(grads[k]).to(dev())
+            p, m, v = gpu[k]
+            entries.append((p, g, m, v, lrs[k]))
+        gsmi.adam_step(entries, n, step, tiles_touched=torch.from_numpy(tt.view(np.int32)).to(dev()),
+                       n_views=views, beta1=0.9, beta2=0.999, eps=1e-15)
+        torch.cuda.synchronize()
+        # the kernel's hyper-parameters are FP32; the oracle takes the same values
+        b1, b2, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-15))
+        for k in shapes:
+            p0, m0, v0 = host[k]
+            p1, m1, v1 = oracle.adam_step(p0, grads[k], m0, v0, float(np.float32(lrs[k])), vis, b1,
+                                          b2, eps, step)
+            gp, gm, gv = (t.cpu().numpy() for t in gpu[k])
+            np.testing.assert_array_equal(gp[:, ~vis], p0[:, ~vis])
+            np.testing.assert_array_equal(gm[:, ~vis], m0[:, ~vis])
+            # m is a sum whose two terms can cancel: measured against the sum of their magnitudes
+            mscale = b1 * np.abs(m0) + (1 - b1) * np.abs(grads[k])
+            assert (np.abs(gm[:, vis] - m1[:, vis]) <= 2e-7 * mscale[:, vis] + 1e-37).all()
+            np.testing.assert_allclose(gv[:, vis], v1[:, vis], rtol=2e-6, atol=1e-37)
+            # the step lr m_hat / (sqrt(v_hat) + eps): FP32 rounding of a few operations
+            if vis.any():
+                step_ref = p1[:, vis] - p0[:, vis].astype(np.float64)
+                np.testing.assert_allclose(gp[:, vis].astype(np.float64) - p0[:, vis], step_ref,
+                                           rtol=1e-4,
+                                           atol=4 * np.spacing(np.abs(p0[:, vis])).max())
+            host[k] = [gp.copy(), gm.copy(), gv.copy()]
+
+
+def test_dense_adam_updates_every_gaussian():
+    n = 4097
+    p = torch.zeros(2, n, device=dev())
+    g = torch.ones(2, n, device=dev())
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    gsmi.adam_step([(p, g, m, v, 0.1)], n, 1)
+    torch.cuda.synchronize()
+    # first step: m_hat = g, v_hat = g^2, so p = -lr g / (|g| + eps)
+    assert torch.allclose(p, torch.full_like(p, -0.1))

@@ -554,3 +554,24 @@ def test_footprint_tiles_match_brute_force_minimum_over_the_square():
             assert qg.min() <= lim + slack
         else:
             assert qg.min() > lim
+
+
+def test_adam_matches_torch_adam_and_skips_invisible_columns():
+    rng = np.random.default_rng(16)
+    n = 50
+    p0 = rng.standard_normal((3, n))
+    p_t = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([p_t], lr=0.01, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros((3, n)), np.zeros((3, n))
+    for step in range(1, 4):
+        g = rng.standard_normal((3, n))
+        p_t.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = oracle.adam_step(p, g, m, v, 0.01, np.ones(n, bool), 0.9, 0.999, 1e-8, step)
+        np.testing.assert_allclose(p, p_t.detach().numpy(), rtol=1e-13, atol=1e-15)
+    vis = rng.random(n) < 0.5
+    g = rng.standard_normal((3, n))
+    p2, m2, v2 = oracle.adam_step(p, g, m, v, 0.01, vis, 0.9, 0.999, 1e-8, 4)
+    np.testing.assert_array_equal(p2[:, ~vis], p[:, ~vis])
+    np.testing.assert_array_equal(m2[:, ~vis], m[:, ~vis])
+    assert not np.allclose(p2[:, vis], p[:, vis])
