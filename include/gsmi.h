@@ -285,6 +285,18 @@ gs_status gs_adaptive_prune_threshold(const float* opacity_logits, int64_t n, in
                                       float upper_logit, float* thr, void* workspace,
                                       uint64_t workspace_bytes, void* stream);
 
+/* Eq. 3 with its D-SSIM term: loss[0] += (1 - lambda) mean|I - T| +
+ * lambda (1 - mean SSIM(I, T)) and dL_dimage = its gradient w.r.t. I
+ * (overwritten).  SSIM per channel with an 11 x 11 Gaussian window of standard
+ * deviation 1.5, zero padding, C1 = 0.01^2, C2 = 0.03^2; means over all
+ * channels and pixels.  image, target, dL_dimage: device FP32 [channels][height][width]
+ * (one view); workspace: gs_ssim_workspace_size bytes of device scratch. */
+gs_status gs_ssim_workspace_size(int32_t channels, int32_t height, int32_t width, uint64_t* bytes);
+gs_status gs_ssim_loss_grad(const float* image, const float* target, int32_t channels,
+                            int32_t height, int32_t width, float lambda, float* loss,
+                            float* dL_dimage, void* workspace, uint64_t workspace_bytes,
+                            void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Optimiser                                                                 */
 /* ------------------------------------------------------------------------ */

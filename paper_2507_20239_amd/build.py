@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libgsmi.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "sort.hip", "project.hip", "bin.hip", "raster.hip", "densify.hip",
-           "optim.hip"]
+           "optim.hip", "loss.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

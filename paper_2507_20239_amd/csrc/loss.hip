@@ -1,0 +1,206 @@
+// Photometric loss of Eq. 3 and its gradient w.r.t. the rendered image:
+//   L = (1 - lambda) mean |I - T| + lambda (1 - mean SSIM(I, T)),
+// SSIM with the 3DGS window: an 11 x 11 Gaussian of standard deviation 1.5,
+// zero padding, C1 = 0.01^2, C2 = 0.03^2, the mean over every channel and
+// pixel.  With mu = G*I, nu = G*T, Exx = G*I^2, Eyy = G*T^2, Exy = G*(I T),
+//   S = (2 mu nu + C1)(2 (Exy - mu nu) + C2) / ((mu^2 + nu^2 + C1)((Exx - mu^2) + (Eyy - nu^2) + C2)),
+// and dL/dI(q) = -lambda/N [ (G*a)(q) + 2 I(q) (G*b)(q) + T(q) (G*c)(q) ] + (1-lambda)/N sign(I-T)(q)
+// where a = dS/dmu, b = dS/dExx, c = dS/dExy are maps over the pixels p
+// (G is symmetric, so correlating with it is convolving with it).
+//
+// Two launches per image: the forward computes S and (a, b, c) for a 16x16
+// tile per workgroup from a 26x26 LDS patch (separable: a horizontal pass to
+// 26x16 partial sums, then a vertical one); the backward filters (a, b, c) the
+// same way and combines them with I and T at each pixel.  HBM-bound: about
+// 44 B per channel-pixel over the two launches.
+#include "gs_internal.h"
+
+namespace {
+
+constexpr int ST = 16;              // output tile edge
+constexpr int SR = 5;               // window radius
+constexpr int SP = ST + 2 * SR;     // patch edge (26)
+
+struct Window {
+    float g[2 * SR + 1];
+};
+
+__device__ __forceinline__ float patch_at(const float* img, int H, int W, int y, int x) {
+    return (y >= 0 && y < H && x >= 0 && x < W) ? img[(int64_t)y * W + x] : 0.f;
+}
+
+__global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__ img,
+                                                       const float* __restrict__ tgt, int H, int W,
+                                                       Window win, float lambda, float inv_n,
+                                                       float* abc, float* loss) {
+    __shared__ float sx[SP][SP], sy[SP][SP];
+    __shared__ float h[5][SP][ST];
+    __shared__ float red[2][4];
+    const int c = blockIdx.z;
+    const int64_t plane = (int64_t)H * W;
+    const float* X = img + c * plane;
+    const float* Y = tgt + c * plane;
+    const int x0 = blockIdx.x * ST - SR, y0 = blockIdx.y * ST - SR;
+    const int t = threadIdx.x;
+    for (int i = t; i < SP * SP; i += 256) {
+        const int r = i / SP, q = i % SP;
+        sx[r][q] = patch_at(X, H, W, y0 + r, x0 + q);
+        sy[r][q] = patch_at(Y, H, W, y0 + r, x0 + q);
+    }
+    __syncthreads();
+    for (int i = t; i < SP * ST; i += 256) {
+        const int r = i / ST, q = i % ST;
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+#pragma unroll
+        for (int k = 0; k <= 2 * SR; ++k) {
+            const float a = sx[r][q + k], b = sy[r][q + k], w = win.g[k];
+            m0 = fmaf(w, a, m0);
+            m1 = fmaf(w, b, m1);
+            m2 = fmaf(w, a * a, m2);
+            m3 = fmaf(w, b * b, m3);
+            m4 = fmaf(w, a * b, m4);
+        }
+        h[0][r][q] = m0;
+        h[1][r][q] = m1;
+        h[2][r][q] = m2;
+        h[3][r][q] = m3;
+        h[4][r][q] = m4;
+    }
+    __syncthreads();
+    const int r = t / ST, q = t % ST;
+    float mu = 0.f, nu = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+#pragma unroll
+    for (int k = 0; k <= 2 * SR; ++k) {
+        const float w = win.g[k];
+        mu = fmaf(w, h[0][r + k][q], mu);
+        nu = fmaf(w, h[1][r + k][q], nu);
+        exx = fmaf(w, h[2][r + k][q], exx);
+        eyy = fmaf(w, h[3][r + k][q], eyy);
+        exy = fmaf(w, h[4][r + k][q], exy);
+    }
+    const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
+    const float A = fmaf(2.f * mu, nu, C1);
+    const float B = fmaf(2.f, exy - mu * nu, C2);
+    const float Cc = fmaf(mu, mu, fmaf(nu, nu, C1));
+    const float D = (exx - mu * mu) + (eyy - nu * nu) + C2;
+    const float S = (A * B) / (Cc * D);
+    const int py = blockIdx.y * ST + r, px = blockIdx.x * ST + q;
+    const bool in = py < H && px < W;
+    float s_sum = 0.f, l1_sum = 0.f;
+    if (in) {
+        const int64_t o = c * plane + (int64_t)py * W + px;
+        // dS/dmu, dS/dExx, dS/dExy
+        const int64_t map = (int64_t)gridDim.z * plane;   // maps a, b, c one after the other
+        abc[o] = S * (2.f * nu / A - 2.f * nu / B - 2.f * mu / Cc + 2.f * mu / D);
+        abc[map + o] = -S / D;
+        abc[2 * map + o] = 2.f * S / B;
+        s_sum = S;
+        l1_sum = fabsf(sx[r + SR][q + SR] - sy[r + SR][q + SR]);
+    }
+    // loss += inv_n ((1 - lambda) sum |I - T| + lambda sum (1 - S)) over this tile
+    s_sum = wave_sum_lane63(s_sum);
+    l1_sum = wave_sum_lane63(l1_sum);
+    const int lane = t & 63, w = t >> 6;
+    if (lane == 63) {
+        red[0][w] = s_sum;
+        red[1][w] = l1_sum;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const float ssum = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        const float lsum = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        const int nin = (min(ST, H - (int)blockIdx.y * ST)) * (min(ST, W - (int)blockIdx.x * ST));
+        atomicAdd(loss, inv_n * ((1.f - lambda) * lsum + lambda * ((float)nin - ssum)));
+    }
+}
+
+__global__ void __launch_bounds__(256) ssim_bwd_kernel(const float* __restrict__ img,
+                                                       const float* __restrict__ tgt, int H, int W,
+                                                       Window win, float lambda, float inv_n,
+                                                       const float* __restrict__ abc,
+                                                       float* __restrict__ grad) {
+    __shared__ float sa[3][SP][SP];
+    __shared__ float h[3][SP][ST];
+    const int c = blockIdx.z;
+    const int64_t plane = (int64_t)H * W;
+    const int x0 = blockIdx.x * ST - SR, y0 = blockIdx.y * ST - SR;
+    const int t = threadIdx.x;
+    for (int i = t; i < SP * SP; i += 256) {
+        const int r = i / SP, q = i % SP;
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            sa[m][r][q] = patch_at(abc + ((int64_t)m * gridDim.z + c) * plane, H, W, y0 + r, x0 + q);
+    }
+    __syncthreads();
+    for (int i = t; i < SP * ST; i += 256) {
+        const int r = i / ST, q = i % ST;
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+        for (int k = 0; k <= 2 * SR; ++k) {
+            const float w = win.g[k];
+            m0 = fmaf(w, sa[0][r][q + k], m0);
+            m1 = fmaf(w, sa[1][r][q + k], m1);
+            m2 = fmaf(w, sa[2][r][q + k], m2);
+        }
+        h[0][r][q] = m0;
+        h[1][r][q] = m1;
+        h[2][r][q] = m2;
+    }
+    __syncthreads();
+    const int r = t / ST, q = t % ST;
+    const int py = blockIdx.y * ST + r, px = blockIdx.x * ST + q;
+    if (py >= H || px >= W) return;
+    float ga = 0.f, gb = 0.f, gc = 0.f;
+#pragma unroll
+    for (int k = 0; k <= 2 * SR; ++k) {
+        const float w = win.g[k];
+        ga = fmaf(w, h[0][r + k][q], ga);
+        gb = fmaf(w, h[1][r + k][q], gb);
+        gc = fmaf(w, h[2][r + k][q], gc);
+    }
+    const int64_t o = c * plane + (int64_t)py * W + px;
+    const float I = img[o], Tt = tgt[o];
+    const float dssim = fmaf(2.f * I, gb, ga) + Tt * gc;
+    const float sgn = I > Tt ? 1.f : (I < Tt ? -1.f : 0.f);
+    grad[o] = inv_n * ((1.f - lambda) * sgn - lambda * dssim);
+}
+
+}  // namespace
+
+extern "C" gs_status gs_ssim_workspace_size(int32_t channels, int32_t height, int32_t width,
+                                            uint64_t* bytes) {
+    if (channels <= 0 || height <= 0 || width <= 0 || !bytes)
+        return gs_fail(GS_ERR_INVALID, "bad image size");
+    *bytes = 3ull * 4ull * (uint64_t)channels * (uint64_t)height * (uint64_t)width;
+    return GS_OK;
+}
+
+extern "C" gs_status gs_ssim_loss_grad(const float* image, const float* target, int32_t channels,
+                                       int32_t height, int32_t width, float lambda, float* loss,
+                                       float* dL_dimage, void* workspace, uint64_t workspace_bytes,
+                                       void* stream) {
+    uint64_t need = 0;
+    GS_TRY(gs_ssim_workspace_size(channels, height, width, &need));
+    if (height > 16384 || width > 16384 || channels > 64)
+        return gs_fail(GS_ERR_INVALID, "image larger than 64 x 16384 x 16384");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return gs_fail(GS_ERR_INVALID, "lambda must be in [0, 1]");
+    if (!image || !target || !loss || !dL_dimage || !workspace)
+        return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (workspace_bytes < need) return gs_fail(GS_ERR_INVALID, "workspace too small");
+    Window win;
+    double sum = 0.0, g[2 * SR + 1];
+    for (int k = 0; k <= 2 * SR; ++k) {
+        g[k] = exp(-(double)((k - SR) * (k - SR)) / (2.0 * 1.5 * 1.5));
+        sum += g[k];
+    }
+    for (int k = 0; k <= 2 * SR; ++k) win.g[k] = (float)(g[k] / sum);
+    const float inv_n = (float)(1.0 / ((double)channels * height * width));
+    dim3 grid((unsigned)((width + ST - 1) / ST), (unsigned)((height + ST - 1) / ST), (unsigned)channels);
+    hipStream_t s = (hipStream_t)stream;
+    float* abc = (float*)workspace;
+    ssim_fwd_kernel<<<grid, 256, 0, s>>>(image, target, height, width, win, lambda, inv_n, abc, loss);
+    GS_TRY(gs_check_launch("ssim_fwd"));
+    ssim_bwd_kernel<<<grid, 256, 0, s>>>(image, target, height, width, win, lambda, inv_n, abc,
+                                         dL_dimage);
+    return gs_check_launch("ssim_bwd");
+}

@@ -101,6 +101,8 @@ _SIGS = {
     "gs_densify_apply": [_P, _P, _I64, _I64, ctypes.POINTER(Attr), _I32, _P, _P, _P, _U64, _U64,
                          _P],
     "gs_split_normals": [_P, _P, _I64, _U64, _U64, _P, _P, _P],
+    "gs_ssim_workspace_size": [_I32, _I32, _I32, ctypes.POINTER(_U64)],
+    "gs_ssim_loss_grad": [_P, _P, _I32, _I32, _I32, ctypes.c_float, _P, _P, _P, _U64, _P],
     "gs_adam_step": [ctypes.POINTER(AdamParam), _I32, _I64, _P, _I32, ctypes.c_float,
                      ctypes.c_float, ctypes.c_float, _I64, _P],
     "gs_radix_select_workspace_size": [_I64, ctypes.POINTER(_U64)],
@@ -391,6 +393,22 @@ def adaptive_prune_threshold(logits, p=0.03, tau_u=0.05, stream=None):
     _check(lib().gs_adaptive_prune_threshold(_ptr(logits), n, k, upper, _ptr(thr), _ptr(ws),
                                              int(nb.value), _stream(stream)))
     return thr, k
+
+
+def ssim_loss_grad(image, target, lam=0.2, loss=None, grad=None, workspace=None, stream=None):
+    """(1 - lam) L1 + lam (1 - SSIM) of one [C, H, W] image and its gradient."""
+    C, H, W = image.shape
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=image.device)
+    if grad is None:
+        grad = torch.empty_like(image)
+    nb = ctypes.c_uint64()
+    _check(lib().gs_ssim_workspace_size(C, H, W, ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=image.device)
+    _check(lib().gs_ssim_loss_grad(_ptr(image), _ptr(target), C, H, W, float(lam), _ptr(loss),
+                                   _ptr(grad), _ptr(workspace), int(nb.value), _stream(stream)))
+    return loss, grad
 
 
 def adam_step(entries, n, step, tiles_touched=None, n_views=1, beta1=0.9, beta2=0.999, eps=1e-15,
