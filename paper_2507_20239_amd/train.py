@@ -1,0 +1,154 @@
+"""Training driver of the paper's method on one GPU, built from the library's
+calls: per iteration the coarse-to-fine schedule picks the resolution, one
+view is rendered and differentiated (projection, binning, compositing, loss of
+Eq. 3, compositing adjoint, projection adjoint with the densification
+statistic), and sparse Adam updates the rendered Gaussians; inside the
+densification window, every `interval` iterations the global-to-local policy
+selects split and clone candidates (clones suppressed in the global phase),
+the adaptive opacity threshold selects the pruned ones, and the compaction
+rebuilds parameters and optimiser state; opacities are reset periodically
+(Methodology; Preliminary; Experiments, implementation details).
+
+Every numerical step runs in libgsmi.so; this module keeps the tensors and
+the iteration logic.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import gsmi, schedule
+
+PARAMS = gsmi.PARAM_NAMES                       # means, log_scales, quats, opacity_logits, sh
+ROWS_POLICY = {"means": gsmi.ATTR_MEAN, "log_scales": gsmi.ATTR_LOGSCALE, "quats": gsmi.ATTR_COPY,
+               "opacity_logits": gsmi.ATTR_COPY, "sh": gsmi.ATTR_COPY}
+
+
+class Trainer:
+    def __init__(self, params: dict, sh_degree: int, cameras, targets, policy, extent: float,
+                 lrs=None, lam: float = 0.2, seed: int = 0, device="cuda", capacity=None):
+        self.dev = torch.device(device)
+        self.p = {k: params[k].to(self.dev).contiguous().clone() for k in PARAMS}
+        self.sh_degree = sh_degree
+        self.cameras = list(cameras)
+        self.targets = [torch.as_tensor(t, dtype=torch.float32).to(self.dev) for t in targets]
+        self.policy = policy
+        self.extent = extent
+        self.lam = lam
+        self.lrs = dict(log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3)
+        if lrs:
+            self.lrs.update(lrs)
+        self.rng = np.random.default_rng(seed)
+        self.seed = seed
+        self.capacity = capacity
+        self.opts = gsmi.raster_opts()
+        self._reset_state()
+        self._frames = {}
+        self._targets = {}
+        self.history = []          # (iteration, loss, n, resolution)
+        self.densify_log = []      # (iteration, n_in, n_out, clones, splits, pruned, allow_clone)
+
+    @property
+    def n(self) -> int:
+        return int(self.p["means"].shape[-1])
+
+    def _reset_state(self):
+        self.m = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.accum = torch.zeros(self.n, device=self.dev)
+        self.denom = torch.zeros(self.n, device=self.dev)
+        self.grads = {k: torch.empty_like(v) for k, v in self.p.items()}
+        self.t = 0
+
+    def _frame(self, cam):
+        key = (self.n, cam.width, cam.height)
+        f = self._frames.get(key)
+        if f is None:
+            cap = self.capacity or max(1 << 20, 64 * ((cam.width + 15) // 16) * ((cam.height + 15) // 16))
+            f = gsmi.Frame(self.n, [(cam.width, cam.height)], cap, self.dev)
+            self._frames = {k: v for k, v in self._frames.items() if k[0] == self.n}
+            self._frames[key] = f
+        return f
+
+    def _target(self, view: int, r: int):
+        key = (view, r)
+        t = self._targets.get(key)
+        if t is None:
+            t = schedule.downscale(self.targets[view], r).contiguous()
+            self._targets[key] = t
+        return t
+
+    def step(self, it: int) -> float:
+        r = self.policy.schedule.resolution(it)
+        view = int(self.rng.integers(len(self.cameras)))
+        cam = self.cameras[view].scaled(r)
+        target = self._target(view, r)
+        frame = self._frame(cam)
+        cams_dev = gsmi.cameras_to_device([cam], self.dev)
+        while True:
+            frame.project(self.p, self.sh_degree, cams_dev, self.opts)
+            image = frame.render(self.opts)
+            nv, ni, ovf = frame.status(raise_on_overflow=False)
+            if not ovf:
+                break
+            self._frames.pop((self.n, cam.width, cam.height), None)
+            self.capacity = max(2 * frame.cap, ni)
+            frame = self._frame(cam)
+        loss, dL = gsmi.ssim_loss_grad(image.view(3, cam.height, cam.width), target, self.lam)
+        frame.render_backward(self.opts, dL.reshape(-1))
+        frame.project_backward(self.p, self.sh_degree, cams_dev, self.opts, self.grads, self.accum,
+                               self.denom)
+        self.t += 1
+        lrs = dict(self.lrs, means=self.policy.position_lr(it, self.extent))
+        gsmi.adam_step([(self.p[k], self.grads[k], self.m[k], self.v[k], lrs[k]) for k in PARAMS],
+                       self.n, self.t, tiles_touched=frame.buffer(gsmi.BUF_TILES_TOUCHED))
+        value = float(loss)
+        self.history.append((it, value, self.n, r))
+        if self.policy.densify_now(it):
+            self.densify(it)
+        if self.policy.opacity_reset_now(it):
+            self.reset_opacity()
+        return value
+
+    def densify(self, it: int):
+        g, ls_thr, lo_upper = self.policy.thresholds(self.extent)
+        allow_clone = self.policy.allow_clone(it)
+        # adaptive opacity threshold tau = min(alpha_sorted[floor(N p)], tau_u), in logit space
+        thr, _ = gsmi.adaptive_prune_threshold(self.p["opacity_logits"], p=self.policy.prune_ratio,
+                                               tau_u=self.policy.prune_upper)
+        split, clone, prune = gsmi.densify_select(self.accum, self.denom, self.p["log_scales"],
+                                                  self.p["opacity_logits"], g, ls_thr,
+                                                  float(thr.item()), allow_clone)
+        src, kind, n_out = gsmi.densify_plan(split, clone, prune)
+        n_in = self.n
+        if n_out == 0:
+            return
+        attrs, names = [], []
+        for k in PARAMS:
+            rows = self.p[k].numel() // n_in
+            attrs.append((self.p[k].reshape(rows, n_in), rows, ROWS_POLICY[k]))
+            names.append(("p", k))
+            for st in ("m", "v"):
+                attrs.append((getattr(self, st)[k].reshape(rows, n_in), rows, gsmi.ATTR_ZERO_NEW))
+                names.append((st, k))
+        outs = gsmi.densify_apply(src, kind, n_in, attrs, self.p["means"], self.p["log_scales"],
+                                  self.p["quats"], self.seed, it)
+        shapes = {k: self.p[k].shape[:-1] for k in PARAMS}
+        for (st, k), o in zip(names, outs):
+            getattr(self, st)[k] = o.reshape(*shapes[k], n_out).contiguous()
+        self.accum = torch.zeros(n_out, device=self.dev)
+        self.denom = torch.zeros(n_out, device=self.dev)
+        self.grads = {k: torch.empty_like(v) for k, v in self.p.items()}
+        kinds = torch.bincount(kind.to(torch.int64), minlength=4).tolist()
+        self.densify_log.append((it, n_in, n_out, kinds[gsmi.KIND_CLONE], kinds[gsmi.KIND_SPLIT0],
+                                 int(prune.sum()), allow_clone))
+
+    def reset_opacity(self, ceiling: float = 0.01):
+        """Opacities above the ceiling are set to it (logit space); their
+        moments restart from zero."""
+        lim = math.log(ceiling / (1.0 - ceiling))
+        self.p["opacity_logits"].clamp_(max=lim)
+        self.m["opacity_logits"].zero_()
+        self.v["opacity_logits"].zero_()
