@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="minimal run for a profiler: metric workload only, no CPU leg")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the densification (3M), D-SSIM loss and sparse Adam timings")
     return ap.parse_args()
 
 
@@ -215,6 +217,92 @@ def cpu_baseline(sc, dL_img, seconds):
             "sample_seconds": round(t_proj + t_pbwd + t_fwd + t_bwd, 2)}
 
 
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def extras(torch, gsmi, synth, st, params, sc, dev, K, W):
+    """Per-call times of the steps around the metric step: Eq. 3's loss with
+    its D-SSIM term on the 1600x1040 image, the sparse Adam step over the 1M
+    Gaussians (rendered ones updated), and one densification of the
+    3,000,000-Gaussian workload (statistic over 100 views, selection,
+    adaptive opacity threshold, compaction map, gather of parameters and
+    Adam moments)."""
+    out = {}
+    img = st.images.view(3, 1040, 1600)
+    tgt = st.targets.view(3, 1040, 1600)
+    loss = torch.zeros(1, device=dev)
+    grad = torch.empty_like(img)
+    ws = torch.empty(3 * 4 * img.numel() + 4 * 3 * 6500, dtype=torch.uint8, device=dev)
+    out["l1_dssim_loss_grad_ms"] = round(timed(
+        torch, lambda: gsmi.ssim_loss_grad(img, tgt, 0.2, loss, grad, ws), K, W), 4)
+    mom = {k: (torch.zeros_like(params[k]), torch.zeros_like(params[k])) for k in gsmi.PARAM_NAMES}
+    pcopy = {k: params[k].clone() for k in gsmi.PARAM_NAMES}
+    tt = st.frame.buffer(gsmi.BUF_TILES_TOUCHED)
+    entries = [(pcopy[k], st.grads[k], mom[k][0], mom[k][1], 1e-3) for k in gsmi.PARAM_NAMES]
+    cnt = [0]
+
+    def adam():
+        cnt[0] += 1
+        gsmi.adam_step(entries, sc.n, cnt[0], tiles_touched=tt)
+
+    out["sparse_adam_ms"] = round(timed(torch, adam, K, W), 4)
+    out["rendered_gaussians"] = int((tt > 0).sum().item())
+    del mom, pcopy, entries
+
+    log("generating the 3M-Gaussian densification workload (100 views)")
+    d = synth.densify_workload()
+    n = d.means.shape[1]
+    g = torch.from_numpy(d.dmean2d).to(dev)
+    vis = torch.from_numpy(d.visible).to(dev)
+    P = {"means": torch.from_numpy(d.means).to(dev), "log_scales": torch.from_numpy(d.log_scales).to(dev),
+         "quats": torch.from_numpy(d.quats).to(dev),
+         "opacity_logits": torch.from_numpy(d.opacity_logits).to(dev),
+         "sh": torch.rand(48, n, device=dev)}
+    acc = torch.zeros(n, device=dev)
+    den = torch.zeros(n, device=dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    import math
+    tg, tls, tlo = 2e-4, math.log(0.01 * d.extent), math.log(0.005 / 0.995)
+    e[0].record()
+    gsmi.accumulate_densify_stats(g, vis, d.view_wh, acc, den)
+    e[1].record()
+    s_, c_, p_ = gsmi.densify_select(acc, den, P["log_scales"], P["opacity_logits"], tg, tls, tlo, True)
+    e[2].record()
+    gsmi.adaptive_prune_threshold(P["opacity_logits"], 0.03, 0.05)
+    e[3].record()
+    src, kind, m = gsmi.densify_plan(s_, c_, p_)           # reads n_out (synchronises)
+    e[4].record()
+    pol = {"means": gsmi.ATTR_MEAN, "log_scales": gsmi.ATTR_LOGSCALE}
+    attrs = []
+    for k in gsmi.PARAM_NAMES:
+        rows = P[k].numel() // n
+        attrs.append((P[k].reshape(rows, n), rows, pol.get(k, gsmi.ATTR_COPY)))
+        attrs.append((torch.zeros(rows, n, device=dev), rows, gsmi.ATTR_ZERO_NEW))
+        attrs.append((torch.zeros(rows, n, device=dev), rows, gsmi.ATTR_ZERO_NEW))
+    e[5].record()
+    gsmi.densify_apply(src, kind, n, attrs, P["means"], P["log_scales"], P["quats"], 0x5EED, 0)
+    e[6].record()
+    torch.cuda.synchronize()
+    out["densify_3m"] = {
+        "gaussians_in": n, "gaussians_out": m, "views": int(d.dmean2d.shape[0]),
+        "stats_100_views_ms": round(e[0].elapsed_time(e[1]), 4),
+        "select_ms": round(e[1].elapsed_time(e[2]), 4),
+        "adaptive_threshold_ms": round(e[2].elapsed_time(e[3]), 4),
+        "plan_ms_incl_readback": round(e[3].elapsed_time(e[4]), 4),
+        "apply_params_and_moments_ms": round(e[5].elapsed_time(e[6]), 4)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -335,6 +423,10 @@ def main():
             "speedup": round(best_plain / ms_b, 3), "tuned": best}
         log("batched %.3f ms, plain %.3f ms (graph) %.3f ms (eager)" % (ms_b, ms_p, ms_p_eager))
         del plain, bst
+
+    # ---------------- the other steps of an iteration and of a densification ----------------
+    if not args.no_extras and not args.profile:
+        result["extras"] = extras(torch, gsmi, synth, st, params, sc, dev, K, W)
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
     if not args.no_cpu and not args.profile:

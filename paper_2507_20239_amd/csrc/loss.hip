@@ -8,10 +8,11 @@
 // where a = dS/dmu, b = dS/dExx, c = dS/dExy are maps over the pixels p
 // (G is symmetric, so correlating with it is convolving with it).
 //
-// Two launches per image: the forward computes S and (a, b, c) for a 16x16
+// Three launches per image: the forward computes S and (a, b, c) for a 16x16
 // tile per workgroup from a 26x26 LDS patch (separable: a horizontal pass to
 // 26x16 partial sums, then a vertical one); the backward filters (a, b, c) the
-// same way and combines them with I and T at each pixel.  HBM-bound: about
+// same way and combines them with I and T at each pixel; a one-workgroup
+// launch sums the per-tile losses in a fixed order.  HBM-bound: about
 // 44 B per channel-pixel over the two launches.
 #include "gs_internal.h"
 
@@ -32,7 +33,7 @@ __device__ __forceinline__ float patch_at(const float* img, int H, int W, int y,
 __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__ img,
                                                        const float* __restrict__ tgt, int H, int W,
                                                        Window win, float lambda, float inv_n,
-                                                       float* abc, float* loss) {
+                                                       float* abc, float* partial) {
     __shared__ float sx[SP][SP], sy[SP][SP];
     __shared__ float h[5][SP][ST];
     __shared__ float red[2][4];
@@ -110,7 +111,25 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__
         const float ssum = red[0][0] + red[0][1] + red[0][2] + red[0][3];
         const float lsum = red[1][0] + red[1][1] + red[1][2] + red[1][3];
         const int nin = (min(ST, H - (int)blockIdx.y * ST)) * (min(ST, W - (int)blockIdx.x * ST));
-        atomicAdd(loss, inv_n * ((1.f - lambda) * lsum + lambda * ((float)nin - ssum)));
+        const u32 b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partial[b] = inv_n * ((1.f - lambda) * lsum + lambda * ((float)nin - ssum));
+    }
+}
+
+// loss[0] += the sum of the per-tile partial losses, in a fixed order (one
+// workgroup; thousands of same-address atomics would serialise).
+__global__ void __launch_bounds__(1024) loss_sum_kernel(const float* __restrict__ partial, u32 count,
+                                                       float* loss) {
+    __shared__ float red[16];
+    float s = 0.f;
+    for (u32 i = threadIdx.x; i < count; i += 1024) s += partial[i];
+    s = wave_sum_lane63(s);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int w = 0; w < 16; ++w) t += red[w];
+        loss[0] += t;
     }
 }
 
@@ -171,7 +190,10 @@ extern "C" gs_status gs_ssim_workspace_size(int32_t channels, int32_t height, in
                                             uint64_t* bytes) {
     if (channels <= 0 || height <= 0 || width <= 0 || !bytes)
         return gs_fail(GS_ERR_INVALID, "bad image size");
-    *bytes = 3ull * 4ull * (uint64_t)channels * (uint64_t)height * (uint64_t)width;
+    // the maps a, b, c and one partial loss per 16 x 16 tile and channel
+    const uint64_t tiles = (uint64_t)((width + ST - 1) / ST) * (uint64_t)((height + ST - 1) / ST);
+    *bytes = 3ull * 4ull * (uint64_t)channels * (uint64_t)height * (uint64_t)width +
+             4ull * tiles * (uint64_t)channels;
     return GS_OK;
 }
 
@@ -198,8 +220,12 @@ extern "C" gs_status gs_ssim_loss_grad(const float* image, const float* target, 
     dim3 grid((unsigned)((width + ST - 1) / ST), (unsigned)((height + ST - 1) / ST), (unsigned)channels);
     hipStream_t s = (hipStream_t)stream;
     float* abc = (float*)workspace;
-    ssim_fwd_kernel<<<grid, 256, 0, s>>>(image, target, height, width, win, lambda, inv_n, abc, loss);
+    float* partial = abc + 3ull * (uint64_t)channels * (uint64_t)height * (uint64_t)width;
+    ssim_fwd_kernel<<<grid, 256, 0, s>>>(image, target, height, width, win, lambda, inv_n, abc,
+                                         partial);
     GS_TRY(gs_check_launch("ssim_fwd"));
+    loss_sum_kernel<<<1, 1024, 0, s>>>(partial, grid.x * grid.y * grid.z, loss);
+    GS_TRY(gs_check_launch("loss_sum"));
     ssim_bwd_kernel<<<grid, 256, 0, s>>>(image, target, height, width, win, lambda, inv_n, abc,
                                          dL_dimage);
     return gs_check_launch("ssim_bwd");
