@@ -368,7 +368,7 @@ def main():
         del src, dst
 
     result = {
-        "metric": "ms per fwd+bwd iter at 1M Gaussians 1600x1040; batched vs plain speedup",
+        "metric": "ms per fwd+bwd iter at 1M Gaussians 1600\u00d71040; batched vs plain speedup",
         "value": round(ms_graph, 4), "unit": "ms", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": round(ms_graph, 4), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
