@@ -19,15 +19,22 @@
 
 namespace {
 
-__global__ void compact_kernel(const u32* tiles_touched, const u32* offs, const u32* depth_key,
-                               u32* keys, u32* vals, int64_t E) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E || tiles_touched[e] == 0) return;
-    const u32 j = offs[e];
-    if (j >= (u64)E) return;   // never taken: offsets are a scan of 0/1 flags
-    keys[j] = depth_key[e];
-    vals[j] = (u32)e;
-}
+// Scan epilogue of the visibility flags: entry i with flag 1 goes to slot
+// ex of the compacted (depth key, entry) arrays; the total is the number of
+// visible entries.
+struct CompactEpi {
+    const u32* depth_key;
+    u32* keys;
+    u32* vals;
+    u32* n_visible;
+    __device__ void item(u32 i, u32 flag, u32 ex) const {
+        if (flag) {
+            keys[ex] = depth_key[i];
+            vals[ex] = i;
+        }
+    }
+    __device__ void finish(u32 t) const { *n_visible = t; }
+};
 
 // Instance emission, balanced per 256 instances.  Pass 1 records, for every
 // chunk of 256 consecutive instance slots, the depth-sorted entry whose tiles
@@ -40,25 +47,28 @@ __global__ void compact_kernel(const u32* tiles_touched, const u32* offs, const 
 // instances rather than on entries is what keeps the workgroups even.
 constexpr u32 EMIT_CHUNK = 256;
 
-// Also publishes counters[5] = min(instances, capacity) (the length the tile
-// sort works on) and the overflow flag counters[2].
-__global__ void chunk_start_kernel(const u32* vals, const u32* offs, const u32* tiles_touched,
-                                   u32* counters, u32 cap, u32* chunk_start, int64_t E) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const u32 total = counters[1];
-    const u32 kept = total < cap ? total : cap;
-    if (j == 0) {
-        counters[5] = kept;
-        counters[2] = total > cap ? 1u : 0u;
+// Scan epilogue of the tile counts in depth order: the instance offset of
+// visible entry j, and for every chunk of 256 instance slots that starts
+// inside its range the entry j itself (chunk_start, below the capacity); the
+// last workgroup publishes the instance total, the kept length min(total,
+// capacity) the tile sort works on, and the overflow flag.
+struct ChunkEpi {
+    u32* inst_off;
+    u32* chunk_start;
+    u32* counters;
+    u32 cap;
+    __device__ void item(u32 j, u32 tt, u32 off) const {
+        inst_off[j] = off;
+        const u64 hi = (u64)off + tt < cap ? (u64)off + tt : cap;
+        for (u64 c = ((u64)off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK < hi; ++c)
+            chunk_start[c] = j;
     }
-    if (j >= E || j >= (int64_t)counters[0]) return;
-    const u32 e = vals[j];
-    const u32 tt = e < (u64)E ? tiles_touched[e] : 0u;
-    const u32 off = offs[j];
-    if (tt == 0 || off >= kept) return;
-    const u32 last = (off + tt - 1) < kept ? off + tt - 1 : kept - 1;
-    for (u32 c = (off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK <= last; ++c) chunk_start[c] = (u32)j;
-}
+    __device__ void finish(u32 t) const {
+        counters[1] = t;
+        counters[5] = t < cap ? t : cap;
+        counters[2] = t > cap ? 1u : 0u;
+    }
+};
 
 __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u32* offs,
                                                         const uint2* rect, const float4* splat,
@@ -164,23 +174,24 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     const int64_t E = f->E;
     u32* cnt = f->counters;
     if (E > 0) {
-        // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection.
-        // The scan goes to inst_off (free until the offsets scan below), leaving the
-        // projection's outputs intact: rendering again repeats the same work.
-        GS_TRY(gs_scan_exclusive(f->flags, f->inst_off, nullptr, (u32)E, cnt + 0, f->scan_part, s));
-        compact_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(f->tiles_touched, f->inst_off, f->depth_key,
-                                                          f->vkeys[0], f->vvals[0], E);
+        // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection;
+        // the compaction reads them without modifying them, so rendering the same
+        // projection again repeats the same work.
+        GS_TRY(gs_scan_reduce(f->flags, nullptr, nullptr, (u32)E, f->scan_part, s));
+        const CompactEpi ce{f->depth_key, f->vkeys[0], f->vvals[0], cnt + 0};
+        scan_down_kernel<CompactEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->flags, nullptr, nullptr,
+                                                                      (u32)E, f->scan_part, ce);
         GS_TRY(gs_check_launch("compact"));
         // depths are positive, so the sign bit is zero: 31 key bits
         GS_TRY(gs_radix_sort(f->vkeys, f->vvals, cnt + 0, 0, E, 31, f->sort_scratch, cnt + 6,
                              &f->vsorted, s));
         const u32* sv = f->vvals[f->vsorted];
-        // instance offsets: exclusive scan of tiles_touched in depth order
-        GS_TRY(gs_scan_exclusive(f->tiles_touched, f->inst_off, cnt + 0, 0, cnt + 1, f->scan_part,
-                                 s, sv));
-        chunk_start_kernel<<<blocks_for(E), GS_BLOCK, 0, s>>>(sv, f->inst_off, f->tiles_touched,
-                                                              cnt, (u32)f->cap, f->chunk_start, E);
-        GS_TRY(gs_check_launch("chunk_start"));
+        // instance offsets: exclusive scan of tiles_touched in depth order, with chunk starts
+        GS_TRY(gs_scan_reduce(f->tiles_touched, sv, cnt + 0, 0, f->scan_part, s));
+        const ChunkEpi he{f->inst_off, f->chunk_start, cnt, (u32)f->cap};
+        scan_down_kernel<ChunkEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, sv, cnt + 0,
+                                                                    0, f->scan_part, he);
+        GS_TRY(gs_check_launch("instance_offsets"));
         emit_kernel<<<2048, GS_BLOCK, 0, s>>>(sv, f->inst_off, f->rect, f->splat, f->d_views, f->n, cnt + 0,
                                               cnt + 5, f->chunk_start, f->ikeys[0], f->ivals[0], E,
                                               (u32)f->T);

@@ -96,6 +96,90 @@ gs_status gs_check_launch(const char* what);
         if (s_ != GS_OK) return s_;      \
     } while (0)
 
+
+// ------------------------------------------------------------------------
+// Two-launch exclusive scan.  The first launch (gs_scan_reduce) sums each of
+// GS_SCAN_PARTS partitions; every workgroup of the second adds up the partial
+// sums before its own partition (at most 1024 values, read by 256 threads),
+// scans its partition and hands each (index, value, exclusive prefix) to an
+// epilogue, which stores the prefix or does more with it (stream compaction,
+// chunk starts); the last workgroup hands the grand total to epi.finish.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ u32 dev_len(const u32* n_dev, u32 n_host) {
+    return n_dev ? *n_dev : n_host;
+}
+
+__device__ __forceinline__ void chunk_of(u32 n, u32 parts, u32 b, u32& beg, u32& end) {
+    u32 chunk = (n + parts - 1) / parts;
+    chunk = (chunk + 63u) & ~63u;
+    const u64 b0 = (u64)b * chunk;
+    beg = b0 < n ? (u32)b0 : n;
+    const u64 e0 = (u64)beg + chunk;
+    end = e0 < n ? (u32)e0 : n;
+}
+
+// Exclusive scan of one value per thread over a 256-thread workgroup.
+__device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* lds4, u32& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u32 x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        u32 y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds4[w] = x;
+    __syncthreads();
+    u32 wbase = 0;
+    for (int j = 0; j < w; ++j) wbase += lds4[j];
+    total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+    __syncthreads();
+    return wbase + x - v;
+}
+
+__device__ __forceinline__ u32 scan_in(const u32* in, const u32* gather, u32 i) {
+    return gather ? in[gather[i]] : in[i];
+}
+
+struct ScanStore {
+    u32* out;
+    u32* total;
+    __device__ void item(u32 i, u32 v, u32 ex) const { (void)v; out[i] = ex; }
+    __device__ void finish(u32 t) const { if (total) *total = t; }
+};
+
+template <class Epi>
+__global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, const u32* gather,
+                                                             const u32* n_dev, u32 n_host,
+                                                             const u32* part, Epi epi) {
+    __shared__ u32 lds4[4];
+    u32 carry = 0;
+    for (u32 i = threadIdx.x; i < blockIdx.x; i += GS_BLOCK) carry += part[i];
+    u32 before;
+    block_exclusive_scan(carry, lds4, before);
+    carry = before;
+    u32 beg, end;
+    chunk_of(dev_len(n_dev, n_host), GS_SCAN_PARTS, blockIdx.x, beg, end);
+    for (u32 base = beg; base < end; base += GS_BLOCK * 4) {
+        u32 v[4];
+        u32 s = 0;
+        const u32 i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = (i0 + j < end) ? scan_in(in, gather, i0 + j) : 0u;
+            s += v[j];
+        }
+        u32 total;
+        u32 ex = block_exclusive_scan(s, lds4, total) + carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < end) epi.item(i0 + j, v[j], ex);
+            ex += v[j];
+        }
+        carry += total;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) epi.finish(carry);
+}
+
 // ------------------------------------------------------------------------
 // Launch helpers implemented in the .hip files
 // ------------------------------------------------------------------------
@@ -109,6 +193,9 @@ gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s);
 // values, latency-bound, against 12 us for these three launches.)
 gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
                             u32* part, hipStream_t s, const u32* gather = nullptr);
+// the first launch of a scan: one partial sum per partition into part[0..GS_SCAN_PARTS)
+gs_status gs_scan_reduce(const u32* in, const u32* gather, const u32* n_dev, u32 n_host, u32* part,
+                         hipStream_t s);
 
 // stable LSD radix sort on the low `bits` bits (8-bit digits; per pass a count
 // kernel, an exclusive scan and a scatter kernel).  Buffers k[0]/v[0] hold the

@@ -18,44 +18,9 @@ namespace {
 constexpr int RADIX_ITEMS = 8;                       // keys per lane per sub-batch
 constexpr int RADIX_SUB = GS_BLOCK * RADIX_ITEMS;    // 2048 keys per sub-batch
 
-__device__ __forceinline__ u32 dev_len(const u32* n_dev, u32 n_host) {
-    return n_dev ? *n_dev : n_host;
-}
-
-__device__ __forceinline__ void chunk_of(u32 n, u32 parts, u32 b, u32& beg, u32& end) {
-    u32 chunk = (n + parts - 1) / parts;
-    chunk = (chunk + 63u) & ~63u;
-    const u64 b0 = (u64)b * chunk;
-    beg = b0 < n ? (u32)b0 : n;
-    const u64 e0 = (u64)beg + chunk;
-    end = e0 < n ? (u32)e0 : n;
-}
-
-// Exclusive scan of one value per thread over a 256-thread workgroup.
-__device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* lds4, u32& total) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    u32 x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        u32 y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    if (lane == 63) lds4[w] = x;
-    __syncthreads();
-    u32 wbase = 0;
-    for (int j = 0; j < w; ++j) wbase += lds4[j];
-    total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
-    __syncthreads();
-    return wbase + x - v;
-}
-
 __global__ void fill_u32_kernel(u32* p, u32 value, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
-}
-
-__device__ __forceinline__ u32 scan_in(const u32* in, const u32* gather, u32 i) {
-    return gather ? in[gather[i]] : in[i];
 }
 
 __global__ void __launch_bounds__(GS_BLOCK) scan_reduce_kernel(const u32* in, const u32* gather,
@@ -69,57 +34,6 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_reduce_kernel(const u32* in, co
     u32 total;
     block_exclusive_scan(s, lds4, total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(GS_SCAN_PARTS) scan_parts_kernel(u32* part, u32* total) {
-    __shared__ u32 lds[GS_SCAN_PARTS / 64];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const u32 v = part[t];
-    u32 x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        u32 y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    if (lane == 63) lds[w] = x;
-    __syncthreads();
-    u32 base = 0, all = 0;
-    for (int j = 0; j < GS_SCAN_PARTS / 64; ++j) {
-        if (j < w) base += lds[j];
-        all += lds[j];
-    }
-    part[t] = base + x - v;
-    if (t == 0) {
-        part[GS_SCAN_PARTS] = all;
-        if (total) *total = all;
-    }
-}
-
-__global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, const u32* gather,
-                                                             u32* out, const u32* n_dev, u32 n_host,
-                                                             const u32* part) {
-    __shared__ u32 lds4[4];
-    u32 beg, end;
-    chunk_of(dev_len(n_dev, n_host), GS_SCAN_PARTS, blockIdx.x, beg, end);
-    u32 carry = part[blockIdx.x];
-    for (u32 base = beg; base < end; base += GS_BLOCK * 4) {
-        u32 v[4];
-        u32 s = 0;
-        const u32 i0 = base + threadIdx.x * 4;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = (i0 + j < end) ? scan_in(in, gather, i0 + j) : 0u;
-            s += v[j];
-        }
-        u32 total;
-        u32 ex = block_exclusive_scan(s, lds4, total) + carry;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (i0 + j < end) out[i0 + j] = ex;
-            ex += v[j];
-        }
-        carry += total;
-    }
 }
 
 // ---- Radix pass: per-workgroup digit counts (digit-major matrix [256][G]),
@@ -286,11 +200,18 @@ gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s) {
     return gs_check_launch("fill_u32");
 }
 
+gs_status gs_scan_reduce(const u32* in, const u32* gather, const u32* n_dev, u32 n_host, u32* part,
+                         hipStream_t s) {
+    scan_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, gather, n_dev, n_host, part);
+    return gs_check_launch("scan_reduce");
+}
+
 gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
                             u32* part, hipStream_t s, const u32* gather) {
-    scan_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, gather, n_dev, n_host, part);
-    scan_parts_kernel<<<1, GS_SCAN_PARTS, 0, s>>>(part, total);
-    scan_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, gather, out, n_dev, n_host, part);
+    GS_TRY(gs_scan_reduce(in, gather, n_dev, n_host, part, s));
+    ScanStore epi{out, total};
+    scan_down_kernel<ScanStore><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(in, gather, n_dev, n_host, part,
+                                                                   epi);
     return gs_check_launch("scan_exclusive");
 }
 
