@@ -336,9 +336,11 @@ def main():
     # dominant kernel: the compositing adjoint (one kernel per gs_render_backward call)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
+    # the renders before each timed adjoint also count the composited splats
+    copts = gsmi.raster_opts(count_composited=True)
     for i in range(K):
         st.frame.project(params, sc.sh_degree, st.cams_dev, opts)
-        st.frame.render(opts, st.images)
+        st.frame.render(copts, st.images)
         ev[i][0].record()
         st.frame.render_backward(opts, st.dL)
         ev[i][1].record()

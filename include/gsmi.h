@@ -106,8 +106,14 @@ typedef struct {
     int32_t persistent_blocks;   /* 0: one wave64 workgroup per (view, tile);  > 0: a persistent
                                     grid of this many wave64 workgroups takes (view, tile) items
                                     from a queue, heaviest tile lists first */
-    int32_t reserved[2];
+    int32_t flags;               /* GS_RASTER_* bits */
+    int32_t reserved;
 } gs_raster_opts;
+
+/* gs_raster_opts.flags: gs_render also counts, per pixel, the splats it
+ * composited into GS_BUF_N_COMPOSITED (a diagnostic; without the flag that
+ * buffer is left as it was). */
+#define GS_RASTER_COUNT_COMPOSITED 1
 
 /* ------------------------------------------------------------------------ */
 /* Frame: the device state of one rendering step for a fixed set of view     */

@@ -139,6 +139,8 @@ gs_status check_opts(const gs_raster_opts* o) {
         return gs_fail(GS_ERR_INVALID, "raster_batch must be 0, 64, 128 or 256");
     if (o->persistent_blocks < 0 || o->persistent_blocks > 65536)
         return gs_fail(GS_ERR_INVALID, "persistent_blocks must be in [0, 65536]");
+    if (o->flags & ~GS_RASTER_COUNT_COMPOSITED)
+        return gs_fail(GS_ERR_INVALID, "unknown bits in raster flags");
     if (!(o->near_plane > 0.f)) return gs_fail(GS_ERR_INVALID, "near_plane must be > 0");
     return GS_OK;
 }

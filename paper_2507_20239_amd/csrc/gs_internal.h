@@ -242,55 +242,6 @@ __device__ __forceinline__ float dpp_mov_zero(float x) {
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  Must be
 // called with all 64 lanes active.  row_shr 1/2/4/8 builds each row's
 // inclusive prefix, row_bcast15 and row_bcast31 carry it across rows.
-// Sum of nine per-lane values over the wave, transposed: afterwards lane l
-// (0 <= l < 9) of every 16-lane row holds the total of value l, lanes 9..15
-// hold 0.  Four butterfly stages inside each row halve the values a lane
-// carries (lanes whose index bit s is 0 keep the even-numbered half, the others
-// the odd half, each adding its partner's copy of what it keeps: partner =
-// lane xor 1, 2 via quad permutations, xor 4 via row rotations by 4 and 12,
-// xor 8 via a row rotation by 8), so 9 values cost 22 adds instead of the 54
-// of nine separate reductions; two row swaps (permlane32 / permlane16) then
-// add the four rows together.
-__device__ __forceinline__ float wave_reduce9(const float v[9], int lane) {
-    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
-    float s[5];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float keep = b0 ? v[2 * k + 1] : v[2 * k];
-        const float send = b0 ? v[2 * k] : v[2 * k + 1];
-        s[k] = keep + dpp_mov_zero<0xB1, 0xF>(send);       // quad_perm [1,0,3,2]: lane ^ 1
-    }
-    const float p8 = dpp_mov_zero<0xB1, 0xF>(v[8]);
-    s[4] = b0 ? 0.f : v[8] + p8;
-    float t[3];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float keep = b1 ? s[2 * k + 1] : s[2 * k];
-        const float send = b1 ? s[2 * k] : s[2 * k + 1];
-        t[k] = keep + dpp_mov_zero<0x4E, 0xF>(send);       // quad_perm [2,3,0,1]: lane ^ 2
-    }
-    const float p4 = dpp_mov_zero<0x4E, 0xF>(s[4]);
-    t[2] = b1 ? 0.f : s[4] + p4;
-    // lane ^ 4 inside a row: rotate by 4 (from lane - 4) or by 12 (from lane + 4)
-    const float keep2 = b2 ? t[1] : t[0];
-    const float send2 = b2 ? t[0] : t[1];
-    const float r4 = dpp_mov_zero<0x124, 0xF>(send2);
-    const float r12 = dpp_mov_zero<0x12C, 0xF>(send2);
-    const float u0 = keep2 + (b2 ? r4 : r12);
-    const float q12 = dpp_mov_zero<0x12C, 0xF>(t[2]);
-    const float u1 = b2 ? 0.f : t[2] + q12;
-    const float keep3 = b3 ? u1 : u0;
-    const float send3 = b3 ? u0 : u1;
-    float w = keep3 + dpp_mov_zero<0x128, 0xF>(send3);     // row rotate by 8: lane ^ 8
-    // rows: (0+2, 1+3) in both halves, then all four in every row
-    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(w), __float_as_uint(w), false,
-                                                    false);
-    w = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w), __float_as_uint(w), false,
-                                                    false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
 __device__ __forceinline__ float wave_sum_lane63(float x) {
     x += dpp_mov_zero<0x111, 0xF>(x);  // row_shr:1
     x += dpp_mov_zero<0x112, 0xF>(x);  // row_shr:2

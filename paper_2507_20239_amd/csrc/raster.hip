@@ -13,10 +13,10 @@
 // composited splat, recovering T_i = T_{i+1} / (1 - alpha_i) from the saved
 // final transmittance instead of storing per-splat state.  Each lane sums
 // the partial derivatives of its four pixels, the wave reduces the nine sums
-// with DPP row shifts and broadcasts, and one lane adds them to HBM with
-// hardware FP32 atomics: one set of atomics per (splat, tile).  Owning a whole
-// tile with one wave is what keeps both the reductions and the atomics at one
-// per (splat, tile) instead of one per (splat, wave).
+// through an LDS transpose, and nine lanes add them to HBM with one hardware
+// FP32 atomic instruction: one set of atomics per (splat, tile).  Owning a
+// whole tile with one wave is what keeps both the reductions and the atomics
+// at one per (splat, tile) instead of one per (splat, wave).
 //
 // Work items are (view, tile) pairs over every view of the frame.  With
 // persistent > 0 a fixed grid of waves takes items from an atomic queue in
@@ -60,7 +60,17 @@ __device__ __forceinline__ u32 next_item(const RasterArgs& a, u32 item, bool fir
     if (!a.queue) return first ? blockIdx.x : (u32)a.T;
     u32 t = 0;
     if (threadIdx.x == 0) t = atomicAdd(a.queue, 1u);
-    return __shfl(t, 0, 64);
+    return __builtin_amdgcn_readfirstlane(t);
+}
+
+constexpr int RED_STRIDE = 68;   // floats per row of the reduction transpose buffer
+
+// Order this wave's LDS accesses before and after the call (compiler-level:
+// a single wave's LDS operations already execute in program order).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 struct TileCoords {
@@ -82,69 +92,82 @@ __device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t) {
     return c;
 }
 
+// Stage splats [b0, b0 + cnt) of the sorted instance list in LDS; the fourth
+// component of the colour record (unused in HBM) carries the entry id.
 template <int BATCH>
 __device__ __forceinline__ void load_batch(const RasterArgs& a, u32 b0, u32 cnt, float4* sp0,
-                                           float4* sp1, float4* sp2, u32* se) {
+                                           float4* sp1, float4* sp2) {
     for (u32 j = threadIdx.x; j < cnt; j += 64) {
         u32 e = a.inst_entry[b0 + j];
         if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
         sp0[j] = a.splat[3 * (u64)e + 0];
         sp1[j] = a.splat[3 * (u64)e + 1];
-        sp2[j] = a.splat[3 * (u64)e + 2];
-        if (se) se[j] = e;
+        float4 c = a.splat[3 * (u64)e + 2];
+        c.w = __uint_as_float(e);
+        sp2[j] = c;
     }
 }
 
-template <int BATCH>
+// Some pixel of the quad still composites (T > 0).  Signed-integer order of
+// the bit patterns agrees with the float order on the sign and on positive
+// values, so one integer max decides it.
+__device__ __forceinline__ bool any_live(const float* T) {
+    const int m = max(max(__float_as_int(T[0]), __float_as_int(T[1])),
+                      max(__float_as_int(T[2]), __float_as_int(T[3])));
+    return m > 0;
+}
+
+template <int BATCH, bool COUNT>
 __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
     for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
-        const u32 t = a.order ? a.order[item] : item;
+        const u32 t = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
         const TileCoords tc = tile_coords(a, t);
+        // T < 0 marks a finished pixel, with |T| its final transmittance
+        // (pixels outside the image start finished); the sign replaces a
+        // per-pixel flag and keeps the state update at two selects.
         float pxc[PIX], pyc[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
         u32 last[PIX], ncomp[PIX];
-        bool done[PIX];
 #pragma unroll
         for (int i = 0; i < PIX; ++i) {
             const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
             pxc[i] = (float)px + 0.5f;
             pyc[i] = (float)py + 0.5f;
-            T[i] = 1.f;
+            T[i] = (px < tc.vi.width && py < tc.vi.height) ? 1.f : -1.f;
             C0[i] = C1[i] = C2[i] = 0.f;
             last[i] = 0;
             ncomp[i] = 0;
-            done[i] = !(px < tc.vi.width && py < tc.vi.height);
         }
         for (u32 b0 = tc.rg.x; b0 < tc.rg.y; b0 += BATCH) {
-            if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0) break;
+            if (__ballot(any_live(T)) == 0) break;
             const u32 cnt = min((u32)BATCH, tc.rg.y - b0);
             __syncthreads();
-            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2, nullptr);
+            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2);
             __syncthreads();
             for (u32 k = 0; k < cnt; ++k) {
                 const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
                 const u32 idx = b0 - tc.rg.x + k + 1;
                 Quad q;
                 quad_setup(p0, p1, pxc[0], pyc[0], q);
-                bool live = false;
 #pragma unroll
                 for (int i = 0; i < PIX; ++i) {
                     const float alpha = fminf(p1.w * quad_G(p1.x, q, i), GS_ALPHA_MAX);
-                    bool take = !done[i] && alpha >= GS_ALPHA_MIN;
+                    const bool hit = alpha >= GS_ALPHA_MIN;
+                    // a finished pixel has T < 0, so Tn < 0 and it never takes
                     const float Tn = T[i] * (1.f - alpha);
-                    const bool stop = take && Tn < GS_T_MIN;
-                    done[i] = done[i] || stop;
-                    take = take && !stop;
-                    const float wgt = take ? alpha * T[i] : 0.f;
+                    const bool take = hit && Tn >= GS_T_MIN;
+                    // alpha T as the drop in transmittance
+                    const float wgt = take ? T[i] - Tn : 0.f;
+                    // a hit that would drop T below the threshold finishes the pixel
+                    const float Tkeep = hit ? -fabsf(T[i]) : T[i];
+                    T[i] = take ? Tn : Tkeep;
                     C0[i] = fmaf(c.x, wgt, C0[i]);
                     C1[i] = fmaf(c.y, wgt, C1[i]);
                     C2[i] = fmaf(c.z, wgt, C2[i]);
-                    T[i] = take ? Tn : T[i];
                     last[i] = take ? idx : last[i];
-                    ncomp[i] += take ? 1u : 0u;
-                    live = live || !done[i];
+                    if (COUNT) ncomp[i] += take ? 1u : 0u;
                 }
-                if (__ballot(live) == 0) break;
+                if (__ballot(any_live(T)) == 0) break;
             }
         }
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
@@ -154,12 +177,13 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
             if (px < tc.vi.width && py < tc.vi.height) {
                 const int64_t off = (int64_t)py * tc.vi.width + px;
                 float* img = a.images + 3 * tc.vi.pix_base + off;
-                img[0] = fmaf(T[i], a.bg0, C0[i]);
-                img[hw] = fmaf(T[i], a.bg1, C1[i]);
-                img[2 * hw] = fmaf(T[i], a.bg2, C2[i]);
-                a.T_final[tc.vi.pix_base + off] = T[i];
+                const float Tf = fabsf(T[i]);
+                img[0] = fmaf(Tf, a.bg0, C0[i]);
+                img[hw] = fmaf(Tf, a.bg1, C1[i]);
+                img[2 * hw] = fmaf(Tf, a.bg2, C2[i]);
+                a.T_final[tc.vi.pix_base + off] = Tf;
                 a.n_contrib[tc.vi.pix_base + off] = last[i];
-                a.n_comp[tc.vi.pix_base + off] = ncomp[i];
+                if (COUNT) a.n_comp[tc.vi.pix_base + off] = ncomp[i];
             }
         }
     }
@@ -168,13 +192,16 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
 template <int BATCH>
 __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
-    __shared__ u32 se[BATCH];
+    // transpose buffer of the per-splat reduction: value j of lane l at red[j][l]
+    // (rows padded by 16 bytes to spread the 16-byte reads over the banks)
+    __shared__ float red[9][RED_STRIDE];
     const int lane = threadIdx.x;
-    // factor of each reduced value (lane l holds value l): fa * o + fb
-    const float fa = lane < 2 ? 1.f / GS_KAPPA : (lane == 2 || lane == 4) ? -0.5f : lane == 3 ? -1.f : 0.f;
-    const float fb = (lane >= 5 && lane < 9) ? 1.f : 0.f;
+    // lanes 4j .. 4j+3 (j < 9) sum value j; its factor is fa * o + fb
+    const int rj = lane >> 2;
+    const float fa = rj < 2 ? 1.f / GS_KAPPA : (rj == 2 || rj == 4) ? -0.5f : rj == 3 ? -1.f : 0.f;
+    const float fb = (rj >= 5 && rj < 9) ? 1.f : 0.f;
     for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
-        const u32 t = a.order ? a.order[item] : item;
+        const u32 t = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
         const TileCoords tc = tile_coords(a, t);
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
         float pxc[PIX], pyc[PIX], T[PIX], g0[PIX], g1[PIX], g2[PIX], sd[PIX];
@@ -207,7 +234,7 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
             const u32 b0 = tc.rg.x + (u32)bi * BATCH;
             const u32 cnt = min((u32)BATCH, mlast - (u32)bi * BATCH);
             __syncthreads();
-            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2, se);
+            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2);
             __syncthreads();
             for (int k = (int)cnt - 1; k >= 0; --k) {
                 const u32 rel = (u32)bi * BATCH + (u32)k;
@@ -246,37 +273,57 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                     go[i] = (use && raw <= GS_ALPHA_MAX) ? dalpha * G : 0.f;
                 }
                 if (__ballot(contrib) == 0) continue;
-                // lane moments of go over the quad: sum go (1, dx, dy, dx^2, dx dy, dy^2),
-                // factored by column (pixels 0, 2 | 1, 3) and row (0, 1 | 2, 3)
+                // lane moments of go over the quad: sums of go (1, dx, dy, dx^2, dx dy,
+                // dy^2), factored by column (pixels 0, 2 | 1, 3) and row (0, 1 | 2, 3).
+                // Every term keeps its own offsets: an expansion around one pixel
+                // would cancel when the others sit next to the splat's centre.
                 const float A0 = go[0] + go[2], A1 = go[1] + go[3];
                 const float B0 = go[0] + go[1], B1 = go[2] + go[3];
-                float gop = A0 + A1;
-                float sx = fmaf(q.dx[0], A0, q.dx[1] * A1);
-                float sy = fmaf(q.dy[0], B0, q.dy[1] * B1);
-                float sxx = fmaf(q.dx[0] * q.dx[0], A0, (q.dx[1] * q.dx[1]) * A1);
-                float syy = fmaf(q.dy[0] * q.dy[0], B0, (q.dy[1] * q.dy[1]) * B1);
-                float sxy = fmaf(q.dx[0], fmaf(go[0], q.dy[0], go[2] * q.dy[1]),
-                                 q.dx[1] * fmaf(go[1], q.dy[0], go[3] * q.dy[1]));
+                const float gop = A0 + A1;
+                const float X0 = q.dx[0] * A0, X1 = q.dx[1] * A1;
+                const float Y0 = q.dy[0] * B0, Y1 = q.dy[1] * B1;
+                const float sx = X0 + X1;
+                const float sy = Y0 + Y1;
+                const float sxx = fmaf(q.dx[0], X0, q.dx[1] * X1);
+                const float syy = fmaf(q.dy[0], Y0, q.dy[1] * Y1);
+                const float sxy = fmaf(q.dx[0], fmaf(go[0], q.dy[0], go[2] * q.dy[1]),
+                                       q.dx[1] * fmaf(go[1], q.dy[0], go[3] * q.dy[1]));
                 // With w = dL/dalpha o G:  dL/dmean = sum w Q d,
                 // dL/d(a, b, c) = -sum w (dx^2/2, dx dy, dy^2/2), dL/do = sum dL/dalpha G;
                 // Q = L L^T / kappa from the stored Cholesky factor.  Q is applied
                 // to the lane sums before the reduction (it is linear), the per-value
-                // factors of o after it, and lanes 0..8 then add the nine totals
-                // with a single 9-lane atomic instruction, which the memory system
-                // coalesces into one request per cache line.
+                // factors of o after it.
                 const float qa = p1.x * p1.x, qb = p1.x * p1.y, qc = fmaf(p1.y, p1.y, p1.z * p1.z);
-                float v[9];
-                v[0] = fmaf(qa, sx, qb * sy);
-                v[1] = fmaf(qb, sx, qc * sy);
-                v[2] = sxx;
-                v[3] = sxy;
-                v[4] = syy;
-                v[5] = gop;
-                v[6] = gr0;
-                v[7] = gr1;
-                v[8] = gr2;
-                const float val = wave_reduce9(v, lane) * fmaf(p1.w, fa, fb);
-                if (lane < 9) unsafeAtomicAdd(a.splat_grad + 9 * (u64)se[k] + lane, val);
+                // The nine lane sums go through LDS: every lane writes its row
+                // entries, lanes 4j .. 4j+3 read back a quarter of row j each (four
+                // 16-byte loads) and two quad DPP adds finish the totals, so lanes
+                // 0, 4, .., 32 hold them and add them to HBM with one atomic
+                // instruction.  The workgroup is this one wave, whose LDS accesses
+                // execute in order; the wavefront fences keep the compiler from
+                // moving the accesses across each other.
+                red[0][lane] = fmaf(qa, sx, qb * sy);
+                red[1][lane] = fmaf(qb, sx, qc * sy);
+                red[2][lane] = sxx;
+                red[3][lane] = sxy;
+                red[4][lane] = syy;
+                red[5][lane] = gop;
+                red[6][lane] = gr0;
+                red[7][lane] = gr1;
+                red[8][lane] = gr2;
+                wave_sync_lds();
+                float tot = 0.f;
+                if (rj < 9) {
+                    const float4* row = reinterpret_cast<const float4*>(&red[rj][16 * (lane & 3)]);
+                    const float4 x0 = row[0], x1 = row[1], x2 = row[2], x3 = row[3];
+                    tot = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w)) +
+                          (((x2.x + x2.y) + (x2.z + x2.w)) + ((x3.x + x3.y) + (x3.z + x3.w)));
+                }
+                wave_sync_lds();
+                tot += dpp_mov_zero<0xB1, 0xF>(tot);   // quad_perm [1,0,3,2]
+                tot += dpp_mov_zero<0x4E, 0xF>(tot);   // quad_perm [2,3,0,1]
+                if ((lane & 3) == 0 && rj < 9)
+                    unsafeAtomicAdd(a.splat_grad + 9 * (u64)__float_as_uint(c.w) + rj,
+                                    tot * fmaf(p1.w, fa, fb));
             }
         }
     }
@@ -327,10 +374,20 @@ gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* imag
     a.images = images;
     unsigned grid;
     GS_TRY(grid_for(f, o, a, 3, s, grid));
+    const bool count = (o->flags & GS_RASTER_COUNT_COMPOSITED) != 0;
     switch (o->raster_batch) {
-        case 64: raster_fwd_kernel<64><<<grid, 64, 0, s>>>(a); break;
-        case 256: raster_fwd_kernel<256><<<grid, 64, 0, s>>>(a); break;
-        default: raster_fwd_kernel<128><<<grid, 64, 0, s>>>(a); break;
+        case 64:
+            if (count) raster_fwd_kernel<64, true><<<grid, 64, 0, s>>>(a);
+            else raster_fwd_kernel<64, false><<<grid, 64, 0, s>>>(a);
+            break;
+        case 256:
+            if (count) raster_fwd_kernel<256, true><<<grid, 64, 0, s>>>(a);
+            else raster_fwd_kernel<256, false><<<grid, 64, 0, s>>>(a);
+            break;
+        default:
+            if (count) raster_fwd_kernel<128, true><<<grid, 64, 0, s>>>(a);
+            else raster_fwd_kernel<128, false><<<grid, 64, 0, s>>>(a);
+            break;
     }
     return gs_check_launch("raster_fwd");
 }

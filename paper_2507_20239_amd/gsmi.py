@@ -29,6 +29,7 @@ BUF_DEPTH_KEY, BUF_TILES_TOUCHED, BUF_RECT, BUF_SPLAT, BUF_SORTED_ENTRIES, BUF_I
     BUF_N_COMPOSITED = range(13)
 KIND_KEEP, KIND_CLONE, KIND_SPLIT0, KIND_SPLIT1 = range(4)
 ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO = range(5)
+RASTER_COUNT_COMPOSITED = 1
 
 
 class GsError(RuntimeError):
@@ -59,7 +60,7 @@ class GaussianGrads(ctypes.Structure):
 class RasterOpts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_float * 3), ("near_plane", ctypes.c_float),
                 ("raster_batch", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Attr(ctypes.Structure):
@@ -195,12 +196,14 @@ def cameras_to_device(cams, device="cuda") -> torch.Tensor:
     return torch.from_numpy(camera_array(cams).copy()).to(device)
 
 
-def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0):
+def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0,
+                count_composited=False):
     o = RasterOpts()
     o.bg[:] = [float(x) for x in bg]
     o.near_plane = float(np.float32(near_plane))
     o.raster_batch = int(raster_batch)
     o.persistent_blocks = int(persistent_blocks)
+    o.flags = RASTER_COUNT_COMPOSITED if count_composited else 0
     return o
 
 

@@ -24,7 +24,7 @@ def params_of(sc, device=None):
 
 def gpu_forward(sc, cams, opts=None, cap=1 << 22, frame=None):
     """Project + render every camera in one frame.  Returns (frame, images list)."""
-    opts = opts or gsmi.raster_opts(bg=tuple(float(x) for x in sc.bg))
+    opts = opts or gsmi.raster_opts(bg=tuple(float(x) for x in sc.bg), count_composited=True)
     params = params_of(sc)
     cams_dev = gsmi.cameras_to_device(cams, dev())
     if frame is None:

@@ -31,7 +31,7 @@ def _sample_pixels(rng, W, H, m):
 def c2():
     sc = synth.single_view_1m(with_targets=False)
     cam = sc.cameras[0]
-    frame, flat, params, cams_dev, opts = gpu_forward(sc, [cam], opts=gsmi.raster_opts(),
+    frame, flat, params, cams_dev, opts = gpu_forward(sc, [cam], opts=gsmi.raster_opts(count_composited=True),
                                                       cap=16 << 20)
     p = oracle.project(sc, cam)
     return sc, cam, frame, flat, params, cams_dev, opts, p

@@ -100,6 +100,9 @@ def test_render_matches_oracle(name):
     scale = np.abs(ref) + np.abs(np.asarray(sc.bg, np.float64))[:, None, None]
     assert_close_scaled(img[:, good], ref[:, good], scale[:, good], what="image")
     assert_close_scaled(T[good], Tref[good], np.abs(Tref[good]), what="T_final")
+    nc = frame.buffer(gsmi.BUF_N_COMPOSITED).cpu().numpy().view(np.uint32).reshape(cam.height,
+                                                                                 cam.width)
+    np.testing.assert_array_equal(nc[good], nref[good])
 
 
 @pytest.mark.parametrize("name", list(SCENES))
@@ -187,6 +190,19 @@ def test_capacity_overflow_is_reported_and_bounded():
     assert ovf == 1 and ni > 1000
     with pytest.raises(gsmi.GsError):
         frame.status()
+
+
+def test_counting_composited_splats_changes_nothing_else():
+    sc = SCENES["ragged_300_37x29_sh3"]
+    cam = sc.cameras[0]
+    bufs = (gsmi.BUF_T_FINAL, gsmi.BUF_N_CONTRIB)
+    out = []
+    for count in (False, True):
+        o = gsmi.raster_opts(bg=tuple(sc.bg), count_composited=count)
+        frame, img, *_ = gpu_forward(sc, [cam], o)
+        out.append([img.clone()] + [frame.buffer(b).clone() for b in bufs])
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
 
 
 def test_persistent_queue_gives_identical_images():
