@@ -102,7 +102,7 @@ typedef struct {
 typedef struct {
     float bg[3];                 /* background colour composited behind every pixel */
     float near_plane;            /* Gaussians with camera depth <= near are culled (default 0.2) */
-    int32_t raster_batch;        /* Gaussians staged in LDS per batch: 64, 128 or 256; 0 = 128 */
+    int32_t raster_batch;        /* Gaussians staged in LDS per batch: 64, 128 or 256; 0 = 64 */
     int32_t persistent_blocks;   /* 0: one wave64 workgroup per (view, tile);  > 0: a persistent
                                     grid of this many wave64 workgroups takes (view, tile) items
                                     from a queue, heaviest tile lists first */

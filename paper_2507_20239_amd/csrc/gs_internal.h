@@ -265,10 +265,12 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 #define GS_KAPPA ((float)GS_KAPPA_D)
 
 // One lane's 2x2 pixel quad relative to a splat: column offsets dx0, dx1 =
-// dx0 + 1, row offsets dy0, dy1 = dy0 + 1, and the per-row terms l21 dy and
-// (l22 dy)^2.  Pixel i of the quad is column i & 1, row i >> 1.
+// dx0 + 1, row offsets dy0, dy1 = dy0 + 1, the exponent coordinate
+// u = l11 dx + l21 dy of each pixel (the other three from the first by adding
+// l11 and l21) and (l22 dy)^2 per row.  Pixel i of the quad is column i & 1,
+// row i >> 1.
 struct Quad {
-    float dx[2], dy[2], t[2], vv[2];
+    float dx[2], dy[2], u[4], vv[2];
 };
 
 __device__ __forceinline__ void quad_setup(float4 p0, float4 p1, float pxc0, float pyc0, Quad& q) {
@@ -276,18 +278,18 @@ __device__ __forceinline__ void quad_setup(float4 p0, float4 p1, float pxc0, flo
     q.dx[1] = q.dx[0] + 1.f;
     q.dy[0] = (pyc0 - p0.y) - p0.w;
     q.dy[1] = q.dy[0] + 1.f;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        q.t[r] = p1.y * q.dy[r];
-        const float v = p1.z * q.dy[r];
-        q.vv[r] = v * v;
-    }
+    q.u[0] = fmaf(p1.x, q.dx[0], p1.y * q.dy[0]);
+    q.u[1] = q.u[0] + p1.x;
+    q.u[2] = q.u[0] + p1.y;
+    q.u[3] = q.u[1] + p1.y;
+    const float v0 = p1.z * q.dy[0], v1 = v0 + p1.z;
+    q.vv[0] = v0 * v0;
+    q.vv[1] = v1 * v1;
 }
 
 // G of pixel i of the quad
-__device__ __forceinline__ float quad_G(float l11, const Quad& q, int i) {
-    const float u = fmaf(l11, q.dx[i & 1], q.t[i >> 1]);
-    return __builtin_amdgcn_exp2f(-fmaf(u, u, q.vv[i >> 1]));
+__device__ __forceinline__ float quad_G(const Quad& q, int i) {
+    return __builtin_amdgcn_exp2f(-fmaf(q.u[i], q.u[i], q.vv[i >> 1]));
 }
 
 // Squared radius of a splat's footprint ellipse in (u, v) coordinates:

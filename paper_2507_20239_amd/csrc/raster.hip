@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
                 quad_setup(p0, p1, pxc[0], pyc[0], q);
 #pragma unroll
                 for (int i = 0; i < PIX; ++i) {
-                    const float alpha = fminf(p1.w * quad_G(p1.x, q, i), GS_ALPHA_MAX);
+                    const float alpha = fminf(p1.w * quad_G(q, i), GS_ALPHA_MAX);
                     const bool hit = alpha >= GS_ALPHA_MIN;
                     // a finished pixel has T < 0, so Tn < 0 and it never takes
                     const float Tn = T[i] * (1.f - alpha);
@@ -229,6 +229,7 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mlast = max(mlast, (u32)__shfl_xor((int)mlast, off, 64));
+        mlast = __builtin_amdgcn_readfirstlane(mlast);   // uniform: keeps the walk on scalar registers
 
         for (int bi = (int)((mlast + BATCH - 1) / BATCH) - 1; bi >= 0; --bi) {
             const u32 b0 = tc.rg.x + (u32)bi * BATCH;
@@ -248,25 +249,28 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                 bool contrib = false;
 #pragma unroll
                 for (int i = 0; i < PIX; ++i) {
-                    const float G = quad_G(p1.x, q, i);
+                    const float G = quad_G(q, i);
                     const float raw = p1.w * G;
                     const float alpha = fminf(raw, GS_ALPHA_MAX);
                     const bool use = rel < last[i] && alpha >= GS_ALPHA_MIN;
                     contrib = contrib || use;
+                    // an unused splat acts as alpha = 0: the reciprocal below is
+                    // then exactly 1, T stays and the weight is 0, with no selects
+                    const float au = use ? alpha : 0.f;
                     // T_i = T_{i+1} / (1 - alpha_i).  The hardware reciprocal is
                     // within 1 ulp but biased, and the bias compounds over a long
                     // back-to-front walk; one Newton step leaves an unbiased error
                     // of about half an ulp.
-                    const float om = 1.f - alpha;
+                    const float om = 1.f - au;
                     float inv = __builtin_amdgcn_rcpf(om);
                     inv = fmaf(fmaf(-om, inv, 1.f), inv, inv);
                     const float Ti = T[i] * inv;
-                    const float wgt = use ? alpha * Ti : 0.f;
+                    const float wgt = au * Ti;
                     const float cd = fmaf(c.x, g0[i], fmaf(c.y, g1[i], c.z * g2[i]));
                     // dL/dalpha = (c . g) T_i - (g . colour behind) / (1 - alpha)
                     const float dalpha = fmaf(cd, Ti, -sd[i] * inv);
                     sd[i] = fmaf(cd, wgt, sd[i]);
-                    T[i] = use ? Ti : T[i];
+                    T[i] = Ti;
                     gr0 = fmaf(wgt, g0[i], gr0);
                     gr1 = fmaf(wgt, g1[i], gr1);
                     gr2 = fmaf(wgt, g2[i], gr2);
@@ -376,17 +380,17 @@ gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* imag
     GS_TRY(grid_for(f, o, a, 3, s, grid));
     const bool count = (o->flags & GS_RASTER_COUNT_COMPOSITED) != 0;
     switch (o->raster_batch) {
-        case 64:
-            if (count) raster_fwd_kernel<64, true><<<grid, 64, 0, s>>>(a);
-            else raster_fwd_kernel<64, false><<<grid, 64, 0, s>>>(a);
+        case 128:
+            if (count) raster_fwd_kernel<128, true><<<grid, 64, 0, s>>>(a);
+            else raster_fwd_kernel<128, false><<<grid, 64, 0, s>>>(a);
             break;
         case 256:
             if (count) raster_fwd_kernel<256, true><<<grid, 64, 0, s>>>(a);
             else raster_fwd_kernel<256, false><<<grid, 64, 0, s>>>(a);
             break;
         default:
-            if (count) raster_fwd_kernel<128, true><<<grid, 64, 0, s>>>(a);
-            else raster_fwd_kernel<128, false><<<grid, 64, 0, s>>>(a);
+            if (count) raster_fwd_kernel<64, true><<<grid, 64, 0, s>>>(a);
+            else raster_fwd_kernel<64, false><<<grid, 64, 0, s>>>(a);
             break;
     }
     return gs_check_launch("raster_fwd");
@@ -400,9 +404,9 @@ gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float
     unsigned grid;
     GS_TRY(grid_for(f, o, a, 4, s, grid));
     switch (o->raster_batch) {
-        case 64: raster_bwd_kernel<64><<<grid, 64, 0, s>>>(a); break;
+        case 128: raster_bwd_kernel<128><<<grid, 64, 0, s>>>(a); break;
         case 256: raster_bwd_kernel<256><<<grid, 64, 0, s>>>(a); break;
-        default: raster_bwd_kernel<128><<<grid, 64, 0, s>>>(a); break;
+        default: raster_bwd_kernel<64><<<grid, 64, 0, s>>>(a); break;
     }
     return gs_check_launch("raster_bwd");
 }
