@@ -145,7 +145,7 @@ enum {
                                  mean = hi + lo; [l11 0; l21 l22] is the Cholesky factor of
                                  kappa Q, Q = Sigma'^-1 the conic, kappa = log2(e)/2, so that
                                  G(d) = 2^-((l11 dx + l21 dy)^2 + (l22 dy)^2) */
-    GS_BUF_SORTED_ENTRIES = 4,/* u32 [V*n]   visible entries in (depth key, entry) order */
+    GS_BUF_VISIBLE = 4,       /* u32 [V*n]   visible entries (tiles_touched > 0), in entry order */
     GS_BUF_INST_TILE = 5,     /* u32 [cap]   tile id of each sorted instance */
     GS_BUF_INST_ENTRY = 6,    /* u32 [cap]   entry id of each sorted instance */
     GS_BUF_RANGES = 7,        /* u32 [T][2]  [start, end) of each tile's instance list */

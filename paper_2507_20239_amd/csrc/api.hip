@@ -81,10 +81,8 @@ void fill_views(gs_frame* f, const int32_t* widths, const int32_t* heights) {
 
 Layout layout_for(gs_frame* f) {
     const uint64_t E = (uint64_t)f->E, cap = (uint64_t)f->cap, T = (uint64_t)f->T, P = (uint64_t)f->P;
-    uint64_t sort_bytes = gs_radix_scratch_bytes(f->E, 31);
-    const uint64_t si = gs_radix_scratch_bytes(f->cap, f->tile_bits);
+    uint64_t sort_bytes = gs_radix_scratch_bytes(f->cap, f->tile_bits);
     const uint64_t st = gs_radix_scratch_bytes(f->T, 24);
-    if (si > sort_bytes) sort_bytes = si;
     if (st > sort_bytes) sort_bytes = st;
     Layout L;
     L.add(4 * E);        // 0 depth_key
@@ -92,29 +90,26 @@ Layout layout_for(gs_frame* f) {
     L.add(8 * E);        // 2 rect
     L.add(48 * E);       // 3 splat
     L.add(4 * E);        // 4 flags
-    L.add(4 * E);        // 5 vkeys0
-    L.add(4 * E);        // 6 vkeys1
-    L.add(4 * E);        // 7 vvals0
-    L.add(4 * E);        // 8 vvals1
-    L.add(4 * E);        // 9 inst_off
-    L.add(4 * cap);      // 10 ikeys0
-    L.add(4 * cap);      // 11 ikeys1
-    L.add(4 * cap);      // 12 ivals0
-    L.add(4 * cap);      // 13 ivals1
-    L.add(8 * T);        // 14 ranges
-    L.add(4 * T);        // 15 tkeys0
-    L.add(4 * T);        // 16 tkeys1
-    L.add(4 * T);        // 17 tvals0
-    L.add(4 * T);        // 18 tvals1
-    L.add(4 * P);        // 19 T_final
-    L.add(4 * P);        // 20 n_contrib
-    L.add(36 * E);       // 21 splat_grad
-    L.add(64);           // 22 counters
-    L.add(sort_bytes);   // 23 sort scratch
-    L.add(4 * (GS_SCAN_PARTS + 8));  // 24 scan_part
-    L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 25 views
-    L.add(4 * P);        // 26 n_comp
-    L.add(4 * (cap / 256 + 2));  // 27 chunk_start
+    L.add(4 * E);        // 5 visible
+    L.add(4 * E);        // 6 inst_off
+    L.add(4 * cap);      // 7 ikeys0
+    L.add(4 * cap);      // 8 ikeys1
+    L.add(4 * cap);      // 9 ivals0
+    L.add(4 * cap);      // 10 ivals1
+    L.add(8 * T);        // 11 ranges
+    L.add(4 * T);        // 12 tkeys0
+    L.add(4 * T);        // 13 tkeys1
+    L.add(4 * T);        // 14 tvals0
+    L.add(4 * T);        // 15 tvals1
+    L.add(4 * P);        // 16 T_final
+    L.add(4 * P);        // 17 n_contrib
+    L.add(36 * E);       // 18 splat_grad
+    L.add(64);           // 19 counters
+    L.add(sort_bytes);   // 20 sort scratch
+    L.add(4 * (GS_SCAN_PARTS + 8));  // 21 scan_part
+    L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 22 views
+    L.add(4 * P);        // 23 n_comp
+    L.add(4 * (cap / 256 + 2));  // 24 chunk_start
     return L;
 }
 
@@ -197,31 +192,27 @@ gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
     f->rect = (uint2*)(b + L.off[2]);
     f->splat = (float4*)(b + L.off[3]);
     f->flags = (u32*)(b + L.off[4]);
-    f->vkeys[0] = (u32*)(b + L.off[5]);
-    f->vkeys[1] = (u32*)(b + L.off[6]);
-    f->vvals[0] = (u32*)(b + L.off[7]);
-    f->vvals[1] = (u32*)(b + L.off[8]);
-    f->inst_off = (u32*)(b + L.off[9]);
-    f->ikeys[0] = (u32*)(b + L.off[10]);
-    f->ikeys[1] = (u32*)(b + L.off[11]);
-    f->ivals[0] = (u32*)(b + L.off[12]);
-    f->ivals[1] = (u32*)(b + L.off[13]);
-    f->ranges = (uint2*)(b + L.off[14]);
-    f->tkeys[0] = (u32*)(b + L.off[15]);
-    f->tkeys[1] = (u32*)(b + L.off[16]);
-    f->tvals[0] = (u32*)(b + L.off[17]);
-    f->tvals[1] = (u32*)(b + L.off[18]);
-    f->T_final = (float*)(b + L.off[19]);
-    f->n_contrib = (u32*)(b + L.off[20]);
-    f->splat_grad = (float*)(b + L.off[21]);
-    f->counters = (u32*)(b + L.off[22]);
-    f->sort_scratch = (void*)(b + L.off[23]);
-    f->scan_part = (u32*)(b + L.off[24]);
-    f->d_views = (gs_view_info*)(b + L.off[25]);
-    f->n_comp = (u32*)(b + L.off[26]);
-    f->chunk_start = (u32*)(b + L.off[27]);
+    f->visible = (u32*)(b + L.off[5]);
+    f->inst_off = (u32*)(b + L.off[6]);
+    f->ikeys[0] = (u32*)(b + L.off[7]);
+    f->ikeys[1] = (u32*)(b + L.off[8]);
+    f->ivals[0] = (u32*)(b + L.off[9]);
+    f->ivals[1] = (u32*)(b + L.off[10]);
+    f->ranges = (uint2*)(b + L.off[11]);
+    f->tkeys[0] = (u32*)(b + L.off[12]);
+    f->tkeys[1] = (u32*)(b + L.off[13]);
+    f->tvals[0] = (u32*)(b + L.off[14]);
+    f->tvals[1] = (u32*)(b + L.off[15]);
+    f->T_final = (float*)(b + L.off[16]);
+    f->n_contrib = (u32*)(b + L.off[17]);
+    f->splat_grad = (float*)(b + L.off[18]);
+    f->counters = (u32*)(b + L.off[19]);
+    f->sort_scratch = (void*)(b + L.off[20]);
+    f->scan_part = (u32*)(b + L.off[21]);
+    f->d_views = (gs_view_info*)(b + L.off[22]);
+    f->n_comp = (u32*)(b + L.off[23]);
+    f->chunk_start = (u32*)(b + L.off[24]);
     // the slots holding sorted results depend only on the pass counts
-    f->vsorted = (((31 + 7) / 8) & 1);
     f->isorted = (((f->tile_bits + 7) / 8) & 1);
     f->tsorted = (((24 + 7) / 8) & 1);
     hipError_t e = hipMemcpy(f->d_views, f->views, sizeof(gs_view_info) * n_views, hipMemcpyHostToDevice);
@@ -247,7 +238,7 @@ gs_status gs_frame_buffer(const gs_frame* f, int32_t which, void** ptr, int64_t*
         case GS_BUF_TILES_TOUCHED: *ptr = f->tiles_touched; *count = f->E; break;
         case GS_BUF_RECT: *ptr = f->rect; *count = 2 * f->E; break;
         case GS_BUF_SPLAT: *ptr = f->splat; *count = 12 * f->E; break;
-        case GS_BUF_SORTED_ENTRIES: *ptr = f->vvals[f->vsorted]; *count = f->E; break;
+        case GS_BUF_VISIBLE: *ptr = f->visible; *count = f->E; break;
         case GS_BUF_INST_TILE: *ptr = f->ikeys[f->isorted]; *count = f->cap; break;
         case GS_BUF_INST_ENTRY: *ptr = f->ivals[f->isorted]; *count = f->cap; break;
         case GS_BUF_RANGES: *ptr = f->ranges; *count = 2 * (int64_t)f->T; break;

@@ -1,53 +1,48 @@
 // Tile binning: per-tile, depth-ordered splat lists.
 //
-// The ordering key of an instance is (global tile id, FP32 depth bits,
-// entry id).  It is built as an LSD radix sort whose depth digits are applied
-// per entry rather than per instance (every instance of an entry shares its
-// depth, so sorting the entries by depth and emitting their instances in that
-// order is exactly the result of the depth passes), followed by stable
-// passes on the tile id alone.  That moves 8 bytes per instance per tile
-// pass instead of 12 bytes per instance for each of ~6 passes over 64-bit
-// keys.
+// The order inside a tile's list is (FP32 depth bits, entry id).  Instances
+// are grouped by tile with a stable radix sort on the tile id alone, and each
+// tile's list is then put in depth order by one wave that owns it:
 //
 //   flags = tiles_touched > 0  -> exclusive scan -> compact visible entries
-//   radix sort (depth bits, entry) over the visible entries
-//   gather tiles_touched in depth order -> exclusive scan -> instance offsets
-//   emit (tile, entry) for every tile of each footprint rectangle, row-major
+//   exclusive scan of their tile counts -> instance offsets (entry order)
+//   emit (tile, entry) for every tile each footprint meets, row-major
 //   radix sort on the tile id (stable)
 //   tile ranges from adjacent keys;  optional heavy-first tile order
+//   per tile: sort the list by (depth bits, entry) in registers, in LDS, or
+//   for very long lists as LDS-sorted runs merged in global memory
+//
+// A global sort of the visible entries by depth before emission would give
+// the same lists; it takes four radix passes over every visible entry, while
+// the per-tile sorts are short, independent and need no pass over the keys'
+// full width.
 #include "gs_internal.h"
 
 namespace {
 
 // Scan epilogue of the visibility flags: entry i with flag 1 goes to slot
-// ex of the compacted (depth key, entry) arrays; the total is the number of
-// visible entries.
+// ex of the compacted list; the total is the number of visible entries.
 struct CompactEpi {
-    const u32* depth_key;
-    u32* keys;
-    u32* vals;
+    u32* visible;
     u32* n_visible;
     __device__ void item(u32 i, u32 flag, u32 ex) const {
-        if (flag) {
-            keys[ex] = depth_key[i];
-            vals[ex] = i;
-        }
+        if (flag) visible[ex] = i;
     }
     __device__ void finish(u32 t) const { *n_visible = t; }
 };
 
 // Instance emission, balanced per 256 instances.  Pass 1 records, for every
-// chunk of 256 consecutive instance slots, the depth-sorted entry whose tiles
+// chunk of 256 consecutive instance slots, the visible entry whose tiles
 // start the chunk.  Pass 2 gives each workgroup whole chunks: it stages the
 // (at most 256) entries a chunk can touch in LDS, and each thread finds the
 // entry of its slot by binary search over their offsets (strictly
 // increasing: every visible entry has at least one tile), then writes
-// (tile, entry) for the k-th tile of the rectangle, row-major.  Depth order
-// puts the largest footprints (nearest Gaussians) together, so balancing on
-// instances rather than on entries is what keeps the workgroups even.
+// (tile, entry) for the k-th tile of the rectangle, row-major.  Balancing on
+// instances rather than on entries keeps the workgroups even when a few
+// footprints cover many tiles.
 constexpr u32 EMIT_CHUNK = 256;
 
-// Scan epilogue of the tile counts in depth order: the instance offset of
+// Scan epilogue of the visible entries' tile counts: the instance offset of
 // visible entry j, and for every chunk of 256 instance slots that starts
 // inside its range the entry j itself (chunk_start, below the capacity); the
 // last workgroup publishes the instance total, the kept length min(total,
@@ -70,7 +65,7 @@ struct ChunkEpi {
     }
 };
 
-__global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u32* offs,
+__global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, const u32* offs,
                                                         const uint2* rect, const float4* splat,
                                                         const gs_view_info* views, int64_t n,
                                                         const u32* n_vis, const u32* n_kept,
@@ -91,7 +86,7 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* vals, const u
         const int m = span < EMIT_CHUNK ? (int)span : (int)EMIT_CHUNK;
         __syncthreads();
         if (t < m) {
-            u32 e = vals[j0 + t];
+            u32 e = visible[j0 + t];
             if (e >= (u64)E) e = 0;
             const uint2 r = rect[e];
             int v = 0;
@@ -156,6 +151,218 @@ __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, 
     }
 }
 
+// ---- depth order inside each tile's list ------------------------------------
+// Keys are (depth bits << 32 | entry): unique, so any correct sort gives the
+// one order.  A list of up to 512 instances is sorted by one wave holding R
+// keys per lane (element lane R + r in register r) with a bitonic network:
+// stages whose partner distance is below R compare registers of a lane,
+// the others exchange with lane ^ (distance / R).  Longer lists go to a
+// 256-thread workgroup: up to SORT_LDS keys sorted by a bitonic network in
+// LDS, beyond that LDS-sorted runs merged pairwise in global memory (each
+// thread produces a contiguous piece of a merged run after locating its
+// start on the merge path by binary search).
+constexpr u32 SORT_WAVE_MAX = 512;
+constexpr int SORT_LDS = 2048;
+constexpr int SORT_THREADS = 256;
+
+__device__ __forceinline__ u64 list_key(const u32* depth_key, u32 e, u32 E) {
+    if (e >= E) e = E - 1;   // only for slots an overflowing frame left unwritten
+    return ((u64)depth_key[e] << 32) | e;
+}
+
+// value of lane ^ m (m a power of two below 64): quad permutations and a row
+// rotation by 8 on the VALU, swizzles inside 32-lane halves, a lane
+// permutation across the halves
+__device__ __forceinline__ u32 xor_lanes(u32 v, int m) {
+    switch (m) {
+        case 1: return (u32)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+        case 2: return (u32)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+        case 4: return (u32)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+        case 8: return (u32)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+        case 16: return (u32)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+        default: return (u32)__shfl_xor((int)v, m, 64);
+    }
+}
+
+__device__ __forceinline__ u64 xor_lanes64(u64 x, int m) {
+    return ((u64)xor_lanes((u32)(x >> 32), m) << 32) | xor_lanes((u32)x, m);
+}
+
+// ascending bitonic sort of the 64 R keys of a wave, x[r] = element lane R + r
+template <int R>
+__device__ __forceinline__ void wave_bitonic(u64 (&x)[R], u32 lane) {
+#pragma unroll
+    for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j < R) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if ((r & j) == 0) {
+                        const int q = r | j;
+                        const bool up = ((lane * R + r) & k) == 0;
+                        const u64 a = x[r], b = x[q];
+                        const bool sw = up ? (a > b) : (a < b);
+                        x[r] = sw ? b : a;
+                        x[q] = sw ? a : b;
+                    }
+                }
+            } else {
+                const int m = j / R;
+                const bool lower = (lane & m) == 0;
+                // all exchanges of the stage first, so their latencies overlap
+                u64 p[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[r] = xor_lanes64(x[r], m);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool up = ((lane * R + r) & k) == 0;
+                    // the lower element of an ascending pair keeps the minimum
+                    x[r] = ((x[r] < p[r]) == (lower == up)) ? x[r] : p[r];
+                }
+            }
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void wave_sort_list(u32* ent, u32 L, const u32* depth_key, u32 E,
+                                               u32 lane) {
+    u64 x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const u32 i = lane * R + r;
+        x[r] = i < L ? list_key(depth_key, ent[i], E) : ~0ull;
+    }
+    wave_bitonic<R>(x, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const u32 i = lane * R + r;
+        if (i < L) ent[i] = (u32)x[r];
+    }
+}
+
+__global__ void __launch_bounds__(64) tile_sort_wave_kernel(const uint2* ranges,
+                                                            const u32* depth_key, u32 E,
+                                                            u32* inst_entry) {
+    const uint2 rg = ranges[blockIdx.x];
+    const u32 L = rg.y - rg.x;
+    if (L <= 1 || L > SORT_WAVE_MAX) return;
+    u32* ent = inst_entry + rg.x;
+    const u32 lane = threadIdx.x;
+    if (L <= 64) wave_sort_list<1>(ent, L, depth_key, E, lane);
+    else if (L <= 128) wave_sort_list<2>(ent, L, depth_key, E, lane);
+    else if (L <= 256) wave_sort_list<4>(ent, L, depth_key, E, lane);
+    else wave_sort_list<8>(ent, L, depth_key, E, lane);
+}
+
+// ascending bitonic sort of s[0..n) by the workgroup, n a power of two
+__device__ void bitonic_lds(u64* s, u32 n) {
+    for (u32 k = 2; k <= n; k <<= 1)
+        for (u32 j = k >> 1; j > 0; j >>= 1) {
+            for (u32 i = threadIdx.x; i < n / 2; i += SORT_THREADS) {
+                const u32 lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const u32 hi = lo + j;
+                const u64 a = s[lo], b = s[hi];
+                if ((a > b) == ((lo & k) == 0)) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+__device__ __forceinline__ u32 pow2_at_least(u32 x) {
+    u32 n = 1;
+    while (n < x) n <<= 1;
+    return n;
+}
+
+__device__ __forceinline__ u64 run_key(const u32* kh, const u32* kl, u32 i) {
+    return ((u64)kh[i] << 32) | kl[i];
+}
+
+// Lists longer than SORT_WAVE_MAX.  Merge scratch: (sh0, sl0) and (sh1, ent),
+// where sh1 holds the list's tile ids, rewritten at the end.
+__global__ void __launch_bounds__(SORT_THREADS) tile_sort_long_kernel(
+    const uint2* ranges, const u32* depth_key, u32 E, u32* inst_entry, u32* inst_tile,
+    u32* sh0_all, u32* sl0_all) {
+    __shared__ u64 s[SORT_LDS];
+    const uint2 rg = ranges[blockIdx.x];
+    const u32 L = rg.y - rg.x;
+    if (L <= SORT_WAVE_MAX) return;
+    u32* ent = inst_entry + rg.x;
+    if (L <= (u32)SORT_LDS) {
+        const u32 n = pow2_at_least(L);
+        for (u32 j = threadIdx.x; j < n; j += SORT_THREADS)
+            s[j] = j < L ? list_key(depth_key, ent[j], E) : ~0ull;
+        __syncthreads();
+        bitonic_lds(s, n);
+        for (u32 j = threadIdx.x; j < L; j += SORT_THREADS) ent[j] = (u32)s[j];
+        return;
+    }
+    u32* ah = sh0_all + rg.x;
+    u32* al = sl0_all + rg.x;
+    u32* bh = inst_tile + rg.x;
+    u32* bl = ent;
+    // runs of SORT_LDS keys, sorted in LDS, into (ah, al)
+    for (u32 r0 = 0; r0 < L; r0 += SORT_LDS) {
+        const u32 m = L - r0 < (u32)SORT_LDS ? L - r0 : (u32)SORT_LDS;
+        const u32 n = pow2_at_least(m);
+        for (u32 j = threadIdx.x; j < n; j += SORT_THREADS)
+            s[j] = j < m ? list_key(depth_key, ent[r0 + j], E) : ~0ull;
+        __syncthreads();
+        bitonic_lds(s, n);
+        for (u32 j = threadIdx.x; j < m; j += SORT_THREADS) {
+            ah[r0 + j] = (u32)(s[j] >> 32);
+            al[r0 + j] = (u32)s[j];
+        }
+        __syncthreads();
+    }
+    // merge passes, ping-pong between (ah, al) and (bh, bl)
+    bool in_a = true;
+    for (u32 w = SORT_LDS; w < L; w <<= 1) {
+        const u32* srh = in_a ? ah : bh;
+        const u32* srl = in_a ? al : bl;
+        u32* dsh = in_a ? bh : ah;
+        u32* dsl = in_a ? bl : al;
+        for (u32 i0 = 0; i0 < L; i0 += 2 * w) {
+            const u32 a0 = i0;
+            const u32 a1 = i0 + w < L ? i0 + w : L;
+            const u32 b1 = i0 + 2 * w < L ? i0 + 2 * w : L;
+            const u32 na = a1 - a0, nb = b1 - a1, tot = na + nb;
+            const u32 per = (tot + SORT_THREADS - 1) / SORT_THREADS;
+            const u32 p0 = threadIdx.x * per;
+            if (p0 >= tot) continue;
+            const u32 p1 = p0 + per < tot ? p0 + per : tot;
+            // merge path: how many of the first p0 outputs come from run A
+            u32 lo = p0 > nb ? p0 - nb : 0, hi = p0 < na ? p0 : na;
+            while (lo < hi) {
+                const u32 mid = (lo + hi) >> 1;
+                if (run_key(srh, srl, a0 + mid) < run_key(srh, srl, a1 + (p0 - mid - 1))) lo = mid + 1;
+                else hi = mid;
+            }
+            u32 ia = lo, ib = p0 - lo;
+            for (u32 p = p0; p < p1; ++p) {
+                const bool take_a =
+                    ib >= nb || (ia < na && run_key(srh, srl, a0 + ia) < run_key(srh, srl, a1 + ib));
+                const u32 src = take_a ? a0 + ia : a1 + ib;
+                dsh[i0 + p] = srh[src];
+                dsl[i0 + p] = srl[src];
+                if (take_a) ++ia;
+                else ++ib;
+            }
+        }
+        __syncthreads();
+        in_a = !in_a;
+    }
+    for (u32 j = threadIdx.x; j < L; j += SORT_THREADS) {
+        if (in_a) ent[j] = al[j];
+        bh[j] = blockIdx.x;   // the tile ids the merge scratch overwrote
+    }
+}
+
 // heavy-first order key: longer lists first, ties by tile id (stable sort)
 __global__ void tile_weight_kernel(const uint2* ranges, u32* keys, u32* vals, int T) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -174,27 +381,23 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     const int64_t E = f->E;
     u32* cnt = f->counters;
     if (E > 0) {
-        // flags[e] = (tiles_touched[e] > 0) and counters[6] = 0 come from the projection;
+        // flags[e] = (tiles_touched[e] > 0) come from the projection;
         // the compaction reads them without modifying them, so rendering the same
         // projection again repeats the same work.
         GS_TRY(gs_scan_reduce(f->flags, nullptr, nullptr, (u32)E, f->scan_part, s));
-        const CompactEpi ce{f->depth_key, f->vkeys[0], f->vvals[0], cnt + 0};
+        const CompactEpi ce{f->visible, cnt + 0};
         scan_down_kernel<CompactEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->flags, nullptr, nullptr,
                                                                       (u32)E, f->scan_part, ce);
         GS_TRY(gs_check_launch("compact"));
-        // depths are positive, so the sign bit is zero: 31 key bits
-        GS_TRY(gs_radix_sort(f->vkeys, f->vvals, cnt + 0, 0, E, 31, f->sort_scratch, cnt + 6,
-                             &f->vsorted, s));
-        const u32* sv = f->vvals[f->vsorted];
-        // instance offsets: exclusive scan of tiles_touched in depth order, with chunk starts
-        GS_TRY(gs_scan_reduce(f->tiles_touched, sv, cnt + 0, 0, f->scan_part, s));
+        // instance offsets: exclusive scan of the visible entries' tile counts, with chunk starts
+        GS_TRY(gs_scan_reduce(f->tiles_touched, f->visible, cnt + 0, 0, f->scan_part, s));
         const ChunkEpi he{f->inst_off, f->chunk_start, cnt, (u32)f->cap};
-        scan_down_kernel<ChunkEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, sv, cnt + 0,
-                                                                    0, f->scan_part, he);
+        scan_down_kernel<ChunkEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(
+            f->tiles_touched, f->visible, cnt + 0, 0, f->scan_part, he);
         GS_TRY(gs_check_launch("instance_offsets"));
-        emit_kernel<<<2048, GS_BLOCK, 0, s>>>(sv, f->inst_off, f->rect, f->splat, f->d_views, f->n, cnt + 0,
-                                              cnt + 5, f->chunk_start, f->ikeys[0], f->ivals[0], E,
-                                              (u32)f->T);
+        emit_kernel<<<2048, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat, f->d_views,
+                                              f->n, cnt + 0, cnt + 5, f->chunk_start, f->ikeys[0],
+                                              f->ivals[0], E, (u32)f->T);
         GS_TRY(gs_check_launch("emit"));
         GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->cap, f->tile_bits, f->sort_scratch,
                              cnt + 6, &f->isorted, s));
@@ -203,6 +406,16 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     }
     ranges_kernel<<<4096, GS_BLOCK, 0, s>>>(f->ikeys[f->isorted], cnt + 5, f->ranges, (u32)f->T);
     GS_TRY(gs_check_launch("ranges"));
+    if (E > 0 && f->T > 0) {
+        const int o = f->isorted ^ 1;
+        tile_sort_wave_kernel<<<(unsigned)f->T, 64, 0, s>>>(f->ranges, f->depth_key, (u32)E,
+                                                           f->ivals[f->isorted]);
+        GS_TRY(gs_check_launch("tile_sort_wave"));
+        tile_sort_long_kernel<<<(unsigned)f->T, SORT_THREADS, 0, s>>>(
+            f->ranges, f->depth_key, (u32)E, f->ivals[f->isorted], f->ikeys[f->isorted], f->ikeys[o],
+            f->ivals[o]);
+        GS_TRY(gs_check_launch("tile_sort_long"));
+    }
     if (heavy_first) {
         tile_weight_kernel<<<blocks_for(f->T), GS_BLOCK, 0, s>>>(f->ranges, f->tkeys[0], f->tvals[0],
                                                                  f->T);

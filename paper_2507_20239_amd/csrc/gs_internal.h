@@ -44,12 +44,10 @@ struct gs_frame {
     u32* tiles_touched;  // [E]
     uint2* rect;         // [E]
     float4* splat;       // [E][3]
-    // visible-entry compaction + depth sort (ping-pong)
-    u32* flags;          // [E] scan input / output
-    u32* vkeys[2];       // [E]
-    u32* vvals[2];       // [E]
-    u32* inst_off;       // [E] instance offsets in depth order
-    int vsorted;         // ping-pong slot holding the sorted entries
+    // visible-entry compaction
+    u32* flags;          // [E] 1 if the entry is rendered (from the projection)
+    u32* visible;        // [E] visible entries, in entry order
+    u32* inst_off;       // [E] instance offset of each visible entry
     // instances (ping-pong)
     u32* ikeys[2];       // [cap]
     u32* ivals[2];       // [cap]

@@ -24,7 +24,7 @@ GS_OK, GS_ERR_INVALID, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(5
 MAX_VIEWS = 32
 TILE = 16
 
-BUF_DEPTH_KEY, BUF_TILES_TOUCHED, BUF_RECT, BUF_SPLAT, BUF_SORTED_ENTRIES, BUF_INST_TILE, \
+BUF_DEPTH_KEY, BUF_TILES_TOUCHED, BUF_RECT, BUF_SPLAT, BUF_VISIBLE, BUF_INST_TILE, \
     BUF_INST_ENTRY, BUF_RANGES, BUF_T_FINAL, BUF_N_CONTRIB, BUF_SPLAT_GRAD, BUF_COUNTERS, \
     BUF_N_COMPOSITED = range(13)
 KIND_KEEP, KIND_CLONE, KIND_SPLIT0, KIND_SPLIT1 = range(4)

@@ -28,7 +28,10 @@ def _scenes():
     rag = synth.random_scene(21, 300, 37, 29, sh_degree=3, log_scale=(-2.6, 0.5), spread=1.0)
     rag.bg = np.array([0.2, 0.4, 0.1], np.float32)
     deg1 = synth.random_scene(22, 500, 70, 45, sh_degree=1, logit=(1.5, 1.0), log_scale=(-2.2, 0.5))
-    return {"c1_2000_128x128_sh0": c1, "ragged_300_37x29_sh3": rag, "sh1_500_70x45": deg1}
+    # tile lists of 1147 .. 6686 instances: LDS sorts, and runs merged once or twice
+    dense = synth.random_scene(23, 7000, 40, 40, sh_degree=0, log_scale=(-2.5, 0.4))
+    return {"c1_2000_128x128_sh0": c1, "ragged_300_37x29_sh3": rag, "sh1_500_70x45": deg1,
+            "dense_7000_40x40_sh0": dense}
 
 
 SCENES = _scenes()
@@ -84,6 +87,13 @@ def test_binning_lists_match_oracle_exactly(name):
     if nflag == 0:
         assert ni == tiles.size and nv == int((p["visible"] > 0).sum())
         np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(ranges))
+
+
+def test_dense_scene_has_lists_beyond_one_lds_sort():
+    sc = SCENES["dense_7000_40x40_sh0"]
+    _, _, ranges = oracle.tile_lists(oracle.project(sc, sc.cameras[0]))
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert lens.max() > 4 * 1024 and ((lens > 2048) & (lens <= 4096)).any()
 
 
 @pytest.mark.parametrize("name", list(SCENES))
