@@ -89,27 +89,26 @@ Layout layout_for(gs_frame* f) {
     L.add(4 * E);        // 1 tiles_touched
     L.add(8 * E);        // 2 rect
     L.add(48 * E);       // 3 splat
-    L.add(4 * E);        // 4 flags
-    L.add(4 * E);        // 5 visible
-    L.add(4 * E);        // 6 inst_off
-    L.add(4 * cap);      // 7 ikeys0
-    L.add(4 * cap);      // 8 ikeys1
-    L.add(4 * cap);      // 9 ivals0
-    L.add(4 * cap);      // 10 ivals1
-    L.add(8 * T);        // 11 ranges
-    L.add(4 * T);        // 12 tkeys0
-    L.add(4 * T);        // 13 tkeys1
-    L.add(4 * T);        // 14 tvals0
-    L.add(4 * T);        // 15 tvals1
-    L.add(4 * P);        // 16 T_final
-    L.add(4 * P);        // 17 n_contrib
-    L.add(36 * E);       // 18 splat_grad
-    L.add(64);           // 19 counters
-    L.add(sort_bytes);   // 20 sort scratch
-    L.add(4 * (GS_SCAN_PARTS + 8));  // 21 scan_part
-    L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 22 views
-    L.add(4 * P);        // 23 n_comp
-    L.add(4 * (cap / 256 + 2));  // 24 chunk_start
+    L.add(4 * E);        // 4 visible
+    L.add(4 * E);        // 5 inst_off
+    L.add(4 * cap);      // 6 ikeys0
+    L.add(4 * cap);      // 7 ikeys1
+    L.add(4 * cap);      // 8 ivals0
+    L.add(4 * cap);      // 9 ivals1
+    L.add(8 * T);        // 10 ranges
+    L.add(4 * T);        // 11 tkeys0
+    L.add(4 * T);        // 12 tkeys1
+    L.add(4 * T);        // 13 tvals0
+    L.add(4 * T);        // 14 tvals1
+    L.add(4 * P);        // 15 T_final
+    L.add(4 * P);        // 16 n_contrib
+    L.add(36 * E);       // 17 splat_grad
+    L.add(64);           // 18 counters
+    L.add(sort_bytes);   // 19 sort scratch
+    L.add(8 * (GS_SCAN_PARTS + 8));  // 20 scan_part
+    L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 21 views
+    L.add(4 * P);        // 22 n_comp
+    L.add(4 * (cap / 256 + 2));  // 23 chunk_start
     return L;
 }
 
@@ -191,27 +190,26 @@ gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
     f->tiles_touched = (u32*)(b + L.off[1]);
     f->rect = (uint2*)(b + L.off[2]);
     f->splat = (float4*)(b + L.off[3]);
-    f->flags = (u32*)(b + L.off[4]);
-    f->visible = (u32*)(b + L.off[5]);
-    f->inst_off = (u32*)(b + L.off[6]);
-    f->ikeys[0] = (u32*)(b + L.off[7]);
-    f->ikeys[1] = (u32*)(b + L.off[8]);
-    f->ivals[0] = (u32*)(b + L.off[9]);
-    f->ivals[1] = (u32*)(b + L.off[10]);
-    f->ranges = (uint2*)(b + L.off[11]);
-    f->tkeys[0] = (u32*)(b + L.off[12]);
-    f->tkeys[1] = (u32*)(b + L.off[13]);
-    f->tvals[0] = (u32*)(b + L.off[14]);
-    f->tvals[1] = (u32*)(b + L.off[15]);
-    f->T_final = (float*)(b + L.off[16]);
-    f->n_contrib = (u32*)(b + L.off[17]);
-    f->splat_grad = (float*)(b + L.off[18]);
-    f->counters = (u32*)(b + L.off[19]);
-    f->sort_scratch = (void*)(b + L.off[20]);
-    f->scan_part = (u32*)(b + L.off[21]);
-    f->d_views = (gs_view_info*)(b + L.off[22]);
-    f->n_comp = (u32*)(b + L.off[23]);
-    f->chunk_start = (u32*)(b + L.off[24]);
+    f->visible = (u32*)(b + L.off[4]);
+    f->inst_off = (u32*)(b + L.off[5]);
+    f->ikeys[0] = (u32*)(b + L.off[6]);
+    f->ikeys[1] = (u32*)(b + L.off[7]);
+    f->ivals[0] = (u32*)(b + L.off[8]);
+    f->ivals[1] = (u32*)(b + L.off[9]);
+    f->ranges = (uint2*)(b + L.off[10]);
+    f->tkeys[0] = (u32*)(b + L.off[11]);
+    f->tkeys[1] = (u32*)(b + L.off[12]);
+    f->tvals[0] = (u32*)(b + L.off[13]);
+    f->tvals[1] = (u32*)(b + L.off[14]);
+    f->T_final = (float*)(b + L.off[15]);
+    f->n_contrib = (u32*)(b + L.off[16]);
+    f->splat_grad = (float*)(b + L.off[17]);
+    f->counters = (u32*)(b + L.off[18]);
+    f->sort_scratch = (void*)(b + L.off[19]);
+    f->scan_part = (u32*)(b + L.off[20]);
+    f->d_views = (gs_view_info*)(b + L.off[21]);
+    f->n_comp = (u32*)(b + L.off[22]);
+    f->chunk_start = (u32*)(b + L.off[23]);
     // the slots holding sorted results depend only on the pass counts
     f->isorted = (((f->tile_bits + 7) / 8) & 1);
     f->tsorted = (((24 + 7) / 8) & 1);

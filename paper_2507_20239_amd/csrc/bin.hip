@@ -4,8 +4,8 @@
 // are grouped by tile with a stable radix sort on the tile id alone, and each
 // tile's list is then put in depth order by one wave that owns it:
 //
-//   flags = tiles_touched > 0  -> exclusive scan -> compact visible entries
-//   exclusive scan of their tile counts -> instance offsets (entry order)
+//   one exclusive scan of (tiles_touched > 0, tiles_touched) -> compacted
+//   visible entries and their instance offsets (entry order)
 //   emit (tile, entry) for every tile each footprint meets, row-major
 //   radix sort on the tile id (stable)
 //   tile ranges from adjacent keys;  optional heavy-first tile order
@@ -20,17 +20,6 @@
 
 namespace {
 
-// Scan epilogue of the visibility flags: entry i with flag 1 goes to slot
-// ex of the compacted list; the total is the number of visible entries.
-struct CompactEpi {
-    u32* visible;
-    u32* n_visible;
-    __device__ void item(u32 i, u32 flag, u32 ex) const {
-        if (flag) visible[ex] = i;
-    }
-    __device__ void finish(u32 t) const { *n_visible = t; }
-};
-
 // Instance emission, balanced per 256 instances.  Pass 1 records, for every
 // chunk of 256 consecutive instance slots, the visible entry whose tiles
 // start the chunk.  Pass 2 gives each workgroup whole chunks: it stages the
@@ -42,28 +31,78 @@ struct CompactEpi {
 // footprints cover many tiles.
 constexpr u32 EMIT_CHUNK = 256;
 
-// Scan epilogue of the visible entries' tile counts: the instance offset of
-// visible entry j, and for every chunk of 256 instance slots that starts
-// inside its range the entry j itself (chunk_start, below the capacity); the
-// last workgroup publishes the instance total, the kept length min(total,
-// capacity) the tile sort works on, and the overflow flag.
-struct ChunkEpi {
+// Visible entries and their instance offsets in one scan: each entry adds
+// (1 << 32 | tiles) if it has tiles, so the exclusive prefix holds its slot in
+// the compacted list (high half) and its instance offset (low half; instance
+// totals stay below 2^32).  The epilogue writes the compacted entry, its
+// offset, and for every chunk of 256 instance slots that starts inside its
+// range the slot itself (chunk_start, below the capacity); the last
+// workgroup publishes the visible count, the instance total, the kept length
+// min(total, capacity) and the overflow flag.
+__device__ __forceinline__ u64 vis_pack(u32 tt) { return tt ? ((u64)1 << 32) | tt : 0ull; }
+
+struct VisEpi {
+    u32* visible;
     u32* inst_off;
     u32* chunk_start;
     u32* counters;
     u32 cap;
-    __device__ void item(u32 j, u32 tt, u32 off) const {
-        inst_off[j] = off;
+    __device__ void item(u32 e, u32 tt, u32 slot, u32 off) const {
+        visible[slot] = e;
+        inst_off[slot] = off;
         const u64 hi = (u64)off + tt < cap ? (u64)off + tt : cap;
         for (u64 c = ((u64)off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK < hi; ++c)
-            chunk_start[c] = j;
+            chunk_start[c] = slot;
     }
-    __device__ void finish(u32 t) const {
+    __device__ void finish(u32 nv, u32 t) const {
+        counters[0] = nv;
         counters[1] = t;
         counters[5] = t < cap ? t : cap;
         counters[2] = t > cap ? 1u : 0u;
     }
 };
+
+__global__ void __launch_bounds__(GS_BLOCK) vis_reduce_kernel(const u32* tt, u32 n, u64* part) {
+    __shared__ u64 lds4[4];
+    u32 beg, end;
+    chunk_of(n, GS_SCAN_PARTS, blockIdx.x, beg, end);
+    u64 s = 0;
+    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) s += vis_pack(tt[i]);
+    u64 total;
+    block_exclusive_scan(s, lds4, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n, const u64* part,
+                                                            VisEpi epi) {
+    __shared__ u64 lds4[4];
+    u64 carry = 0;
+    for (u32 i = threadIdx.x; i < blockIdx.x; i += GS_BLOCK) carry += part[i];
+    u64 before;
+    block_exclusive_scan(carry, lds4, before);
+    carry = before;
+    u32 beg, end;
+    chunk_of(n, GS_SCAN_PARTS, blockIdx.x, beg, end);
+    for (u32 base = beg; base < end; base += GS_BLOCK * 4) {
+        u32 t[4];
+        u64 s = 0;
+        const u32 i0 = base + threadIdx.x * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            t[j] = i0 + j < end ? tt[i0 + j] : 0u;
+            s += vis_pack(t[j]);
+        }
+        u64 total;
+        u64 ex = block_exclusive_scan(s, lds4, total) + carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (t[j]) epi.item(i0 + j, t[j], (u32)(ex >> 32), (u32)ex);
+            ex += vis_pack(t[j]);
+        }
+        carry += total;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) epi.finish((u32)(carry >> 32), (u32)carry);
+}
 
 __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, const u32* offs,
                                                         const uint2* rect, const float4* splat,
@@ -283,15 +322,12 @@ __device__ __forceinline__ u64 run_key(const u32* kh, const u32* kl, u32 i) {
     return ((u64)kh[i] << 32) | kl[i];
 }
 
-// Lists longer than SORT_WAVE_MAX.  Merge scratch: (sh0, sl0) and (sh1, ent),
-// where sh1 holds the list's tile ids, rewritten at the end.
-__global__ void __launch_bounds__(SORT_THREADS) tile_sort_long_kernel(
-    const uint2* ranges, const u32* depth_key, u32 E, u32* inst_entry, u32* inst_tile,
-    u32* sh0_all, u32* sl0_all) {
-    __shared__ u64 s[SORT_LDS];
-    const uint2 rg = ranges[blockIdx.x];
+// One list longer than SORT_WAVE_MAX, by the whole workgroup.  Merge scratch:
+// (sh0, sl0) and (sh1, ent), where sh1 holds the list's tile ids, rewritten at
+// the end.
+__device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key, u32 E,
+                               u32* inst_entry, u32* inst_tile, u32* sh0_all, u32* sl0_all) {
     const u32 L = rg.y - rg.x;
-    if (L <= SORT_WAVE_MAX) return;
     u32* ent = inst_entry + rg.x;
     if (L <= (u32)SORT_LDS) {
         const u32 n = pow2_at_least(L);
@@ -359,7 +395,21 @@ __global__ void __launch_bounds__(SORT_THREADS) tile_sort_long_kernel(
     }
     for (u32 j = threadIdx.x; j < L; j += SORT_THREADS) {
         if (in_a) ent[j] = al[j];
-        bh[j] = blockIdx.x;   // the tile ids the merge scratch overwrote
+        bh[j] = tile;   // the tile ids the merge scratch overwrote
+    }
+}
+
+// A fixed grid of workgroups walks the tiles and sorts the long lists (few
+// or none), so the launch costs little when there are none.
+__global__ void __launch_bounds__(SORT_THREADS) tile_sort_long_kernel(
+    const uint2* ranges, u32 T, const u32* depth_key, u32 E, u32* inst_entry, u32* inst_tile,
+    u32* sh0_all, u32* sl0_all) {
+    __shared__ u64 s[SORT_LDS];
+    for (u32 t = blockIdx.x; t < T; t += gridDim.x) {
+        const uint2 rg = ranges[t];
+        if (rg.y - rg.x <= SORT_WAVE_MAX) continue;
+        sort_long_list(s, t, rg, depth_key, E, inst_entry, inst_tile, sh0_all, sl0_all);
+        __syncthreads();
     }
 }
 
@@ -381,21 +431,15 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     const int64_t E = f->E;
     u32* cnt = f->counters;
     if (E > 0) {
-        // flags[e] = (tiles_touched[e] > 0) come from the projection;
-        // the compaction reads them without modifying them, so rendering the same
-        // projection again repeats the same work.
-        GS_TRY(gs_scan_reduce(f->flags, nullptr, nullptr, (u32)E, f->scan_part, s));
-        const CompactEpi ce{f->visible, cnt + 0};
-        scan_down_kernel<CompactEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->flags, nullptr, nullptr,
-                                                                      (u32)E, f->scan_part, ce);
-        GS_TRY(gs_check_launch("compact"));
-        // instance offsets: exclusive scan of the visible entries' tile counts, with chunk starts
-        GS_TRY(gs_scan_reduce(f->tiles_touched, f->visible, cnt + 0, 0, f->scan_part, s));
-        const ChunkEpi he{f->inst_off, f->chunk_start, cnt, (u32)f->cap};
-        scan_down_kernel<ChunkEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(
-            f->tiles_touched, f->visible, cnt + 0, 0, f->scan_part, he);
-        GS_TRY(gs_check_launch("instance_offsets"));
-        emit_kernel<<<2048, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat, f->d_views,
+        // visible entries and instance offsets from the projection's tile
+        // counts (read only, so rendering one projection twice repeats the work)
+        u64* part = (u64*)f->scan_part;
+        vis_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part);
+        GS_TRY(gs_check_launch("visible_reduce"));
+        const VisEpi ve{f->visible, f->inst_off, f->chunk_start, cnt, (u32)f->cap};
+        vis_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part, ve);
+        GS_TRY(gs_check_launch("visible_scan"));
+        emit_kernel<<<8192, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat, f->d_views,
                                               f->n, cnt + 0, cnt + 5, f->chunk_start, f->ikeys[0],
                                               f->ivals[0], E, (u32)f->T);
         GS_TRY(gs_check_launch("emit"));
@@ -411,9 +455,10 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         tile_sort_wave_kernel<<<(unsigned)f->T, 64, 0, s>>>(f->ranges, f->depth_key, (u32)E,
                                                            f->ivals[f->isorted]);
         GS_TRY(gs_check_launch("tile_sort_wave"));
-        tile_sort_long_kernel<<<(unsigned)f->T, SORT_THREADS, 0, s>>>(
-            f->ranges, f->depth_key, (u32)E, f->ivals[f->isorted], f->ikeys[f->isorted], f->ikeys[o],
-            f->ivals[o]);
+        const unsigned lg = f->T < 1024 ? (unsigned)f->T : 1024u;
+        tile_sort_long_kernel<<<lg, SORT_THREADS, 0, s>>>(f->ranges, (u32)f->T, f->depth_key, (u32)E,
+                                                         f->ivals[f->isorted], f->ikeys[f->isorted],
+                                                         f->ikeys[o], f->ivals[o]);
         GS_TRY(gs_check_launch("tile_sort_long"));
     }
     if (heavy_first) {

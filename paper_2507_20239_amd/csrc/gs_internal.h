@@ -45,7 +45,6 @@ struct gs_frame {
     uint2* rect;         // [E]
     float4* splat;       // [E][3]
     // visible-entry compaction
-    u32* flags;          // [E] 1 if the entry is rendered (from the projection)
     u32* visible;        // [E] visible entries, in entry order
     u32* inst_off;       // [E] instance offset of each visible entry
     // instances (ping-pong)
@@ -70,7 +69,7 @@ struct gs_frame {
     u32* counters;
     // sort and scan scratch
     void* sort_scratch;
-    u32* scan_part;      // [GS_SCAN_PARTS + 1]
+    u32* scan_part;      // [2 (GS_SCAN_PARTS + 8)] (u32 or u64 partial sums)
 };
 
 #define GS_SCAN_PARTS 1024
@@ -116,18 +115,26 @@ __device__ __forceinline__ void chunk_of(u32 n, u32 parts, u32 b, u32& beg, u32&
     end = e0 < n ? (u32)e0 : n;
 }
 
-// Exclusive scan of one value per thread over a 256-thread workgroup.
-__device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* lds4, u32& total) {
+__device__ __forceinline__ u32 shfl_up_any(u32 x, int d) { return (u32)__shfl_up((int)x, d, 64); }
+__device__ __forceinline__ u64 shfl_up_any(u64 x, int d) {
+    const u32 lo = (u32)__shfl_up((int)(u32)x, d, 64);
+    const u32 hi = (u32)__shfl_up((int)(u32)(x >> 32), d, 64);
+    return ((u64)hi << 32) | lo;
+}
+
+// Exclusive scan of one value per thread over a 256-thread workgroup (u32 or u64).
+template <class V>
+__device__ __forceinline__ V block_exclusive_scan(V v, V* lds4, V& total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    u32 x = v;
+    V x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        u32 y = __shfl_up(x, d, 64);
+        const V y = shfl_up_any(x, d);
         if (lane >= d) x += y;
     }
     if (lane == 63) lds4[w] = x;
     __syncthreads();
-    u32 wbase = 0;
+    V wbase = 0;
     for (int j = 0; j < w; ++j) wbase += lds4[j];
     total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
     __syncthreads();

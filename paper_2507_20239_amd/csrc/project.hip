@@ -126,7 +126,6 @@ struct ProjArgs {
     uint2* rect;
     float4* splat;
     float* splat_grad;     // [E][9], cleared here for the adjoint of this step
-    u32* flags;            // [E] 1 if rendered (input of the visible-entry compaction)
     u32* counters;         // frame counters; [6] (sort error) is cleared here
 };
 
@@ -141,26 +140,39 @@ struct Activated {
     double SigD[6];    // the same in FP64 (input of the screen-space covariance)
 };
 
-// Position, scales and opacity: all the culling test needs.
-__device__ __forceinline__ void activate_light(const ProjArgs& a, int64_t i, float mu[3],
-                                              Activated& g) {
+// Raw parameters of one Gaussian (structure-of-arrays loads).
+struct Raw {
+    float mu[3], ls[3], q[4], logit;
+};
+
+__device__ __forceinline__ Raw load_raw(const ProjArgs& a, int64_t i) {
     const int64_t n = a.n;
-    mu[0] = a.means[i];
-    mu[1] = a.means[n + i];
-    mu[2] = a.means[2 * n + i];
+    Raw r;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) g.s[k] = expf(a.log_scales[k * n + i]);
-    g.o = 1.0f / (1.0f + expf(-a.logits[i]));
+    for (int k = 0; k < 3; ++k) r.mu[k] = a.means[k * n + i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.ls[k] = a.log_scales[k * n + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r.q[k] = a.quats[k * n + i];
+    r.logit = a.logits[i];
+    return r;
+}
+
+// Position, scales and opacity: all the culling test needs.
+__device__ __forceinline__ void activate_light(const Raw& r, float mu[3], Activated& g) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mu[k] = r.mu[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.s[k] = expf(r.ls[k]);
+    g.o = 1.0f / (1.0f + expf(-r.logit));
 }
 
 // Rotation and covariance (Eq. 1: Sigma = R S S^T R^T).  Evaluated in FP64:
 // an elongated Gaussian seen edge-on has a screen-space covariance whose
 // determinant cancels to a few 1e-4 of its terms, so FP32 products here would
 // leave the conic with relative errors far above FP32 rounding.
-__device__ __forceinline__ void activate_rot(const ProjArgs& a, int64_t i, Activated& g) {
-    const int64_t n = a.n;
-    const double q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i],
-                 q3 = a.quats[3 * n + i];
+__device__ __forceinline__ void activate_rot(const Raw& r, Activated& g) {
+    const double q0 = r.q[0], q1 = r.q[1], q2 = r.q[2], q3 = r.q[3];
     const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     g.qnorm = (float)qn;
     const double inv = 1.0 / qn;
@@ -269,15 +281,20 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
     if (i == 0) a.counters[6] = 0;   // sort look-back error flag of this step
     if (i >= a.n) return;
     const int64_t n = a.n;
-    float mu[3];
-    Activated g;
-    activate_light(a, i, mu, g);
-    activate_rot(a, i, g);
+    // every load first, so one memory latency covers the parameters and the
+    // colour coefficients (the scheduler would otherwise sink the colour loads
+    // below the activation arithmetic, serialising two latencies)
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) f[k][ch] = a.sh[((int64_t)k * 3 + ch) * n + i];
+    const Raw raw = load_raw(a, i);
+    __builtin_amdgcn_sched_barrier(0);
+    float mu[3];
+    Activated g;
+    activate_light(raw, mu, g);
+    activate_rot(raw, g);
 
     for (int v = 0; v < a.V; ++v) {
         const gs_camera c = a.cams[v];
@@ -337,7 +354,6 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
             }
         }
         a.tiles_touched[e] = tt;
-        a.flags[e] = tt ? 1u : 0u;
         if (tt) {
             a.rect[e] = rc;
             // the adjoint of this step accumulates into these
@@ -371,15 +387,20 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     // zeros): with visibility scattered over the index order every 128-byte
     // line of the SoA arrays is fetched anyway, and a divergent early exit
     // would split each store into partial-line writes.
-    float mu[3];
-    Activated g;
-    activate_light(a, i, mu, g);
-    activate_rot(a, i, g);
+    // every load first, so one memory latency covers the parameters and the
+    // colour coefficients (the scheduler would otherwise sink the colour loads
+    // below the activation arithmetic, serialising two latencies)
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) f[k][ch] = a.sh[((int64_t)k * 3 + ch) * n + i];
+    const Raw raw = load_raw(a, i);
+    __builtin_amdgcn_sched_barrier(0);
+    float mu[3];
+    Activated g;
+    activate_light(raw, mu, g);
+    activate_rot(raw, g);
 
     float dmu[3] = {0.f, 0.f, 0.f};
     float dls[3] = {0.f, 0.f, 0.f};
@@ -585,7 +606,6 @@ ProjArgs make_args(gs_frame* f, const gs_gaussians* g, const gs_camera* cams, fl
     a.rect = f->rect;
     a.splat = f->splat;
     a.splat_grad = f->splat_grad;
-    a.flags = f->flags;
     a.counters = f->counters;
     return a;
 }
