@@ -112,7 +112,8 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
                                                         u32* entries, int64_t E, u32 T) {
     __shared__ u32 s_off[EMIT_CHUNK], s_e[EMIT_CHUNK], s_rx[EMIT_CHUNK], s_ry[EMIT_CHUNK];
     __shared__ u32 s_tb[EMIT_CHUNK], s_tw[EMIT_CHUNK];
-    __shared__ float4 s_p0[EMIT_CHUNK], s_p1[EMIT_CHUNK];
+    // the footprint row constants of each staged entry, computed once per entry
+    __shared__ float s_fr[9][EMIT_CHUNK];
     const int t = threadIdx.x;
     const u32 nv = *n_vis, kept = *n_kept;
     const u32 chunks = (kept + EMIT_CHUNK - 1) / EMIT_CHUNK;
@@ -136,8 +137,16 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
             s_ry[t] = r.y;
             s_tb[t] = (u32)views[v].tile_base;
             s_tw[t] = (u32)views[v].tiles_x;
-            s_p0[t] = splat[3 * (u64)e];
-            s_p1[t] = splat[3 * (u64)e + 1];
+            const FootprintRows fr = footprint_rows(splat[3 * (u64)e], splat[3 * (u64)e + 1]);
+            s_fr[0][t] = fr.l21;
+            s_fr[1][t] = fr.l22;
+            s_fr[2][t] = fr.r2;
+            s_fr[3][t] = fr.ry;
+            s_fr[4][t] = fr.ds;
+            s_fr[5][t] = fr.il11;
+            s_fr[6][t] = fr.mx;
+            s_fr[7][t] = fr.hy;
+            s_fr[8][t] = fr.ly;
         }
         __syncthreads();
         const u32 o = c * EMIT_CHUNK + (u32)t;
@@ -154,7 +163,16 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
             const u32 rx = s_rx[lo], ry = s_ry[lo];
             const int x0 = (int)(rx & 0xffffu), x1 = (int)(rx >> 16);
             const int y0 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
-            const FootprintRows fr = footprint_rows(s_p0[lo], s_p1[lo]);
+            FootprintRows fr;
+            fr.l21 = s_fr[0][lo];
+            fr.l22 = s_fr[1][lo];
+            fr.r2 = s_fr[2][lo];
+            fr.ry = s_fr[3][lo];
+            fr.ds = s_fr[4][lo];
+            fr.il11 = s_fr[5][lo];
+            fr.mx = s_fr[6][lo];
+            fr.hy = s_fr[7][lo];
+            fr.ly = s_fr[8][lo];
             u32 tile = T;   // not reached: the rows hold exactly the counted tiles
             for (int ty = y0; ty <= y1; ++ty) {
                 int first = 0;
