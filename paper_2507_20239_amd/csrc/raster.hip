@@ -153,8 +153,9 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
                 for (int i = 0; i < PIX; ++i) {
                     const float alpha = fminf(p1.w * quad_G(q, i), GS_ALPHA_MAX);
                     const bool hit = alpha >= GS_ALPHA_MIN;
-                    // a finished pixel has T < 0, so Tn < 0 and it never takes
-                    const float Tn = T[i] * (1.f - alpha);
+                    // T (1 - alpha) with one rounding; a finished pixel has T < 0,
+                    // so Tn < 0 and it never takes
+                    const float Tn = fmaf(-alpha, T[i], T[i]);
                     const bool take = hit && Tn >= GS_T_MIN;
                     // alpha T as the drop in transmittance
                     const float wgt = take ? T[i] - Tn : 0.f;
