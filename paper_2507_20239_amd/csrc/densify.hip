@@ -140,34 +140,24 @@ __global__ void split_normals_kernel(const int64_t* parents, const int32_t* chil
     z[3 * k + 2] = zz[2];
 }
 
-__global__ void apply_rows_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                  const int32_t* __restrict__ src, const uint8_t* __restrict__ kind,
-                                  int64_t n_in, int64_t n_out, int policy) {
-    const int64_t j = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-    if (j >= n_out) return;
-    const int r = blockIdx.y;
-    const uint8_t k = kind[j];
-    float v;
-    if (policy == GS_ATTR_ZERO) {
-        v = 0.f;
-    } else if (policy == GS_ATTR_ZERO_NEW && k != GS_KIND_KEEP) {
-        v = 0.f;
-    } else {
-        v = in[r * n_in + src[j]];
-        if (policy == GS_ATTR_LOGSCALE && (k == GS_KIND_SPLIT0 || k == GS_KIND_SPLIT1))
-            v = v - 0.47000362924573558f;  // ln(1.6)
-    }
-    out[r * n_out + j] = v;
-}
+// Every attribute of the compaction in one pass: a thread owns one output
+// slot, reads its source index and kind once, and writes that slot of every
+// row of every attribute (rows of one attribute four at a time, so their loads
+// are in flight together).  Consecutive threads touch consecutive slots of a
+// row: the writes are sequential and the reads nearly so (sources ascend).
+constexpr int APPLY_MAX_ATTRS = 16;
 
-__global__ void apply_means_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                   const int32_t* __restrict__ src, const uint8_t* __restrict__ kind,
-                                   int64_t n_in, int64_t n_out, const float* __restrict__ ls,
-                                   const float* __restrict__ quats, u64 seed, u64 step) {
-    const int64_t j = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-    if (j >= n_out) return;
-    const int64_t i = src[j];
-    const uint8_t k = kind[j];
+struct ApplyTable {
+    gs_attr a[APPLY_MAX_ATTRS];
+    int count;
+};
+
+// position of a kept or cloned Gaussian, or of a split child: the parent's
+// mean plus R(q) diag(s) z with z from the Philox stream
+__device__ __forceinline__ void apply_mean(const float* __restrict__ in, float* __restrict__ out,
+                                           int64_t i, int64_t j, uint8_t k, int64_t n_in,
+                                           int64_t n_out, const float* __restrict__ ls,
+                                           const float* __restrict__ quats, u64 seed, u64 step) {
     float m0 = in[i], m1 = in[n_in + i], m2 = in[2 * n_in + i];
     if (k == GS_KIND_SPLIT0 || k == GS_KIND_SPLIT1) {
         float z[3];
@@ -190,6 +180,41 @@ __global__ void apply_means_kernel(const float* __restrict__ in, float* __restri
     out[j] = m0;
     out[n_out + j] = m1;
     out[2 * n_out + j] = m2;
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) apply_kernel(ApplyTable t, const int32_t* __restrict__ src,
+                                                         const uint8_t* __restrict__ kind,
+                                                         int64_t n_in, int64_t n_out,
+                                                         const float* __restrict__ ls,
+                                                         const float* __restrict__ quats, u64 seed,
+                                                         u64 step) {
+    const int64_t j = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+    if (j >= n_out) return;
+    const int64_t i = src[j];
+    const uint8_t k = kind[j];
+    const bool split = k == GS_KIND_SPLIT0 || k == GS_KIND_SPLIT1;
+    for (int a = 0; a < t.count; ++a) {
+        const gs_attr at = t.a[a];
+        const float* in = at.in;
+        float* out = at.out;
+        if (at.policy == GS_ATTR_MEAN) {
+            apply_mean(in, out, i, j, k, n_in, n_out, ls, quats, seed, step);
+            continue;
+        }
+        const bool zero = at.policy == GS_ATTR_ZERO || (at.policy == GS_ATTR_ZERO_NEW && k != GS_KIND_KEEP);
+        // log-scales of split children shrink by 1.6 (ln 1.6 subtracted)
+        const float sub = (at.policy == GS_ATTR_LOGSCALE && split) ? 0.47000362924573558f : 0.f;
+        int r = 0;
+        for (; r + 4 <= at.rows; r += 4) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = zero ? 0.f : in[(int64_t)(r + u) * n_in + i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) out[(int64_t)(r + u) * n_out + j] = zero ? 0.f : v[u] - sub;
+        }
+        for (; r < at.rows; ++r)
+            out[(int64_t)r * n_out + j] = zero ? 0.f : in[(int64_t)r * n_in + i] - sub;
+    }
 }
 
 // --- adaptive opacity threshold: radix select of the k-th smallest logit ---
@@ -377,7 +402,7 @@ gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_ou
                            const gs_attr* attrs, int32_t n_attrs, const float* parent_means,
                            const float* parent_log_scales, const float* parent_quats,
                            uint64_t seed, uint64_t step, void* stream) {
-    if (n_out < 0 || n_in < 0 || n_attrs < 0 || n_attrs > 16)
+    if (n_out < 0 || n_in < 0 || n_attrs < 0 || n_attrs > APPLY_MAX_ATTRS)
         return gs_fail(GS_ERR_INVALID, "bad sizes");
     if (n_out == 0) return GS_OK;
     if (!src || !kind || (n_attrs > 0 && !attrs)) return gs_fail(GS_ERR_INVALID, "null pointer");
@@ -394,19 +419,13 @@ gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_ou
         }
     }
     (void)parent_means;
-    for (int a = 0; a < n_attrs; ++a) {
-        const gs_attr& at = attrs[a];
-        if (at.policy == GS_ATTR_MEAN) {
-            apply_means_kernel<<<blocks_for(n_out), GS_BLOCK, 0, s>>>(
-                at.in, at.out, src, kind, n_in, n_out, parent_log_scales, parent_quats, seed, step);
-        } else {
-            dim3 grid(blocks_for(n_out), (unsigned)at.rows);
-            apply_rows_kernel<<<grid, GS_BLOCK, 0, s>>>(at.in, at.out, src, kind, n_in, n_out,
-                                                        at.policy);
-        }
-        GS_TRY(gs_check_launch("densify_apply"));
-    }
-    return GS_OK;
+    if (n_attrs == 0) return GS_OK;
+    ApplyTable t;
+    t.count = n_attrs;
+    for (int a = 0; a < n_attrs; ++a) t.a[a] = attrs[a];
+    apply_kernel<<<blocks_for(n_out), GS_BLOCK, 0, s>>>(t, src, kind, n_in, n_out, parent_log_scales,
+                                                        parent_quats, seed, step);
+    return gs_check_launch("densify_apply");
 }
 
 gs_status gs_split_normals(const int64_t* parents, const int32_t* children, int64_t m,

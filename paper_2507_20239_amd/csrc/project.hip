@@ -283,12 +283,14 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
     const int64_t n = a.n;
     // every load first, so one memory latency covers the parameters and the
     // colour coefficients (the scheduler would otherwise sink the colour loads
-    // below the activation arithmetic, serialising two latencies)
+    // below the activation arithmetic, serialising two latencies); the colour
+    // coefficients, 192 of the 236 bytes, are read once per pass: non-temporal
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) f[k][ch] = a.sh[((int64_t)k * 3 + ch) * n + i];
+        for (int ch = 0; ch < 3; ++ch)
+            f[k][ch] = __builtin_nontemporal_load(a.sh + ((int64_t)k * 3 + ch) * n + i);
     const Raw raw = load_raw(a, i);
     __builtin_amdgcn_sched_barrier(0);
     float mu[3];
@@ -389,12 +391,14 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     // would split each store into partial-line writes.
     // every load first, so one memory latency covers the parameters and the
     // colour coefficients (the scheduler would otherwise sink the colour loads
-    // below the activation arithmetic, serialising two latencies)
+    // below the activation arithmetic, serialising two latencies); the colour
+    // coefficients, 192 of the 236 bytes, are read once per pass: non-temporal
     float f[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) f[k][ch] = a.sh[((int64_t)k * 3 + ch) * n + i];
+        for (int ch = 0; ch < 3; ++ch)
+            f[k][ch] = __builtin_nontemporal_load(a.sh + ((int64_t)k * 3 + ch) * n + i);
     const Raw raw = load_raw(a, i);
     __builtin_amdgcn_sched_barrier(0);
     float mu[3];
@@ -571,18 +575,22 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
         dq[3] = (gz - z * dot) * iq;
     }
 
+    // Gradients and colour coefficients stream through once: non-temporal
+    // stores and loads keep them from evicting the step's reused data and leave
+    // no dirty lines for the next kernel to write back.
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        b.d_means[k * n + i] = dmu[k];
-        b.d_log_scales[k * n + i] = dls[k];
+        __builtin_nontemporal_store(dmu[k], b.d_means + k * n + i);
+        __builtin_nontemporal_store(dls[k], b.d_log_scales + k * n + i);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) b.d_quats[k * n + i] = dq[k];
-    b.d_logits[i] = dlogit;
+    for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(dq[k], b.d_quats + k * n + i);
+    __builtin_nontemporal_store(dlogit, b.d_logits + i);
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) b.d_sh[((int64_t)k * 3 + ch) * n + i] = dsh[k][ch];
+        for (int ch = 0; ch < 3; ++ch)
+            __builtin_nontemporal_store(dsh[k][ch], b.d_sh + ((int64_t)k * 3 + ch) * n + i);
     if (b.accum) {
         b.accum[i] += st_acc;
         b.denom[i] += st_den;
