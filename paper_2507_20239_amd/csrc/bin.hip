@@ -210,14 +210,11 @@ __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, 
 
 // ---- depth order inside each tile's list ------------------------------------
 // Keys are (depth bits << 32 | entry): unique, so any correct sort gives the
-// one order.  A list of up to 512 instances is sorted by one wave holding R
-// keys per lane (element lane R + r in register r) with a bitonic network:
-// stages whose partner distance is below R compare registers of a lane,
-// the others exchange with lane ^ (distance / R).  Longer lists go to a
-// 256-thread workgroup: up to SORT_LDS keys sorted by a bitonic network in
-// LDS, beyond that LDS-sorted runs merged pairwise in global memory (each
-// thread produces a contiguous piece of a merged run after locating its
-// start on the merge path by binary search).
+// one order.  Lists are sorted by a bitonic network on keys held in registers
+// (R per thread): by one wave up to 512 instances, by a 256-thread workgroup
+// up to 2048; longer lists as workgroup-sorted runs of 2048 merged pairwise in
+// global memory (each thread produces a contiguous piece of a merged run
+// after locating its start on the merge path by binary search).
 constexpr u32 SORT_WAVE_MAX = 512;
 constexpr int SORT_LDS = 2048;
 constexpr int SORT_THREADS = 256;
@@ -245,56 +242,80 @@ __device__ __forceinline__ u64 xor_lanes64(u64 x, int m) {
     return ((u64)xor_lanes((u32)(x >> 32), m) << 32) | xor_lanes((u32)x, m);
 }
 
-// ascending bitonic sort of the 64 R keys of a wave, x[r] = element lane R + r
-template <int R>
-__device__ __forceinline__ void wave_bitonic(u64 (&x)[R], u32 lane) {
+// One stage (merge size K, partner distance J) of the ascending bitonic
+// network over the NT R keys of NT threads (one wave or a 256-thread
+// workgroup), x[r] = element t R + r of thread t.  Partners at distance
+// below R are registers of the thread; below 64 R, lanes of the same wave
+// (DPP, swizzle or lane permutation); farther, other waves, through LDS
+// (register-major, so the accesses are conflict-free).  The stages are
+// template instances, so every register index is a constant.
+template <int R, int NT, int K, int J>
+__device__ __forceinline__ void bitonic_stage(u64 (&x)[R], u32 t, u64* lds) {
+    if constexpr (J < R) {
 #pragma unroll
-    for (int k = 2; k <= 64 * R; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j < R) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if ((r & j) == 0) {
-                        const int q = r | j;
-                        const bool up = ((lane * R + r) & k) == 0;
-                        const u64 a = x[r], b = x[q];
-                        const bool sw = up ? (a > b) : (a < b);
-                        x[r] = sw ? b : a;
-                        x[q] = sw ? a : b;
-                    }
-                }
-            } else {
-                const int m = j / R;
-                const bool lower = (lane & m) == 0;
-                // all exchanges of the stage first, so their latencies overlap
-                u64 p[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) p[r] = xor_lanes64(x[r], m);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const bool up = ((lane * R + r) & k) == 0;
-                    // the lower element of an ascending pair keeps the minimum
-                    x[r] = ((x[r] < p[r]) == (lower == up)) ? x[r] : p[r];
-                }
+        for (int r = 0; r < R; ++r) {
+            if ((r & J) == 0) {
+                const int q = r | J;
+                const bool up = ((t * R + r) & K) == 0;
+                const u64 a = x[r], b = x[q];
+                const bool sw = up ? (a > b) : (a < b);
+                x[r] = sw ? b : a;
+                x[q] = sw ? a : b;
             }
         }
+    } else {
+        constexpr int m = J / R;
+        const bool lower = (t & m) == 0;
+        u64 p[R];
+        if constexpr (m < 64) {
+            // all exchanges of the stage first, so their latencies overlap
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r] = xor_lanes64(x[r], m);
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[r * NT + t] = x[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[r] = lds[r * NT + (t ^ m)];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool up = ((t * R + r) & K) == 0;
+            // the lower element of an ascending pair keeps the minimum
+            x[r] = ((x[r] < p[r]) == (lower == up)) ? x[r] : p[r];
+        }
+    }
+    if constexpr (J > 1) bitonic_stage<R, NT, K, J / 2>(x, t, lds);
+}
+
+template <int R, int NT, int K>
+__device__ __forceinline__ void bitonic_merges(u64 (&x)[R], u32 t, u64* lds) {
+    bitonic_stage<R, NT, K, K / 2>(x, t, lds);
+    if constexpr (K < NT * R) bitonic_merges<R, NT, 2 * K>(x, t, lds);
+}
+
+// keys of elements [0, L) of a list (L <= NT R), padded with the largest key
+template <int R, int NT>
+__device__ __forceinline__ void load_list_keys(u64 (&x)[R], const u32* ent, u32 L,
+                                               const u32* depth_key, u32 E, u32 t) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const u32 i = t * R + r;
+        x[r] = i < L ? list_key(depth_key, ent[i], E) : ~0ull;
     }
 }
 
-template <int R>
-__device__ __forceinline__ void wave_sort_list(u32* ent, u32 L, const u32* depth_key, u32 E,
-                                               u32 lane) {
+// sort one list of L <= NT R instances in place
+template <int R, int NT>
+__device__ __forceinline__ void group_sort_list(u32* ent, u32 L, const u32* depth_key, u32 E,
+                                                u32 t, u64* lds) {
     u64 x[R];
+    load_list_keys<R, NT>(x, ent, L, depth_key, E, t);
+    bitonic_merges<R, NT, 2>(x, t, lds);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const u32 i = lane * R + r;
-        x[r] = i < L ? list_key(depth_key, ent[i], E) : ~0ull;
-    }
-    wave_bitonic<R>(x, lane);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const u32 i = lane * R + r;
+        const u32 i = t * R + r;
         if (i < L) ent[i] = (u32)x[r];
     }
 }
@@ -307,73 +328,44 @@ __global__ void __launch_bounds__(64) tile_sort_wave_kernel(const uint2* ranges,
     if (L <= 1 || L > SORT_WAVE_MAX) return;
     u32* ent = inst_entry + rg.x;
     const u32 lane = threadIdx.x;
-    if (L <= 64) wave_sort_list<1>(ent, L, depth_key, E, lane);
-    else if (L <= 128) wave_sort_list<2>(ent, L, depth_key, E, lane);
-    else if (L <= 256) wave_sort_list<4>(ent, L, depth_key, E, lane);
-    else wave_sort_list<8>(ent, L, depth_key, E, lane);
-}
-
-// ascending bitonic sort of s[0..n) by the workgroup, n a power of two
-__device__ void bitonic_lds(u64* s, u32 n) {
-    for (u32 k = 2; k <= n; k <<= 1)
-        for (u32 j = k >> 1; j > 0; j >>= 1) {
-            for (u32 i = threadIdx.x; i < n / 2; i += SORT_THREADS) {
-                const u32 lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-                const u32 hi = lo + j;
-                const u64 a = s[lo], b = s[hi];
-                if ((a > b) == ((lo & k) == 0)) {
-                    s[lo] = b;
-                    s[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-}
-
-__device__ __forceinline__ u32 pow2_at_least(u32 x) {
-    u32 n = 1;
-    while (n < x) n <<= 1;
-    return n;
+    if (L <= 64) group_sort_list<1, 64>(ent, L, depth_key, E, lane, nullptr);
+    else if (L <= 128) group_sort_list<2, 64>(ent, L, depth_key, E, lane, nullptr);
+    else if (L <= 256) group_sort_list<4, 64>(ent, L, depth_key, E, lane, nullptr);
+    else group_sort_list<8, 64>(ent, L, depth_key, E, lane, nullptr);
 }
 
 __device__ __forceinline__ u64 run_key(const u32* kh, const u32* kl, u32 i) {
     return ((u64)kh[i] << 32) | kl[i];
 }
 
-// One list longer than SORT_WAVE_MAX, by the whole workgroup.  Merge scratch:
-// (sh0, sl0) and (sh1, ent), where sh1 holds the list's tile ids, rewritten at
-// the end.
+// One list longer than SORT_LDS, by the whole workgroup: runs of SORT_LDS
+// sorted in registers into (sh0, sl0), then merged pairwise, ping-pong with
+// (sh1, ent), where sh1 holds the list's tile ids, rewritten at the end.
 __device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key, u32 E,
                                u32* inst_entry, u32* inst_tile, u32* sh0_all, u32* sl0_all) {
     const u32 L = rg.y - rg.x;
+    const u32 t = threadIdx.x;
     u32* ent = inst_entry + rg.x;
-    if (L <= (u32)SORT_LDS) {
-        const u32 n = pow2_at_least(L);
-        for (u32 j = threadIdx.x; j < n; j += SORT_THREADS)
-            s[j] = j < L ? list_key(depth_key, ent[j], E) : ~0ull;
-        __syncthreads();
-        bitonic_lds(s, n);
-        for (u32 j = threadIdx.x; j < L; j += SORT_THREADS) ent[j] = (u32)s[j];
-        return;
-    }
     u32* ah = sh0_all + rg.x;
     u32* al = sl0_all + rg.x;
     u32* bh = inst_tile + rg.x;
     u32* bl = ent;
-    // runs of SORT_LDS keys, sorted in LDS, into (ah, al)
+    constexpr int R = SORT_LDS / SORT_THREADS;
     for (u32 r0 = 0; r0 < L; r0 += SORT_LDS) {
         const u32 m = L - r0 < (u32)SORT_LDS ? L - r0 : (u32)SORT_LDS;
-        const u32 n = pow2_at_least(m);
-        for (u32 j = threadIdx.x; j < n; j += SORT_THREADS)
-            s[j] = j < m ? list_key(depth_key, ent[r0 + j], E) : ~0ull;
-        __syncthreads();
-        bitonic_lds(s, n);
-        for (u32 j = threadIdx.x; j < m; j += SORT_THREADS) {
-            ah[r0 + j] = (u32)(s[j] >> 32);
-            al[r0 + j] = (u32)s[j];
+        u64 x[R];
+        load_list_keys<R, SORT_THREADS>(x, ent + r0, m, depth_key, E, t);
+        bitonic_merges<R, SORT_THREADS, 2>(x, t, s);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const u32 i = t * R + r;
+            if (i < m) {
+                ah[r0 + i] = (u32)(x[r] >> 32);
+                al[r0 + i] = (u32)x[r];
+            }
         }
-        __syncthreads();
     }
+    __syncthreads();
     // merge passes, ping-pong between (ah, al) and (bh, bl)
     bool in_a = true;
     for (u32 w = SORT_LDS; w < L; w <<= 1) {
@@ -387,7 +379,7 @@ __device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key,
             const u32 b1 = i0 + 2 * w < L ? i0 + 2 * w : L;
             const u32 na = a1 - a0, nb = b1 - a1, tot = na + nb;
             const u32 per = (tot + SORT_THREADS - 1) / SORT_THREADS;
-            const u32 p0 = threadIdx.x * per;
+            const u32 p0 = t * per;
             if (p0 >= tot) continue;
             const u32 p1 = p0 + per < tot ? p0 + per : tot;
             // merge path: how many of the first p0 outputs come from run A
@@ -411,22 +403,33 @@ __device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key,
         __syncthreads();
         in_a = !in_a;
     }
-    for (u32 j = threadIdx.x; j < L; j += SORT_THREADS) {
+    for (u32 j = t; j < L; j += SORT_THREADS) {
         if (in_a) ent[j] = al[j];
         bh[j] = tile;   // the tile ids the merge scratch overwrote
     }
 }
 
-// A fixed grid of workgroups walks the tiles and sorts the long lists (few
-// or none), so the launch costs little when there are none.
+// Lists longer than one wave sorts: each workgroup takes LONG_TILES
+// consecutive tiles and sorts their long lists one after the other, in
+// registers across its four waves up to SORT_LDS instances, beyond that as
+// runs and merges.
+constexpr u32 LONG_TILES = 2;
+
 __global__ void __launch_bounds__(SORT_THREADS) tile_sort_long_kernel(
     const uint2* ranges, u32 T, const u32* depth_key, u32 E, u32* inst_entry, u32* inst_tile,
     u32* sh0_all, u32* sl0_all) {
     __shared__ u64 s[SORT_LDS];
-    for (u32 t = blockIdx.x; t < T; t += gridDim.x) {
-        const uint2 rg = ranges[t];
-        if (rg.y - rg.x <= SORT_WAVE_MAX) continue;
-        sort_long_list(s, t, rg, depth_key, E, inst_entry, inst_tile, sh0_all, sl0_all);
+    const u32 t0 = blockIdx.x * LONG_TILES;
+    for (u32 k = 0; k < LONG_TILES; ++k) {
+        const uint2 rg = t0 + k < T ? ranges[t0 + k] : make_uint2(0u, 0u);
+        const u32 L = rg.y - rg.x;
+        if (L <= SORT_WAVE_MAX) continue;
+        if (L <= 1024)
+            group_sort_list<4, SORT_THREADS>(inst_entry + rg.x, L, depth_key, E, threadIdx.x, s);
+        else if (L <= (u32)SORT_LDS)
+            group_sort_list<8, SORT_THREADS>(inst_entry + rg.x, L, depth_key, E, threadIdx.x, s);
+        else
+            sort_long_list(s, t0 + k, rg, depth_key, E, inst_entry, inst_tile, sh0_all, sl0_all);
         __syncthreads();
     }
 }
@@ -473,7 +476,7 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         tile_sort_wave_kernel<<<(unsigned)f->T, 64, 0, s>>>(f->ranges, f->depth_key, (u32)E,
                                                            f->ivals[f->isorted]);
         GS_TRY(gs_check_launch("tile_sort_wave"));
-        const unsigned lg = f->T < 1024 ? (unsigned)f->T : 1024u;
+        const unsigned lg = (unsigned)((f->T + LONG_TILES - 1) / LONG_TILES);
         tile_sort_long_kernel<<<lg, SORT_THREADS, 0, s>>>(f->ranges, (u32)f->T, f->depth_key, (u32)E,
                                                          f->ivals[f->isorted], f->ikeys[f->isorted],
                                                          f->ikeys[o], f->ivals[o]);

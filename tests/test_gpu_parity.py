@@ -28,10 +28,11 @@ def _scenes():
     rag = synth.random_scene(21, 300, 37, 29, sh_degree=3, log_scale=(-2.6, 0.5), spread=1.0)
     rag.bg = np.array([0.2, 0.4, 0.1], np.float32)
     deg1 = synth.random_scene(22, 500, 70, 45, sh_degree=1, logit=(1.5, 1.0), log_scale=(-2.2, 0.5))
-    # tile lists of 1147 .. 6686 instances: LDS sorts, and runs merged once or twice
-    dense = synth.random_scene(23, 7000, 40, 40, sh_degree=0, log_scale=(-2.5, 0.4))
+    # tile lists of 676 .. 13458 instances: wave sorts in registers, LDS sorts, and LDS-sorted
+    # runs merged once to three times
+    dense = synth.random_scene(23, 24000, 64, 40, sh_degree=0, log_scale=(-2.6, 0.4))
     return {"c1_2000_128x128_sh0": c1, "ragged_300_37x29_sh3": rag, "sh1_500_70x45": deg1,
-            "dense_7000_40x40_sh0": dense}
+            "dense_24000_64x40_sh0": dense}
 
 
 SCENES = _scenes()
@@ -89,11 +90,16 @@ def test_binning_lists_match_oracle_exactly(name):
         np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(ranges))
 
 
-def test_dense_scene_has_lists_beyond_one_lds_sort():
-    sc = SCENES["dense_7000_40x40_sh0"]
-    _, _, ranges = oracle.tile_lists(oracle.project(sc, sc.cameras[0]))
-    lens = ranges[:, 1] - ranges[:, 0]
-    assert lens.max() > 4 * 1024 and ((lens > 2048) & (lens <= 4096)).any()
+def test_scenes_cover_every_list_sort_path():
+    # one wave with R <= 8 (<= 512) and R = 16 (<= 1024), one LDS sort (<= 2048), LDS runs merged
+    # once (<= 4096), twice (<= 8192) and more
+    lens = []
+    for sc in SCENES.values():
+        _, _, ranges = oracle.tile_lists(oracle.project(sc, sc.cameras[0]))
+        lens.append(ranges[:, 1] - ranges[:, 0])
+    lens = np.concatenate(lens)
+    for lo, hi in ((1, 512), (512, 1024), (1024, 2048), (2048, 4096), (4096, 8192), (8192, 1 << 30)):
+        assert ((lens > lo) & (lens <= hi)).any(), (lo, hi)
 
 
 @pytest.mark.parametrize("name", list(SCENES))
