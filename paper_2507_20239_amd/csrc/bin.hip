@@ -320,14 +320,9 @@ __device__ __forceinline__ void group_sort_list(u32* ent, u32 L, const u32* dept
     }
 }
 
-__global__ void __launch_bounds__(64) tile_sort_wave_kernel(const uint2* ranges,
-                                                            const u32* depth_key, u32 E,
-                                                            u32* inst_entry) {
-    const uint2 rg = ranges[blockIdx.x];
-    const u32 L = rg.y - rg.x;
-    if (L <= 1 || L > SORT_WAVE_MAX) return;
-    u32* ent = inst_entry + rg.x;
-    const u32 lane = threadIdx.x;
+// sort one list of 2 .. 512 instances by one wave (lane = thread index in the wave)
+__device__ __forceinline__ void wave_sort_short_list(u32* ent, u32 L, const u32* depth_key, u32 E,
+                                                     u32 lane) {
     if (L <= 64) group_sort_list<1, 64>(ent, L, depth_key, E, lane, nullptr);
     else if (L <= 128) group_sort_list<2, 64>(ent, L, depth_key, E, lane, nullptr);
     else if (L <= 256) group_sort_list<4, 64>(ent, L, depth_key, E, lane, nullptr);
@@ -409,18 +404,26 @@ __device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key,
     }
 }
 
-// Lists longer than one wave sorts: each workgroup takes LONG_TILES
-// consecutive tiles and sorts their long lists one after the other, in
-// registers across its four waves up to SORT_LDS instances, beyond that as
-// runs and merges.
-constexpr u32 LONG_TILES = 2;
+// Every tile list in one launch: each 256-thread workgroup takes four
+// consecutive tiles, wave w sorts tile t0 + w if its list is short (up to 512
+// instances), then the workgroup sorts the longer lists among the four one
+// after the other: in registers across its four waves up to SORT_LDS
+// instances, beyond that as runs and merges.
+constexpr u32 SORT_TILES = SORT_THREADS / 64;
 
-__global__ void __launch_bounds__(SORT_THREADS) tile_sort_long_kernel(
+__global__ void __launch_bounds__(SORT_THREADS) tile_sort_kernel(
     const uint2* ranges, u32 T, const u32* depth_key, u32 E, u32* inst_entry, u32* inst_tile,
     u32* sh0_all, u32* sl0_all) {
     __shared__ u64 s[SORT_LDS];
-    const u32 t0 = blockIdx.x * LONG_TILES;
-    for (u32 k = 0; k < LONG_TILES; ++k) {
+    const u32 t0 = blockIdx.x * SORT_TILES;
+    {
+        const u32 t = t0 + (threadIdx.x >> 6);
+        const uint2 rg = t < T ? ranges[t] : make_uint2(0u, 0u);
+        const u32 L = rg.y - rg.x;
+        if (L > 1 && L <= SORT_WAVE_MAX)
+            wave_sort_short_list(inst_entry + rg.x, L, depth_key, E, threadIdx.x & 63);
+    }
+    for (u32 k = 0; k < SORT_TILES; ++k) {
         const uint2 rg = t0 + k < T ? ranges[t0 + k] : make_uint2(0u, 0u);
         const u32 L = rg.y - rg.x;
         if (L <= SORT_WAVE_MAX) continue;
@@ -473,14 +476,11 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
     GS_TRY(gs_check_launch("ranges"));
     if (E > 0 && f->T > 0) {
         const int o = f->isorted ^ 1;
-        tile_sort_wave_kernel<<<(unsigned)f->T, 64, 0, s>>>(f->ranges, f->depth_key, (u32)E,
-                                                           f->ivals[f->isorted]);
-        GS_TRY(gs_check_launch("tile_sort_wave"));
-        const unsigned lg = (unsigned)((f->T + LONG_TILES - 1) / LONG_TILES);
-        tile_sort_long_kernel<<<lg, SORT_THREADS, 0, s>>>(f->ranges, (u32)f->T, f->depth_key, (u32)E,
-                                                         f->ivals[f->isorted], f->ikeys[f->isorted],
-                                                         f->ikeys[o], f->ivals[o]);
-        GS_TRY(gs_check_launch("tile_sort_long"));
+        const unsigned sg = (unsigned)((f->T + SORT_TILES - 1) / SORT_TILES);
+        tile_sort_kernel<<<sg, SORT_THREADS, 0, s>>>(f->ranges, (u32)f->T, f->depth_key, (u32)E,
+                                                    f->ivals[f->isorted], f->ikeys[f->isorted],
+                                                    f->ikeys[o], f->ivals[o]);
+        GS_TRY(gs_check_launch("tile_sort"));
     }
     if (heavy_first) {
         tile_weight_kernel<<<blocks_for(f->T), GS_BLOCK, 0, s>>>(f->ranges, f->tkeys[0], f->tvals[0],
