@@ -146,8 +146,8 @@ enum {
                                  kappa Q, Q = Sigma'^-1 the conic, kappa = log2(e)/2, so that
                                  G(d) = 2^-((l11 dx + l21 dy)^2 + (l22 dy)^2) */
     GS_BUF_VISIBLE = 4,       /* u32 [V*n]   visible entries (tiles_touched > 0), in entry order */
-    GS_BUF_INST_TILE = 5,     /* u32 [cap]   tile id of each sorted instance */
-    GS_BUF_INST_ENTRY = 6,    /* u32 [cap]   entry id of each sorted instance */
+    GS_BUF_INST_TILE = 5,     /* u32 [cap]   tile id of each instance, in (tile, depth bits, entry) order */
+    GS_BUF_INST_ENTRY = 6,    /* u32 [cap]   entry id of each instance, same order */
     GS_BUF_RANGES = 7,        /* u32 [T][2]  [start, end) of each tile's instance list */
     GS_BUF_T_FINAL = 8,       /* f32 [P]     final transmittance per pixel */
     GS_BUF_N_CONTRIB = 9,     /* u32 [P]     instances walked per pixel (last composited + 1) */
@@ -178,7 +178,8 @@ gs_status gs_project(gs_frame* frame, const gs_gaussians* g, const gs_camera* ca
                      const gs_raster_opts* opts, void* stream);
 
 /* render(view, resolution): sort the projected footprints into per-tile,
- * depth-ordered lists (prefix sums and LSD radix sorts) and composite every
+ * depth-ordered lists (prefix sums, an LSD radix sort on the tile id, then
+ * each tile's list ordered by (depth bits, entry)) and composite every
  * pixel of every view front to back (Eq. 2).  images: device FP32, the views'
  * planar images one after the other (sum_v 3 H_v W_v floats).  Also keeps the
  * per-pixel final transmittance and walk length for the backward. */
