@@ -8,19 +8,22 @@
 // where a = dS/dmu, b = dS/dExx, c = dS/dExy are maps over the pixels p
 // (G is symmetric, so correlating with it is convolving with it).
 //
-// Three launches per image: the forward computes S and (a, b, c) for a 16x16
-// tile per workgroup from a 26x26 LDS patch (separable: a horizontal pass to
-// 26x16 partial sums, then a vertical one); the backward filters (a, b, c) the
-// same way and combines them with I and T at each pixel; a one-workgroup
-// launch sums the per-tile losses in a fixed order.  HBM-bound: about
-// 44 B per channel-pixel over the two launches.
+// Three launches per image: the forward computes S and (a, b, c) for a 32x16
+// tile per workgroup from a 42x26 LDS patch (separable: a horizontal pass to
+// 26x32 partial sums, then a vertical one, two output pixels per thread); the
+// backward filters (a, b, c) the same way and combines them with I and T at
+// each pixel; a one-workgroup launch sums the per-tile losses in a fixed
+// order.  HBM-bound: about 44 B per channel-pixel over the two launches.
 #include "gs_internal.h"
 
 namespace {
 
-constexpr int ST = 16;              // output tile edge
+constexpr int TW = 32;              // output tile width
+constexpr int TH = 16;              // output tile height
 constexpr int SR = 5;               // window radius
-constexpr int SP = ST + 2 * SR;     // patch edge (26)
+constexpr int PW = TW + 2 * SR;     // patch width (42)
+constexpr int PH = TH + 2 * SR;     // patch height (26)
+constexpr int OUT_PER_THREAD = TW * TH / 256;   // 2 output pixels per thread
 
 struct Window {
     float g[2 * SR + 1];
@@ -34,23 +37,23 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__
                                                        const float* __restrict__ tgt, int H, int W,
                                                        Window win, float lambda, float inv_n,
                                                        float* abc, float* partial) {
-    __shared__ float sx[SP][SP], sy[SP][SP];
-    __shared__ float h[5][SP][ST];
+    __shared__ float sx[PH][PW], sy[PH][PW];
+    __shared__ float h[5][PH][TW];
     __shared__ float red[2][4];
     const int c = blockIdx.z;
     const int64_t plane = (int64_t)H * W;
     const float* X = img + c * plane;
     const float* Y = tgt + c * plane;
-    const int x0 = blockIdx.x * ST - SR, y0 = blockIdx.y * ST - SR;
+    const int x0 = blockIdx.x * TW - SR, y0 = blockIdx.y * TH - SR;
     const int t = threadIdx.x;
-    for (int i = t; i < SP * SP; i += 256) {
-        const int r = i / SP, q = i % SP;
+    for (int i = t; i < PH * PW; i += 256) {
+        const int r = i / PW, q = i % PW;
         sx[r][q] = patch_at(X, H, W, y0 + r, x0 + q);
         sy[r][q] = patch_at(Y, H, W, y0 + r, x0 + q);
     }
     __syncthreads();
-    for (int i = t; i < SP * ST; i += 256) {
-        const int r = i / ST, q = i % ST;
+    for (int i = t; i < PH * TW; i += 256) {
+        const int r = i / TW, q = i % TW;
         float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
 #pragma unroll
         for (int k = 0; k <= 2 * SR; ++k) {
@@ -68,35 +71,37 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__
         h[4][r][q] = m4;
     }
     __syncthreads();
-    const int r = t / ST, q = t % ST;
-    float mu = 0.f, nu = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
-#pragma unroll
-    for (int k = 0; k <= 2 * SR; ++k) {
-        const float w = win.g[k];
-        mu = fmaf(w, h[0][r + k][q], mu);
-        nu = fmaf(w, h[1][r + k][q], nu);
-        exx = fmaf(w, h[2][r + k][q], exx);
-        eyy = fmaf(w, h[3][r + k][q], eyy);
-        exy = fmaf(w, h[4][r + k][q], exy);
-    }
     const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
-    const float A = fmaf(2.f * mu, nu, C1);
-    const float B = fmaf(2.f, exy - mu * nu, C2);
-    const float Cc = fmaf(mu, mu, fmaf(nu, nu, C1));
-    const float D = (exx - mu * mu) + (eyy - nu * nu) + C2;
-    const float S = (A * B) / (Cc * D);
-    const int py = blockIdx.y * ST + r, px = blockIdx.x * ST + q;
-    const bool in = py < H && px < W;
+    const int64_t map = (int64_t)gridDim.z * plane;   // maps a, b, c one after the other
     float s_sum = 0.f, l1_sum = 0.f;
-    if (in) {
-        const int64_t o = c * plane + (int64_t)py * W + px;
-        // dS/dmu, dS/dExx, dS/dExy
-        const int64_t map = (int64_t)gridDim.z * plane;   // maps a, b, c one after the other
-        abc[o] = S * (2.f * nu / A - 2.f * nu / B - 2.f * mu / Cc + 2.f * mu / D);
-        abc[map + o] = -S / D;
-        abc[2 * map + o] = 2.f * S / B;
-        s_sum = S;
-        l1_sum = fabsf(sx[r + SR][q + SR] - sy[r + SR][q + SR]);
+#pragma unroll
+    for (int j = 0; j < OUT_PER_THREAD; ++j) {
+        const int r = t / TW + j * (256 / TW), q = t % TW;
+        float mu = 0.f, nu = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+#pragma unroll
+        for (int k = 0; k <= 2 * SR; ++k) {
+            const float w = win.g[k];
+            mu = fmaf(w, h[0][r + k][q], mu);
+            nu = fmaf(w, h[1][r + k][q], nu);
+            exx = fmaf(w, h[2][r + k][q], exx);
+            eyy = fmaf(w, h[3][r + k][q], eyy);
+            exy = fmaf(w, h[4][r + k][q], exy);
+        }
+        const float A = fmaf(2.f * mu, nu, C1);
+        const float B = fmaf(2.f, exy - mu * nu, C2);
+        const float Cc = fmaf(mu, mu, fmaf(nu, nu, C1));
+        const float D = (exx - mu * mu) + (eyy - nu * nu) + C2;
+        const float S = (A * B) / (Cc * D);
+        const int py = blockIdx.y * TH + r, px = blockIdx.x * TW + q;
+        if (py < H && px < W) {
+            const int64_t o = c * plane + (int64_t)py * W + px;
+            // dS/dmu, dS/dExx, dS/dExy
+            abc[o] = S * (2.f * nu / A - 2.f * nu / B - 2.f * mu / Cc + 2.f * mu / D);
+            abc[map + o] = -S / D;
+            abc[2 * map + o] = 2.f * S / B;
+            s_sum += S;
+            l1_sum += fabsf(sx[r + SR][q + SR] - sy[r + SR][q + SR]);
+        }
     }
     // loss += inv_n ((1 - lambda) sum |I - T| + lambda sum (1 - S)) over this tile
     s_sum = wave_sum_lane63(s_sum);
@@ -110,7 +115,7 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__
     if (t == 0) {
         const float ssum = red[0][0] + red[0][1] + red[0][2] + red[0][3];
         const float lsum = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-        const int nin = (min(ST, H - (int)blockIdx.y * ST)) * (min(ST, W - (int)blockIdx.x * ST));
+        const int nin = (min(TH, H - (int)blockIdx.y * TH)) * (min(TW, W - (int)blockIdx.x * TW));
         const u32 b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
         partial[b] = inv_n * ((1.f - lambda) * lsum + lambda * ((float)nin - ssum));
     }
@@ -138,21 +143,21 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float* __restrict__
                                                        Window win, float lambda, float inv_n,
                                                        const float* __restrict__ abc,
                                                        float* __restrict__ grad) {
-    __shared__ float sa[3][SP][SP];
-    __shared__ float h[3][SP][ST];
+    __shared__ float sa[3][PH][PW];
+    __shared__ float h[3][PH][TW];
     const int c = blockIdx.z;
     const int64_t plane = (int64_t)H * W;
-    const int x0 = blockIdx.x * ST - SR, y0 = blockIdx.y * ST - SR;
+    const int x0 = blockIdx.x * TW - SR, y0 = blockIdx.y * TH - SR;
     const int t = threadIdx.x;
-    for (int i = t; i < SP * SP; i += 256) {
-        const int r = i / SP, q = i % SP;
+    for (int i = t; i < PH * PW; i += 256) {
+        const int r = i / PW, q = i % PW;
 #pragma unroll
         for (int m = 0; m < 3; ++m)
             sa[m][r][q] = patch_at(abc + ((int64_t)m * gridDim.z + c) * plane, H, W, y0 + r, x0 + q);
     }
     __syncthreads();
-    for (int i = t; i < SP * ST; i += 256) {
-        const int r = i / ST, q = i % ST;
+    for (int i = t; i < PH * TW; i += 256) {
+        const int r = i / TW, q = i % TW;
         float m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
         for (int k = 0; k <= 2 * SR; ++k) {
@@ -166,22 +171,25 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float* __restrict__
         h[2][r][q] = m2;
     }
     __syncthreads();
-    const int r = t / ST, q = t % ST;
-    const int py = blockIdx.y * ST + r, px = blockIdx.x * ST + q;
-    if (py >= H || px >= W) return;
-    float ga = 0.f, gb = 0.f, gc = 0.f;
 #pragma unroll
-    for (int k = 0; k <= 2 * SR; ++k) {
-        const float w = win.g[k];
-        ga = fmaf(w, h[0][r + k][q], ga);
-        gb = fmaf(w, h[1][r + k][q], gb);
-        gc = fmaf(w, h[2][r + k][q], gc);
+    for (int j = 0; j < OUT_PER_THREAD; ++j) {
+        const int r = t / TW + j * (256 / TW), q = t % TW;
+        const int py = blockIdx.y * TH + r, px = blockIdx.x * TW + q;
+        if (py >= H || px >= W) continue;
+        float ga = 0.f, gb = 0.f, gc = 0.f;
+#pragma unroll
+        for (int k = 0; k <= 2 * SR; ++k) {
+            const float w = win.g[k];
+            ga = fmaf(w, h[0][r + k][q], ga);
+            gb = fmaf(w, h[1][r + k][q], gb);
+            gc = fmaf(w, h[2][r + k][q], gc);
+        }
+        const int64_t o = c * plane + (int64_t)py * W + px;
+        const float I = img[o], Tt = tgt[o];
+        const float dssim = fmaf(2.f * I, gb, ga) + Tt * gc;
+        const float sgn = I > Tt ? 1.f : (I < Tt ? -1.f : 0.f);
+        grad[o] = inv_n * ((1.f - lambda) * sgn - lambda * dssim);
     }
-    const int64_t o = c * plane + (int64_t)py * W + px;
-    const float I = img[o], Tt = tgt[o];
-    const float dssim = fmaf(2.f * I, gb, ga) + Tt * gc;
-    const float sgn = I > Tt ? 1.f : (I < Tt ? -1.f : 0.f);
-    grad[o] = inv_n * ((1.f - lambda) * sgn - lambda * dssim);
 }
 
 }  // namespace
@@ -190,8 +198,8 @@ extern "C" gs_status gs_ssim_workspace_size(int32_t channels, int32_t height, in
                                             uint64_t* bytes) {
     if (channels <= 0 || height <= 0 || width <= 0 || !bytes)
         return gs_fail(GS_ERR_INVALID, "bad image size");
-    // the maps a, b, c and one partial loss per 16 x 16 tile and channel
-    const uint64_t tiles = (uint64_t)((width + ST - 1) / ST) * (uint64_t)((height + ST - 1) / ST);
+    // the maps a, b, c and one partial loss per 32 x 16 tile and channel
+    const uint64_t tiles = (uint64_t)((width + TW - 1) / TW) * (uint64_t)((height + TH - 1) / TH);
     *bytes = 3ull * 4ull * (uint64_t)channels * (uint64_t)height * (uint64_t)width +
              4ull * tiles * (uint64_t)channels;
     return GS_OK;
@@ -217,7 +225,7 @@ extern "C" gs_status gs_ssim_loss_grad(const float* image, const float* target, 
     }
     for (int k = 0; k <= 2 * SR; ++k) win.g[k] = (float)(g[k] / sum);
     const float inv_n = (float)(1.0 / ((double)channels * height * width));
-    dim3 grid((unsigned)((width + ST - 1) / ST), (unsigned)((height + ST - 1) / ST), (unsigned)channels);
+    dim3 grid((unsigned)((width + TW - 1) / TW), (unsigned)((height + TH - 1) / TH), (unsigned)channels);
     hipStream_t s = (hipStream_t)stream;
     float* abc = (float*)workspace;
     float* partial = abc + 3ull * (uint64_t)channels * (uint64_t)height * (uint64_t)width;
