@@ -29,6 +29,11 @@ struct Window {
     float g[2 * SR + 1];
 };
 
+__device__ __forceinline__ float rcp_refined(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.f), r, r);
+}
+
 __device__ __forceinline__ float patch_at(const float* img, int H, int W, int y, int x) {
     return (y >= 0 && y < H && x >= 0 && x < W) ? img[(int64_t)y * W + x] : 0.f;
 }
@@ -91,14 +96,18 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__
         const float B = fmaf(2.f, exy - mu * nu, C2);
         const float Cc = fmaf(mu, mu, fmaf(nu, nu, C1));
         const float D = (exx - mu * mu) + (eyy - nu * nu) + C2;
-        const float S = (A * B) / (Cc * D);
+        // the four reciprocals once (hardware reciprocal + one Newton step)
+        // instead of seven divisions
+        const float rA = rcp_refined(A), rB = rcp_refined(B), rC = rcp_refined(Cc),
+                    rD = rcp_refined(D);
+        const float S = (A * B) * (rC * rD);
         const int py = blockIdx.y * TH + r, px = blockIdx.x * TW + q;
         if (py < H && px < W) {
             const int64_t o = c * plane + (int64_t)py * W + px;
             // dS/dmu, dS/dExx, dS/dExy
-            abc[o] = S * (2.f * nu / A - 2.f * nu / B - 2.f * mu / Cc + 2.f * mu / D);
-            abc[map + o] = -S / D;
-            abc[2 * map + o] = 2.f * S / B;
+            abc[o] = S * fmaf(2.f * nu, rA - rB, 2.f * mu * (rD - rC));
+            abc[map + o] = -S * rD;
+            abc[2 * map + o] = 2.f * S * rB;
             s_sum += S;
             l1_sum += fabsf(sx[r + SR][q + SR] - sy[r + SR][q + SR]);
         }
