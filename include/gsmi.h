@@ -322,7 +322,8 @@ typedef struct {
 /* Sparse Adam, the optimiser step of the accelerated 3DGS training the paper
  * builds on (Experiments, implementation details): Gaussians that no view
  * rendered (tiles_touched[v][i] == 0 for every v) keep their parameters and
- * moments; the others take m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * moments (the kernel stores every element back, these unchanged, so no other
+ * work may touch the arrays while it runs); the others take m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
  * params: HOST array of n_params <= 8 entries; tiles_touched: device u32
  * [n_views][n] (a frame's GS_BUF_TILES_TOUCHED) or NULL to update every

@@ -44,6 +44,7 @@ def test_sparse_adam_matches_oracle(n, views):
             gp, gm, gv = (t.cpu().numpy() for t in gpu[k])
             np.testing.assert_array_equal(gp[:, ~vis], p0[:, ~vis])
             np.testing.assert_array_equal(gm[:, ~vis], m0[:, ~vis])
+            np.testing.assert_array_equal(gv[:, ~vis], v0[:, ~vis])
             # m is a sum whose two terms can cancel: measured against the sum of their magnitudes
             mscale = b1 * np.abs(m0) + (1 - b1) * np.abs(grads[k])
             assert (np.abs(gm[:, vis] - m1[:, vis]) <= 2e-7 * mscale[:, vis] + 1e-37).all()
