@@ -220,17 +220,34 @@ gs_status gs_accumulate_densify_stats(const float* dmean2d, const int32_t* visib
                                       const int32_t* view_wh, int32_t n_views, int64_t n,
                                       float* accum, float* denom, void* stream);
 
+/* Which densification a selected ("hot") Gaussian receives.  ADAPTIVE is the
+ * 3DGS rule of the Preliminary section's last paragraph (large ones split,
+ * small ones clone); SPLIT_LARGE is the global phase of the global-to-local
+ * framework (large ones split, clones suppressed); SPLIT_ONLY and CLONE_ONLY
+ * are the single-operation variants the paper compares its strategy against
+ * (Global-to-local framework, Gaussian distribution comparison): every hot
+ * Gaussian splits, or every hot Gaussian clones.  0 and 1 keep the meaning of
+ * a clone-allowed flag. */
+enum {
+    GS_DENSIFY_SPLIT_LARGE = 0,
+    GS_DENSIFY_ADAPTIVE = 1,
+    GS_DENSIFY_SPLIT_ONLY = 2,
+    GS_DENSIFY_CLONE_ONLY = 3
+};
+
 /* Split / clone / prune masks (u8, 0 or 1):
  *   avg = accum/denom (0 where denom == 0), FP32 correctly rounded;
- *   split = avg >= grad_threshold and max_k log_scales[k][i] > log_scale_threshold;
- *   clone = avg >= grad_threshold and not (max log-scale > threshold) and allow_clone;
+ *   hot = avg >= grad_threshold;  large = max_k log_scales[k][i] > log_scale_threshold;
+ *   split = hot and (large for SPLIT_LARGE and ADAPTIVE, always for SPLIT_ONLY,
+ *           never for CLONE_ONLY);
+ *   clone = hot and not split, except under SPLIT_LARGE (no clones);
  *   prune = opacity_logits[i] < logit_threshold.
  * Thresholds are in raw-parameter space: log_scale_threshold = ln(rho * extent),
- * logit_threshold = ln(tau_o / (1 - tau_o)).  allow_clone = 0 is the global
- * (split-only) phase. */
+ * logit_threshold = ln(tau_o / (1 - tau_o)).  mode: GS_DENSIFY_*; any other
+ * value is GS_ERR_INVALID. */
 gs_status gs_densify_select(const float* accum, const float* denom, const float* log_scales,
                             const float* opacity_logits, int64_t n, float grad_threshold,
-                            float log_scale_threshold, float logit_threshold, int32_t allow_clone,
+                            float log_scale_threshold, float logit_threshold, int32_t mode,
                             uint8_t* split, uint8_t* clone, uint8_t* prune, void* stream);
 
 enum { GS_KIND_KEEP = 0, GS_KIND_CLONE = 1, GS_KIND_SPLIT0 = 2, GS_KIND_SPLIT1 = 3 };
@@ -255,7 +272,12 @@ enum {
     GS_ATTR_MEAN = 1,      /* SPLITk rows: mu + R(q) (s * z_k), z_k ~ N(0, I3) from Philox; else copy */
     GS_ATTR_LOGSCALE = 2,  /* SPLITk rows: parent - ln(1.6); else copy */
     GS_ATTR_ZERO_NEW = 3,  /* KEEP rows copy, CLONE/SPLIT rows are zero (optimizer moments) */
-    GS_ATTR_ZERO = 4       /* every output row is zero (densification statistics) */
+    GS_ATTR_ZERO = 4,      /* every output row is zero (densification statistics) */
+    /* Lineage counters of the Spatial diffusion analysis (Methodology): each
+     * Gaussian carries its parent point's original position (GS_ATTR_COPY) and
+     * the number of splits and clones on its line of descent. */
+    GS_ATTR_SPLIT_COUNT = 5,  /* SPLITk rows: parent + 1; else copy */
+    GS_ATTR_CLONE_COUNT = 6   /* CLONE rows: parent + 1; KEEP and SPLITk rows copy */
 };
 
 /* One attribute: in [rows][n_in] -> out [rows][n_out] (device FP32). */
@@ -272,7 +294,7 @@ typedef struct {
  * child k of parent i come from Philox4x32-10 with counter
  * (i lo, i hi, k, step) and key (seed lo, seed hi): u1 = ((x0 >> 8) + 1) 2^-24,
  * u2 = (x1 >> 8) 2^-24, z0/z1 = Box-Muller cos/sin, z2 = Box-Muller cos of
- * (x2, x3).  attrs: HOST array of n_attrs <= 16. */
+ * (x2, x3).  attrs: HOST array of n_attrs <= 24. */
 gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_out, int64_t n_in,
                            const gs_attr* attrs, int32_t n_attrs, const float* parent_means,
                            const float* parent_log_scales, const float* parent_quats,

@@ -356,14 +356,23 @@ def thresholds(grad_threshold=2e-4, scale_ratio=0.01, extent=4.4, prune_opacity=
             np.float32(math.log(prune_opacity / (1.0 - prune_opacity))))
 
 
-def select(accum, denom, log_scales, logits, tau_g, log_scale_thr, logit_thr, allow_clone=True):
+# what a selected Gaussian becomes (the C oracle's mode argument)
+SPLIT_LARGE, ADAPTIVE, SPLIT_ONLY, CLONE_ONLY = 0, 1, 2, 3
+
+
+def select(accum, denom, log_scales, logits, tau_g, log_scale_thr, logit_thr, mode=ADAPTIVE):
+    """Split / clone / prune masks; mode SPLIT_LARGE (global phase), ADAPTIVE
+    (3DGS rule), SPLIT_ONLY or CLONE_ONLY (the single-operation variants).  A
+    bool mode reads as clones allowed (True = ADAPTIVE, False = SPLIT_LARGE)."""
+    if int(mode) not in (SPLIT_LARGE, ADAPTIVE, SPLIT_ONLY, CLONE_ONLY):
+        raise ValueError("unknown densification mode %r" % (mode,))
     n = int(np.asarray(accum).size)
     s = np.zeros(n, np.uint8)
     c = np.zeros(n, np.uint8)
     p = np.zeros(n, np.uint8)
     lib().oracle_select(n, _ptr(_c(accum, np.float32)), _ptr(_c(denom, np.float32)),
                         _ptr(_c(log_scales, np.float32)), _ptr(_c(logits, np.float32)),
-                        float(tau_g), float(log_scale_thr), float(logit_thr), int(allow_clone),
+                        float(tau_g), float(log_scale_thr), float(logit_thr), int(mode),
                         _ptr(s), _ptr(c), _ptr(p))
     return s, c, p
 
@@ -406,6 +415,26 @@ def densify_apply(params: dict, src, kind, seed: int, step: int):
         out["log_scales"][:, sp] = np.asarray(params["log_scales"], np.float64)[:, src[sp]] - \
             LN_SPLIT_SHRINK
     return out
+
+
+def lineage_apply(origin, splits, clones, src, kind):
+    """Lineage attributes through one densification (Methodology, Spatial
+    diffusion): every output row keeps its parent's original position; a split
+    child counts one more split than its parent and a clone one more clone,
+    while a kept row is the parent itself and keeps its counts.  FP64."""
+    src = np.asarray(src, np.int64)
+    kind = np.asarray(kind)
+    o = np.asarray(origin, np.float64)[..., src].copy()
+    s = np.asarray(splits, np.float64)[..., src] + ((kind == SPLIT0) | (kind == SPLIT1))
+    c = np.asarray(clones, np.float64)[..., src] + (kind == CLONE)
+    return o, s, c
+
+
+def lineage_categories(splits, clones):
+    """Split-dominated (splits > clones) = 0, clone-dominated = 1, equal = 2."""
+    s = np.asarray(splits)
+    c = np.asarray(clones)
+    return np.where(s > c, 0, np.where(c > s, 1, 2)).astype(np.int8)
 
 
 def adaptive_prune_logit(logits, p=0.03, tau_u=0.05):

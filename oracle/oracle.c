@@ -777,23 +777,34 @@ void oracle_stats_f32(int64_t n, int32_t V, const float* dmean2d, const int32_t*
     }
 }
 
-/* Masks (Preliminary, last paragraph; global-to-local phases: split only in
- * the global phase, clone suppressed): avg = accum/denom (0 when denom = 0)
- * in FP32; split = avg >= tau_g and max log-scale > ln(rho E);
- * clone = avg >= tau_g and max log-scale <= ln(rho E) and allow_clone;
+/* Masks (Preliminary, last paragraph): avg = accum/denom (0 when denom = 0)
+ * in FP32; a Gaussian is "hot" when avg >= tau_g and "large" when its largest
+ * log-scale exceeds ln(rho E).  What a hot Gaussian becomes depends on mode:
+ *   0  global phase of the global-to-local framework: large ones split, no clones
+ *   1  the 3DGS rule: large ones split, the others clone
+ *   2  split-only variant (Gaussian distribution comparison): every hot one splits
+ *   3  clone-only variant: every hot one clones
  * prune = logit < logit(tau_o).  Thresholds are given in raw-parameter space
  * (log-scale and logit) so every decision is an exact FP32 comparison. */
 void oracle_select(int64_t n, const float* accum, const float* denom, const float* log_scales,
                    const float* logits, float tau_g, float log_scale_thr, float logit_thr,
-                   int allow_clone, uint8_t* split, uint8_t* clone, uint8_t* prune) {
+                   int mode, uint8_t* split, uint8_t* clone, uint8_t* prune) {
     for (int64_t i = 0; i < n; ++i) {
         const float avg = denom[i] > 0.0f ? accum[i] / denom[i] : 0.0f;
         float mx = log_scales[i];
         if (log_scales[n + i] > mx) mx = log_scales[n + i];
         if (log_scales[2 * n + i] > mx) mx = log_scales[2 * n + i];
         const int hot = avg >= tau_g;
-        split[i] = (uint8_t)(hot && mx > log_scale_thr);
-        clone[i] = (uint8_t)(hot && !(mx > log_scale_thr) && allow_clone);
+        const int large = mx > log_scale_thr;
+        int s = 0, c = 0;
+        switch (mode) {
+            case 0: s = hot && large; break;
+            case 1: s = hot && large; c = hot && !large; break;
+            case 2: s = hot; break;
+            case 3: c = hot; break;
+        }
+        split[i] = (uint8_t)s;
+        clone[i] = (uint8_t)c;
         prune[i] = (uint8_t)(logits[i] < logit_thr);
     }
 }

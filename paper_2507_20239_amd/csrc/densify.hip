@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(GS_BLOCK) stats_kernel(const float* __restrict
 __global__ void __launch_bounds__(GS_BLOCK) select_kernel(
     const float* __restrict__ accum, const float* __restrict__ denom,
     const float* __restrict__ log_scales, const float* __restrict__ logits, int64_t n,
-    float tau_g, float ls_thr, float logit_thr, int allow_clone, uint8_t* split, uint8_t* clone,
+    float tau_g, float ls_thr, float logit_thr, int mode, uint8_t* split, uint8_t* clone,
     uint8_t* prune) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= n) return;
@@ -54,8 +54,10 @@ __global__ void __launch_bounds__(GS_BLOCK) select_kernel(
     if (l2 > mx) mx = l2;
     const bool hot = avg >= tau_g;
     const bool big = mx > ls_thr;
-    split[i] = (uint8_t)(hot && big);
-    clone[i] = (uint8_t)(hot && !big && allow_clone);
+    // the operation a hot Gaussian takes under this mode
+    const bool sp = mode == GS_DENSIFY_SPLIT_ONLY || (mode != GS_DENSIFY_CLONE_ONLY && big);
+    split[i] = (uint8_t)(hot && sp);
+    clone[i] = (uint8_t)(hot && !sp && mode != GS_DENSIFY_SPLIT_LARGE);
     prune[i] = (uint8_t)(logits[i] < logit_thr);
 }
 
@@ -145,7 +147,7 @@ __global__ void split_normals_kernel(const int64_t* parents, const int32_t* chil
 // row of every attribute (rows of one attribute four at a time, so their loads
 // are in flight together).  Consecutive threads touch consecutive slots of a
 // row: the writes are sequential and the reads nearly so (sources ascend).
-constexpr int APPLY_MAX_ATTRS = 16;
+constexpr int APPLY_MAX_ATTRS = 24;
 
 struct ApplyTable {
     gs_attr a[APPLY_MAX_ATTRS];
@@ -202,8 +204,13 @@ __global__ void __launch_bounds__(GS_BLOCK) apply_kernel(ApplyTable t, const int
             continue;
         }
         const bool zero = at.policy == GS_ATTR_ZERO || (at.policy == GS_ATTR_ZERO_NEW && k != GS_KIND_KEEP);
-        // log-scales of split children shrink by 1.6 (ln 1.6 subtracted)
-        const float sub = (at.policy == GS_ATTR_LOGSCALE && split) ? 0.47000362924573558f : 0.f;
+        // log-scales of split children shrink by 1.6 (ln 1.6 subtracted); a
+        // lineage counter of the row's operation grows by one
+        float sub = 0.f;
+        if (at.policy == GS_ATTR_LOGSCALE && split) sub = 0.47000362924573558f;
+        if ((at.policy == GS_ATTR_SPLIT_COUNT && split) ||
+            (at.policy == GS_ATTR_CLONE_COUNT && k == GS_KIND_CLONE))
+            sub = -1.f;
         int r = 0;
         for (; r + 4 <= at.rows; r += 4) {
             float v[4];
@@ -347,15 +354,17 @@ gs_status gs_accumulate_densify_stats(const float* dmean2d, const int32_t* visib
 
 gs_status gs_densify_select(const float* accum, const float* denom, const float* log_scales,
                             const float* opacity_logits, int64_t n, float grad_threshold,
-                            float log_scale_threshold, float logit_threshold, int32_t allow_clone,
+                            float log_scale_threshold, float logit_threshold, int32_t mode,
                             uint8_t* split, uint8_t* clone, uint8_t* prune, void* stream) {
     if (n < 0) return gs_fail(GS_ERR_INVALID, "negative size");
+    if (mode < GS_DENSIFY_SPLIT_LARGE || mode > GS_DENSIFY_CLONE_ONLY)
+        return gs_fail(GS_ERR_INVALID, "unknown densification mode %d", mode);
     if (n == 0) return GS_OK;
     if (!accum || !denom || !log_scales || !opacity_logits || !split || !clone || !prune)
         return gs_fail(GS_ERR_INVALID, "null pointer");
     select_kernel<<<blocks_for(n), GS_BLOCK, 0, (hipStream_t)stream>>>(
         accum, denom, log_scales, opacity_logits, n, grad_threshold, log_scale_threshold,
-        logit_threshold, allow_clone, split, clone, prune);
+        logit_threshold, mode, split, clone, prune);
     return gs_check_launch("densify_select");
 }
 
@@ -411,7 +420,7 @@ gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_ou
         const gs_attr& at = attrs[a];
         if (!at.out || at.rows <= 0 || (at.policy != GS_ATTR_ZERO && !at.in))
             return gs_fail(GS_ERR_INVALID, "attribute %d: bad pointer or rows", a);
-        if (at.policy < GS_ATTR_COPY || at.policy > GS_ATTR_ZERO)
+        if (at.policy < GS_ATTR_COPY || at.policy > GS_ATTR_CLONE_COUNT)
             return gs_fail(GS_ERR_INVALID, "attribute %d: unknown policy %d", a, at.policy);
         if (at.policy == GS_ATTR_MEAN) {
             if (at.rows != 3 || !parent_log_scales || !parent_quats)

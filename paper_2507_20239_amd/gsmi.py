@@ -28,7 +28,9 @@ BUF_DEPTH_KEY, BUF_TILES_TOUCHED, BUF_RECT, BUF_SPLAT, BUF_VISIBLE, BUF_INST_TIL
     BUF_INST_ENTRY, BUF_RANGES, BUF_T_FINAL, BUF_N_CONTRIB, BUF_SPLAT_GRAD, BUF_COUNTERS, \
     BUF_N_COMPOSITED = range(13)
 KIND_KEEP, KIND_CLONE, KIND_SPLIT0, KIND_SPLIT1 = range(4)
-ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO = range(5)
+ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO, ATTR_SPLIT_COUNT, ATTR_CLONE_COUNT = \
+    range(7)
+DENSIFY_SPLIT_LARGE, DENSIFY_ADAPTIVE, DENSIFY_SPLIT_ONLY, DENSIFY_CLONE_ONLY = range(4)
 RASTER_COUNT_COMPOSITED = 1
 
 
@@ -324,7 +326,9 @@ def accumulate_densify_stats(dmean2d, visible, view_wh, accum, denom, stream=Non
 
 
 def densify_select(accum, denom, log_scales, logits, grad_threshold, log_scale_threshold,
-                   logit_threshold, allow_clone=True, stream=None):
+                   logit_threshold, mode=DENSIFY_ADAPTIVE, stream=None):
+    """Split / clone / prune masks.  mode: DENSIFY_* (a bool reads as clones
+    allowed: True = DENSIFY_ADAPTIVE, False = DENSIFY_SPLIT_LARGE)."""
     n = accum.numel()
     dev = accum.device
     split = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -332,7 +336,7 @@ def densify_select(accum, denom, log_scales, logits, grad_threshold, log_scale_t
     prune = torch.empty(n, dtype=torch.uint8, device=dev)
     _check(lib().gs_densify_select(_ptr(accum), _ptr(denom), _ptr(log_scales), _ptr(logits), n,
                                    float(grad_threshold), float(log_scale_threshold),
-                                   float(logit_threshold), int(bool(allow_clone)), _ptr(split),
+                                   float(logit_threshold), int(mode), _ptr(split),
                                    _ptr(clone), _ptr(prune), _stream(stream)))
     return split, clone, prune
 

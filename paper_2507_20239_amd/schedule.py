@@ -27,6 +27,8 @@ import math
 import torch
 import torch.nn.functional as F
 
+from . import gsmi
+
 
 def downscale(image: torch.Tensor, r: int) -> torch.Tensor:
     """D_r (Eq. 4): bilinear resampling with antialiasing by 1/r; [C, H, W]."""
@@ -96,7 +98,13 @@ class GlobalToLocal:
     """Densification policy.  Defaults: 3DGS cadence (every 100 iterations from
     500, opacity reset every 3000) extended to T_densify = 25000, adaptive
     pruning p = 0.03, tau_u = 0.05, split threshold 2e-4 on the view-space
-    gradient, scale threshold 1% of the scene extent."""
+    gradient, scale threshold 1% of the scene extent.
+
+    strategy picks what a selected Gaussian becomes: "g2l" (the paper's
+    global-to-local framework: split-only while below full resolution, the
+    3DGS rule after), "3dgs" (the 3DGS rule throughout), "split_only" or
+    "clone_only" (the single-operation variants of the Gaussian distribution
+    comparison)."""
     schedule: C2FSchedule
     t_densify: int = 25000
     densify_from: int = 500
@@ -109,13 +117,27 @@ class GlobalToLocal:
     lr_position_init: float = 1.6e-4
     lr_position_final: float = 1.6e-6
     total_iterations: int = 30000
+    strategy: str = "g2l"
+
+    STRATEGIES = ("g2l", "3dgs", "split_only", "clone_only")
+
+    def __post_init__(self):
+        if self.strategy not in self.STRATEGIES:
+            raise ValueError("strategy must be one of %s" % (self.STRATEGIES,))
 
     def global_phase(self, it: int) -> bool:
         """Split only (clones suppressed) while training below full resolution."""
         return it < self.schedule.full_resolution_from()
 
     def allow_clone(self, it: int) -> bool:
-        return not self.global_phase(it)
+        return self.densify_mode(it) in (gsmi.DENSIFY_ADAPTIVE, gsmi.DENSIFY_CLONE_ONLY)
+
+    def densify_mode(self, it: int) -> int:
+        """The gsmi.DENSIFY_* mode of the selection at iteration it."""
+        if self.strategy == "g2l":
+            return gsmi.DENSIFY_SPLIT_LARGE if self.global_phase(it) else gsmi.DENSIFY_ADAPTIVE
+        return {"3dgs": gsmi.DENSIFY_ADAPTIVE, "split_only": gsmi.DENSIFY_SPLIT_ONLY,
+                "clone_only": gsmi.DENSIFY_CLONE_ONLY}[self.strategy]
 
     def densify_now(self, it: int) -> bool:
         return self.densify_from <= it < self.t_densify and it % self.interval == 0

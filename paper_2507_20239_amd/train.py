@@ -7,7 +7,10 @@ densification window, every `interval` iterations the global-to-local policy
 selects split and clone candidates (clones suppressed in the global phase),
 the adaptive opacity threshold selects the pruned ones, and the compaction
 rebuilds parameters and optimiser state; opacities are reset periodically
-(Methodology; Preliminary; Experiments, implementation details).
+(Methodology; Preliminary; Experiments, implementation details).  With
+lineage=True every Gaussian also carries the attributes of the Spatial
+diffusion analysis (its parent point's original position and the splits and
+clones on its line of descent), carried through each compaction.
 
 Every numerical step runs in libgsmi.so; this module keeps the tensors and
 the iteration logic.
@@ -24,11 +27,14 @@ from . import gsmi, schedule
 PARAMS = gsmi.PARAM_NAMES                       # means, log_scales, quats, opacity_logits, sh
 ROWS_POLICY = {"means": gsmi.ATTR_MEAN, "log_scales": gsmi.ATTR_LOGSCALE, "quats": gsmi.ATTR_COPY,
                "opacity_logits": gsmi.ATTR_COPY, "sh": gsmi.ATTR_COPY}
+LINEAGE_POLICY = {"origin": gsmi.ATTR_COPY, "splits": gsmi.ATTR_SPLIT_COUNT,
+                  "clones": gsmi.ATTR_CLONE_COUNT}
 
 
 class Trainer:
     def __init__(self, params: dict, sh_degree: int, cameras, targets, policy, extent: float,
-                 lrs=None, lam: float = 0.2, seed: int = 0, device="cuda", capacity=None):
+                 lrs=None, lam: float = 0.2, seed: int = 0, device="cuda", capacity=None,
+                 lineage: bool = False):
         self.dev = torch.device(device)
         self.p = {k: params[k].to(self.dev).contiguous().clone() for k in PARAMS}
         self.sh_degree = sh_degree
@@ -45,10 +51,16 @@ class Trainer:
         self.capacity = capacity
         self.opts = gsmi.raster_opts()
         self._reset_state()
+        # original position [3][n], split count [1][n], clone count [1][n] (FP32)
+        self.lineage = None
+        if lineage:
+            self.lineage = {"origin": self.p["means"].clone(),
+                            "splits": torch.zeros(1, self.n, device=self.dev),
+                            "clones": torch.zeros(1, self.n, device=self.dev)}
         self._frames = {}
         self._targets = {}
         self.history = []          # (iteration, loss, n, resolution)
-        self.densify_log = []      # (iteration, n_in, n_out, clones, splits, pruned, allow_clone)
+        self.densify_log = []      # (iteration, n_in, n_out, clones, splits, pruned, mode)
 
     @property
     def n(self) -> int:
@@ -114,13 +126,13 @@ class Trainer:
 
     def densify(self, it: int):
         g, ls_thr, lo_upper = self.policy.thresholds(self.extent)
-        allow_clone = self.policy.allow_clone(it)
+        mode = self.policy.densify_mode(it)
         # adaptive opacity threshold tau = min(alpha_sorted[floor(N p)], tau_u), in logit space
         thr, _ = gsmi.adaptive_prune_threshold(self.p["opacity_logits"], p=self.policy.prune_ratio,
                                                tau_u=self.policy.prune_upper)
         split, clone, prune = gsmi.densify_select(self.accum, self.denom, self.p["log_scales"],
                                                   self.p["opacity_logits"], g, ls_thr,
-                                                  float(thr.item()), allow_clone)
+                                                  float(thr.item()), mode)
         src, kind, n_out = gsmi.densify_plan(split, clone, prune)
         n_in = self.n
         if n_out == 0:
@@ -133,17 +145,25 @@ class Trainer:
             for st in ("m", "v"):
                 attrs.append((getattr(self, st)[k].reshape(rows, n_in), rows, gsmi.ATTR_ZERO_NEW))
                 names.append((st, k))
+        if self.lineage is not None:
+            for k, policy in LINEAGE_POLICY.items():
+                a = self.lineage[k]
+                attrs.append((a, a.shape[0], policy))
+                names.append(("lineage", k))
         outs = gsmi.densify_apply(src, kind, n_in, attrs, self.p["means"], self.p["log_scales"],
                                   self.p["quats"], self.seed, it)
         shapes = {k: self.p[k].shape[:-1] for k in PARAMS}
         for (st, k), o in zip(names, outs):
-            getattr(self, st)[k] = o.reshape(*shapes[k], n_out).contiguous()
+            if st == "lineage":
+                self.lineage[k] = o.contiguous()
+            else:
+                getattr(self, st)[k] = o.reshape(*shapes[k], n_out).contiguous()
         self.accum = torch.zeros(n_out, device=self.dev)
         self.denom = torch.zeros(n_out, device=self.dev)
         self.grads = {k: torch.empty_like(v) for k, v in self.p.items()}
         kinds = torch.bincount(kind.to(torch.int64), minlength=4).tolist()
         self.densify_log.append((it, n_in, n_out, kinds[gsmi.KIND_CLONE], kinds[gsmi.KIND_SPLIT0],
-                                 int(prune.sum()), allow_clone))
+                                 int(prune.sum()), mode))
 
     def reset_opacity(self, ceiling: float = 0.01):
         """Opacities above the ceiling are set to it (logit space); their
@@ -152,3 +172,20 @@ class Trainer:
         self.p["opacity_logits"].clamp_(max=lim)
         self.m["opacity_logits"].zero_()
         self.v["opacity_logits"].zero_()
+
+    def lineage_summary(self):
+        """Per category of the Spatial diffusion analysis -- split-dominated
+        (more splits than clones on the line of descent), clone-dominated, equal
+        -- the number of Gaussians and their mean distance from the original
+        position of their parent point.  Host-side analysis of the lineage
+        attributes (requires lineage=True)."""
+        if self.lineage is None:
+            raise RuntimeError("the trainer was built without lineage=True")
+        s = self.lineage["splits"][0].cpu().numpy()
+        c = self.lineage["clones"][0].cpu().numpy()
+        d = np.linalg.norm((self.p["means"] - self.lineage["origin"]).cpu().numpy().astype(np.float64),
+                           axis=0)
+        out = {}
+        for name, sel in (("split", s > c), ("clone", c > s), ("equal", s == c)):
+            out[name] = (int(sel.sum()), float(d[sel].mean()) if sel.any() else float("nan"))
+        return out

@@ -66,16 +66,17 @@ def test_stats_bit_exact(n, views):
     np.testing.assert_array_equal(den, den_o)
 
 
-def _select_both(acc, den, d, allow_clone, thr):
+def _select_both(acc, den, d, mode, thr):
     tg, tls, tlo = thr
     s, c, p = gsmi.densify_select(_t(acc), _t(den), _t(d.log_scales), _t(d.opacity_logits),
-                                  tg, tls, tlo, allow_clone)
-    so, co, po = oracle.select(acc, den, d.log_scales, d.opacity_logits, tg, tls, tlo, allow_clone)
+                                  tg, tls, tlo, mode)
+    so, co, po = oracle.select(acc, den, d.log_scales, d.opacity_logits, tg, tls, tlo, mode)
     return (s.cpu().numpy(), c.cpu().numpy(), p.cpu().numpy()), (so, co, po)
 
 
-@pytest.mark.parametrize("allow_clone", [True, False])
-def test_select_bit_exact(allow_clone):
+@pytest.mark.parametrize("mode", [gsmi.DENSIFY_SPLIT_LARGE, gsmi.DENSIFY_ADAPTIVE,
+                                  gsmi.DENSIFY_SPLIT_ONLY, gsmi.DENSIFY_CLONE_ONLY])
+def test_select_bit_exact(mode):
     n = 100_001
     d, _ = _workload(5, n, 4)
     acc, den = oracle.stats_f32(d.dmean2d, d.visible, d.view_wh)
@@ -85,12 +86,20 @@ def test_select_bit_exact(allow_clone):
     acc[100:110] = thr[0] * den[100:110]
     d.log_scales[:, 200:210] = thr[1]
     d.opacity_logits[300:310] = thr[2]
-    got, want = _select_both(acc, den, d, allow_clone, thr)
+    got, want = _select_both(acc, den, d, mode, thr)
     for g, w in zip(got, want):
         np.testing.assert_array_equal(g, w)
     s, c, p = got
-    assert s.sum() > 100 and p.sum() > 100
-    assert (c.sum() > 100) == allow_clone
+    assert p.sum() > 100 and not (s & c).any()
+    assert (s.sum() > 100) == (mode != gsmi.DENSIFY_CLONE_ONLY)
+    assert (c.sum() > 100) == (mode in (gsmi.DENSIFY_ADAPTIVE, gsmi.DENSIFY_CLONE_ONLY))
+
+
+def test_select_rejects_unknown_mode():
+    acc = torch.zeros(4, device=dev)
+    ls = torch.zeros(3, 4, device=dev)
+    with pytest.raises(gsmi.GsError, match="mode"):
+        gsmi.densify_select(acc, acc, ls, acc, 1e-4, 0.0, 0.0, 4)
 
 
 def _plan_both(s, c, p, capacity=None):
@@ -158,13 +167,20 @@ def _apply_both(d, s, c, p, seed, step):
     params = {"means": d.means, "log_scales": d.log_scales, "quats": d.quats,
               "opacity_logits": d.opacity_logits[None, :], "sh": sh}
     pm, pl, pq = _t(d.means), _t(d.log_scales), _t(d.quats)
+    # lineage: an original position and split / clone counts already on the rows
+    origin = rng.normal(0, 2, (3, n)).astype(np.float32)
+    nsplit = rng.integers(0, 5, (1, n)).astype(np.float32)
+    nclone = rng.integers(0, 5, (1, n)).astype(np.float32)
     attrs = [(pm, 3, gsmi.ATTR_MEAN), (pl, 3, gsmi.ATTR_LOGSCALE), (pq, 4, gsmi.ATTR_COPY),
              (_t(d.opacity_logits[None, :]), 1, gsmi.ATTR_COPY), (_t(sh), 48, gsmi.ATTR_COPY),
-             (_t(moment), 3, gsmi.ATTR_ZERO_NEW), (None, 2, gsmi.ATTR_ZERO)]
+             (_t(moment), 3, gsmi.ATTR_ZERO_NEW), (None, 2, gsmi.ATTR_ZERO),
+             (_t(origin), 3, gsmi.ATTR_COPY), (_t(nsplit), 1, gsmi.ATTR_SPLIT_COUNT),
+             (_t(nclone), 1, gsmi.ATTR_CLONE_COUNT)]
     outs = gsmi.densify_apply(src, kind, n, attrs, pm, pl, pq, seed, step)
     outs = [o.cpu().numpy() for o in outs]
     src_np, kind_np = src.cpu().numpy(), kind.cpu().numpy()
     want = oracle.densify_apply(params, src_np, kind_np, seed, step)
+    want["lineage"] = oracle.lineage_apply(origin, nsplit, nclone, src_np, kind_np)
     return outs, want, src_np, kind_np, moment
 
 
@@ -178,7 +194,10 @@ def test_apply_rows(seed, step):
     c = (rng.random(n) < 0.15).astype(np.uint8)
     p = (rng.random(n) < 0.05).astype(np.uint8)
     outs, want, src, kind, moment = _apply_both(d, s, c, p, seed, step)
-    mean_o, ls_o, q_o, lo_o, sh_o, mom_o, st_o = outs
+    mean_o, ls_o, q_o, lo_o, sh_o, mom_o, st_o = outs[:7]
+    # lineage attributes: small integers and copies, bit-exact
+    for got, w in zip(outs[7:], want["lineage"]):
+        np.testing.assert_array_equal(got, w.astype(np.float32))
     split = (kind == oracle.SPLIT0) | (kind == oracle.SPLIT1)
     assert split.sum() > 1000 and (kind == oracle.CLONE).sum() > 1000
     # copies are bit-exact

@@ -427,12 +427,48 @@ def test_select_rule_and_global_phase():
     ls[1, 0] = -2.0          # max scale exp(-2) = 0.135 > 0.044  -> split
     ls[2, 4] = float(lthr)   # exactly at the threshold -> not split (strict) -> clone
     lg = np.array([0.0, -6.0, 0.0, -5.2, 1.0], np.float32)
-    s, c, p = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, allow_clone=True)
+    s, c, p = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, mode=oracle.ADAPTIVE)
     assert s.tolist() == [1, 0, 0, 0, 0]
     assert c.tolist() == [0, 1, 0, 0, 1]
     assert p.tolist() == [0, 1, 0, 0, 0]   # sigmoid(-6) = 0.0025 < 0.005; sigmoid(-5.2) = 0.0055
-    s2, c2, _ = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, allow_clone=False)
+    s2, c2, _ = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, mode=oracle.SPLIT_LARGE)
     assert s2.tolist() == s.tolist() and c2.sum() == 0
+    # the single-operation variants: every hot Gaussian (0, 1, 4) takes the one operation
+    s3, c3, p3 = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, mode=oracle.SPLIT_ONLY)
+    assert s3.tolist() == [1, 1, 0, 0, 1] and c3.sum() == 0 and p3.tolist() == p.tolist()
+    s4, c4, _ = oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, mode=oracle.CLONE_ONLY)
+    assert s4.sum() == 0 and c4.tolist() == [1, 1, 0, 0, 1]
+    # a boolean reads as "clones allowed"
+    assert oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, True)[1].tolist() == c.tolist()
+    assert oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, False)[1].sum() == 0
+    with pytest.raises(ValueError):
+        oracle.select(acc, den, ls, lg, tau_g, lthr, pthr, mode=4)
+
+
+def test_lineage_follows_the_papers_worked_example():
+    """Spatial diffusion (Methodology): A splits into B (and a sibling), then B
+    clones into C; C's parent point is A's and C belongs to the equal category
+    (one split, one clone), while the kept B stays split-dominated."""
+    origin = np.array([[0.5], [-1.0], [2.0]])
+    splits, clones = np.zeros((1, 1)), np.zeros((1, 1))
+    # A splits
+    src, kind = oracle.densify_plan([True], [False], [False])
+    origin, splits, clones = oracle.lineage_apply(origin, splits, clones, src, kind)
+    assert kind.tolist() == [oracle.SPLIT0, oracle.SPLIT1]
+    assert splits.tolist() == [[1, 1]] and clones.tolist() == [[0, 0]]
+    # the first child (B) clones, its sibling is kept
+    src, kind = oracle.densify_plan([False, False], [True, False], [False, False])
+    origin, splits, clones = oracle.lineage_apply(origin, splits, clones, src, kind)
+    assert kind.tolist() == [oracle.KEEP, oracle.CLONE, oracle.KEEP]
+    assert splits.tolist() == [[1, 1, 1]] and clones.tolist() == [[0, 1, 0]]
+    np.testing.assert_array_equal(origin, np.repeat([[0.5], [-1.0], [2.0]], 3, axis=1))
+    cat = oracle.lineage_categories(splits[0], clones[0])
+    assert cat.tolist() == [0, 2, 0]          # B split-dominated, C equal, sibling split-dominated
+    # a pruned parent takes its lineage with it
+    src, kind = oracle.densify_plan([False] * 3, [False] * 3, [False, True, False])
+    _, s2, c2 = oracle.lineage_apply(origin, splits, clones, src, kind)
+    assert s2.tolist() == [[1, 1]] and c2.tolist() == [[0, 0]]
+    assert oracle.lineage_categories([0, 2, 3], [1, 1, 3]).tolist() == [1, 0, 2]
 
 
 def test_densify_plan_brute_force_and_counts():

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from oracle import schedule as ref
-from paper_2507_20239_amd import schedule
+from paper_2507_20239_amd import gsmi, schedule
 
 
 def _smooth_images(seed, n=3, H=96, W=128):
@@ -111,3 +111,17 @@ def test_global_to_local_policy():
     assert p.position_lr(9000) > p.position_lr(20000) > p.position_lr(30000)
     g, ls, lo = p.thresholds(4.4)
     assert ls == pytest.approx(math.log(0.044)) and lo == pytest.approx(math.log(0.05 / 0.95))
+
+
+def test_densification_strategies():
+    s = schedule.C2FSchedule([25000, 9000, 6000, 4000])
+    g2l = schedule.GlobalToLocal(s)
+    assert g2l.densify_mode(8999) == gsmi.DENSIFY_SPLIT_LARGE
+    assert g2l.densify_mode(9000) == gsmi.DENSIFY_ADAPTIVE
+    for strategy, mode in (("3dgs", gsmi.DENSIFY_ADAPTIVE), ("split_only", gsmi.DENSIFY_SPLIT_ONLY),
+                           ("clone_only", gsmi.DENSIFY_CLONE_ONLY)):
+        p = schedule.GlobalToLocal(s, strategy=strategy)
+        assert p.densify_mode(0) == p.densify_mode(20000) == mode
+        assert p.allow_clone(0) == (strategy != "split_only")
+    with pytest.raises(ValueError):
+        schedule.GlobalToLocal(s, strategy="clone-only")
