@@ -198,6 +198,31 @@ def test_empty_and_culled_scene_renders_background():
         assert torch.count_nonzero(grads[k]).item() == 0
 
 
+def test_nonfinite_gaussians_are_culled():
+    """Gaussians with a NaN mean, log-scale or opacity, an infinite mean, or a
+    zero quaternion get no tiles, and the image equals that of the scene
+    without them, bit for bit (the others keep their relative order)."""
+    sc = synth.random_scene(25, 600, 70, 45, sh_degree=1, log_scale=(-2.2, 0.5))
+    rng = np.random.default_rng(25)
+    bad = rng.choice(sc.n, 50, replace=False)
+    sc.means[0, bad[:10]] = np.nan
+    sc.means[2, bad[10:20]] = np.inf
+    sc.log_scales[1, bad[20:30]] = np.nan
+    sc.quats[:, bad[30:40]] = 0.0
+    sc.opacity_logits[bad[40:]] = np.nan
+    keep = np.setdiff1d(np.arange(sc.n), bad)
+    clean = synth.Scene(sc.means[:, keep].copy(), sc.log_scales[:, keep].copy(),
+                        sc.quats[:, keep].copy(), sc.opacity_logits[keep].copy(),
+                        sc.sh[:, :, keep].copy(), sc.sh_degree, sc.cameras, [], sc.bg)
+    cam = sc.cameras[0]
+    frame, img, *_ = gpu_forward(sc, [cam])
+    tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy()[: sc.n]
+    assert not tt[bad].any() and tt[keep].any()
+    _, img_clean, *_ = gpu_forward(clean, [cam])
+    assert torch.isfinite(img).all()
+    assert torch.equal(img, img_clean)
+
+
 def test_capacity_overflow_is_reported_and_bounded():
     sc = SCENES["c1_2000_128x128_sh0"]
     cam = sc.cameras[0]
