@@ -277,7 +277,7 @@ enum {
      * Gaussian carries its parent point's original position (GS_ATTR_COPY) and
      * the number of splits and clones on its line of descent. */
     GS_ATTR_SPLIT_COUNT = 5,  /* SPLITk rows: parent + 1; else copy */
-    GS_ATTR_CLONE_COUNT = 6   /* CLONE rows: parent + 1; KEEP and SPLITk rows copy */
+    GS_ATTR_CLONE_COUNT = 6   /* both rows of a cloned parent (KEEP, CLONE): parent + 1; else copy */
 };
 
 /* One attribute: in [rows][n_in] -> out [rows][n_out] (device FP32). */

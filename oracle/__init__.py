@@ -419,14 +419,16 @@ def densify_apply(params: dict, src, kind, seed: int, step: int):
 
 def lineage_apply(origin, splits, clones, src, kind):
     """Lineage attributes through one densification (Methodology, Spatial
-    diffusion): every output row keeps its parent's original position; a split
-    child counts one more split than its parent and a clone one more clone,
-    while a kept row is the parent itself and keeps its counts.  FP64."""
+    diffusion): every output row keeps its parent's original position; both
+    children of a split count one more split than the parent, and both copies
+    of a cloned parent (the kept one and the clone, which are identical) one
+    more clone.  FP64."""
     src = np.asarray(src, np.int64)
     kind = np.asarray(kind)
     o = np.asarray(origin, np.float64)[..., src].copy()
     s = np.asarray(splits, np.float64)[..., src] + ((kind == SPLIT0) | (kind == SPLIT1))
-    c = np.asarray(clones, np.float64)[..., src] + (kind == CLONE)
+    cloned_parents = np.unique(src[kind == CLONE])
+    c = np.asarray(clones, np.float64)[..., src] + np.isin(src, cloned_parents)
     return o, s, c
 
 

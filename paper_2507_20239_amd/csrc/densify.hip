@@ -195,6 +195,9 @@ __global__ void __launch_bounds__(GS_BLOCK) apply_kernel(ApplyTable t, const int
     const int64_t i = src[j];
     const uint8_t k = kind[j];
     const bool split = k == GS_KIND_SPLIT0 || k == GS_KIND_SPLIT1;
+    // both rows of a cloned parent: its KEEP row is followed by its CLONE row
+    const bool cloned = k == GS_KIND_CLONE ||
+                        (k == GS_KIND_KEEP && j + 1 < n_out && kind[j + 1] == GS_KIND_CLONE);
     for (int a = 0; a < t.count; ++a) {
         const gs_attr at = t.a[a];
         const float* in = at.in;
@@ -208,8 +211,7 @@ __global__ void __launch_bounds__(GS_BLOCK) apply_kernel(ApplyTable t, const int
         // lineage counter of the row's operation grows by one
         float sub = 0.f;
         if (at.policy == GS_ATTR_LOGSCALE && split) sub = 0.47000362924573558f;
-        if ((at.policy == GS_ATTR_SPLIT_COUNT && split) ||
-            (at.policy == GS_ATTR_CLONE_COUNT && k == GS_KIND_CLONE))
+        if ((at.policy == GS_ATTR_SPLIT_COUNT && split) || (at.policy == GS_ATTR_CLONE_COUNT && cloned))
             sub = -1.f;
         int r = 0;
         for (; r + 4 <= at.rows; r += 4) {

@@ -74,8 +74,8 @@ def test_global_to_local_training_on_a_synthetic_scene():
     assert any(d[4] > 0 for d in glob) and loc and any(d[3] > 0 for d in loc)
     assert after < 0.8 * before
     # lineage: every original position is an initial mean; counts are whole numbers;
-    # the categories cover every Gaussian.  Clones only start in the local phase, from
-    # Gaussians that split before, so here the clone-dominated category stays empty.
+    # the categories cover every Gaussian.  Clones only start in the local phase,
+    # mostly from Gaussians that split before (the equal category).
     _origins_are_initial_means(tr, init)
     ns = tr.lineage["splits"].cpu().numpy()
     nc = tr.lineage["clones"].cpu().numpy()

@@ -448,7 +448,8 @@ def test_select_rule_and_global_phase():
 def test_lineage_follows_the_papers_worked_example():
     """Spatial diffusion (Methodology): A splits into B (and a sibling), then B
     clones into C; C's parent point is A's and C belongs to the equal category
-    (one split, one clone), while the kept B stays split-dominated."""
+    (one split, one clone).  The kept B is C's identical twin and counts the
+    clone as well."""
     origin = np.array([[0.5], [-1.0], [2.0]])
     splits, clones = np.zeros((1, 1)), np.zeros((1, 1))
     # A splits
@@ -460,14 +461,20 @@ def test_lineage_follows_the_papers_worked_example():
     src, kind = oracle.densify_plan([False, False], [True, False], [False, False])
     origin, splits, clones = oracle.lineage_apply(origin, splits, clones, src, kind)
     assert kind.tolist() == [oracle.KEEP, oracle.CLONE, oracle.KEEP]
-    assert splits.tolist() == [[1, 1, 1]] and clones.tolist() == [[0, 1, 0]]
+    assert splits.tolist() == [[1, 1, 1]] and clones.tolist() == [[1, 1, 0]]
     np.testing.assert_array_equal(origin, np.repeat([[0.5], [-1.0], [2.0]], 3, axis=1))
     cat = oracle.lineage_categories(splits[0], clones[0])
-    assert cat.tolist() == [0, 2, 0]          # B split-dominated, C equal, sibling split-dominated
+    assert cat.tolist() == [2, 2, 0]          # B and C equal, the sibling split-dominated
     # a pruned parent takes its lineage with it
     src, kind = oracle.densify_plan([False] * 3, [False] * 3, [False, True, False])
     _, s2, c2 = oracle.lineage_apply(origin, splits, clones, src, kind)
-    assert s2.tolist() == [[1, 1]] and c2.tolist() == [[0, 0]]
+    assert s2.tolist() == [[1, 1]] and c2.tolist() == [[1, 0]]
+    # C clones twice more: both copies each time; the sibling's split children stay apart
+    src, kind = oracle.densify_plan([False, False, True], [False, True, False], [False] * 3)
+    _, s3, c3 = oracle.lineage_apply(origin, splits, clones, src, kind)
+    assert kind.tolist() == [oracle.KEEP, oracle.KEEP, oracle.CLONE, oracle.SPLIT0, oracle.SPLIT1]
+    assert s3.tolist() == [[1, 1, 1, 2, 2]] and c3.tolist() == [[1, 2, 2, 0, 0]]
+    assert oracle.lineage_categories(s3[0], c3[0]).tolist() == [2, 1, 1, 0, 0]
     assert oracle.lineage_categories([0, 2, 3], [1, 1, 3]).tolist() == [1, 0, 2]
 
 
