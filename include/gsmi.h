@@ -114,6 +114,16 @@ typedef struct {
  * composited into GS_BUF_N_COMPOSITED (a diagnostic; without the flag that
  * buffer is left as it was). */
 #define GS_RASTER_COUNT_COMPOSITED 1
+/* gs_raster_opts.flags: gs_project bins every Gaussian in front of the camera
+ * to the tiles whose 16x16 squares meet its 3-sigma square [u - r, u + r] x
+ * [v - r, v + r], r = ceil(3 sqrt(largest eigenvalue of Sigma')) pixels,
+ * whatever its opacity: the footprint of the original 3DGS rasterizer.  A
+ * pixel then sees only the splats binned to its tile, so the image depends on
+ * the tile grid (a splat of opacity above about 0.35 reaches 1/255 beyond
+ * 3 sigma).  Without the flag the footprint is the tiles that meet the
+ * ellipse o G >= 1/255, and images do not depend on the grid.  gs_render and
+ * its adjoint use the footprint of the frame's last gs_project. */
+#define GS_RASTER_FOOTPRINT_3SIGMA 2
 
 /* ------------------------------------------------------------------------ */
 /* Frame: the device state of one rendering step for a fixed set of view     */

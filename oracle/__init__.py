@@ -119,10 +119,12 @@ def camera_array(cam) -> np.ndarray:
     return _c(cam.as_floats(), np.float64)
 
 
-def project(scene_or_params, cam, near_plane: float = NEAR_PLANE) -> dict:
+def project(scene_or_params, cam, near_plane: float = NEAR_PLANE, footprint: str = "ellipse") -> dict:
     """Project every Gaussian into one camera (FP64).  tiles_touched counts the
     tiles footprint_tiles bins a Gaussian to; flags bit 0 also marks Gaussians
-    with a tile decision within rounding distance of flipping."""
+    with a tile decision within rounding distance of flipping.  footprint:
+    "ellipse" (the tiles meeting o G >= 1/255) or "3sigma" (the tiles meeting
+    the 3-sigma square, whatever the opacity; see footprint_3sigma)."""
     p = scene_or_params
     n = int(p.means.shape[1])
     deg = int(p.sh_degree)
@@ -141,11 +143,16 @@ def project(scene_or_params, cam, near_plane: float = NEAR_PLANE) -> dict:
                          _ptr(out["cov2d"]), _ptr(out["opacity"]), _ptr(out["rgb"]),
                          _ptr(out["depth"]), _ptr(out["depth_key"]), _ptr(out["visible"]),
                          _ptr(out["rect"]), _ptr(out["flags"]))
+    if footprint not in ("ellipse", "3sigma"):
+        raise ValueError("footprint must be 'ellipse' or '3sigma'")
+    out["footprint"] = footprint
+    out["width"], out["height"] = int(cam.width), int(cam.height)
+    if footprint == "3sigma":
+        footprint_3sigma(out, near_plane)
     gid, tx, ty, hit, border = footprint_tiles(out)
     out["tiles_touched"] = np.bincount(gid[hit], minlength=n).astype(np.int64)
     out["flags"] |= (np.bincount(gid[border], minlength=n) > 0).astype(np.int32)
     out["n"] = n
-    out["width"], out["height"] = int(cam.width), int(cam.height)
     return out
 
 
@@ -166,10 +173,21 @@ def render_pixels(proj: dict, pixels, bg=(0.0, 0.0, 0.0)):
     nc = np.zeros(m, np.int32)
     mg = np.zeros(m)
     bgd = _c(bg, np.float64)
-    lib().oracle_render_pixels(proj["n"], _ptr(proj["mean2d"]), _ptr(proj["conic"]),
-                               _ptr(proj["opacity"]), _ptr(proj["rgb"]), _ptr(proj["depth_key"]),
-                               _ptr(proj["visible"]), m, _ptr(pix), _ptr(bgd), _ptr(color),
-                               _ptr(T), _ptr(nc), _ptr(mg))
+
+    def run(visible, rows):
+        sub = np.ascontiguousarray(pix[rows])
+        c, t, k, g = np.zeros((rows.size, 3)), np.zeros(rows.size), np.zeros(rows.size, np.int32), \
+            np.zeros(rows.size)
+        lib().oracle_render_pixels(proj["n"], _ptr(proj["mean2d"]), _ptr(proj["conic"]),
+                                   _ptr(proj["opacity"]), _ptr(proj["rgb"]), _ptr(proj["depth_key"]),
+                                   _ptr(visible), rows.size, _ptr(sub), _ptr(bgd), _ptr(c),
+                                   _ptr(t), _ptr(k), _ptr(g))
+        color[rows], T[rows], nc[rows], mg[rows] = c, t, k, g
+
+    if proj.get("footprint") == "3sigma":
+        _tile_restricted(proj, pix, run)
+    else:
+        run(_c(proj["visible"], np.int32), np.arange(m))
     return color, T, nc, mg
 
 
@@ -189,11 +207,22 @@ def render_backward_pixels(proj: dict, pixels, dL_dC, bg=(0.0, 0.0, 0.0)):
     n = proj["n"]
     grad = np.zeros((n, 9))
     gabs = np.zeros((n, 9))
-    lib().oracle_render_backward_pixels(n, _ptr(proj["mean2d"]), _ptr(proj["conic"]),
-                                        _ptr(proj["opacity"]), _ptr(proj["rgb"]),
-                                        _ptr(proj["depth_key"]), _ptr(proj["visible"]),
-                                        pix.shape[0], _ptr(pix), _ptr(_c(bg, np.float64)),
-                                        _ptr(g), _ptr(grad), _ptr(gabs))
+
+    def run(visible, rows):
+        gr, ga = np.zeros((n, 9)), np.zeros((n, 9))
+        lib().oracle_render_backward_pixels(n, _ptr(proj["mean2d"]), _ptr(proj["conic"]),
+                                            _ptr(proj["opacity"]), _ptr(proj["rgb"]),
+                                            _ptr(proj["depth_key"]), _ptr(visible), rows.size,
+                                            _ptr(np.ascontiguousarray(pix[rows])),
+                                            _ptr(_c(bg, np.float64)),
+                                            _ptr(np.ascontiguousarray(g[rows])), _ptr(gr), _ptr(ga))
+        grad[:] += gr
+        gabs[:] += ga
+
+    if proj.get("footprint") == "3sigma":
+        _tile_restricted(proj, pix, run)
+    else:
+        run(_c(proj["visible"], np.int32), np.arange(pix.shape[0]))
     return grad, gabs
 
 
@@ -239,6 +268,58 @@ def l1_loss_grad(image, target):
 FOOTPRINT_INFLATE = 1.0 + 1.0 / 1024.0
 
 
+def footprint_3sigma(proj: dict, near_plane: float = NEAR_PLANE):
+    """The original 3DGS binning, in place on a projection: every Gaussian in
+    front of the camera is binned to the tiles whose 16x16 squares meet the
+    square [u - r, u + r] x [v - r, v + r], r = ceil(3 sqrt(lambda_max)) with
+    lambda_max the larger eigenvalue of Sigma' (dilation included), whatever
+    its opacity.  Sets visible (non-empty), rect (tiles, inclusive) and flags
+    bit 0 where the radius or a square edge lies within rounding distance of
+    a decision."""
+    m = proj["mean2d"]
+    cv = proj["cov2d"]
+    d = proj["depth"]
+    txn = (proj["width"] + TILE - 1) // TILE
+    tyn = (proj["height"] + TILE - 1) // TILE
+    with np.errstate(invalid="ignore", over="ignore"):
+        front = (d > near_plane) & np.isfinite(m).all(axis=1)
+        a, b, c = cv[:, 0], cv[:, 1], cv[:, 2]
+        mid = 0.5 * (a + c)
+        lam = mid + np.sqrt(np.maximum(mid * mid - (a * c - b * b), 0.0))
+        r3 = 3.0 * np.sqrt(lam)
+        r = np.ceil(r3)
+        edges = [(m[:, 0] - r) / TILE, (m[:, 0] + r) / TILE, (m[:, 1] - r) / TILE, (m[:, 1] + r) / TILE]
+        x0 = np.maximum(np.ceil(edges[0]) - 1, 0)
+        x1 = np.minimum(np.floor(edges[1]), txn - 1)
+        y0 = np.maximum(np.ceil(edges[2]) - 1, 0)
+        y1 = np.minimum(np.floor(edges[3]), tyn - 1)
+        vis = front & (x0 <= x1) & (y0 <= y1)
+
+        def near_int(v):
+            return np.abs(v - np.round(v)) <= 1e-6 * np.maximum(1.0, np.abs(v))
+        border = near_int(r3)
+        for e in edges:
+            border |= near_int(e)
+    rect = np.zeros((proj["n"] if "n" in proj else m.shape[0], 4), np.int32)
+    rect[vis] = np.stack([x0, x1, y0, y1], axis=1)[vis].astype(np.int32)
+    proj["visible"] = vis.astype(np.int32)
+    proj["rect"] = rect
+    proj["flags"] = (proj["flags"] & ~1) | (front & border).astype(np.int32)
+
+
+def _tile_restricted(proj: dict, pix, call):
+    """Under the 3-sigma footprint a pixel sees only the Gaussians binned to
+    its tile: run call(visible, pixel rows) once per tile with visibility
+    restricted to those Gaussians."""
+    txn = (proj["width"] + TILE - 1) // TILE
+    tile = (pix[:, 1] // TILE) * txn + pix[:, 0] // TILE
+    r = proj["rect"]
+    for t in np.unique(tile):
+        tx, ty = t % txn, t // txn
+        vis = proj["visible"] * ((r[:, 0] <= tx) & (tx <= r[:, 1]) & (r[:, 2] <= ty) & (ty <= r[:, 3]))
+        call(np.ascontiguousarray(vis, np.int32), np.flatnonzero(tile == t))
+
+
 def footprint_tiles(proj: dict):
     """The tiles a Gaussian is binned to: the tiles of its footprint rectangle
     whose 16x16 square [16 tx, 16 tx + 16] x [16 ty, 16 ty + 16] meets the ellipse
@@ -248,7 +329,18 @@ def footprint_tiles(proj: dict):
     within 1e-5 (relative) of flipping.  The minimum of the quadratic form over a
     square is 0 if the centre lies inside, else its minimum over the four edges
     (on an edge the minimiser of a convex quadratic is its stationary point
-    clamped to the edge)."""
+    clamped to the edge).  Under the 3-sigma footprint every rectangle tile is
+    binned."""
+    if proj.get("footprint") == "3sigma":
+        vis = np.flatnonzero(proj["visible"] > 0)
+        r = proj["rect"][vis].astype(np.int64)
+        w = r[:, 1] - r[:, 0] + 1
+        cnt = w * (r[:, 3] - r[:, 2] + 1)
+        j = np.repeat(np.arange(vis.size), cnt)
+        k = np.arange(int(cnt.sum())) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        gid = vis[j]
+        return (gid, r[j, 0] + k % w[j], r[j, 2] + k // w[j], np.ones(gid.size, bool),
+                (proj["flags"][gid] & 1) > 0)
     vis = np.flatnonzero(proj["visible"] > 0)
     r = proj["rect"][vis].astype(np.int64)
     w = r[:, 1] - r[:, 0] + 1

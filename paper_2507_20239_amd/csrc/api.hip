@@ -133,7 +133,7 @@ gs_status check_opts(const gs_raster_opts* o) {
         return gs_fail(GS_ERR_INVALID, "raster_batch must be 0, 64, 128 or 256");
     if (o->persistent_blocks < 0 || o->persistent_blocks > 65536)
         return gs_fail(GS_ERR_INVALID, "persistent_blocks must be in [0, 65536]");
-    if (o->flags & ~GS_RASTER_COUNT_COMPOSITED)
+    if (o->flags & ~(GS_RASTER_COUNT_COMPOSITED | GS_RASTER_FOOTPRINT_3SIGMA))
         return gs_fail(GS_ERR_INVALID, "unknown bits in raster flags");
     if (!(o->near_plane > 0.f)) return gs_fail(GS_ERR_INVALID, "near_plane must be > 0");
     return GS_OK;
@@ -259,7 +259,6 @@ gs_status gs_frame_status(gs_frame* f, void* stream, int64_t* n_visible, int64_t
     if (n_visible) *n_visible = h[0];
     if (n_instances) *n_instances = h[1];
     if (overflow) *overflow = (int32_t)h[2];
-    if (h[6]) return gs_fail(GS_ERR_HIP, "a sort look-back wait gave up; results are invalid");
     return h[2] ? gs_fail(GS_ERR_CAPACITY, "instance capacity %lld exceeded (%u needed)",
                           (long long)f->cap, h[1])
                 : GS_OK;
@@ -271,7 +270,8 @@ gs_status gs_project(gs_frame* f, const gs_gaussians* g, const gs_camera* camera
     GS_TRY(check_gaussians(f, g));
     GS_TRY(check_opts(opts));
     if (!cameras) return gs_fail(GS_ERR_INVALID, "cameras is null");
-    return gs_launch_project(f, g, cameras, opts->near_plane, (hipStream_t)stream);
+    return gs_launch_project(f, g, cameras, opts->near_plane,
+                             (opts->flags & GS_RASTER_FOOTPRINT_3SIGMA) != 0, (hipStream_t)stream);
 }
 
 gs_status gs_render(gs_frame* f, const gs_raster_opts* opts, float* images, void* stream) {
@@ -308,8 +308,7 @@ gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camer
 
 gs_status gs_sort_workspace_size(int64_t n, uint64_t* bytes) {
     if (n < 0 || n >= ((int64_t)1 << 30) || !bytes) return gs_fail(GS_ERR_INVALID, "bad argument");
-    *bytes = 2 * align256(4 * (uint64_t)(n > 0 ? n : 1)) + align256(gs_radix_scratch_bytes(n, 32)) +
-             256;
+    *bytes = 2 * align256(4 * (uint64_t)(n > 0 ? n : 1)) + align256(gs_radix_scratch_bytes(n, 32));
     return GS_OK;
 }
 
@@ -327,10 +326,8 @@ gs_status gs_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int32_t key_b
     u32* k[2] = {keys, (u32*)b};
     u32* v[2] = {vals, (u32*)(b + nb)};
     void* scratch = (void*)(b + 2 * nb);
-    u32* err = (u32*)(b + 2 * nb + align256(gs_radix_scratch_bytes(n, 32)));
     int slot = 0;
-    GS_TRY(gs_fill_u32(err, 0u, 1, s));
-    GS_TRY(gs_radix_sort(k, v, nullptr, (u32)n, n, key_bits, scratch, err, &slot, s));
+    GS_TRY(gs_radix_sort(k, v, nullptr, (u32)n, n, key_bits, scratch, &slot, s));
     if (slot == 1) {
         GS_HIP(hipMemcpyAsync(keys, k[1], 4 * n, hipMemcpyDeviceToDevice, s));
         GS_HIP(hipMemcpyAsync(vals, v[1], 4 * n, hipMemcpyDeviceToDevice, s));

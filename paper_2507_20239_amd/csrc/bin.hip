@@ -104,6 +104,7 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) epi.finish((u32)(carry >> 32), (u32)carry);
 }
 
+template <bool SIGMA3>
 __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, const u32* offs,
                                                         const uint2* rect, const float4* splat,
                                                         const gs_view_info* views, int64_t n,
@@ -137,16 +138,18 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
             s_ry[t] = r.y;
             s_tb[t] = (u32)views[v].tile_base;
             s_tw[t] = (u32)views[v].tiles_x;
-            const FootprintRows fr = footprint_rows(splat[3 * (u64)e], splat[3 * (u64)e + 1]);
-            s_fr[0][t] = fr.l21;
-            s_fr[1][t] = fr.l22;
-            s_fr[2][t] = fr.r2;
-            s_fr[3][t] = fr.ry;
-            s_fr[4][t] = fr.ds;
-            s_fr[5][t] = fr.il11;
-            s_fr[6][t] = fr.mx;
-            s_fr[7][t] = fr.hy;
-            s_fr[8][t] = fr.ly;
+            if (!SIGMA3) {
+                const FootprintRows fr = footprint_rows(splat[3 * (u64)e], splat[3 * (u64)e + 1]);
+                s_fr[0][t] = fr.l21;
+                s_fr[1][t] = fr.l22;
+                s_fr[2][t] = fr.r2;
+                s_fr[3][t] = fr.ry;
+                s_fr[4][t] = fr.ds;
+                s_fr[5][t] = fr.il11;
+                s_fr[6][t] = fr.mx;
+                s_fr[7][t] = fr.hy;
+                s_fr[8][t] = fr.ly;
+            }
         }
         __syncthreads();
         const u32 o = c * EMIT_CHUNK + (u32)t;
@@ -163,25 +166,31 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
             const u32 rx = s_rx[lo], ry = s_ry[lo];
             const int x0 = (int)(rx & 0xffffu), x1 = (int)(rx >> 16);
             const int y0 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
-            FootprintRows fr;
-            fr.l21 = s_fr[0][lo];
-            fr.l22 = s_fr[1][lo];
-            fr.r2 = s_fr[2][lo];
-            fr.ry = s_fr[3][lo];
-            fr.ds = s_fr[4][lo];
-            fr.il11 = s_fr[5][lo];
-            fr.mx = s_fr[6][lo];
-            fr.hy = s_fr[7][lo];
-            fr.ly = s_fr[8][lo];
             u32 tile = T;   // not reached: the rows hold exactly the counted tiles
-            for (int ty = y0; ty <= y1; ++ty) {
-                int first = 0;
-                const u32 cnt = footprint_row_count(fr, ty, x0, x1, &first);
-                if (k < cnt) {
-                    tile = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first + k;
-                    break;
+            if (SIGMA3) {
+                // every tile of the rectangle
+                const u32 w = (u32)(x1 - x0 + 1);
+                tile = s_tb[lo] + ((u32)y0 + k / w) * s_tw[lo] + (u32)x0 + k % w;
+            } else {
+                FootprintRows fr;
+                fr.l21 = s_fr[0][lo];
+                fr.l22 = s_fr[1][lo];
+                fr.r2 = s_fr[2][lo];
+                fr.ry = s_fr[3][lo];
+                fr.ds = s_fr[4][lo];
+                fr.il11 = s_fr[5][lo];
+                fr.mx = s_fr[6][lo];
+                fr.hy = s_fr[7][lo];
+                fr.ly = s_fr[8][lo];
+                for (int ty = y0; ty <= y1; ++ty) {
+                    int first = 0;
+                    const u32 cnt = footprint_row_count(fr, ty, x0, x1, &first);
+                    if (k < cnt) {
+                        tile = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first + k;
+                        break;
+                    }
+                    k -= cnt;
                 }
-                k -= cnt;
             }
             tile_keys[o] = tile;
             entries[o] = s_e[lo];
@@ -463,12 +472,19 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         const VisEpi ve{f->visible, f->inst_off, f->chunk_start, cnt, (u32)f->cap};
         vis_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part, ve);
         GS_TRY(gs_check_launch("visible_scan"));
-        emit_kernel<<<8192, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat, f->d_views,
-                                              f->n, cnt + 0, cnt + 5, f->chunk_start, f->ikeys[0],
-                                              f->ivals[0], E, (u32)f->T);
+        if (f->sigma3)
+            emit_kernel<true><<<8192, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat,
+                                                        f->d_views, f->n, cnt + 0, cnt + 5,
+                                                        f->chunk_start, f->ikeys[0], f->ivals[0],
+                                                        E, (u32)f->T);
+        else
+            emit_kernel<false><<<8192, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat,
+                                                         f->d_views, f->n, cnt + 0, cnt + 5,
+                                                         f->chunk_start, f->ikeys[0], f->ivals[0],
+                                                         E, (u32)f->T);
         GS_TRY(gs_check_launch("emit"));
         GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->cap, f->tile_bits, f->sort_scratch,
-                             cnt + 6, &f->isorted, s));
+                             &f->isorted, s));
     } else {
         GS_TRY(gs_fill_u32(cnt, 0u, 8, s));
     }
@@ -487,7 +503,7 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
                                                                  f->T);
         GS_TRY(gs_check_launch("tile_weight"));
         GS_TRY(gs_radix_sort(f->tkeys, f->tvals, nullptr, (u32)f->T, f->T, 24, f->sort_scratch,
-                             cnt + 6, &f->tsorted, s));
+                             &f->tsorted, s));
     }
     return GS_OK;
 }

@@ -58,6 +58,7 @@ struct gs_frame {
     u32* tvals[2];       // [T]
     int tsorted;
     int32_t tile_bits;   // bits needed for a global tile id
+    bool sigma3;         // the last projection binned by 3-sigma squares
     // per pixel
     float* T_final;      // [P]
     u32* n_contrib;      // [P]
@@ -65,7 +66,7 @@ struct gs_frame {
     // per splat gradient
     float* splat_grad;   // [E][9]
     // counters: [0] visible, [1] instances, [2] overflow, [3] fwd queue, [4] bwd queue,
-    // [5] instances kept (min(instances, capacity)), [6] sort look-back error
+    // [5] instances kept (min(instances, capacity))
     u32* counters;
     // sort and scan scratch
     void* sort_scratch;
@@ -206,14 +207,15 @@ gs_status gs_scan_reduce(const u32* in, const u32* gather, const u32* n_dev, u32
 // kernel, an exclusive scan and a scatter kernel).  Buffers k[0]/v[0] hold the
 // input; *slot receives the buffer index (0 or 1) that holds the result.  The
 // length is n_dev[0] when n_dev != NULL, else n_host, and never exceeds
-// `capacity` (< 2^30).  `scratch` needs gs_radix_scratch_bytes(capacity, bits);
-// `err` is unused.
+// `capacity` (< 2^30).  `scratch` needs gs_radix_scratch_bytes(capacity, bits).
 gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
-                        int bits, void* scratch, u32* err, int* slot, hipStream_t s);
+                        int bits, void* scratch, int* slot, hipStream_t s);
 uint64_t gs_radix_scratch_bytes(int64_t capacity, int bits);
 
+// sigma3: bin by 3-sigma squares (GS_RASTER_FOOTPRINT_3SIGMA) instead of the
+// opacity-aware ellipse; recorded in the frame for the binning that follows
 gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
-                            float near_plane, hipStream_t s);
+                            float near_plane, bool sigma3, hipStream_t s);
 gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first);
 gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* images,
                                hipStream_t s);

@@ -126,7 +126,6 @@ struct ProjArgs {
     uint2* rect;
     float4* splat;
     float* splat_grad;     // [E][9], cleared here for the adjoint of this step
-    u32* counters;         // frame counters; [6] (sort error) is cleared here
 };
 
 // Per-Gaussian activated parameters.
@@ -274,11 +273,10 @@ __device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_i
     return true;
 }
 
-template <int DEG>
+template <int DEG, bool SIGMA3>
 __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-    if (i == 0) a.counters[6] = 0;   // sort look-back error flag of this step
     if (i >= a.n) return;
     const int64_t n = a.n;
     // every load first, so one memory latency covers the parameters and the
@@ -307,22 +305,50 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
         a.depth_key[e] = __float_as_uint((float)p.tz);
         u32 tt = 0;
         uint2 rc = make_uint2(0u, 0u);
-        if (ok && g.o >= GS_ALPHA_MIN) {
+        if (ok && (SIGMA3 || g.o >= GS_ALPHA_MIN)) {
             const double u = (double)c.fx * p.tx / p.tz + (double)c.cx;
             const double w = (double)c.fy * p.ty / p.tz + (double)c.cy;
-            // footprint: bounding box of { o G >= 1/255 }, inflated by 2^-10
-            const float L = 2.0f * logf(255.0f * g.o);
-            const double ex = (double)(sqrtf(L * p.cov[0]) * (float)GS_FOOTPRINT_INFLATE);
-            const double ey = (double)(sqrtf(L * p.cov[2]) * (float)GS_FOOTPRINT_INFLATE);
-            double x0 = ceil(u - ex - 0.5), x1 = floor(u + ex - 0.5);
-            double y0 = ceil(w - ey - 0.5), y1 = floor(w + ey - 0.5);
-            x0 = x0 < 0.0 ? 0.0 : x0;
-            y0 = y0 < 0.0 ? 0.0 : y0;
-            x1 = x1 > vi.width - 1 ? (double)(vi.width - 1) : x1;
-            y1 = y1 > vi.height - 1 ? (double)(vi.height - 1) : y1;
-            if (x0 <= x1 && y0 <= y1) {
-                const u32 tx0 = (u32)x0 / GS_TILE, tx1 = (u32)x1 / GS_TILE;
-                const u32 ty0 = (u32)y0 / GS_TILE, ty1 = (u32)y1 / GS_TILE;
+            double x0, x1, y0, y1;   // tile columns and rows, inclusive
+            bool nonempty;
+            if (SIGMA3) {
+                // the tiles whose squares meet [u - r, u + r] x [w - r, w + r],
+                // r = ceil(3 sqrt(largest eigenvalue of Sigma'))
+                const double s0 = p.cov[0], s1 = p.cov[1], s2 = p.cov[2];
+                const double mid = 0.5 * (s0 + s2);
+                const double lam = mid + sqrt(fmax(mid * mid - (s0 * s2 - s1 * s1), 0.0));
+                const double r = ceil(3.0 * sqrt(lam));
+                x0 = ceil((u - r) / GS_TILE) - 1.0;
+                x1 = floor((u + r) / GS_TILE);
+                y0 = ceil((w - r) / GS_TILE) - 1.0;
+                y1 = floor((w + r) / GS_TILE);
+                x0 = x0 < 0.0 ? 0.0 : x0;
+                y0 = y0 < 0.0 ? 0.0 : y0;
+                x1 = x1 > vi.tiles_x - 1 ? (double)(vi.tiles_x - 1) : x1;
+                y1 = y1 > vi.tiles_y - 1 ? (double)(vi.tiles_y - 1) : y1;
+                nonempty = x0 <= x1 && y0 <= y1;
+            } else {
+                // footprint: bounding box of { o G >= 1/255 }, inflated by 2^-10
+                const float L = 2.0f * logf(255.0f * g.o);
+                const double ex = (double)(sqrtf(L * p.cov[0]) * (float)GS_FOOTPRINT_INFLATE);
+                const double ey = (double)(sqrtf(L * p.cov[2]) * (float)GS_FOOTPRINT_INFLATE);
+                x0 = ceil(u - ex - 0.5);
+                x1 = floor(u + ex - 0.5);
+                y0 = ceil(w - ey - 0.5);
+                y1 = floor(w + ey - 0.5);
+                x0 = x0 < 0.0 ? 0.0 : x0;
+                y0 = y0 < 0.0 ? 0.0 : y0;
+                x1 = x1 > vi.width - 1 ? (double)(vi.width - 1) : x1;
+                y1 = y1 > vi.height - 1 ? (double)(vi.height - 1) : y1;
+                // some pixel centre inside; then the tiles of those pixels
+                nonempty = x0 <= x1 && y0 <= y1;
+                x0 = floor(x0 / GS_TILE);
+                x1 = floor(x1 / GS_TILE);
+                y0 = floor(y0 / GS_TILE);
+                y1 = floor(y1 / GS_TILE);
+            }
+            if (nonempty) {
+                const u32 tx0 = (u32)x0, tx1 = (u32)x1;
+                const u32 ty0 = (u32)y0, ty1 = (u32)y1;
                 rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
                 // colour for the direction from the camera centre C = -R^T t
                 const float cx = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
@@ -348,11 +374,15 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
                 a.splat[3 * e + 0] = s0;
                 a.splat[3 * e + 1] = s1;
                 a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
-                // bin to the tiles of the rectangle whose squares meet the ellipse
-                const FootprintRows fr = footprint_rows(s0, s1);
-                int first;
-                for (u32 ty = ty0; ty <= ty1; ++ty)
-                    tt += footprint_row_count(fr, (int)ty, (int)tx0, (int)tx1, &first);
+                if (SIGMA3) {
+                    tt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                } else {
+                    // bin to the tiles of the rectangle whose squares meet the ellipse
+                    const FootprintRows fr = footprint_rows(s0, s1);
+                    int first;
+                    for (u32 ty = ty0; ty <= ty1; ++ty)
+                        tt += footprint_row_count(fr, (int)ty, (int)tx0, (int)tx1, &first);
+                }
             }
         }
         a.tiles_touched[e] = tt;
@@ -614,23 +644,29 @@ ProjArgs make_args(gs_frame* f, const gs_gaussians* g, const gs_camera* cams, fl
     a.rect = f->rect;
     a.splat = f->splat;
     a.splat_grad = f->splat_grad;
-    a.counters = f->counters;
     return a;
 }
 
 }  // namespace
 
+template <bool SIGMA3>
+void launch_project_fwd(const ProjArgs& a, int sh_degree, unsigned blocks, hipStream_t s) {
+    switch (sh_degree) {
+        case 0: project_fwd_kernel<0, SIGMA3><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+        case 1: project_fwd_kernel<1, SIGMA3><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+        case 2: project_fwd_kernel<2, SIGMA3><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+        default: project_fwd_kernel<3, SIGMA3><<<blocks, GS_BLOCK, 0, s>>>(a); break;
+    }
+}
+
 gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
-                            float near_plane, hipStream_t s) {
+                            float near_plane, bool sigma3, hipStream_t s) {
+    f->sigma3 = sigma3;
     if (f->n == 0) return GS_OK;
     ProjArgs a = make_args(f, g, cams, near_plane);
     const unsigned blocks = (unsigned)((f->n + GS_BLOCK - 1) / GS_BLOCK);
-    switch (g->sh_degree) {
-        case 0: project_fwd_kernel<0><<<blocks, GS_BLOCK, 0, s>>>(a); break;
-        case 1: project_fwd_kernel<1><<<blocks, GS_BLOCK, 0, s>>>(a); break;
-        case 2: project_fwd_kernel<2><<<blocks, GS_BLOCK, 0, s>>>(a); break;
-        default: project_fwd_kernel<3><<<blocks, GS_BLOCK, 0, s>>>(a); break;
-    }
+    if (sigma3) launch_project_fwd<true>(a, g->sh_degree, blocks, s);
+    else launch_project_fwd<false>(a, g->sh_degree, blocks, s);
     return gs_check_launch("project_fwd");
 }
 

@@ -216,8 +216,7 @@ gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_hos
 }
 
 gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
-                        int bits, void* scratch, u32* err, int* slot, hipStream_t s) {
-    (void)err;
+                        int bits, void* scratch, int* slot, hipStream_t s) {
     const unsigned G = sort_blocks(capacity);
     u32* counts = (u32*)scratch;
     u32* part = counts + 256 * (uint64_t)G;

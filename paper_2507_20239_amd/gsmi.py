@@ -32,6 +32,7 @@ ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO, ATTR_SPLIT_COUNT,
     range(7)
 DENSIFY_SPLIT_LARGE, DENSIFY_ADAPTIVE, DENSIFY_SPLIT_ONLY, DENSIFY_CLONE_ONLY = range(4)
 RASTER_COUNT_COMPOSITED = 1
+RASTER_FOOTPRINT_3SIGMA = 2
 
 
 class GsError(RuntimeError):
@@ -199,13 +200,17 @@ def cameras_to_device(cams, device="cuda") -> torch.Tensor:
 
 
 def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0,
-                count_composited=False):
+                count_composited=False, footprint_3sigma=False):
+    """footprint_3sigma: bin by 3-sigma squares as the original 3DGS
+    rasterizer does (images then depend on the tile grid) instead of by the
+    opacity-aware ellipse (GS_RASTER_FOOTPRINT_3SIGMA)."""
     o = RasterOpts()
     o.bg[:] = [float(x) for x in bg]
     o.near_plane = float(np.float32(near_plane))
     o.raster_batch = int(raster_batch)
     o.persistent_blocks = int(persistent_blocks)
-    o.flags = RASTER_COUNT_COMPOSITED if count_composited else 0
+    o.flags = ((RASTER_COUNT_COMPOSITED if count_composited else 0) |
+               (RASTER_FOOTPRINT_3SIGMA if footprint_3sigma else 0))
     return o
 
 

@@ -108,6 +108,48 @@ def test_projection_isotropic_on_axis_closed_form():
         assert p["depth"][0] == zf
 
 
+def test_3sigma_footprint_closed_form_and_tile_cut():
+    """The 3-sigma footprint of an on-axis isotropic Gaussian: r = ceil(3 sigma')
+    with sigma'^2 = (f s / z)^2 + 0.3, the tiles meeting the square; a pixel of
+    the next tile column inside the 1/255 ellipse but outside the square is
+    composited under the ellipse footprint only; a Gaussian below 1/255 is
+    binned under the 3-sigma footprint and composited nowhere."""
+    W, H, f, z = 64, 32, 64.0, 2.0
+    cam = _cam(W, H, f, cx=19.5, cy=16.0)
+    bg = np.array([0.1, 0.2, 0.3])
+    sc = _one_gaussian([0, 0, z], [-2.096] * 3, [1, 0, 0, 0], 6.0, [0.9, 0.5, 0.2])
+    s = math.exp(float(np.float32(-2.096)))
+    sig = math.sqrt((f * s / z) ** 2 + float(np.float32(0.3)))
+    r = math.ceil(3 * sig)
+    assert r == 12 and 3 * sig < 12 - 1e-3
+    p3 = oracle.project(sc, cam, footprint="3sigma")
+    pe = oracle.project(sc, cam)
+    x0, x1 = math.ceil((19.5 - r) / 16) - 1, math.floor((19.5 + r) / 16)
+    y0, y1 = max(math.ceil((16.0 - r) / 16) - 1, 0), min(math.floor((16.0 + r) / 16), H // 16 - 1)
+    assert p3["rect"][0].tolist() == [x0, x1, y0, y1] == [0, 1, 0, 1]
+    assert p3["tiles_touched"][0] == 4 and p3["visible"][0] == 1 and p3["flags"][0] == 0
+    # pixel (32, 16): centre 13 px right of the mean, inside o G >= 1/255, in tile column 2
+    o = 1.0 / (1.0 + math.exp(-float(np.float32(6.0))))
+    assert o * math.exp(-0.5 * (13.0 ** 2 + 0.5 ** 2) / sig ** 2) > 1.0 / 255.0
+    assert pe["rect"][0][1] == 2
+    ce, Te, ne, _ = oracle.render_pixels(pe, [[32, 16]], bg)
+    c3, T3, n3, _ = oracle.render_pixels(p3, [[32, 16]], bg)
+    assert ne[0] == 1 and Te[0] < 1.0
+    assert n3[0] == 0 and T3[0] == 1.0 and np.array_equal(c3[0], bg)
+    # inside the square both footprints agree
+    a = oracle.render_pixels(pe, [[25, 16], [19, 16]], bg)
+    b = oracle.render_pixels(p3, [[25, 16], [19, 16]], bg)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    # opacity below 1/255: binned by the 3-sigma footprint only, never composited
+    faint = _one_gaussian([0, 0, z], [-2.096] * 3, [1, 0, 0, 0], -6.0, [0.9, 0.5, 0.2])
+    assert oracle.project(faint, cam)["visible"][0] == 0
+    pf = oracle.project(faint, cam, footprint="3sigma")
+    assert pf["visible"][0] == 1 and pf["tiles_touched"][0] == 4
+    _, Tf, nf, _ = oracle.render_pixels(pf, [[19, 16], [20, 17]], bg)
+    assert nf.tolist() == [0, 0] and Tf.tolist() == [1.0, 1.0]
+
+
 def test_projection_covariance_matches_finite_difference_jacobian():
     rng = np.random.default_rng(4)
     R, t = synth.look_at((0.3, -0.2, -0.5), (0.1, 0.05, 3.0), up=(0, -1, 0))
