@@ -24,16 +24,19 @@ class GaussianRasterizer:
 
     cameras: list of objects with R (3x3), t (3), fx, fy, cx, cy, width, height
     (see synth.Camera); their sizes fix the frame.  The instance capacity
-    grows (and the step re-runs) when a render overflows it.
+    grows (and the step re-runs) when a render overflows it.  footprint_3sigma
+    bins by the original 3DGS 3-sigma squares (gsmi.raster_opts).
     """
 
     def __init__(self, n, cameras, sh_degree, device="cuda", bg=(0.0, 0.0, 0.0),
-                 raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2):
+                 raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2,
+                 footprint_3sigma=False):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.device = torch.device(device)
         self.opts = gsmi.raster_opts(bg=bg, near_plane=near_plane, raster_batch=raster_batch,
-                                     persistent_blocks=persistent_blocks)
+                                     persistent_blocks=persistent_blocks,
+                                     footprint_3sigma=footprint_3sigma)
         self.set_cameras(cameras)
         sizes = [(c.width, c.height) for c in cameras]
         if capacity is None:

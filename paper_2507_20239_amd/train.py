@@ -10,7 +10,8 @@ rebuilds parameters and optimiser state; opacities are reset periodically
 (Methodology; Preliminary; Experiments, implementation details).  With
 lineage=True every Gaussian also carries the attributes of the Spatial
 diffusion analysis (its parent point's original position and the splits and
-clones on its line of descent), carried through each compaction.
+clones on its line of descent), carried through each compaction;
+footprint_3sigma=True bins by the original 3DGS 3-sigma squares.
 
 Every numerical step runs in libgsmi.so; this module keeps the tensors and
 the iteration logic.
@@ -34,7 +35,7 @@ LINEAGE_POLICY = {"origin": gsmi.ATTR_COPY, "splits": gsmi.ATTR_SPLIT_COUNT,
 class Trainer:
     def __init__(self, params: dict, sh_degree: int, cameras, targets, policy, extent: float,
                  lrs=None, lam: float = 0.2, seed: int = 0, device="cuda", capacity=None,
-                 lineage: bool = False):
+                 lineage: bool = False, footprint_3sigma: bool = False):
         self.dev = torch.device(device)
         self.p = {k: params[k].to(self.dev).contiguous().clone() for k in PARAMS}
         self.sh_degree = sh_degree
@@ -49,7 +50,7 @@ class Trainer:
         self.rng = np.random.default_rng(seed)
         self.seed = seed
         self.capacity = capacity
-        self.opts = gsmi.raster_opts()
+        self.opts = gsmi.raster_opts(footprint_3sigma=footprint_3sigma)
         self._reset_state()
         # original position [3][n], split count [1][n], clone count [1][n] (FP32)
         self.lineage = None
