@@ -180,6 +180,56 @@ def test_multiview_frame_matches_per_view_oracle():
     assert base == frame.T
 
 
+def test_thirty_two_views_in_one_frame():
+    """The largest frame (32 views, mixed sizes): every view's image and tile
+    lists against the oracle, and the adjoint summed over the views with the
+    statistic counting each view that renders a Gaussian."""
+    sc = synth.random_scene(26, 300, 40, 30, sh_degree=1, n_views=32, log_scale=(-2.3, 0.5))
+    cams = [c.scaled(2) if v % 3 == 1 else c for v, c in enumerate(sc.cameras)]
+    assert len(cams) == gsmi.MAX_VIEWS
+    frame, flat, params, cams_dev, opts = gpu_forward(sc, cams)
+    imgs = frame.split_images(flat)
+    nv, ni, _ = frame.status()
+    gt = frame.buffer(gsmi.BUF_INST_TILE).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    ge = frame.buffer(gsmi.BUF_INST_ENTRY).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    rng = np.random.default_rng(26)
+    dLs, projs, base = [], [], 0
+    for v, cam in enumerate(cams):
+        p = oracle.project(sc, cam)
+        ref, _, _, margin = oracle.render_image(p)
+        good = margin > MARGIN
+        got = imgs[v].cpu().numpy()
+        assert_close_scaled(got[:, good], ref[:, good], np.abs(ref[:, good]), what="view %d" % v)
+        tiles, gids, rr = oracle.tile_lists(p, tile_base=base)
+        sel = (gt >= base) & (gt < base + rr.shape[0])
+        _compare_lists(p, gt[sel], ge[sel], tiles, gids, entry_base=v * sc.n)
+        base += rr.shape[0]
+        dL = rng.standard_normal((3, cam.height, cam.width)) * 1e-3
+        dL[:, ~good] = 0.0
+        dLs.append(dL.astype(np.float32))
+        projs.append(p)
+    assert base == frame.T
+    frame.render_backward(opts, torch.from_numpy(np.concatenate([d.reshape(-1) for d in dLs])).to(dev()))
+    grads = gsmi.empty_grads(params)
+    acc = torch.zeros(sc.n, device=dev())
+    den = torch.zeros(sc.n, device=dev())
+    frame.project_backward(params, sc.sh_degree, cams_dev, opts, grads, acc, den)
+    torch.cuda.synchronize()
+    want = {k: 0.0 for k in gsmi.PARAM_NAMES}
+    scale = {k: 0.0 for k in gsmi.PARAM_NAMES}
+    racc, rden = np.zeros(sc.n), np.zeros(sc.n)
+    for cam, p, dL in zip(cams, projs, dLs):
+        gproj, gabs = oracle.render_backward_image(p, dL.astype(np.float64))
+        g = oracle.project_backward(sc, cam, p["visible"], gproj, stats=(racc, rden))
+        s = raw_grad_scale(sc, cam, p, gabs)
+        for k in gsmi.PARAM_NAMES:
+            want[k] = want[k] + g[k]
+            scale[k] = scale[k] + s[k]
+    for k in gsmi.PARAM_NAMES:
+        assert_close_scaled(grads[k].cpu().numpy(), want[k], scale[k], what=k)
+    np.testing.assert_array_equal(den.cpu().numpy(), rden)
+
+
 def test_empty_and_culled_scene_renders_background():
     sc = synth.random_scene(24, 64, 33, 17, sh_degree=0)
     sc.means[2] = -1.0          # every Gaussian behind the camera
