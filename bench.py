@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batc
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -138,10 +139,15 @@ def breakdown(torch, step, reps):
 
 
 def source_hash(*files):
+    """Hash of the code of the given sources, comments and blank space aside,
+    so a counter summary stays valid across comment edits."""
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -196,7 +196,7 @@ gs_status gs_fill_u32(u32* p, u32 value, int64_t count, hipStream_t s);
 // else n_host.  total (device, may be NULL) receives the sum.  `part` needs
 // GS_SCAN_PARTS + 1 u32.  gather (may be NULL): scan in[gather[i]] instead of
 // in[i].  (A one-workgroup scan for short arrays was measured: 43 us for 62720
-// values, latency-bound, against 12 us for these three launches.)
+// values, latency-bound, against 12 us for the multi-workgroup scan.)
 gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_host, u32* total,
                             u32* part, hipStream_t s, const u32* gather = nullptr);
 // the first launch of a scan: one partial sum per partition into part[0..GS_SCAN_PARTS)
@@ -259,9 +259,6 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
     return x;
 }
 
-// Alpha of one splat at a pixel centre, shared by the forward and the
-// adjoint so both evaluate bit-identical values.  p0 = (mean hi x, y, mean lo x, y),
-// p1 = (conic a, b, c, opacity).  Returns o G (before the 0.99 clamp).
 // A projected splat is three float4: (mean hi x, y, mean lo x, y), (l11, l21,
 // l22, opacity), (r, g, b, pad).  L = [l11 0; l21 l22] is the Cholesky factor
 // of kappa Q, Q the conic (inverse screen-space covariance) and kappa =
@@ -294,7 +291,8 @@ __device__ __forceinline__ void quad_setup(float4 p0, float4 p1, float pxc0, flo
     q.vv[1] = v1 * v1;
 }
 
-// G of pixel i of the quad
+// G of pixel i of the quad; the forward and the adjoint both evaluate it
+// through this function, so they see bit-identical values.
 __device__ __forceinline__ float quad_G(const Quad& q, int i) {
     return __builtin_amdgcn_exp2f(-fmaf(q.u[i], q.u[i], q.vv[i >> 1]));
 }
