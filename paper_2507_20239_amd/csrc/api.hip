@@ -105,7 +105,7 @@ Layout layout_for(gs_frame* f) {
     L.add(36 * E);       // 17 splat_grad
     L.add(64);           // 18 counters
     L.add(sort_bytes);   // 19 sort scratch
-    L.add(8 * (GS_SCAN_PARTS + 8));  // 20 scan_part
+    L.add(16 * (GS_SCAN_PARTS + 8));  // 20 scan_part
     L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 21 views
     L.add(4 * P);        // 22 n_comp
     L.add(4 * (cap / 256 + 2));  // 23 chunk_start

@@ -33,12 +33,15 @@ constexpr u32 EMIT_CHUNK = 256;
 
 // Visible entries and their instance offsets in one scan: each entry adds
 // (1 << 32 | tiles) if it has tiles, so the exclusive prefix holds its slot in
-// the compacted list (high half) and its instance offset (low half; instance
-// totals stay below 2^32).  The epilogue writes the compacted entry, its
-// offset, and for every chunk of 256 instance slots that starts inside its
-// range the slot itself (chunk_start, below the capacity); the last
-// workgroup publishes the visible count, the instance total, the kept length
-// min(total, capacity) and the overflow flag.
+// the compacted list (high half) and its instance offset (low half).  The
+// epilogue writes the compacted entry, its offset, and for every chunk of 256
+// instance slots that starts inside its range the slot itself (chunk_start,
+// below the capacity); the last workgroup publishes the visible count, the
+// instance total, the kept length min(total, capacity) and the overflow flag.
+// A total of 2^32 instances or more would carry into the high half; the first
+// launch also sums the tiles alone (64-bit), and such a step is reported as an
+// overflow with nothing kept (no capacity holds it), its slots bounded by the
+// entry count.
 __device__ __forceinline__ u64 vis_pack(u32 tt) { return tt ? ((u64)1 << 32) | tt : 0ull; }
 
 struct VisEpi {
@@ -47,14 +50,23 @@ struct VisEpi {
     u32* chunk_start;
     u32* counters;
     u32 cap;
+    u32 n;           // entries: bound of the compacted slots
     __device__ void item(u32 e, u32 tt, u32 slot, u32 off) const {
+        if (slot >= n) return;   // only after a carry out of the low half
         visible[slot] = e;
         inst_off[slot] = off;
         const u64 hi = (u64)off + tt < cap ? (u64)off + tt : cap;
         for (u64 c = ((u64)off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK < hi; ++c)
             chunk_start[c] = slot;
     }
-    __device__ void finish(u32 nv, u32 t) const {
+    __device__ void finish(u32 nv, u32 t, u64 tiles) const {
+        if (tiles >> 32) {
+            counters[0] = nv < n ? nv : n;
+            counters[1] = 0xffffffffu;
+            counters[5] = 0;
+            counters[2] = 1;
+            return;
+        }
         counters[0] = nv;
         counters[1] = t;
         counters[5] = t < cap ? t : cap;
@@ -62,15 +74,26 @@ struct VisEpi {
     }
 };
 
+// part[0 .. GS_SCAN_PARTS): packed partition sums; part[GS_SCAN_PARTS ..
+// 2 GS_SCAN_PARTS): tile sums alone
 __global__ void __launch_bounds__(GS_BLOCK) vis_reduce_kernel(const u32* tt, u32 n, u64* part) {
     __shared__ u64 lds4[4];
     u32 beg, end;
     chunk_of(n, GS_SCAN_PARTS, blockIdx.x, beg, end);
-    u64 s = 0;
-    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) s += vis_pack(tt[i]);
-    u64 total;
+    u64 s = 0, st = 0;
+    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) {
+        const u32 v = tt[i];
+        s += vis_pack(v);
+        st += v;
+    }
+    u64 total, tiles;
     block_exclusive_scan(s, lds4, total);
-    if (threadIdx.x == 0) part[blockIdx.x] = total;
+    __syncthreads();
+    block_exclusive_scan(st, lds4, tiles);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = total;
+        part[GS_SCAN_PARTS + blockIdx.x] = tiles;
+    }
 }
 
 __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n, const u64* part,
@@ -101,7 +124,14 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n
         }
         carry += total;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) epi.finish((u32)(carry >> 32), (u32)carry);
+    if (blockIdx.x == gridDim.x - 1) {
+        u64 tiles = 0;
+        for (u32 i = threadIdx.x; i < GS_SCAN_PARTS; i += GS_BLOCK) tiles += part[GS_SCAN_PARTS + i];
+        u64 all;
+        __syncthreads();
+        block_exclusive_scan(tiles, lds4, all);
+        if (threadIdx.x == 0) epi.finish((u32)(carry >> 32), (u32)carry, all);
+    }
 }
 
 template <bool SIGMA3>
@@ -469,7 +499,7 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         u64* part = (u64*)f->scan_part;
         vis_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part);
         GS_TRY(gs_check_launch("visible_reduce"));
-        const VisEpi ve{f->visible, f->inst_off, f->chunk_start, cnt, (u32)f->cap};
+        const VisEpi ve{f->visible, f->inst_off, f->chunk_start, cnt, (u32)f->cap, (u32)E};
         vis_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part, ve);
         GS_TRY(gs_check_launch("visible_scan"));
         if (f->sigma3)

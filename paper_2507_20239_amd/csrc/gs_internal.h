@@ -70,7 +70,7 @@ struct gs_frame {
     u32* counters;
     // sort and scan scratch
     void* sort_scratch;
-    u32* scan_part;      // [2 (GS_SCAN_PARTS + 8)] (u32 or u64 partial sums)
+    u32* scan_part;      // [4 (GS_SCAN_PARTS + 8)] (u32 or u64 partial sums)
 };
 
 #define GS_SCAN_PARTS 1024

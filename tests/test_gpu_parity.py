@@ -283,6 +283,35 @@ def test_capacity_overflow_is_reported_and_bounded():
         frame.status()
 
 
+@pytest.mark.parametrize("n,wraps", [((1 << 20) - 1, False), ((1 << 20) + 1, True)])
+def test_instance_totals_at_and_beyond_2_to_32(n, wraps):
+    """n Gaussians that each cover all 4096 tiles of a 1024x1024 view: 2^32 - 4096
+    instances is an ordinary overflow with the exact total; 2^32 + 4096 (whose
+    low 32 bits would look like a small total) is reported as an overflow with
+    nothing kept, and the view renders as background."""
+    rng = np.random.default_rng(27)
+    means = np.stack([rng.uniform(-1e-3, 1e-3, n), rng.uniform(-1e-3, 1e-3, n),
+                      np.full(n, 3.0)]).astype(np.float32)
+    sc = synth.Scene(means, np.full((3, n), 1.5, np.float32), np.tile([[1.0], [0], [0], [0]], n).astype(np.float32),
+                     np.zeros(n, np.float32), np.full((1, 3, n), 0.3, np.float32), 0,
+                     [synth.Camera(np.eye(3), np.zeros(3), 1024.0, 1024.0, 512.0, 512.0, 1024, 1024)],
+                     [], np.array([0.25, 0.5, 0.75], np.float32))
+    frame, flat, *_ = gpu_forward(sc, sc.cameras, cap=1 << 20)
+    tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy().view(np.uint32)
+    assert (tt == 4096).all()
+    nv, ni, ovf = frame.status(raise_on_overflow=False)
+    assert ovf == 1
+    with pytest.raises(gsmi.GsError):
+        frame.status()
+    if wraps:
+        assert ni == 0xFFFFFFFF and nv <= n
+        img = flat.view(3, 1024, 1024).cpu().numpy()
+        for c in range(3):
+            assert np.all(img[c] == sc.bg[c])
+    else:
+        assert ni == 4096 * n and nv == n
+
+
 def test_counting_composited_splats_changes_nothing_else():
     sc = SCENES["ragged_300_37x29_sh3"]
     cam = sc.cameras[0]
