@@ -321,8 +321,8 @@ def extras(torch, gsmi, synth, st, params, sc, dev, K, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the view-parallel "
-              "sharding is a design only); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (sharding the views "
+              "across GPUs is a design only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -55,7 +55,7 @@ typedef enum {
     GS_ERR_INVALID = 1,     /* bad argument; nothing was enqueued */
     GS_ERR_CAPACITY = 2,    /* a device-side capacity was exceeded (see gs_frame_status) */
     GS_ERR_HIP = 3,         /* a HIP runtime call failed */
-    GS_ERR_UNSUPPORTED = 4  /* valid but not supported by this build */
+    GS_ERR_UNSUPPORTED = 4  /* valid but not supported by the library */
 } gs_status;
 
 /* Text of the last non-OK status on the calling thread (never NULL). */
