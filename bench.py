@@ -344,7 +344,7 @@ def main():
     st.capture()
     ms_graph = time_loop(torch, st.launch, K, W)
     ms_eager = time_loop(torch, st.eager, K, W)
-    log("C2 graph %.3f ms eager %.3f ms" % (ms_graph, ms_eager))
+    log("1M-Gaussian 1600x1040 step: graph %.3f ms eager %.3f ms" % (ms_graph, ms_eager))
     parts = breakdown(torch, st, max(3, K // 2))
     log("breakdown", json.dumps({k: round(v, 4) for k, v in parts.items()}))
 

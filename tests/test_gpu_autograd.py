@@ -122,7 +122,7 @@ def _tiles_of(rect):
 
 
 @pytest.fixture(scope="module")
-def c5():
+def scene_6m_1920x1080():
     sc = synth.procedural_scene()
     cams = synth.procedural_cameras()[:4]
     sc.cameras = cams
@@ -305,9 +305,9 @@ def check_fd(gg, fdiff, gid):
 
 
 @pytest.fixture(scope="module")
-def c5_grads(c5):
+def slice_grads(scene_6m_1920x1080):
     """GPU autograd over the whole scene with the slice's loss weights."""
-    sc, cams, projs = c5
+    sc, cams, projs = scene_6m_1920x1080
     slice_ids, Ws, support = c5_slice_and_weights(sc, cams, projs)
     r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev())
     P = _leaf_params(sc)
@@ -320,20 +320,20 @@ def c5_grads(c5):
     return slice_ids, Ws, support, got
 
 
-def test_c5_slice_gradients_match_oracle_adjoint(c5, c5_grads):
-    sc, cams, projs = c5
-    slice_ids, Ws, support, got = c5_grads
+def test_6m_slice_gradients_match_oracle_adjoint(scene_6m_1920x1080, slice_grads):
+    sc, cams, projs = scene_6m_1920x1080
+    slice_ids, Ws, support, got = slice_grads
     want, scale = oracle_slice_grads(sc, cams, projs, Ws, support, slice_ids)
     for k in gsmi.PARAM_NAMES:
-        assert_close_scaled(got[k], want[k], scale[k], what="C5 slice " + k)
+        assert_close_scaled(got[k], want[k], scale[k], what="6M-Gaussian slice " + k)
 
 
 @pytest.mark.parametrize("part", range(4))
-def test_c5_slice_gradients_match_finite_differences(c5, c5_grads, part):
+def test_6m_slice_gradients_match_finite_differences(scene_6m_1920x1080, slice_grads, part):
     """Central differences on all 64 Gaussians of the slice (16 per part), all
     59 raw parameters each."""
-    sc, cams, projs = c5
-    slice_ids, Ws, support, got = c5_grads
+    sc, cams, projs = scene_6m_1920x1080
+    slice_ids, Ws, support, got = slice_grads
     skipped = 0
     for j in range(16 * part, 16 * part + 16):
         gid = slice_ids[j]

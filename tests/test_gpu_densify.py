@@ -255,13 +255,13 @@ def test_adaptive_threshold_bit_exact(n, p):
 
 
 @pytest.fixture(scope="module")
-def c4():
+def densify_3m():
     return synth.densify_workload()
 
 
-def test_c4_densify_3m_bit_exact(c4):
+def test_densify_3m_100_views_bit_exact(densify_3m):
     """3,000,000 Gaussians, statistics over 100 views, the paper's thresholds."""
-    d = c4
+    d = densify_3m
     n = d.means.shape[1]
     acc, den = _gpu_stats(d)
     acc_o, den_o = oracle.stats_f32(d.dmean2d, d.visible, d.view_wh)

@@ -28,7 +28,7 @@ def _sample_pixels(rng, W, H, m):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def view_1m_1600x1040():
     sc = synth.single_view_1m(with_targets=False)
     cam = sc.cameras[0]
     frame, flat, params, cams_dev, opts = gpu_forward(sc, [cam], opts=gsmi.raster_opts(count_composited=True),
@@ -37,8 +37,8 @@ def c2():
     return sc, cam, frame, flat, params, cams_dev, opts, p
 
 
-def test_c2_projection_and_tile_lists(c2):
-    sc, cam, frame, flat, params, cams_dev, opts, p = c2
+def test_1m_1600x1040_projection_and_tile_lists(view_1m_1600x1040):
+    sc, cam, frame, flat, params, cams_dev, opts, p = view_1m_1600x1040
     nv, ni, ovf = frame.status()
     assert ovf == 0 and ni > 2_000_000
     sp = splat_view(frame)
@@ -62,8 +62,8 @@ def test_c2_projection_and_tile_lists(c2):
     _check_ranges_partition(gr, gt)
 
 
-def test_c2_sampled_pixels(c2):
-    sc, cam, frame, flat, params, cams_dev, opts, p = c2
+def test_1m_1600x1040_sampled_pixels(view_1m_1600x1040):
+    sc, cam, frame, flat, params, cams_dev, opts, p = view_1m_1600x1040
     rng = np.random.default_rng(17)
     pix = _sample_pixels(rng, cam.width, cam.height, 2000)
     # the image corners and edges are part of every sample
@@ -81,8 +81,8 @@ def test_c2_sampled_pixels(c2):
     np.testing.assert_array_equal(ncg[pix[good, 1], pix[good, 0]], nc[good])
 
 
-def test_c2_backward_from_sampled_pixels(c2):
-    sc, cam, frame, flat, params, cams_dev, opts, p = c2
+def test_1m_1600x1040_backward_from_sampled_pixels(view_1m_1600x1040):
+    sc, cam, frame, flat, params, cams_dev, opts, p = view_1m_1600x1040
     rng = np.random.default_rng(23)
     pix = _sample_pixels(rng, cam.width, cam.height, 400)
     _, _, _, margin = oracle.render_pixels(p, pix)
@@ -111,7 +111,7 @@ def test_c2_backward_from_sampled_pixels(c2):
 
 
 @pytest.mark.parametrize("batch,persistent", [(128, 0), (64, 8192)])
-def test_c3_batched_views_sampled(batch, persistent):
+def test_batched_8_views_500k_sampled(batch, persistent):
     sc = synth.batched_c2f(with_targets=False)
     cams = sc.cameras
     opts = gsmi.raster_opts(raster_batch=batch, persistent_blocks=persistent)

@@ -24,14 +24,14 @@ pytestmark = pytest.mark.gpu
 
 
 def _scenes():
-    c1 = synth.tiny_scene(seed=0, n=2000)
+    tiny = synth.tiny_scene(seed=0, n=2000)
     rag = synth.random_scene(21, 300, 37, 29, sh_degree=3, log_scale=(-2.6, 0.5), spread=1.0)
     rag.bg = np.array([0.2, 0.4, 0.1], np.float32)
     deg1 = synth.random_scene(22, 500, 70, 45, sh_degree=1, logit=(1.5, 1.0), log_scale=(-2.2, 0.5))
     # tile lists of 676 .. 13458 instances: wave sorts in registers, LDS sorts, and LDS-sorted
     # runs merged once to three times
     dense = synth.random_scene(23, 24000, 64, 40, sh_degree=0, log_scale=(-2.6, 0.4))
-    return {"c1_2000_128x128_sh0": c1, "ragged_300_37x29_sh3": rag, "sh1_500_70x45": deg1,
+    return {"tiny_2000_128x128_sh0": tiny, "ragged_300_37x29_sh3": rag, "sh1_500_70x45": deg1,
             "dense_24000_64x40_sh0": dense}
 
 
@@ -274,7 +274,7 @@ def test_nonfinite_gaussians_are_culled():
 
 
 def test_capacity_overflow_is_reported_and_bounded():
-    sc = SCENES["c1_2000_128x128_sh0"]
+    sc = SCENES["tiny_2000_128x128_sh0"]
     cam = sc.cameras[0]
     frame, flat, *_ = gpu_forward(sc, [cam], cap=1000)
     nv, ni, ovf = frame.status(raise_on_overflow=False)
