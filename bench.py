@@ -318,6 +318,39 @@ def extras(torch, gsmi, synth, st, params, sc, dev, K, W):
     return out
 
 
+def autograd_step_6m(torch, gsmi, synth, dev, K, W):
+    """The large training step: 6M Gaussians on spheres and planes, SH3, four
+    1920x1080 views per step through the torch.autograd.Function (projection,
+    binning, compositing and both adjoints with the statistic), the image
+    gradients supplied directly (no loss kernels)."""
+    import numpy as np
+    from paper_2507_20239_amd.autograd import GaussianRasterizer
+    log("generating the 6M-Gaussian procedural scene (4 x 1920x1080 views)")
+    sc = synth.procedural_scene()
+    cams = synth.procedural_cameras()[:4]
+    P = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(dev).requires_grad_()
+         for k in gsmi.PARAM_NAMES}
+    r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    Ws = [torch.randn(3, c.height, c.width, device=dev, generator=g) * 1e-6 for c in cams]
+
+    def step():
+        for t in P.values():
+            t.grad = None
+        imgs = r(P["means"], P["log_scales"], P["quats"], P["opacity_logits"], P["sh"])
+        torch.autograd.backward(imgs, Ws)
+
+    ms = timed(torch, step, K, W)
+    nv, ni, _ = r.frame.status()
+    out = {"workload": "6,000,000 Gaussians (64 spheres, 16 planes), SH3, 4 views of 1920x1080 "
+                       "per step, autograd fwd+bwd with the statistic",
+           "ms_per_step": round(ms, 4), "visible_entries": int(nv), "instances": int(ni)}
+    del r, P, Ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -453,6 +486,8 @@ def main():
     # ---------------- the other steps of an iteration and of a densification ----------------
     if not args.no_extras and not args.profile:
         result["extras"] = extras(torch, gsmi, synth, st, params, sc, dev, K, W)
+        result["extras"]["autograd_step_6m_4x1920x1080"] = autograd_step_6m(torch, gsmi, synth, dev,
+                                                                             min(K, 10), 2)
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
     if not args.no_cpu and not args.profile:

@@ -423,15 +423,24 @@ __device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key,
                 if (run_key(srh, srl, a0 + mid) < run_key(srh, srl, a1 + (p0 - mid - 1))) lo = mid + 1;
                 else hi = mid;
             }
+            // the two head keys stay in registers (an exhausted run reads as all
+            // ones, above every key: depth bits are below the infinity pattern);
+            // each step writes the smaller and loads the next of its run
             u32 ia = lo, ib = p0 - lo;
+            u64 ka = ia < na ? run_key(srh, srl, a0 + ia) : ~0ull;
+            u64 kb = ib < nb ? run_key(srh, srl, a1 + ib) : ~0ull;
             for (u32 p = p0; p < p1; ++p) {
-                const bool take_a =
-                    ib >= nb || (ia < na && run_key(srh, srl, a0 + ia) < run_key(srh, srl, a1 + ib));
-                const u32 src = take_a ? a0 + ia : a1 + ib;
-                dsh[i0 + p] = srh[src];
-                dsl[i0 + p] = srl[src];
-                if (take_a) ++ia;
-                else ++ib;
+                const bool take_a = ka < kb;
+                const u64 k = take_a ? ka : kb;
+                dsh[i0 + p] = (u32)(k >> 32);
+                dsl[i0 + p] = (u32)k;
+                if (take_a) {
+                    ++ia;
+                    ka = ia < na ? run_key(srh, srl, a0 + ia) : ~0ull;
+                } else {
+                    ++ib;
+                    kb = ib < nb ? run_key(srh, srl, a1 + ib) : ~0ull;
+                }
             }
         }
         __syncthreads();
@@ -443,27 +452,29 @@ __device__ void sort_long_list(u64* s, u32 tile, uint2 rg, const u32* depth_key,
     }
 }
 
-// Every tile list in one launch: each 256-thread workgroup takes four
-// consecutive tiles, wave w sorts tile t0 + w if its list is short (up to 512
-// instances), then the workgroup sorts the longer lists among the four one
-// after the other: in registers across its four waves up to SORT_LDS
-// instances, beyond that as runs and merges.
+// Every tile list in one launch: each 256-thread workgroup takes four tiles a
+// grid apart (b, b + G, b + 2G, b + 3G), so the long lists of a dense image
+// region, which sit on neighbouring tiles, land on different workgroups; wave
+// w sorts tile b + w G if its list is short (up to 512 instances), then the
+// workgroup sorts the longer lists among the four one after the other: in
+// registers across its four waves up to SORT_LDS instances, beyond that as
+// runs and merges.
 constexpr u32 SORT_TILES = SORT_THREADS / 64;
 
 __global__ void __launch_bounds__(SORT_THREADS) tile_sort_kernel(
     const uint2* ranges, u32 T, const u32* depth_key, u32 E, u32* inst_entry, u32* inst_tile,
     u32* sh0_all, u32* sl0_all) {
     __shared__ u64 s[SORT_LDS];
-    const u32 t0 = blockIdx.x * SORT_TILES;
     {
-        const u32 t = t0 + (threadIdx.x >> 6);
+        const u32 t = blockIdx.x + (threadIdx.x >> 6) * gridDim.x;
         const uint2 rg = t < T ? ranges[t] : make_uint2(0u, 0u);
         const u32 L = rg.y - rg.x;
         if (L > 1 && L <= SORT_WAVE_MAX)
             wave_sort_short_list(inst_entry + rg.x, L, depth_key, E, threadIdx.x & 63);
     }
     for (u32 k = 0; k < SORT_TILES; ++k) {
-        const uint2 rg = t0 + k < T ? ranges[t0 + k] : make_uint2(0u, 0u);
+        const u32 tk = blockIdx.x + k * gridDim.x;
+        const uint2 rg = tk < T ? ranges[tk] : make_uint2(0u, 0u);
         const u32 L = rg.y - rg.x;
         if (L <= SORT_WAVE_MAX) continue;
         if (L <= 1024)
@@ -471,7 +482,7 @@ __global__ void __launch_bounds__(SORT_THREADS) tile_sort_kernel(
         else if (L <= (u32)SORT_LDS)
             group_sort_list<8, SORT_THREADS>(inst_entry + rg.x, L, depth_key, E, threadIdx.x, s);
         else
-            sort_long_list(s, t0 + k, rg, depth_key, E, inst_entry, inst_tile, sh0_all, sl0_all);
+            sort_long_list(s, tk, rg, depth_key, E, inst_entry, inst_tile, sh0_all, sl0_all);
         __syncthreads();
     }
 }
