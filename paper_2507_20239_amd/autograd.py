@@ -14,9 +14,11 @@ pointers.  A frame holds the state of one forward at a time: calling the
 rasterizer again before the backward of an earlier call invalidates that
 backward, which then raises instead of returning wrong gradients.
 """
+import types
+
 import torch
 
-from . import gsmi
+from . import autotune, gsmi
 
 
 class GaussianRasterizer:
@@ -25,18 +27,24 @@ class GaussianRasterizer:
     cameras: list of objects with R (3x3), t (3), fx, fy, cx, cy, width, height
     (see synth.Camera); their sizes fix the frame.  The instance capacity
     grows (and the step re-runs) when a render overflows it.  footprint_3sigma
-    bins by the original 3DGS 3-sigma squares (gsmi.raster_opts).
+    bins by the original 3DGS 3-sigma squares (gsmi.raster_opts).  With
+    autotune=True the first call times the launch shapes of the autotuner
+    (LDS batch, plain grid or heavy-first persistent grid) on these views and
+    parameters and keeps the fastest, instead of raster_batch and
+    persistent_blocks.
     """
 
     def __init__(self, n, cameras, sh_degree, device="cuda", bg=(0.0, 0.0, 0.0),
                  raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2,
-                 footprint_3sigma=False):
+                 footprint_3sigma=False, autotune=False):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.device = torch.device(device)
-        self.opts = gsmi.raster_opts(bg=bg, near_plane=near_plane, raster_batch=raster_batch,
-                                     persistent_blocks=persistent_blocks,
-                                     footprint_3sigma=footprint_3sigma)
+        self._opt_args = dict(bg=bg, near_plane=near_plane, footprint_3sigma=footprint_3sigma)
+        self.opts = gsmi.raster_opts(raster_batch=raster_batch, persistent_blocks=persistent_blocks,
+                                     **self._opt_args)
+        self.autotune = bool(autotune)
+        self.tuned = None
         self.set_cameras(cameras)
         sizes = [(c.width, c.height) for c in cameras]
         if capacity is None:
@@ -59,6 +67,15 @@ class GaussianRasterizer:
     def reset_stats(self):
         self.accum.zero_()
         self.denom.zero_()
+
+    def _tune(self, params):
+        """Pick the launch shape by timing the autotuner's candidates."""
+        scene = types.SimpleNamespace(n=self.n, sh_degree=self.sh_degree)
+        best = autotune.tune_batched(scene, self.cameras, params, self.device, cap=self.frame.cap,
+                                     opts=self._opt_args)
+        self.opts = gsmi.raster_opts(raster_batch=best["raster_batch"],
+                                     persistent_blocks=best["persistent_blocks"], **self._opt_args)
+        self.tuned = best
 
     def _grow(self, needed):
         cap = self.frame.cap
@@ -83,12 +100,19 @@ class _Rasterize(torch.autograd.Function):
         for k, t in params.items():
             if t.dtype != torch.float32 or t.device != r.device:
                 raise TypeError("%s must be float32 on %s" % (k, r.device))
+        tune = r.autotune and r.tuned is None
         while True:
             r.frame.project(params, r.sh_degree, r.cams_dev, r.opts)
             images = r.frame.render(r.opts)
             nv, ni, ovf = r.frame.status(raise_on_overflow=False)
             if not ovf:
-                break
+                if not tune:
+                    break
+                # the capacity now holds the step: time the candidates, then
+                # render once more with the chosen shape
+                r._tune(params)
+                tune = False
+                continue
             r._grow(ni)
         r.generation += 1
         ctx.r = r

@@ -25,10 +25,13 @@ def _cache_path():
                           os.path.join(os.path.expanduser("~"), ".cache", "gsmi_autotune.json"))
 
 
-def _signature(n, cams, sh_degree):
+def _signature(n, cams, sh_degree, opts=None):
     dev = torch.cuda.get_device_name(0)
     sizes = ",".join("%dx%d" % (c.width, c.height) for c in cams)
-    return "%s|n=%d|sh=%d|%s" % (dev, n, sh_degree, sizes)
+    extra = ""
+    if opts and opts.get("footprint_3sigma"):
+        extra = "|3sigma"
+    return "%s|n=%d|sh=%d|%s%s" % (dev, n, sh_degree, sizes, extra)
 
 
 def _load():
@@ -68,9 +71,12 @@ def _time_step(frame, params, sh_degree, cams_dev, opts, images, targets, scale,
     return e0.elapsed_time(e1) / reps
 
 
-def tune_batched(scene, cams, params, device, cap=32 << 20, use_cache=True):
-    """Best {raster_batch, persistent_blocks, ms} for a step over `cams`."""
-    sig = _signature(scene.n, cams, scene.sh_degree)
+def tune_batched(scene, cams, params, device, cap=32 << 20, use_cache=True, opts=None):
+    """Best {raster_batch, persistent_blocks, ms} for a step over `cams`.
+    opts: the other gsmi.raster_opts arguments (background, near plane,
+    footprint), kept fixed."""
+    opts = dict(opts or {})
+    sig = _signature(scene.n, cams, scene.sh_degree, opts)
     cache = _load() if use_cache else {}
     if sig in cache:
         return cache[sig]
@@ -85,8 +91,8 @@ def tune_batched(scene, cams, params, device, cap=32 << 20, use_cache=True):
     results = []
     for b in BATCHES:
         for pb in PERSISTENT:
-            opts = gsmi.raster_opts(raster_batch=b, persistent_blocks=pb)
-            ms = _time_step(frame, params, scene.sh_degree, cams_dev, opts, images, targets, scale,
+            o = gsmi.raster_opts(raster_batch=b, persistent_blocks=pb, **opts)
+            ms = _time_step(frame, params, scene.sh_degree, cams_dev, o, images, targets, scale,
                             loss, dL, grads)
             results.append({"raster_batch": b, "persistent_blocks": pb, "ms": round(ms, 4)})
     best = dict(min(results, key=lambda r: r["ms"]))

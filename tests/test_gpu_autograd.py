@@ -68,6 +68,30 @@ def test_autograd_gradients_match_oracle_adjoint():
     np.testing.assert_array_equal(r.denom.cpu().numpy(), den)
 
 
+def test_autotuned_rasterizer_matches_the_default_shape(tmp_path, monkeypatch):
+    """autotune=True picks a launch shape on the first call; the images are
+    the same bit for bit and the gradients agree to FP32 summation order."""
+    monkeypatch.setenv("GSMI_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    sc = synth.random_scene(52, 3000, 96, 80, sh_degree=2, n_views=3, log_scale=(-2.3, 0.5))
+    cams = [sc.cameras[0], sc.cameras[1].scaled(2), sc.cameras[2]]
+    out = []
+    for tune in (False, True):
+        r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev(), autotune=tune)
+        P = _leaf_params(sc)
+        imgs = _call(r, P)
+        loss = sum((img * (k + 1.0)).sum() for k, img in enumerate(imgs))
+        loss.backward()
+        out.append(([i.detach().clone() for i in imgs], {k: P[k].grad.clone() for k in P}))
+        if tune:
+            assert r.tuned is not None and r.tuned["candidates"] >= 4
+            assert (tmp_path / "tune.json").exists()
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
+    for k in gsmi.PARAM_NAMES:
+        a, b = out[0][1][k], out[1][1][k]
+        assert torch.allclose(a, b, rtol=1e-4, atol=1e-6 * float(a.abs().max())), k
+
+
 def test_capacity_grows_and_images_do_not_change():
     sc = synth.random_scene(52, 1500, 128, 96, sh_degree=1, log_scale=(-2.0, 0.5))
     P = _leaf_params(sc)
