@@ -5,6 +5,8 @@ procedural scene (4 views of 1920x1080), the densification statistic as a side
 effect of the backward, instance-capacity growth, and the guard against a
 backward whose frame was overwritten."""
 
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -329,13 +331,23 @@ def check_fd(gg, fdiff, gid):
 
 
 @pytest.fixture(scope="module")
-def slice_grads(scene_6m_1920x1080):
-    """GPU autograd over the whole scene with the slice's loss weights."""
+def slice_grads(scene_6m_1920x1080, tmp_path_factory):
+    """GPU autograd over the whole scene with the slice's loss weights, in the
+    autotuned launch shape the benchmark times."""
     sc, cams, projs = scene_6m_1920x1080
     slice_ids, Ws, support = c5_slice_and_weights(sc, cams, projs)
-    r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev())
-    P = _leaf_params(sc)
-    imgs = _call(r, P)
+    old = os.environ.get("GSMI_AUTOTUNE_CACHE")
+    os.environ["GSMI_AUTOTUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "tune.json")
+    try:
+        r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev(), autotune=True)
+        P = _leaf_params(sc)
+        imgs = _call(r, P)
+    finally:
+        if old is None:
+            os.environ.pop("GSMI_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["GSMI_AUTOTUNE_CACHE"] = old
+    print("tuned", r.tuned, flush=True)
     loss = sum((img * torch.from_numpy(w).to(dev())).sum() for img, w in zip(imgs, Ws))
     loss.backward()
     got = {k: P[k].grad.cpu().numpy()[..., slice_ids] for k in gsmi.PARAM_NAMES}
