@@ -144,3 +144,38 @@ def test_batched_8_views_500k_sampled(batch, persistent):
         gproj, gabs = oracle.render_backward_pixels(p, pb, g.astype(np.float64))
         assert np.all(gabs[~tt[v]] == 0)
         assert_close_scaled(sg[v][tt[v]], gproj[tt[v]], gabs[tt[v]], what="view %d grads" % v)
+
+
+def test_largest_view_16384x16384():
+    """The largest view the frame accepts (16384 x 16384: 1,048,576 tiles,
+    268 M pixels): per-tile lists exact and sampled pixels, corners included,
+    against the oracle."""
+    W = H = 16384
+    sc = synth.random_scene(28, 20000, W, H, sh_degree=1, log_scale=(-6.5, 0.5))
+    cam = sc.cameras[0]
+    frame, flat, *_ = gpu_forward(sc, [cam], cap=1 << 22)
+    assert frame.T == (W // 16) * (H // 16)
+    p = oracle.project(sc, cam)
+    tiles, gids, _ = oracle.tile_lists(p)
+    nv, ni, ovf = frame.status()
+    gt = frame.buffer(gsmi.BUF_INST_TILE).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    ge = frame.buffer(gsmi.BUF_INST_ENTRY).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    _compare_lists(p, gt, ge, tiles, gids)
+    assert gt.max() > (1 << 19)
+    rng = np.random.default_rng(28)
+    # pixels inside footprints (where the image is not background), plus random ones and the corners
+    vis = np.flatnonzero(p["visible"] > 0)
+    centres = np.clip(np.round(p["mean2d"][rng.choice(vis, 1500)] - 0.5), 0, W - 1).astype(np.int32)
+    pix = np.concatenate([centres, _sample_pixels(rng, W, H, 496),
+                          [[0, 0], [W - 1, 0], [0, H - 1], [W - 1, H - 1]]]).astype(np.int32)
+    C, T, nc, margin = oracle.render_pixels(p, pix)
+    good = margin > MARGIN
+    assert good.mean() > 0.98 and (nc[good] > 0).sum() > 1000
+    img = flat.view(3, H, W)
+    got = img[:, torch.from_numpy(pix[:, 1]).long().to(img.device),
+              torch.from_numpy(pix[:, 0]).long().to(img.device)].T.cpu().numpy()
+    assert_close_scaled(got[good], C[good], np.abs(C[good]), what="pixels")
+    Tg = frame.buffer(gsmi.BUF_T_FINAL, torch.float32).view(H, W)
+    Tgot = Tg[torch.from_numpy(pix[:, 1]).long().to(Tg.device),
+              torch.from_numpy(pix[:, 0]).long().to(Tg.device)].cpu().numpy()
+    assert_close_scaled(Tgot[good], T[good], np.abs(T[good]), what="T_final")
