@@ -273,11 +273,10 @@ class Frame:
         return 3 * self.P
 
     def split_images(self, flat: torch.Tensor):
-        out, o = [], 0
-        for (w, h) in self.sizes:
-            out.append(flat[o:o + 3 * w * h].view(3, h, w))
-            o += 3 * w * h
-        return out
+        """Per-view [3, H, W] views of a flat image buffer (one split, so the
+        gradient of all views is gathered back with a single concatenation)."""
+        parts = torch.split(flat, [3 * w * h for (w, h) in self.sizes])
+        return [t.view(3, h, w) for t, (w, h) in zip(parts, self.sizes)]
 
     def project(self, params, sh_degree, cams_dev, opts, stream=None):
         g = gaussians_struct(params, sh_degree)
