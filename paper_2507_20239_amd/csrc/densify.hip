@@ -24,7 +24,30 @@ __global__ void __launch_bounds__(GS_BLOCK) stats_kernel(const float* __restrict
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= n) return;
     float a = accum[i], d = denom[i];
-    for (int k = 0; k < vc; ++k) {
+    // eight views' loads in flight at once, then their sums in view order
+    // (the same additions in the same order as one view at a time)
+    int k = 0;
+    for (; k + 8 <= vc; k += 8) {
+        int vv[8];
+        float gx[8], gy[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t v = v0 + k + j;
+            vv[j] = vis[v * n + i];
+            gx[j] = g[(2 * v) * n + i];
+            gy[j] = g[(2 * v + 1) * n + i];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (!vv[j]) continue;
+            const float x = gx[j] * sc.sx[k + j];
+            const float y = gy[j] * sc.sy[k + j];
+            const float nrm = sqrtf(fmaf(x, x, y * y));
+            a = a + nrm;
+            d = d + 1.0f;
+        }
+    }
+    for (; k < vc; ++k) {
         const int64_t v = v0 + k;
         if (!vis[v * n + i]) continue;
         const float gx = g[(2 * v) * n + i] * sc.sx[k];
