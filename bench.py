@@ -54,6 +54,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the densification (3M), D-SSIM loss and sparse Adam timings")
+    ap.add_argument("--profile-workload", choices=("batched_8_views", "step_6m_4_views"),
+                    help="for a profiler: time only this workload with the launch shape given by "
+                         "--raster-batch / --persistent and print one JSON line")
+    ap.add_argument("--raster-batch", type=int, default=0)
+    ap.add_argument("--persistent", type=int, default=0)
     return ap.parse_args()
 
 
@@ -352,8 +357,49 @@ def autograd_step_6m(torch, gsmi, synth, dev, K, W):
     return out
 
 
+def profile_workload(args):
+    """One of the secondary workloads alone, with a fixed launch shape (no
+    tuner runs in the trace)."""
+    import numpy as np
+    import torch
+    from paper_2507_20239_amd import gsmi, synth
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    shape = {"raster_batch": args.raster_batch, "persistent_blocks": args.persistent}
+    if args.profile_workload == "batched_8_views":
+        sb = synth.batched_c2f()
+        pb = to_dev(sb, dev, torch, gsmi)
+        st = Step(sb, sb.cameras, pb, gsmi.raster_opts(**shape), 32 << 20, torch, gsmi, dev)
+        st.eager()
+        st.capture()
+        ms = time_loop(torch, st.launch, K, W)
+    else:
+        from paper_2507_20239_amd.autograd import GaussianRasterizer
+        sc = synth.procedural_scene()
+        cams = synth.procedural_cameras()[:4]
+        P = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(dev).requires_grad_()
+             for k in gsmi.PARAM_NAMES}
+        r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev, **shape)
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        Ws = [torch.randn(3, c.height, c.width, device=dev, generator=g) * 1e-6 for c in cams]
+
+        def step():
+            for t in P.values():
+                t.grad = None
+            torch.autograd.backward(r(P["means"], P["log_scales"], P["quats"],
+                                      P["opacity_logits"], P["sh"]), Ws)
+
+        ms = timed(torch, step, K, W)
+    print(json.dumps({"workload": args.profile_workload, "ms_per_step": round(ms, 4),
+                      "launch_shape": shape}), flush=True)
+
+
 def main():
     args = parse()
+    if args.profile_workload:
+        profile_workload(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (sharding the views "
               "across GPUs is a design only); run with --gpus 1", file=sys.stderr)
