@@ -487,13 +487,16 @@ __global__ void __launch_bounds__(SORT_THREADS) tile_sort_kernel(
     }
 }
 
-// heavy-first order key: longer lists first, ties by tile id (stable sort)
+// heavy-first order key: longer lists first (lists of 65535 instances or
+// more tie), ties by tile id (stable sort); 16 bits, two radix passes
+constexpr int TILE_WEIGHT_BITS = 16;
 __global__ void tile_weight_kernel(const uint2* ranges, u32* keys, u32* vals, int T) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
+    constexpr u32 top = (1u << TILE_WEIGHT_BITS) - 1u;
     u32 len = ranges[t].y - ranges[t].x;
-    if (len > 0xFFFFFFu) len = 0xFFFFFFu;
-    keys[t] = 0xFFFFFFu - len;
+    if (len > top) len = top;
+    keys[t] = top - len;
     vals[t] = (u32)t;
 }
 
@@ -543,8 +546,8 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         tile_weight_kernel<<<blocks_for(f->T), GS_BLOCK, 0, s>>>(f->ranges, f->tkeys[0], f->tvals[0],
                                                                  f->T);
         GS_TRY(gs_check_launch("tile_weight"));
-        GS_TRY(gs_radix_sort(f->tkeys, f->tvals, nullptr, (u32)f->T, f->T, 24, f->sort_scratch,
-                             &f->tsorted, s));
+        GS_TRY(gs_radix_sort(f->tkeys, f->tvals, nullptr, (u32)f->T, f->T, TILE_WEIGHT_BITS,
+                             f->sort_scratch, &f->tsorted, s));
     }
     return GS_OK;
 }
