@@ -81,7 +81,19 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_reduce_kernel(const u32* tt, u32
     u32 beg, end;
     chunk_of(n, GS_SCAN_PARTS, blockIdx.x, beg, end);
     u64 s = 0, st = 0;
-    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) {
+    u32 i = beg + threadIdx.x;
+    // four loads in flight per thread: a partition holds E / 1024 entries
+    for (; i + 3 * GS_BLOCK < end; i += 4 * GS_BLOCK) {
+        u32 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = tt[i + j * GS_BLOCK];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s += vis_pack(v[j]);
+            st += v[j];
+        }
+    }
+    for (; i < end; i += GS_BLOCK) {
         const u32 v = tt[i];
         s += vis_pack(v);
         st += v;
