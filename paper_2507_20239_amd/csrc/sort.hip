@@ -55,18 +55,28 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_count_kernel(const u32* __restr
     u32 beg, end;
     chunk_of(dev_len(n_dev, n_host), gridDim.x, blockIdx.x, beg, end);
     const u32 mask = (1u << bits) - 1u;
-    for (u32 base = beg; base < end; base += GS_BLOCK) {
-        const u32 i = base + threadIdx.x;
-        const bool valid = i < end;
-        const u32 d = valid ? (keys[i] >> shift) & mask : 0u;
-        // one LDS add per group of equal digits in the wave
-        u64 peers = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const u64 bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
+    // four keys per thread loaded before their digits are counted, so their
+    // loads are in flight together
+    for (u32 base = beg; base < end; base += 4 * GS_BLOCK) {
+        u32 k[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const u32 i = base + j * GS_BLOCK + threadIdx.x;
+            k[j] = i < end ? keys[i] : 0u;
         }
-        if (valid && popc_below(peers) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool valid = base + j * GS_BLOCK + threadIdx.x < end;
+            const u32 d = valid ? (k[j] >> shift) & mask : 0u;
+            // one LDS add per group of equal digits in the wave
+            u64 peers = __ballot(valid);
+            for (int b = 0; b < bits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const u64 bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            if (valid && popc_below(peers) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
+        }
     }
     __syncthreads();
     counts[(u64)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
