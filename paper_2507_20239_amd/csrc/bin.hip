@@ -6,11 +6,13 @@
 //
 //   one exclusive scan of (tiles_touched > 0, tiles_touched) -> compacted
 //   visible entries and their instance offsets (entry order)
-//   emit (tile, entry) for every tile each footprint meets, row-major
+//   emit (tile, entry) for every tile each footprint meets (or, with the
+//   3-sigma footprint, every tile of its rectangle), row-major
 //   radix sort on the tile id (stable)
 //   tile ranges from adjacent keys;  optional heavy-first tile order
-//   per tile: sort the list by (depth bits, entry) in registers, in LDS, or
-//   for very long lists as LDS-sorted runs merged in global memory
+//   per tile: sort the list by (depth bits, entry) in registers (one wave up
+//   to 512, the workgroup up to 2048), or for longer lists as register-sorted
+//   runs of 2048 merged in global memory
 //
 // A global sort of the visible entries by depth before emission would give
 // the same lists; it takes four radix passes over every visible entry, while
