@@ -8,7 +8,10 @@
 // HBM-bound kernel) and the mean is stored as an FP32 hi/lo pair, which keeps
 // the pixel offset exact to ~1e-7 px on 1600-pixel images.  The depth used
 // for ordering is the FP32 rounding of the FP64 depth evaluated as a fused
-// multiply-add chain.
+// multiply-add chain.  Each (view, Gaussian) entry also gets its footprint:
+// the tiles whose squares meet the ellipse o G >= 1/255, counted row by row,
+// or with the 3-sigma option every tile of the square of half-side
+// ceil(3 sqrt(largest eigenvalue of Sigma')).
 //
 // Adjoint: one thread per Gaussian again; it recomputes the projection
 // (instead of storing intermediates), applies the chain rule to the raw
