@@ -134,8 +134,8 @@ typedef struct gs_frame gs_frame;
 
 /* Bytes of device workspace a frame needs (host call, no device work).
  * n: Gaussians; n_views <= GS_MAX_VIEWS; widths/heights: host arrays of the
- * view sizes; max_instances: capacity for (view, tile, Gaussian) instances
- * (<= 2^31 - 1). */
+ * view sizes; max_instances: capacity for (view, tile, Gaussian) instances,
+ * in [1, 2^30); n_views * n must be below 2^30. */
 gs_status gs_frame_workspace_size(int64_t n, int32_t n_views, const int32_t* widths,
                                   const int32_t* heights, int64_t max_instances, uint64_t* bytes);
 
@@ -199,14 +199,20 @@ gs_status gs_render(gs_frame* frame, const gs_raster_opts* opts, float* images, 
  * per-splat gradients GS_BUF_SPLAT_GRAD, which gs_project cleared; call it
  * once per gs_project/gs_render.  Walks each pixel's list back to front,
  * recovering transmittance from the saved final value.  One kernel launch
- * (plus a one-word queue reset when persistent_blocks > 0). */
+ * (plus a one-word queue reset when persistent_blocks > 0).  persistent_blocks
+ * > 0 walks the heavy-first tile order, which only a gs_render with
+ * persistent_blocks > 0 builds: after a plain gs_render it is GS_ERR_INVALID. */
 gs_status gs_render_backward(gs_frame* frame, const gs_raster_opts* opts,
                              const float* dL_dimages, void* stream);
 
-/* Adjoint of gs_project: from the per-splat gradients to the raw parameters,
- * summed over the frame's views (grads are overwritten, every Gaussian gets a
- * value).  When accum and denom are not NULL, also accumulates the
- * densification statistic: for each view where entry (v, i) was rendered,
+/* Adjoint of gs_project (the chain rule through Sigma = R S S^T R^T,
+ * Sigma' = J W Sigma W^T J^T and the SH colour of the Preliminary section):
+ * from the per-splat gradients to the raw parameters, summed over the frame's
+ * views (grads are overwritten, every Gaussian gets a value).  When accum and
+ * denom are not NULL, also accumulates the densification statistic of the
+ * Preliminary section's last paragraph (the view-space position gradient whose
+ * norm selects Gaussians for densification), read as the mean over views of
+ * the per-view norm: for each view where entry (v, i) was rendered,
  * accum[i] += ||(dL/dmean2d_x W_v/2, dL/dmean2d_y H_v/2)|| and denom[i] += 1. */
 gs_status gs_project_backward(gs_frame* frame, const gs_gaussians* g, const gs_camera* cameras,
                               const gs_raster_opts* opts, const gs_gaussian_grads* grads,
@@ -221,7 +227,9 @@ gs_status gs_l1_loss_grad(const float* image, const float* target, int64_t numel
 /* Densification                                                             */
 /* ------------------------------------------------------------------------ */
 
-/* accumulate_densify_stats: for v in 0..n_views-1 in order, for every i with
+/* accumulate_densify_stats (Preliminary, last paragraph: the view-space
+ * position-gradient statistic that drives densification, as the mean over
+ * views of its per-view norm in NDC units): for v in 0..n_views-1 in order, for every i with
  * visible[v][i] != 0: gx = dmean2d[v][0][i] * W_v/2, gy = dmean2d[v][1][i] * H_v/2
  * (FP32), accum[i] += sqrt(fma(gx, gx, gy*gy)) (correctly rounded), denom[i] += 1.
  * dmean2d: device [V][2][n] pixel-space gradients; visible: device int32 [V][n];
@@ -265,7 +273,9 @@ enum { GS_KIND_KEEP = 0, GS_KIND_CLONE = 1, GS_KIND_SPLIT0 = 2, GS_KIND_SPLIT1 =
 /* Device workspace bytes for gs_densify_plan over n parents. */
 gs_status gs_densify_plan_workspace_size(int64_t n, uint64_t* bytes);
 
-/* densify(split_mask, clone_mask, prune_mask), step 1: the compaction map.
+/* densify(split_mask, clone_mask, prune_mask), step 1: the compaction map of
+ * the densification rule (Preliminary, last paragraph: large Gaussians are
+ * split in two, small ones cloned, transparent ones removed).
  * Parent i emits nothing if prune[i]; else [SPLIT0, SPLIT1] if split[i];
  * else [KEEP, CLONE] if clone[i]; else [KEEP].  Outputs follow parent order:
  * src[j] = parent of output row j, kind[j] = GS_KIND_*.  n_out (device int64)
@@ -315,7 +325,9 @@ gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_ou
 gs_status gs_split_normals(const int64_t* parents, const int32_t* children, int64_t m,
                            uint64_t seed, uint64_t step, uint32_t* words, float* z, void* stream);
 
-/* Adaptive opacity threshold in logit space: thr[0] = min(logits_sorted[k],
+/* Adaptive opacity threshold (Methodology, Adaptive Opacity Pruning: the
+ * pruning threshold is the opacity at the p-quantile, capped by an upper
+ * limit), in logit space: thr[0] = min(logits_sorted[k],
  * upper_logit) where logits_sorted is the ascending order of opacity_logits
  * and k = floor(n p) is given by the caller (radix select, exact).  Then
  * prune = logit < thr.  workspace: gs_radix_select_workspace_size(n). */

@@ -210,9 +210,11 @@ gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
     f->d_views = (gs_view_info*)(b + L.off[21]);
     f->n_comp = (u32*)(b + L.off[22]);
     f->chunk_start = (u32*)(b + L.off[23]);
-    // the slots holding sorted results depend only on the pass counts
+    // the slot holding the sorted instances depends only on the pass count; the
+    // heavy-first order exists only after a binning that built it
     f->isorted = (((f->tile_bits + 7) / 8) & 1);
-    f->tsorted = (((24 + 7) / 8) & 1);
+    f->tsorted = 0;
+    f->heavy_built = false;
     hipError_t e = hipMemcpy(f->d_views, f->views, sizeof(gs_view_info) * n_views, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(f->counters, 0, 64);
     if (e != hipSuccess) {
@@ -288,6 +290,10 @@ gs_status gs_render_backward(gs_frame* f, const gs_raster_opts* opts, const floa
     GS_TRY(check_frame(f));
     GS_TRY(check_opts(opts));
     if (!dL_dimages) return gs_fail(GS_ERR_INVALID, "dL_dimages is null");
+    if (opts->persistent_blocks > 0 && !f->heavy_built)
+        return gs_fail(GS_ERR_INVALID,
+                       "persistent_blocks > 0 needs the heavy-first tile order, which the last "
+                       "gs_render did not build (it ran with persistent_blocks = 0)");
     return gs_launch_raster_bwd(f, opts, dL_dimages, (hipStream_t)stream);
 }
 

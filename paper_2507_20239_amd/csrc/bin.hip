@@ -556,6 +556,7 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
                                                     f->ikeys[o], f->ivals[o]);
         GS_TRY(gs_check_launch("tile_sort"));
     }
+    f->heavy_built = heavy_first;
     if (heavy_first) {
         tile_weight_kernel<<<blocks_for(f->T), GS_BLOCK, 0, s>>>(f->ranges, f->tkeys[0], f->tvals[0],
                                                                  f->T);

@@ -57,6 +57,7 @@ struct gs_frame {
     u32* tkeys[2];       // [T]
     u32* tvals[2];       // [T]
     int tsorted;
+    bool heavy_built;    // the last binning built the heavy-first order (tvals[tsorted])
     int32_t tile_bits;   // bits needed for a global tile id
     bool sigma3;         // the last projection binned by 3-sigma squares
     // per pixel

@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
     for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
         const u32 t = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
+        if (t >= (u32)a.T) continue;   // never taken for an order the binning built
         const TileCoords tc = tile_coords(a, t);
         // T < 0 marks a finished pixel, with |T| its final transmittance
         // (pixels outside the image start finished); the sign replaces a
@@ -203,6 +204,7 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
     const float fb = (rj >= 5 && rj < 9) ? 1.f : 0.f;
     for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
         const u32 t = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
+        if (t >= (u32)a.T) continue;   // never taken for an order the binning built
         const TileCoords tc = tile_coords(a, t);
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
         float pxc[PIX], pyc[PIX], T[PIX], g0[PIX], g1[PIX], g2[PIX], sd[PIX];

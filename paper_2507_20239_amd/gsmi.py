@@ -359,8 +359,17 @@ def densify_plan(split, clone, prune, capacity=None, stream=None):
     n_out = torch.zeros(1, dtype=torch.int64, device=dev)
     _check(lib().gs_densify_plan(_ptr(split), _ptr(clone), _ptr(prune), n, _ptr(src), _ptr(kind),
                                  capacity, _ptr(n_out), _ptr(ws), int(nb.value), _stream(stream)))
-    m = int(n_out.item())
+    m = plan_rows_checked(int(n_out.item()), capacity)
     return src[:m], kind[:m], m
+
+
+def plan_rows_checked(n_out: int, capacity: int) -> int:
+    """The plan's row count, or an error when the map did not fit: rows past
+    the capacity are not written, so src/kind would be incomplete."""
+    if n_out > capacity:
+        raise GsError(GS_ERR_CAPACITY, "densify plan has %d rows but capacity is %d; call again "
+                      "with capacity >= %d" % (n_out, capacity, n_out))
+    return n_out
 
 
 def densify_apply(src, kind, n_in, attrs, parent_means, parent_log_scales, parent_quats, seed,

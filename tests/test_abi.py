@@ -84,3 +84,13 @@ def test_product_path_has_no_cpu_fallback(monkeypatch):
     monkeypatch.setattr(gsmi, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         gsmi.lib()
+
+
+def test_densify_plan_rows_beyond_capacity_raise():
+    """A plan whose rows do not fit the capacity is an error, not a truncated
+    map (rows past the capacity are never written)."""
+    assert gsmi.plan_rows_checked(10, 10) == 10
+    assert gsmi.plan_rows_checked(0, 1) == 0
+    with pytest.raises(gsmi.GsError, match="capacity") as e:
+        gsmi.plan_rows_checked(11, 10)
+    assert e.value.status == gsmi.GS_ERR_CAPACITY

@@ -8,6 +8,7 @@ transmittance stop 1e-4) lies within 1e-5 (relative) of its threshold are
 excluded from the image comparison, and their loss gradient is set to zero for
 the gradient comparison, on both sides.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -373,3 +374,30 @@ def test_render_twice_after_one_projection_is_identical():
     b = frame.render(opts)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_persistent_backward_after_plain_render_is_rejected_on_the_host():
+    """A persistent adjoint walks the heavy-first tile order, which only a
+    persistent render builds.  After a plain render the call is refused by
+    host-side validation (nothing is launched), and the frame stays usable."""
+    sc = SCENES["sh1_500_70x45"]
+    cam = sc.cameras[0]
+    plain = gsmi.raster_opts(bg=tuple(sc.bg))
+    pers = gsmi.raster_opts(bg=tuple(sc.bg), persistent_blocks=16)
+    frame, img, params, cams_dev, _ = gpu_forward(sc, [cam], plain)
+    dL = torch.full_like(img, 1e-3)
+    L = gsmi.lib()
+    st = L.gs_render_backward(frame.handle, ctypes.byref(pers), gsmi._ptr(dL), gsmi._stream())
+    assert st == gsmi.GS_ERR_INVALID
+    assert b"heavy-first" in L.gs_last_error()
+    # the same frame then runs both adjoints once the persistent render built the order
+    frame.render_backward(plain, dL)
+    a = frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).clone()
+    frame.project(params, sc.sh_degree, cams_dev, pers)
+    frame.render(pers, img)
+    frame.render_backward(pers, dL)
+    torch.cuda.synchronize()
+    b = frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32)
+    tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).view(-1) > 0
+    ga, gb = a.view(-1, 9)[tt], b.view(-1, 9)[tt]
+    assert torch.allclose(ga, gb, rtol=1e-4, atol=1e-6 * float(ga.abs().max()))
