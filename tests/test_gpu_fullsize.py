@@ -17,7 +17,7 @@ import torch
 import oracle
 from paper_2507_20239_amd import gsmi, synth
 from parity_util import (MARGIN, _check_ranges_partition, _compare_lists, assert_close_scaled,
-                         check_chol, dev, gpu_forward, gpu_mean2d, splat_view)
+                         check_chol, dev, gpu_forward, gpu_mean2d, raw_grad_scale, splat_view)
 
 pytestmark = pytest.mark.gpu
 
@@ -103,11 +103,22 @@ def test_1m_1600x1040_backward_from_sampled_pixels(view_1m_1600x1040):
     hit = (gabs > 0).any(1)
     assert hit.sum() > 1000
     assert_close_scaled(sg[rendered], gproj[rendered], gabs[rendered], what="splat gradients")
+    # the five raw-parameter gradients and the statistic against the oracle's
+    # chain rule (FP64) of the oracle's splat gradients, over every Gaussian
+    # whose binning is not within rounding distance of a tile decision
+    racc, rden = np.zeros(sc.n), np.zeros(sc.n)
+    gref = oracle.project_backward(sc, cam, p["visible"], gproj, stats=(racc, rden))
+    scales = raw_grad_scale(sc, cam, p, gabs)
+    ok = p["flags"] == 0
+    assert ok.mean() > 0.99
+    for k in gsmi.PARAM_NAMES:
+        g = grads[k].cpu().numpy()
+        assert_close_scaled(g[..., ok], gref[k][..., ok], scales[k][..., ok], what=k)
     # the statistic counts every rendered Gaussian once
     np.testing.assert_array_equal(den.cpu().numpy(), rendered.astype(np.float32))
+    np.testing.assert_array_equal(rden[ok], rendered[ok].astype(np.float64))
     gn = np.hypot(gabs[:, 0] * cam.width / 2, gabs[:, 1] * cam.height / 2)
-    ref = np.hypot(gproj[:, 0] * cam.width / 2, gproj[:, 1] * cam.height / 2)
-    assert_close_scaled(acc.cpu().numpy(), ref, gn, what="densify statistic")
+    assert_close_scaled(acc.cpu().numpy()[ok], racc[ok], gn[ok], what="densify statistic")
 
 
 @pytest.mark.parametrize("batch,persistent", [(128, 0), (64, 8192)])
@@ -137,13 +148,36 @@ def test_batched_8_views_500k_sampled(batch, persistent):
         picks.append((pb, g))
     flat_dL = torch.cat([torch.from_numpy(d).reshape(-1) for d in dL]).to(dev())
     frame.render_backward(opts, flat_dL)
+    grads = gsmi.empty_grads(params)
+    acc = torch.zeros(sc.n, device=dev())
+    den = torch.zeros(sc.n, device=dev())
+    frame.project_backward(params, sc.sh_degree, cams_dev, opts, grads, acc, den)
     torch.cuda.synchronize()
     sg = frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).view(len(cams), sc.n, 9).cpu().numpy()
     tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy().reshape(len(cams), sc.n) > 0
+    # the raw-parameter gradients summed over the 8 views and the statistic over
+    # them, against the oracle's chain rule applied view by view
+    gref, scales = None, None
+    racc, rden, gn = np.zeros(sc.n), np.zeros(sc.n), np.zeros(sc.n)
+    ok = np.ones(sc.n, bool)
     for v, (p, (pb, g)) in enumerate(zip(projs, picks)):
         gproj, gabs = oracle.render_backward_pixels(p, pb, g.astype(np.float64))
         assert np.all(gabs[~tt[v]] == 0)
         assert_close_scaled(sg[v][tt[v]], gproj[tt[v]], gabs[tt[v]], what="view %d grads" % v)
+        gref = oracle.project_backward(sc, cams[v], p["visible"], gproj, grads=gref,
+                                       stats=(racc, rden))
+        gn += np.hypot(gabs[:, 0] * cams[v].width / 2, gabs[:, 1] * cams[v].height / 2)
+        sv = raw_grad_scale(sc, cams[v], p, gabs)
+        scales = sv if scales is None else {k: scales[k] + sv[k] for k in sv}
+        ok &= p["flags"] == 0
+    assert ok.mean() > 0.99
+    for k in gsmi.PARAM_NAMES:
+        gk = grads[k].cpu().numpy()
+        assert_close_scaled(gk[..., ok], gref[k][..., ok], scales[k][..., ok],
+                            what="8-view sum " + k)
+    np.testing.assert_array_equal(den.cpu().numpy(), tt.sum(0).astype(np.float32))
+    np.testing.assert_array_equal(rden[ok], tt.sum(0)[ok].astype(np.float64))
+    assert_close_scaled(acc.cpu().numpy()[ok], racc[ok], gn[ok], what="8-view statistic")
 
 
 def test_largest_view_16384x16384():

@@ -660,3 +660,49 @@ def test_adam_matches_torch_adam_and_skips_invisible_columns():
     np.testing.assert_array_equal(p2[:, ~vis], p[:, ~vis])
     np.testing.assert_array_equal(m2[:, ~vis], m[:, ~vis])
     assert not np.allclose(p2[:, vis], p[:, vis])
+
+
+def test_project_backward_statistic_hand_computed():
+    """The FP64 statistic branch of the chain rule, on hand-picked numbers:
+    two views of different sizes (NDC factors W/2, H/2 = 30, 20 and 50, 24)
+    and position gradients chosen so every per-view norm is a Pythagorean
+    triple.  Gaussian 0 is rendered in both views: 5 + 13 = 18 over 2 views.
+    Gaussian 1 only in view 0: 10 over 1.  Gaussian 2 only in view 1: 25 over 1.
+    A wrong NDC factor (W instead of W/2), swapped W/H, or a view counted where
+    the Gaussian was not rendered changes these sums.  The other seven gradient
+    components are non-zero and must not enter."""
+    sc = synth.random_scene(3, 3, 60, 40, sh_degree=1)
+    sc.means[:] = np.array([[0.0, 0.1, -0.1], [0.0, -0.05, 0.05], [3.0, 3.5, 4.0]], np.float32)
+    cam0 = sc.cameras[0]
+    cam1 = synth.Camera(cam0.R, cam0.t, cam0.fx * 100 / 60, cam0.fy * 48 / 40, 50.0, 24.0, 100, 48)
+    per_view = [
+        (cam0, np.array([1, 1, 0], np.int32), [(0.1, 0.2), (0.2, 0.4), (9.0, 9.0)]),
+        (cam1, np.array([1, 0, 1], np.int32), [(0.1, 0.5), (7.0, 7.0), (0.3, 5.0 / 6.0)]),
+    ]
+    acc, den = np.zeros(3), np.zeros(3)
+    rng = np.random.default_rng(0)
+    for cam, vis, g2 in per_view:
+        g = rng.standard_normal((3, 9))
+        g[:, :2] = g2
+        oracle.project_backward(sc, cam, vis, g, stats=(acc, den))
+    np.testing.assert_allclose(acc, [18.0, 10.0, 25.0], rtol=1e-14)
+    np.testing.assert_array_equal(den, [2.0, 1.0, 1.0])
+
+
+def test_l1_loss_grad_hand_values_and_loss_oracle():
+    """The L1 term of Eq. 3: hand values (sign(0) = 0, mean over every
+    element), and the FD-pinned loss oracle at lambda = 0, where it reduces
+    to the same L1 term (its gradient at non-zero differences)."""
+    img = np.array([0.5, 0.25, 1.0, 0.0, 0.75, 0.5], np.float32)
+    tgt = np.array([0.25, 0.5, 1.0, 0.5, 0.75, 0.0], np.float32)
+    L, g = oracle.l1_loss_grad(img, tgt)
+    assert L == (0.25 + 0.25 + 0.0 + 0.5 + 0.0 + 0.5) / 6
+    np.testing.assert_array_equal(g, np.array([1, -1, 0, -1, 0, 1]) / 6.0)
+    from oracle import loss as ref
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 1, (3, 9, 11))
+    y = rng.uniform(0, 1, (3, 9, 11))
+    L0, g0 = ref.loss_and_grad(x, y, lam=0.0)
+    L1, g1 = oracle.l1_loss_grad(x, y)
+    assert L1 == pytest.approx(L0, rel=1e-14)
+    np.testing.assert_allclose(g1, g0, rtol=1e-14, atol=0)
