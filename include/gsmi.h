@@ -286,6 +286,19 @@ gs_status gs_densify_plan(const uint8_t* split, const uint8_t* clone, const uint
                           int64_t* n_out, void* workspace, uint64_t workspace_bytes,
                           void* stream);
 
+/* gs_densify_plan for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same map, with the scan scratch in a fixed device array inside the library
+ * instead of a workspace argument.  At most 2^23 parents per call (larger n is
+ * GS_ERR_INVALID before anything is enqueued); the array takes 32 MiB of each
+ * GPU the library runs on until the process ends.  The first call on a device
+ * looks the array up (with that device current); no call allocates.  Every
+ * call on one GPU uses the same array, so calls that overlap on one GPU (two
+ * streams at once) race; calls in stream order do not. */
+gs_status gs_densify_plan_noalloc(const uint8_t* split, const uint8_t* clone,
+                                  const uint8_t* prune, int64_t n, int32_t* src, uint8_t* kind,
+                                  int64_t capacity, int64_t* n_out, void* stream);
+
 /* How an attribute row is produced from its parent row. */
 enum {
     GS_ATTR_COPY = 0,      /* every output row copies its parent's row */

@@ -5,6 +5,8 @@
 //
 // All elementwise passes are HBM-bound: one thread per Gaussian, coalesced
 // SoA reads, no atomics, fixed order (bit-reproducible results).
+#include <mutex>
+
 #include "gs_internal.h"
 
 namespace {
@@ -352,6 +354,61 @@ __global__ void __launch_bounds__(GS_BLOCK) l1_kernel(const float* __restrict__ 
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + GS_BLOCK - 1) / GS_BLOCK); }
 
+// The compaction map: per-parent row counts, their exclusive scan (in place)
+// and the rows.  cnt holds n words, part GS_SCAN_PARTS + 2 (the last one
+// receives the total).
+gs_status plan_enqueue(const uint8_t* split, const uint8_t* clone, const uint8_t* prune, int64_t n,
+                       int32_t* src, uint8_t* kind, int64_t capacity, int64_t* n_out, u32* cnt,
+                       u32* part, hipStream_t s) {
+    u32* total = part + GS_SCAN_PARTS + 1;
+    if (n > 0) {
+        plan_count_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(split, clone, prune, n, cnt);
+        GS_TRY(gs_check_launch("plan_count"));
+        GS_TRY(gs_scan_exclusive(cnt, cnt, nullptr, (u32)n, total, part, s));
+        plan_write_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(split, clone, prune, cnt, n, src, kind,
+                                                             capacity);
+        GS_TRY(gs_check_launch("plan_write"));
+    } else {
+        GS_TRY(gs_fill_u32(total, 0u, 1, s));
+    }
+    plan_total_kernel<<<1, 1, 0, s>>>(total, n_out);
+    return gs_check_launch("plan_total");
+}
+
+// ---- scratch of the allocation-free plan --------------------------------
+// gs_densify_plan_noalloc keeps its scan scratch (row counts of up to
+// NOALLOC_PLAN_MAX parents, then the scan's partition sums) in this
+// file-scope device array instead of a caller workspace.  Each GPU holds its
+// own copy until the process ends.  In host code the name `scratch` is a
+// host-side stand-in, not a device address: the device address is looked up
+// once per device with hipGetSymbolAddress (with that device current) and
+// only that address is handed to kernels.
+constexpr int64_t NOALLOC_PLAN_MAX = (int64_t)1 << 23;
+constexpr int64_t NOALLOC_PART_WORDS = GS_SCAN_PARTS + 64;
+static __device__ __align__(256) u32 scratch[NOALLOC_PLAN_MAX + NOALLOC_PART_WORDS];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+u32* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+gs_status scratch_of_current_device(u32** out) {
+    int dev = 0;
+    GS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return gs_fail(GS_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return gs_fail(GS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                           hipGetErrorString(e));
+        g_scratch_dev[dev] = (u32*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return GS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -414,22 +471,26 @@ gs_status gs_densify_plan(const uint8_t* split, const uint8_t* clone, const uint
     if (workspace_bytes < need) return gs_fail(GS_ERR_INVALID, "workspace too small (%llu < %llu)",
                                                (unsigned long long)workspace_bytes,
                                                (unsigned long long)need);
-    hipStream_t s = (hipStream_t)stream;
     u32* cnt = (u32*)workspace;
     u32* part = (u32*)((char*)workspace + align256(4 * (uint64_t)(n > 0 ? n : 1)));
-    u32* total = part + GS_SCAN_PARTS + 1;
-    if (n > 0) {
-        plan_count_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(split, clone, prune, n, cnt);
-        GS_TRY(gs_check_launch("plan_count"));
-        GS_TRY(gs_scan_exclusive(cnt, cnt, nullptr, (u32)n, total, part, s));
-        plan_write_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(split, clone, prune, cnt, n, src, kind,
-                                                             capacity);
-        GS_TRY(gs_check_launch("plan_write"));
-    } else {
-        GS_TRY(gs_fill_u32(total, 0u, 1, s));
-    }
-    plan_total_kernel<<<1, 1, 0, s>>>(total, n_out);
-    return gs_check_launch("plan_total");
+    return plan_enqueue(split, clone, prune, n, src, kind, capacity, n_out, cnt, part,
+                        (hipStream_t)stream);
+}
+
+gs_status gs_densify_plan_noalloc(const uint8_t* split, const uint8_t* clone,
+                                  const uint8_t* prune, int64_t n, int32_t* src, uint8_t* kind,
+                                  int64_t capacity, int64_t* n_out, void* stream) {
+    if (n < 0 || capacity < 0) return gs_fail(GS_ERR_INVALID, "n and capacity must be >= 0");
+    if (n > NOALLOC_PLAN_MAX)
+        return gs_fail(GS_ERR_INVALID,
+                       "gs_densify_plan_noalloc takes at most %lld parents (got %lld); use "
+                       "gs_densify_plan with a workspace", (long long)NOALLOC_PLAN_MAX, (long long)n);
+    if (!n_out || (n > 0 && (!split || !clone || !prune)) || (capacity > 0 && (!src || !kind)))
+        return gs_fail(GS_ERR_INVALID, "null pointer");
+    u32* sc = nullptr;
+    GS_TRY(scratch_of_current_device(&sc));
+    return plan_enqueue(split, clone, prune, n, src, kind, capacity, n_out, sc,
+                        sc + NOALLOC_PLAN_MAX, (hipStream_t)stream);
 }
 
 gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_out, int64_t n_in,

@@ -102,6 +102,7 @@ _SIGS = {
     "gs_densify_select": [_P, _P, _P, _P, _I64, _F, _F, _F, _I32, _P, _P, _P, _P],
     "gs_densify_plan_workspace_size": [_I64, ctypes.POINTER(_U64)],
     "gs_densify_plan": [_P, _P, _P, _I64, _P, _P, _I64, _P, _P, _U64, _P],
+    "gs_densify_plan_noalloc": [_P, _P, _P, _I64, _P, _P, _I64, _P, _P],
     "gs_densify_apply": [_P, _P, _I64, _I64, ctypes.POINTER(Attr), _I32, _P, _P, _P, _U64, _U64,
                          _P],
     "gs_split_normals": [_P, _P, _I64, _U64, _U64, _P, _P, _P],
@@ -361,6 +362,15 @@ def densify_plan(split, clone, prune, capacity=None, stream=None):
                                  capacity, _ptr(n_out), _ptr(ws), int(nb.value), _stream(stream)))
     m = plan_rows_checked(int(n_out.item()), capacity)
     return src[:m], kind[:m], m
+
+
+def densify_plan_noalloc(split, clone, prune, src, kind, n_out, stream=None):
+    """gs_densify_plan_noalloc into caller-provided src/kind (capacity = their
+    length) and n_out (device int64[1]); nothing is allocated or synchronised."""
+    n = split.numel()
+    _check(lib().gs_densify_plan_noalloc(_ptr(split), _ptr(clone), _ptr(prune), n, _ptr(src),
+                                         _ptr(kind), min(src.numel(), kind.numel()), _ptr(n_out),
+                                         _stream(stream)))
 
 
 def plan_rows_checked(n_out: int, capacity: int) -> int:
