@@ -80,6 +80,17 @@ def _declare(L):
     L.oracle_stats_f32.argtypes = [_I64, _I32, _P, _P, _P, _P, _P]
     L.oracle_select.argtypes = [_I64, _P, _P, _P, _P, _F, _F, _F, ctypes.c_int, _P, _P, _P]
     L.oracle_covariance3d.argtypes = [_P, _P, _P]
+    L.oracle_set_threads.argtypes = [ctypes.c_int]
+    L.oracle_max_threads.restype = ctypes.c_int
+
+
+def set_threads(threads: int) -> None:
+    """Thread count of the oracle's OpenMP loops (results do not depend on it)."""
+    lib().oracle_set_threads(int(threads))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
 
 
 def _ptr(a):

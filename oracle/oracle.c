@@ -30,6 +30,7 @@
  *   real spherical harmonics with the Condon-Shortley phase, rgb = max(0, sum + 1/2).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -469,77 +470,132 @@ void oracle_render_pixels(int64_t n, const double* mean2d, const double* conic,
  *   dC/dalpha_k = rgb_k T_k - (sum_{j>k} rgb_j w_j + T_final bg) / (1 - alpha_k);
  *   alpha = o G unless clamped at 0.99 (then no gradient through o or G);
  *   dG/dmean2d = G Q d with d = p - mean2d; dG/da = -G dx^2/2, dG/db = -G dx dy,
- *   dG/dc = -G dy^2/2.  Pixels run serially so the sums are deterministic. */
+ *   dG/dc = -G dy^2/2.
+ * Each pixel's terms are computed independently (in parallel over pixels) and
+ * then added into the outputs pixel by pixel in input order, so the sums are
+ * the same, bit for bit, for any number of threads. */
+typedef struct {
+    int32_t idx, clamped;
+    double g[9], a[9];   /* the pixel's terms of grad and g_abs for Gaussian idx */
+} term_t;
+
+/* the terms one pixel contributes, in compositing order; returns their count
+ * (*out is malloc'ed, NULL when there are none) */
+static int64_t pixel_adjoint_terms(int64_t n, const double* mean2d, const double* conic,
+                                   const double* opacity, const double* rgb,
+                                   const uint32_t* depth_key, const int32_t* visible, double px,
+                                   double py, const double* bg, const double* g, cand_t* cand,
+                                   double* Tk, term_t** out) {
+    double mg;
+    int64_t m = pixel_candidates(n, mean2d, conic, opacity, depth_key, visible, px, py, cand, &mg);
+    double T = 1.0;
+    int64_t used = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        const double Tn = T * (1.0 - cand[j].alpha);
+        if (Tn < T_MIN) break;
+        Tk[j] = T;
+        T = Tn;
+        ++used;
+    }
+    *out = NULL;
+    if (used == 0) return 0;
+    term_t* t = (term_t*)calloc((size_t)used, sizeof(term_t));
+    const double Tf = T;
+    for (int64_t j = 0; j < used; ++j) {
+        const int32_t i = cand[j].idx;
+        const double al = cand[j].alpha;
+        t[j].idx = i;
+        t[j].clamped = cand[j].clamped;
+        /* colour of everything behind j, including the background */
+        double behind[3];
+        for (int c = 0; c < 3; ++c) behind[c] = Tf * bg[c];
+        for (int64_t h = j + 1; h < used; ++h) {
+            const int32_t ih = cand[h].idx;
+            for (int c = 0; c < 3; ++c) behind[c] += rgb[3 * ih + c] * cand[h].alpha * Tk[h];
+        }
+        /* dal: dL/dalpha; dal_abs: the sum of the magnitudes of its terms (the
+         * scale of the rounding error of any evaluation of it) */
+        double dal = 0.0, dal_abs = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double front = rgb[3 * i + c] * Tk[j], back = behind[c] / (1.0 - al);
+            dal += g[c] * (front - back);
+            dal_abs += fabs(g[c]) * (fabs(front) + fabs(back));
+            const double dr = g[c] * al * Tk[j];
+            t[j].g[6 + c] = dr;
+            t[j].a[6 + c] = fabs(dr);
+        }
+        if (cand[j].clamped) continue;
+        const double G = cand[j].G, o = opacity[i];
+        const double dG = dal * o, dG_abs = dal_abs * o;
+        t[j].g[5] = dal * G;
+        t[j].a[5] = dal_abs * G;
+        const double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
+        const double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
+        t[j].g[0] = dG * G * (a * dx + b * dy);
+        t[j].g[1] = dG * G * (b * dx + c * dy);
+        t[j].a[0] = dG_abs * G * (fabs(a * dx) + fabs(b * dy));
+        t[j].a[1] = dG_abs * G * (fabs(b * dx) + fabs(c * dy));
+        t[j].g[2] = -0.5 * dG * G * dx * dx;
+        t[j].g[3] = -dG * G * dx * dy;
+        t[j].g[4] = -0.5 * dG * G * dy * dy;
+        t[j].a[2] = 0.5 * dG_abs * G * dx * dx;
+        t[j].a[3] = dG_abs * G * fabs(dx * dy);
+        t[j].a[4] = 0.5 * dG_abs * G * dy * dy;
+    }
+    *out = t;
+    return used;
+}
+
 void oracle_render_backward_pixels(int64_t n, const double* mean2d, const double* conic,
                                    const double* opacity, const double* rgb,
                                    const uint32_t* depth_key, const int32_t* visible,
                                    int64_t npix, const int32_t* pix, const double* bg,
                                    const double* dL_dC, double* grad, double* g_abs) {
-    cand_t* cand = (cand_t*)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
-    double* Tk = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    for (int64_t k = 0; k < npix; ++k) {
-        double mg;
-        const double px = pix[2 * k] + 0.5, py = pix[2 * k + 1] + 0.5;
-        int64_t m = pixel_candidates(n, mean2d, conic, opacity, depth_key, visible, px, py, cand, &mg);
-        double T = 1.0;
-        int64_t used = 0;
-        for (int64_t j = 0; j < m; ++j) {
-            const double Tn = T * (1.0 - cand[j].alpha);
-            if (Tn < T_MIN) break;
-            Tk[j] = T;
-            T = Tn;
-            ++used;
+    enum { BLOCK = 512 };
+    term_t* terms[BLOCK];
+    int64_t nterms[BLOCK];
+    for (int64_t k0 = 0; k0 < npix; k0 += BLOCK) {
+        const int64_t kb = npix - k0 < BLOCK ? npix - k0 : BLOCK;
+#pragma omp parallel
+        {
+            cand_t* cand = (cand_t*)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+            double* Tk = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t k = 0; k < kb; ++k) {
+                const int64_t p = k0 + k;
+                nterms[k] = pixel_adjoint_terms(n, mean2d, conic, opacity, rgb, depth_key, visible,
+                                                pix[2 * p] + 0.5, pix[2 * p + 1] + 0.5, bg,
+                                                dL_dC + 3 * p, cand, Tk, &terms[k]);
+            }
+            free(Tk);
+            free(cand);
         }
-        const double Tf = T;
-        const double* g = dL_dC + 3 * k;
-        for (int64_t j = 0; j < used; ++j) {
-            const int32_t i = cand[j].idx;
-            const double al = cand[j].alpha;
-            /* colour of everything behind j, including the background */
-            double behind[3];
-            for (int c = 0; c < 3; ++c) behind[c] = Tf * bg[c];
-            for (int64_t h = j + 1; h < used; ++h) {
-                const int32_t ih = cand[h].idx;
-                for (int c = 0; c < 3; ++c) behind[c] += rgb[3 * ih + c] * cand[h].alpha * Tk[h];
+        /* pixel order, then compositing order: the order a serial walk adds in */
+        for (int64_t k = 0; k < kb; ++k) {
+            for (int64_t j = 0; j < nterms[k]; ++j) {
+                const term_t* t = &terms[k][j];
+                const int64_t i = t->idx;
+                for (int c = 0; c < 3; ++c) {
+                    grad[9 * i + 6 + c] += t->g[6 + c];
+                    g_abs[9 * i + 6 + c] += t->a[6 + c];
+                }
+                if (t->clamped) continue;
+                grad[9 * i + 5] += t->g[5];
+                g_abs[9 * i + 5] += t->a[5];
+                for (int u = 0; u < 5; ++u) {
+                    grad[9 * i + u] += t->g[u];
+                    g_abs[9 * i + u] += t->a[u];
+                }
             }
-            /* dal: dL/dalpha; dal_abs: the sum of the magnitudes of its terms (the
-             * scale of the rounding error of any evaluation of it) */
-            double dal = 0.0, dal_abs = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                const double front = rgb[3 * i + c] * Tk[j], back = behind[c] / (1.0 - al);
-                dal += g[c] * (front - back);
-                dal_abs += fabs(g[c]) * (fabs(front) + fabs(back));
-                const double dr = g[c] * al * Tk[j];
-                grad[9 * i + 6 + c] += dr;
-                g_abs[9 * i + 6 + c] += fabs(dr);
-            }
-            if (cand[j].clamped) continue;
-            const double G = cand[j].G, o = opacity[i];
-            const double dG = dal * o, dG_abs = dal_abs * o;
-            const double dop = dal * G;
-            grad[9 * i + 5] += dop;
-            g_abs[9 * i + 5] += dal_abs * G;
-            const double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
-            const double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
-            const double gm[2] = {dG * G * (a * dx + b * dy), dG * G * (b * dx + c * dy)};
-            const double gm_abs[2] = {dG_abs * G * (fabs(a * dx) + fabs(b * dy)),
-                                      dG_abs * G * (fabs(b * dx) + fabs(c * dy))};
-            const double gc[3] = {-0.5 * dG * G * dx * dx, -dG * G * dx * dy, -0.5 * dG * G * dy * dy};
-            const double gc_abs[3] = {0.5 * dG_abs * G * dx * dx, dG_abs * G * fabs(dx * dy),
-                                      0.5 * dG_abs * G * dy * dy};
-            for (int u = 0; u < 2; ++u) {
-                grad[9 * i + u] += gm[u];
-                g_abs[9 * i + u] += gm_abs[u];
-            }
-            for (int u = 0; u < 3; ++u) {
-                grad[9 * i + 2 + u] += gc[u];
-                g_abs[9 * i + 2 + u] += gc_abs[u];
-            }
+            free(terms[k]);
         }
     }
-    free(Tk);
-    free(cand);
 }
+
+/* Thread count of the OpenMP regions above (the CPU-baseline timing runs the
+ * oracle on one thread and on every core). */
+void oracle_set_threads(int threads) { omp_set_num_threads(threads > 0 ? threads : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Chain rule to the raw parameters                                           */

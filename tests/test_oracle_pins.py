@@ -706,3 +706,19 @@ def test_l1_loss_grad_hand_values_and_loss_oracle():
     L1, g1 = oracle.l1_loss_grad(x, y)
     assert L1 == pytest.approx(L0, rel=1e-14)
     np.testing.assert_allclose(g1, g0, rtol=1e-14, atol=0)
+
+
+def test_adjoint_sums_do_not_depend_on_the_thread_count():
+    """The oracle's adjoint is computed in parallel over pixels but added in
+    pixel order, so its sums are bit-identical for any thread count."""
+    sc = synth.random_scene(5, 800, 40, 32, sh_degree=1)
+    p = oracle.project(sc, sc.cameras[0])
+    pix = oracle.all_pixels(40, 32)
+    g = np.random.default_rng(1).standard_normal((pix.shape[0], 3))
+    out = []
+    for t in (1, 4):
+        oracle.set_threads(t)
+        out.append(oracle.render_backward_pixels(p, pix, g))
+    oracle.set_threads(os.cpu_count() or 1)
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
