@@ -124,6 +124,19 @@ typedef struct {
  * ellipse o G >= 1/255, and images do not depend on the grid.  gs_render and
  * its adjoint use the footprint of the frame's last gs_project. */
 #define GS_RASTER_FOOTPRINT_3SIGMA 2
+/* gs_raster_opts.flags: how gs_render (gs_bin) puts each tile's list in
+ * (depth bits, entry) order.  Without the flag every list is sorted on its own
+ * after a radix sort of the instances by tile.  With it the visible entries
+ * are radix sorted by depth first and emitted in that order, so the stable
+ * sort by tile leaves every list in order with no per-tile sort.  The lists,
+ * images and gradients are identical; the cost differs with the list lengths
+ * (long lists favour the presort), which is what the autotuner measures. */
+#define GS_RASTER_DEPTH_PRESORT 4
+/* gs_raster_opts.flags: the radix sort of the instances by tile splits the
+ * tile id's bits into digits of equal width (13 bits: 7 + 6) instead of 8-bit
+ * digits and a narrower last one (8 + 5).  Same passes, same result; a tuning
+ * knob. */
+#define GS_RASTER_BALANCED_DIGITS 8
 
 /* ------------------------------------------------------------------------ */
 /* Frame: the device state of one rendering step for a fixed set of view     */
@@ -163,7 +176,10 @@ enum {
     GS_BUF_N_CONTRIB = 9,     /* u32 [P]     instances walked per pixel (last composited + 1) */
     GS_BUF_SPLAT_GRAD = 10,   /* f32 [V*n][9] dL/d(mean2d x, y, conic a, b, c, opacity, r, g, b);
                                  defined for rendered entries (tiles_touched > 0) only */
-    GS_BUF_COUNTERS = 11,     /* u32 [16]    [0] visible entries, [1] instances, [2] overflow flag */
+    GS_BUF_COUNTERS = 11,     /* u32 [16]    [0] visible entries, [1] instances, [2] overflow flag of
+                                 the last binning, [6] sticky overflow flag: set by every binning
+                                 that overflowed, cleared only by the caller (write 0), so a caller
+                                 that does not read [2] after each render can check many at once */
     GS_BUF_N_COMPOSITED = 12  /* u32 [P]     splats composited per pixel */
 };
 gs_status gs_frame_buffer(const gs_frame* frame, int32_t which, void** ptr, int64_t* count);
@@ -194,6 +210,15 @@ gs_status gs_project(gs_frame* frame, const gs_gaussians* g, const gs_camera* ca
  * planar images one after the other (sum_v 3 H_v W_v floats).  Also keeps the
  * per-pixel final transmittance and walk length for the backward. */
 gs_status gs_render(gs_frame* frame, const gs_raster_opts* opts, float* images, void* stream);
+
+/* The two halves of gs_render, for callers that time or schedule them apart.
+ * gs_bin: the per-tile, depth-ordered lists of the frame's last gs_project
+ * (and, with persistent_blocks > 0, the heavy-first tile order).
+ * gs_composite: compositing (Eq. 2) over the lists of the frame's last gs_bin;
+ * persistent_blocks > 0 needs a gs_bin that ran with persistent_blocks > 0
+ * (else GS_ERR_INVALID).  gs_bin followed by gs_composite is gs_render. */
+gs_status gs_bin(gs_frame* frame, const gs_raster_opts* opts, void* stream);
+gs_status gs_composite(gs_frame* frame, const gs_raster_opts* opts, float* images, void* stream);
 
 /* Adjoint of gs_render: from dL/dimages (same layout as images) to the
  * per-splat gradients GS_BUF_SPLAT_GRAD, which gs_project cleared; call it
@@ -332,6 +357,22 @@ gs_status gs_densify_apply(const int32_t* src, const uint8_t* kind, int64_t n_ou
                            const gs_attr* attrs, int32_t n_attrs, const float* parent_means,
                            const float* parent_log_scales, const float* parent_quats,
                            uint64_t seed, uint64_t step, void* stream);
+
+/* Spatial order of the Gaussians, a memory layout (not a step of the paper's
+ * method): the permutation that sorts them by the Morton (Z-order) code of
+ * their means on a 1024^3 grid over the cube of the means' bounding box (side
+ * = its longest extent; cell q = min(1023, trunc((x - min) * (1024 / side))) in
+ * FP32 per axis, x in the code's bit 0; non-finite means last), ties by index.
+ * Output as a densification map, src[j] = the Gaussian placed at row j and
+ * kind[j] = GS_KIND_KEEP (src and kind: [n]); gs_densify_apply with this map
+ * gathers parameters, optimiser moments and any other per-Gaussian attribute.
+ * Images are unchanged and gradients are permuted alike, while the Gaussians a
+ * view renders become neighbours in memory, so the projection, its adjoint and
+ * sparse Adam touch whole cache lines and skip whole waves of Gaussians that
+ * no view rendered.  workspace: gs_spatial_order_workspace_size(n) bytes. */
+gs_status gs_spatial_order_workspace_size(int64_t n, uint64_t* bytes);
+gs_status gs_spatial_order(const float* means, int64_t n, int32_t* src, uint8_t* kind,
+                           void* workspace, uint64_t workspace_bytes, void* stream);
 
 /* The split normals of (parent, child) pairs as the apply step draws them:
  * words [m][4] (raw Philox output) and z [m][3]. */

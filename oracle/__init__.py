@@ -520,6 +520,42 @@ def densify_apply(params: dict, src, kind, seed: int, step: int):
     return out
 
 
+def morton_code(qx: int, qy: int, qz: int) -> int:
+    """Interleave three 10-bit cell coordinates bit by bit: bit b of qx goes to
+    bit 3b, of qy to 3b + 1, of qz to 3b + 2."""
+    code = 0
+    for b in range(10):
+        code |= ((qx >> b) & 1) << (3 * b)
+        code |= ((qy >> b) & 1) << (3 * b + 1)
+        code |= ((qz >> b) & 1) << (3 * b + 2)
+    return code
+
+
+def spatial_order(means):
+    """The Morton-order permutation of Gaussians (a memory layout, not a step
+    of the paper's method): cells of a 1024^3 grid over the cube of the finite
+    means' bounding box (side = longest extent), q = min(1023, trunc((x - lo) *
+    (1024 / side))) evaluated in FP32 (the precision the layout is decided in),
+    non-finite means last, ties by index.  Returns (src, codes)."""
+    m = np.asarray(means, np.float32)
+    n = m.shape[1]
+    fin = np.isfinite(m).all(axis=0)
+    codes = np.full(n, 0x3FFFFFFF, np.int64)
+    if fin.any():
+        lo = m[:, fin].min(axis=1)
+        hi = m[:, fin].max(axis=1)
+        side = np.float32(max(np.float32(hi[a] - lo[a]) for a in range(3)))
+        inv = np.float32(np.float32(1024.0) / side) if side > 0 else np.float32(0.0)
+        for i in np.flatnonzero(fin):
+            q = []
+            for a in range(3):
+                t = np.float32(np.float32(m[a, i] - lo[a]) * inv)
+                q.append(1023 if t >= np.float32(1023.0) else int(t))
+            codes[i] = morton_code(*q)
+    src = np.argsort(codes, kind="stable").astype(np.int32)
+    return src, codes
+
+
 def lineage_apply(origin, splits, clones, src, kind):
     """Lineage attributes through one densification (Methodology, Spatial
     diffusion): every output row keeps its parent's original position; both

@@ -36,10 +36,14 @@ class GaussianRasterizer:
 
     def __init__(self, n, cameras, sh_degree, device="cuda", bg=(0.0, 0.0, 0.0),
                  raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2,
-                 footprint_3sigma=False, autotune=False):
+                 footprint_3sigma=False, autotune=False, lazy_overflow=False):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.device = torch.device(device)
+        # lazy_overflow: the forward does not read the overflow flag back (no host
+        # synchronisation per call); the caller checks overflowed() when it
+        # chooses and repeats the affected steps with a larger capacity (grow())
+        self.lazy_overflow = bool(lazy_overflow)
         self._opt_args = dict(bg=bg, near_plane=near_plane, footprint_3sigma=footprint_3sigma)
         self.opts = gsmi.raster_opts(raster_batch=raster_batch, persistent_blocks=persistent_blocks,
                                      **self._opt_args)
@@ -64,6 +68,24 @@ class GaussianRasterizer:
         self.cameras = list(cameras)
         self.cams_dev = gsmi.cameras_to_device(self.cameras, self.device)
 
+    def use_device_cameras(self, cams_dev):
+        """Cameras already packed on the device (gs_camera rows, e.g. rows of
+        gsmi.cameras_to_device of a larger table indexed on the device), so a
+        training loop can change views without a host-to-device copy.  The
+        views must have the frame's sizes; that is the caller's contract."""
+        if cams_dev.numel() != self.cams_dev.numel() or cams_dev.device != self.cams_dev.device:
+            raise ValueError("expected %d bytes of cameras on %s"
+                             % (self.cams_dev.numel(), self.cams_dev.device))
+        self.cams_dev = cams_dev.contiguous()
+
+    def overflowed(self, clear=True):
+        """Whether any forward since the last check overflowed the instance
+        capacity (synchronises).  Only needed with lazy_overflow=True."""
+        return self.frame.overflowed(clear=clear)
+
+    def grow(self, factor=2):
+        self._grow(self.frame.cap * factor)
+
     def reset_stats(self):
         self.accum.zero_()
         self.denom.zero_()
@@ -73,8 +95,7 @@ class GaussianRasterizer:
         scene = types.SimpleNamespace(n=self.n, sh_degree=self.sh_degree)
         best = autotune.tune_batched(scene, self.cameras, params, self.device, cap=self.frame.cap,
                                      opts=self._opt_args)
-        self.opts = gsmi.raster_opts(raster_batch=best["raster_batch"],
-                                     persistent_blocks=best["persistent_blocks"], **self._opt_args)
+        self.opts = autotune.opts_of(best, **self._opt_args)
         self.tuned = best
 
     def _grow(self, needed):
@@ -104,6 +125,8 @@ class _Rasterize(torch.autograd.Function):
         while True:
             r.frame.project(params, r.sh_degree, r.cams_dev, r.opts)
             images = r.frame.render(r.opts)
+            if r.lazy_overflow and not tune:
+                break
             nv, ni, ovf = r.frame.status(raise_on_overflow=False)
             if not ovf:
                 if not tune:
@@ -118,6 +141,7 @@ class _Rasterize(torch.autograd.Function):
         ctx.r = r
         ctx.generation = r.generation
         ctx.params = params
+        ctx.cams_dev = r.cams_dev
         return images
 
     @staticmethod
@@ -128,7 +152,31 @@ class _Rasterize(torch.autograd.Function):
                                "longer holds this forward's state")
         r.frame.render_backward(r.opts, dL_dimages.contiguous())
         grads = gsmi.empty_grads(ctx.params)
-        r.frame.project_backward(ctx.params, r.sh_degree, r.cams_dev, r.opts, grads, r.accum,
+        r.frame.project_backward(ctx.params, r.sh_degree, ctx.cams_dev, r.opts, grads, r.accum,
                                  r.denom)
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"],
                 grads["sh"], None)
+
+
+class _PhotometricLoss(torch.autograd.Function):
+    """Eq. 3 of one view, (1 - lambda) L1 + lambda D-SSIM, with its gradient
+    computed in the same kernel launches as the loss (gs_ssim_loss_grad)."""
+
+    @staticmethod
+    def forward(ctx, image, target, lam, workspace):
+        loss = torch.zeros(1, dtype=torch.float32, device=image.device)
+        loss, grad = gsmi.ssim_loss_grad(image.contiguous(), target.contiguous(), lam, loss=loss,
+                                         workspace=workspace)
+        ctx.save_for_backward(grad)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g, None, None, None
+
+
+def photometric_loss(image, target, lam=0.2, workspace=None):
+    """Differentiable Eq. 3 loss of a [3, H, W] image against its target.
+    workspace: optional uint8 device buffer of gsmi.ssim_workspace_bytes."""
+    return _PhotometricLoss.apply(image, target, float(lam), workspace)

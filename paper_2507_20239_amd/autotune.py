@@ -1,11 +1,13 @@
 """Autotuner for the rasterizer launch shape.
 
-Searches the LDS batch size (splats staged per batch: 64, 128, 256) and the
+Searches the LDS batch size (splats staged per batch: 64, 128, 256), the
 work distribution (one wave64 workgroup per (view, tile), or a persistent grid
-of 2048 / 4096 / 8192 waves pulling tiles heaviest-first from a queue) by timing
-the captured training step of the given views, and caches the winner per
-(device, workload signature) in a JSON file ($GSMI_AUTOTUNE_CACHE, default
-~/.cache/gsmi_autotune.json).
+of 2048 / 4096 / 8192 waves pulling tiles heaviest-first from a queue), how the
+per-tile lists are put in depth order (a sort per tile, or a depth presort of
+the visible entries) and the digit split of the radix sort by tile (48
+candidates), by timing the captured training step of the given views, and
+caches the winner per (device, workload signature) in a JSON file
+($GSMI_AUTOTUNE_CACHE, default ~/.cache/gsmi_autotune.json).
 """
 from __future__ import annotations
 
@@ -18,6 +20,17 @@ from . import gsmi
 
 BATCHES = (64, 128, 256)
 PERSISTENT = (0, 2048, 4096, 8192)
+# how each tile's list gets its depth order: per-tile sorts, or a depth presort of
+# the visible entries (long lists favour the presort); and the digit split of the
+# radix sort by tile (8-bit digits, or digits of equal width)
+PRESORT = (False, True)
+BALANCED = (False, True)
+SHAPE_KEYS = ("raster_batch", "persistent_blocks", "depth_presort", "balanced_digits")
+
+
+def opts_of(best, **other):
+    """gsmi.raster_opts for a tuned shape (the other options as given)."""
+    return gsmi.raster_opts(**{k: best[k] for k in SHAPE_KEYS if k in best}, **other)
 
 
 def _cache_path():
@@ -91,10 +104,14 @@ def tune_batched(scene, cams, params, device, cap=32 << 20, use_cache=True, opts
     results = []
     for b in BATCHES:
         for pb in PERSISTENT:
-            o = gsmi.raster_opts(raster_batch=b, persistent_blocks=pb, **opts)
-            ms = _time_step(frame, params, scene.sh_degree, cams_dev, o, images, targets, scale,
-                            loss, dL, grads)
-            results.append({"raster_batch": b, "persistent_blocks": pb, "ms": round(ms, 4)})
+            for ps in PRESORT:
+                for bd in BALANCED:
+                    shape = {"raster_batch": b, "persistent_blocks": pb, "depth_presort": ps,
+                             "balanced_digits": bd}
+                    o = opts_of(shape, **opts)
+                    ms = _time_step(frame, params, scene.sh_degree, cams_dev, o, images, targets,
+                                    scale, loss, dL, grads)
+                    results.append(dict(shape, ms=round(ms, 4)))
     best = dict(min(results, key=lambda r: r["ms"]))
     best["candidates"] = len(results)
     cache[sig] = best

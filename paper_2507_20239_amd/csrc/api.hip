@@ -84,6 +84,8 @@ Layout layout_for(gs_frame* f) {
     uint64_t sort_bytes = gs_radix_scratch_bytes(f->cap, f->tile_bits);
     const uint64_t st = gs_radix_scratch_bytes(f->T, 24);
     if (st > sort_bytes) sort_bytes = st;
+    const uint64_t sd = gs_radix_scratch_bytes(f->E, 32);
+    if (sd > sort_bytes) sort_bytes = sd;
     Layout L;
     L.add(4 * E);        // 0 depth_key
     L.add(4 * E);        // 1 tiles_touched
@@ -109,6 +111,9 @@ Layout layout_for(gs_frame* f) {
     L.add(sizeof(gs_view_info) * GS_MAX_VIEWS);  // 21 views
     L.add(4 * P);        // 22 n_comp
     L.add(4 * (cap / 256 + 2));  // 23 chunk_start
+    L.add(4 * E);        // 24 dkeys0
+    L.add(4 * E);        // 25 dkeys1
+    L.add(4 * E);        // 26 dvals1
     return L;
 }
 
@@ -133,7 +138,8 @@ gs_status check_opts(const gs_raster_opts* o) {
         return gs_fail(GS_ERR_INVALID, "raster_batch must be 0, 64, 128 or 256");
     if (o->persistent_blocks < 0 || o->persistent_blocks > 65536)
         return gs_fail(GS_ERR_INVALID, "persistent_blocks must be in [0, 65536]");
-    if (o->flags & ~(GS_RASTER_COUNT_COMPOSITED | GS_RASTER_FOOTPRINT_3SIGMA))
+    if (o->flags & ~(GS_RASTER_COUNT_COMPOSITED | GS_RASTER_FOOTPRINT_3SIGMA | GS_RASTER_DEPTH_PRESORT |
+                     GS_RASTER_BALANCED_DIGITS))
         return gs_fail(GS_ERR_INVALID, "unknown bits in raster flags");
     if (!(o->near_plane > 0.f)) return gs_fail(GS_ERR_INVALID, "near_plane must be > 0");
     return GS_OK;
@@ -210,6 +216,9 @@ gs_status gs_frame_create(int64_t n, int32_t n_views, const int32_t* widths,
     f->d_views = (gs_view_info*)(b + L.off[21]);
     f->n_comp = (u32*)(b + L.off[22]);
     f->chunk_start = (u32*)(b + L.off[23]);
+    f->dkeys[0] = (u32*)(b + L.off[24]);
+    f->dkeys[1] = (u32*)(b + L.off[25]);
+    f->dvals1 = (u32*)(b + L.off[26]);
     // the slot holding the sorted instances depends only on the pass count; the
     // heavy-first order exists only after a binning that built it
     f->isorted = (((f->tile_bits + 7) / 8) & 1);
@@ -276,13 +285,31 @@ gs_status gs_project(gs_frame* f, const gs_gaussians* g, const gs_camera* camera
                              (opts->flags & GS_RASTER_FOOTPRINT_3SIGMA) != 0, (hipStream_t)stream);
 }
 
+gs_status gs_bin(gs_frame* f, const gs_raster_opts* opts, void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_opts(opts));
+    return gs_launch_bin(f, (hipStream_t)stream, opts->persistent_blocks > 0,
+                         (opts->flags & GS_RASTER_DEPTH_PRESORT) != 0,
+                         (opts->flags & GS_RASTER_BALANCED_DIGITS) != 0);
+}
+
+gs_status gs_composite(gs_frame* f, const gs_raster_opts* opts, float* images, void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_opts(opts));
+    if (!images) return gs_fail(GS_ERR_INVALID, "images is null");
+    if (opts->persistent_blocks > 0 && !f->heavy_built)
+        return gs_fail(GS_ERR_INVALID,
+                       "persistent_blocks > 0 needs the heavy-first tile order, which the last "
+                       "binning did not build (it ran with persistent_blocks = 0)");
+    return gs_launch_raster_fwd(f, opts, images, (hipStream_t)stream);
+}
+
 gs_status gs_render(gs_frame* f, const gs_raster_opts* opts, float* images, void* stream) {
     GS_TRY(check_frame(f));
     GS_TRY(check_opts(opts));
     if (!images) return gs_fail(GS_ERR_INVALID, "images is null");
-    hipStream_t s = (hipStream_t)stream;
-    GS_TRY(gs_launch_bin(f, s, opts->persistent_blocks > 0));
-    return gs_launch_raster_fwd(f, opts, images, s);
+    GS_TRY(gs_bin(f, opts, stream));
+    return gs_composite(f, opts, images, stream);
 }
 
 gs_status gs_render_backward(gs_frame* f, const gs_raster_opts* opts, const float* dL_dimages,

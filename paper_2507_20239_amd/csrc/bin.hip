@@ -46,6 +46,14 @@ constexpr u32 EMIT_CHUNK = 256;
 // entry count.
 __device__ __forceinline__ u64 vis_pack(u32 tt) { return tt ? ((u64)1 << 32) | tt : 0ull; }
 
+// The slots of the chunks of 256 instance slots that start inside the range
+// [off, off + tt) of a visible entry (below the capacity).
+__device__ __forceinline__ void mark_chunks(u32* chunk_start, u32 cap, u32 slot, u32 off, u32 tt) {
+    const u64 hi = (u64)off + tt < cap ? (u64)off + tt : cap;
+    for (u64 c = ((u64)off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK < hi; ++c)
+        chunk_start[c] = slot;
+}
+
 struct VisEpi {
     u32* visible;
     u32* inst_off;
@@ -53,13 +61,18 @@ struct VisEpi {
     u32* counters;
     u32 cap;
     u32 n;           // entries: bound of the compacted slots
+    // depth presort: the compacted entries' depth keys instead of their offsets
+    const u32* depth_key;
+    u32* dkey;
     __device__ void item(u32 e, u32 tt, u32 slot, u32 off) const {
         if (slot >= n) return;   // only after a carry out of the low half
         visible[slot] = e;
+        if (dkey) {
+            dkey[slot] = depth_key[e];
+            return;
+        }
         inst_off[slot] = off;
-        const u64 hi = (u64)off + tt < cap ? (u64)off + tt : cap;
-        for (u64 c = ((u64)off + EMIT_CHUNK - 1) / EMIT_CHUNK; c * EMIT_CHUNK < hi; ++c)
-            chunk_start[c] = slot;
+        mark_chunks(chunk_start, cap, slot, off, tt);
     }
     __device__ void finish(u32 nv, u32 t, u64 tiles) const {
         if (tiles >> 32) {
@@ -67,12 +80,14 @@ struct VisEpi {
             counters[1] = 0xffffffffu;
             counters[5] = 0;
             counters[2] = 1;
+            counters[6] = 1;
             return;
         }
         counters[0] = nv;
         counters[1] = t;
         counters[5] = t < cap ? t : cap;
         counters[2] = t > cap ? 1u : 0u;
+        if (t > cap) counters[6] = 1;   // sticky: cleared only by the caller
     }
 };
 
@@ -501,6 +516,20 @@ __global__ void __launch_bounds__(SORT_THREADS) tile_sort_kernel(
     }
 }
 
+// Instance offsets and chunk starts of the visible entries in depth order
+// (the epilogue of a scan of their tile counts, gathered through the sorted
+// entry list); the totals were published by the entry-order scan.
+struct PresortEpi {
+    u32* inst_off;
+    u32* chunk_start;
+    u32 cap;
+    __device__ void item(u32 slot, u32 tt, u32 off) const {
+        inst_off[slot] = off;
+        mark_chunks(chunk_start, cap, slot, off, tt);
+    }
+    __device__ void finish(u32) const {}
+};
+
 // heavy-first order key: longer lists first (lists of 65535 instances or
 // more tie), ties by tile id (stable sort); 16 bits, two radix passes
 constexpr int TILE_WEIGHT_BITS = 16;
@@ -518,7 +547,8 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + GS_BLOCK - 1) / GS_BLOCK
 
 }  // namespace
 
-gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
+gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first, bool presort,
+                        bool balanced) {
     const int64_t E = f->E;
     u32* cnt = f->counters;
     if (E > 0) {
@@ -527,9 +557,26 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
         u64* part = (u64*)f->scan_part;
         vis_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part);
         GS_TRY(gs_check_launch("visible_reduce"));
-        const VisEpi ve{f->visible, f->inst_off, f->chunk_start, cnt, (u32)f->cap, (u32)E};
+        const VisEpi ve{f->visible, f->inst_off, f->chunk_start, cnt, (u32)f->cap, (u32)E,
+                        f->depth_key, presort ? f->dkeys[0] : nullptr};
         vis_down_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(f->tiles_touched, (u32)E, part, ve);
         GS_TRY(gs_check_launch("visible_scan"));
+        if (presort) {
+            // the visible entries in (depth bits, entry) order: a stable radix sort of
+            // their depth keys over the entry-ordered list (four passes end in slot 0,
+            // f->visible), then their instance offsets in that order
+            u32* k[2] = {f->dkeys[0], f->dkeys[1]};
+            u32* v[2] = {f->visible, f->dvals1};
+            int slot = 0;
+            GS_TRY(gs_radix_sort(k, v, cnt + 0, 0, E, 32, f->sort_scratch, &slot, s));
+            if (slot != 0) return gs_fail(GS_ERR_HIP, "depth presort ended in the wrong buffer");
+            u32* sp = f->scan_part;
+            GS_TRY(gs_scan_reduce(f->tiles_touched, f->visible, cnt + 0, 0, sp, s));
+            const PresortEpi pe{f->inst_off, f->chunk_start, (u32)f->cap};
+            scan_down_kernel<PresortEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(
+                f->tiles_touched, f->visible, cnt + 0, 0, sp, pe);
+            GS_TRY(gs_check_launch("presort_offsets"));
+        }
         if (f->sigma3)
             emit_kernel<true><<<8192, GS_BLOCK, 0, s>>>(f->visible, f->inst_off, f->rect, f->splat,
                                                         f->d_views, f->n, cnt + 0, cnt + 5,
@@ -542,13 +589,13 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first) {
                                                          E, (u32)f->T);
         GS_TRY(gs_check_launch("emit"));
         GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->cap, f->tile_bits, f->sort_scratch,
-                             &f->isorted, s));
+                             &f->isorted, s, balanced));
     } else {
-        GS_TRY(gs_fill_u32(cnt, 0u, 8, s));
+        GS_TRY(gs_fill_u32(cnt, 0u, 6, s));
     }
     ranges_kernel<<<4096, GS_BLOCK, 0, s>>>(f->ikeys[f->isorted], cnt + 5, f->ranges, (u32)f->T);
     GS_TRY(gs_check_launch("ranges"));
-    if (E > 0 && f->T > 0) {
+    if (E > 0 && f->T > 0 && !presort) {
         const int o = f->isorted ^ 1;
         const unsigned sg = (unsigned)((f->T + SORT_TILES - 1) / SORT_TILES);
         tile_sort_kernel<<<sg, SORT_THREADS, 0, s>>>(f->ranges, (u32)f->T, f->depth_key, (u32)E,

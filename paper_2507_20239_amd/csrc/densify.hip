@@ -261,6 +261,89 @@ __device__ __forceinline__ float float_from_order_key(u32 k) {
     return __uint_as_float(b);
 }
 
+// --- spatial order: Morton (Z-order) codes of the means --------------------
+// box: order keys of min x, y, z (slots 0..2) and of max x, y, z (3..5) over
+// the finite means, reduced with integer atomics on the order keys.
+__global__ void box_init_kernel(u32* box) {
+    const int t = threadIdx.x;
+    if (t < 6) box[t] = t < 3 ? 0xffffffffu : 0u;
+}
+
+__global__ void __launch_bounds__(GS_BLOCK) box_kernel(const float* __restrict__ means, int64_t n,
+                                                       u32* box) {
+    u32 lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u};
+    const int64_t stride = (int64_t)gridDim.x * GS_BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x; i < n; i += stride) {
+        const float x = means[i], y = means[n + i], z = means[2 * n + i];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) continue;
+        const u32 k[3] = {float_order_key(x), float_order_key(y), float_order_key(z)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], k[a]);
+            hi[a] = max(hi[a], k[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[a] = min(lo[a], (u32)__shfl_xor((int)lo[a], off, 64));
+            hi[a] = max(hi[a], (u32)__shfl_xor((int)hi[a], off, 64));
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&box[a], lo[a]);
+            atomicMax(&box[3 + a], hi[a]);
+        }
+    }
+}
+
+// the low 10 bits of q spread to every third bit
+__device__ __forceinline__ u32 spread3(u32 q) {
+    q &= 0x3ffu;
+    q = (q | (q << 16)) & 0x030000ffu;
+    q = (q | (q << 8)) & 0x0300f00fu;
+    q = (q | (q << 4)) & 0x030c30c3u;
+    q = (q | (q << 2)) & 0x09249249u;
+    return q;
+}
+
+// code = interleaved bits of the cell (qx, qy, qz) of a 1024^3 grid over the
+// bounding box's cube (side = its longest extent), qx in bit 0; a non-finite
+// mean gets the largest code.  FP32: d = x - lo, q = min(1023, trunc(d * (1024 / side))).
+__global__ void __launch_bounds__(GS_BLOCK) morton_kernel(const float* __restrict__ means, int64_t n,
+                                                          const u32* box, u32* codes, u32* idx) {
+    const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float lo[3], side = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = float_from_order_key(box[a]);
+        side = fmaxf(side, float_from_order_key(box[3 + a]) - lo[a]);
+    }
+    const float inv = side > 0.f ? 1024.0f / side : 0.f;
+    const float p[3] = {means[i], means[n + i], means[2 * n + i]};
+    u32 code = 0x3fffffffu;
+    if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+        code = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float t = (p[a] - lo[a]) * inv;
+            const u32 q = t >= 1023.0f ? 1023u : (u32)t;
+            code |= spread3(q) << a;
+        }
+    }
+    codes[i] = code;
+    idx[i] = (u32)i;
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, uint8_t v, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * GS_BLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
 // state: [0] prefix, [1] prefix mask, [2] remaining rank; hist: 256 counters
 __global__ void select_init_kernel(u32* state, u32* hist, u32 k) {
     const int t = threadIdx.x;
@@ -531,6 +614,47 @@ gs_status gs_split_normals(const int64_t* parents, const int32_t* children, int6
     split_normals_kernel<<<blocks_for(m), GS_BLOCK, 0, (hipStream_t)stream>>>(
         parents, children, m, seed, step, (uint4*)words, z);
     return gs_check_launch("split_normals");
+}
+
+gs_status gs_spatial_order_workspace_size(int64_t n, uint64_t* bytes) {
+    if (n < 0 || n >= ((int64_t)1 << 30) || !bytes) return gs_fail(GS_ERR_INVALID, "bad argument");
+    const uint64_t nb = align256(4 * (uint64_t)(n > 0 ? n : 1));
+    *bytes = 3 * nb + align256(gs_radix_scratch_bytes(n, 30)) + 256;
+    return GS_OK;
+}
+
+gs_status gs_spatial_order(const float* means, int64_t n, int32_t* src, uint8_t* kind,
+                           void* workspace, uint64_t workspace_bytes, void* stream) {
+    uint64_t need;
+    GS_TRY(gs_spatial_order_workspace_size(n, &need));
+    if (n == 0) return GS_OK;
+    if (!means || !src || !kind || !workspace) return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (workspace_bytes < need) return gs_fail(GS_ERR_INVALID, "workspace too small (%llu < %llu)",
+                                               (unsigned long long)workspace_bytes,
+                                               (unsigned long long)need);
+    hipStream_t s = (hipStream_t)stream;
+    char* b = (char*)workspace;
+    const uint64_t nb = align256(4 * (uint64_t)n);
+    u32* k0 = (u32*)b;
+    u32* k1 = (u32*)(b + nb);
+    u32* v1 = (u32*)(b + 2 * nb);
+    void* scratch = (void*)(b + 3 * nb);
+    u32* box = (u32*)(b + 3 * nb + align256(gs_radix_scratch_bytes(n, 30)));
+    box_init_kernel<<<1, 64, 0, s>>>(box);
+    GS_TRY(gs_check_launch("spatial_box_init"));
+    int64_t blocks = blocks_for(n);
+    box_kernel<<<(unsigned)(blocks > 2048 ? 2048 : blocks), GS_BLOCK, 0, s>>>(means, n, box);
+    GS_TRY(gs_check_launch("spatial_box"));
+    morton_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(means, n, box, k0, (u32*)src);
+    GS_TRY(gs_check_launch("morton_codes"));
+    // stable: equal codes keep index order; four passes end in slot 0 (src)
+    u32* k[2] = {k0, k1};
+    u32* v[2] = {(u32*)src, v1};
+    int slot = 0;
+    GS_TRY(gs_radix_sort(k, v, nullptr, (u32)n, n, 30, scratch, &slot, s));
+    if (slot != 0) return gs_fail(GS_ERR_HIP, "spatial order ended in the wrong buffer");
+    fill_u8_kernel<<<(unsigned)(blocks > 2048 ? 2048 : blocks), GS_BLOCK, 0, s>>>(kind, GS_KIND_KEEP, n);
+    return gs_check_launch("spatial_kind");
 }
 
 gs_status gs_radix_select_workspace_size(int64_t n, uint64_t* bytes) {

@@ -47,6 +47,9 @@ struct gs_frame {
     // visible-entry compaction
     u32* visible;        // [E] visible entries, in entry order
     u32* inst_off;       // [E] instance offset of each visible entry
+    // depth presort of the visible entries: keys (ping-pong) and the second value slot
+    u32* dkeys[2];       // [E]
+    u32* dvals1;         // [E]
     // instances (ping-pong)
     u32* ikeys[2];       // [cap]
     u32* ivals[2];       // [cap]
@@ -67,7 +70,8 @@ struct gs_frame {
     // per splat gradient
     float* splat_grad;   // [E][9]
     // counters: [0] visible, [1] instances, [2] overflow, [3] fwd queue, [4] bwd queue,
-    // [5] instances kept (min(instances, capacity))
+    // [5] instances kept (min(instances, capacity)), [6] sticky overflow (set by any
+    // binning that overflowed, cleared only by the caller)
     u32* counters;
     // sort and scan scratch
     void* sort_scratch;
@@ -209,15 +213,21 @@ gs_status gs_scan_reduce(const u32* in, const u32* gather, const u32* n_dev, u32
 // input; *slot receives the buffer index (0 or 1) that holds the result.  The
 // length is n_dev[0] when n_dev != NULL, else n_host, and never exceeds
 // `capacity` (< 2^30).  `scratch` needs gs_radix_scratch_bytes(capacity, bits).
+// balanced: digits of equal width (ceil(bits / passes)) instead of 8 bits and a
+// narrower last digit; the pass count, and so the result slot, is the same.
 gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
-                        int bits, void* scratch, int* slot, hipStream_t s);
+                        int bits, void* scratch, int* slot, hipStream_t s, bool balanced = false);
 uint64_t gs_radix_scratch_bytes(int64_t capacity, int bits);
 
 // sigma3: bin by 3-sigma squares (GS_RASTER_FOOTPRINT_3SIGMA) instead of the
 // opacity-aware ellipse; recorded in the frame for the binning that follows
 gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                             float near_plane, bool sigma3, hipStream_t s);
-gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first);
+// heavy_first: also build the heavy-first tile order (persistent launches);
+// presort: order the visible entries by depth before emission instead of
+// sorting each tile's list afterwards (GS_RASTER_DEPTH_PRESORT)
+// balanced: balanced digit widths in the radix sort by tile (GS_RASTER_BALANCED_DIGITS)
+gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first, bool presort, bool balanced);
 gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* images,
                                hipStream_t s);
 gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float* dL,

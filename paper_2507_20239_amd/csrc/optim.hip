@@ -50,6 +50,9 @@ __global__ void __launch_bounds__(GS_BLOCK) adam_kernel(AdamTable t, int64_t n,
         u32 any = 0;
         for (int v = 0; v < n_views; ++v) any |= tiles_touched[(int64_t)v * n + i];
         upd = any != 0;
+        // a wave with no rendered Gaussian leaves its rows as they are without
+        // touching them (whole waves of them, when the Gaussians are in spatial order)
+        if (__ballot(upd) == 0) return;
     }
     for (int a = 0; a < t.count; ++a) {
         const gs_adam_param q = t.p[a];

@@ -38,31 +38,56 @@ constexpr float SH_C3c = 0.4570457994644658f;
 constexpr float SH_C3d = 0.3731763325901154f;
 constexpr float SH_C3e = 1.445305721320277f;
 
+// The basis is evaluated in FP64 and rounded once to FP32: the higher
+// degrees are differences of products of the direction's coordinates (x^2 -
+// 3 y^2 and the like), which near their zeros would leave FP32 rounding far
+// above the value, and the colour coefficients' gradient is the basis itself.
 template <int DEG>
-__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
+__device__ __forceinline__ void sh_eval(double x, double y, double z, float* Y) {
     Y[0] = SH_Y00;
     if (DEG >= 1) {
-        Y[1] = -SH_C1 * y;
-        Y[2] = SH_C1 * z;
-        Y[3] = -SH_C1 * x;
+        Y[1] = (float)(-(double)SH_C1 * y);
+        Y[2] = (float)((double)SH_C1 * z);
+        Y[3] = (float)(-(double)SH_C1 * x);
     }
     if (DEG >= 2) {
-        const float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = SH_C2a * x * y;
-        Y[5] = -SH_C2a * y * z;
-        Y[6] = SH_C2b * (2.f * zz - xx - yy);
-        Y[7] = -SH_C2a * x * z;
-        Y[8] = SH_C2c * (xx - yy);
+        const double xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = (float)((double)SH_C2a * x * y);
+        Y[5] = (float)(-(double)SH_C2a * y * z);
+        Y[6] = (float)((double)SH_C2b * (2.0 * zz - xx - yy));
+        Y[7] = (float)(-(double)SH_C2a * x * z);
+        Y[8] = (float)((double)SH_C2c * (xx - yy));
         if (DEG >= 3) {
-            Y[9] = -SH_C3a * y * (3.f * xx - yy);
-            Y[10] = SH_C3b * x * y * z;
-            Y[11] = -SH_C3c * y * (4.f * zz - xx - yy);
-            Y[12] = SH_C3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
-            Y[13] = -SH_C3c * x * (4.f * zz - xx - yy);
-            Y[14] = SH_C3e * z * (xx - yy);
-            Y[15] = -SH_C3a * x * (xx - 3.f * yy);
+            Y[9] = (float)(-(double)SH_C3a * y * (3.0 * xx - yy));
+            Y[10] = (float)((double)SH_C3b * x * y * z);
+            Y[11] = (float)(-(double)SH_C3c * y * (4.0 * zz - xx - yy));
+            Y[12] = (float)((double)SH_C3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+            Y[13] = (float)(-(double)SH_C3c * x * (4.0 * zz - xx - yy));
+            Y[14] = (float)((double)SH_C3e * z * (xx - yy));
+            Y[15] = (float)(-(double)SH_C3a * x * (xx - 3.0 * yy));
         }
     }
+}
+
+// The unit direction from the camera centre C = -R^T t to the mean (FP64) and
+// the colour basis there; also the direction and 1/distance in FP32 for the
+// adjoint of the direction.
+template <int DEG>
+__device__ __forceinline__ void view_basis(const gs_camera& c, const float mu[3], float* Y,
+                                           float dir[3], float& idist) {
+    const double cx = -((double)c.R[0] * c.t[0] + (double)c.R[3] * c.t[1] + (double)c.R[6] * c.t[2]);
+    const double cy = -((double)c.R[1] * c.t[0] + (double)c.R[4] * c.t[1] + (double)c.R[7] * c.t[2]);
+    const double cz = -((double)c.R[2] * c.t[0] + (double)c.R[5] * c.t[1] + (double)c.R[8] * c.t[2]);
+    double dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
+    const double id = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    dx *= id;
+    dy *= id;
+    dz *= id;
+    sh_eval<DEG>(dx, dy, dz, Y);
+    dir[0] = (float)dx;
+    dir[1] = (float)dy;
+    dir[2] = (float)dz;
+    idist = (float)id;
 }
 
 // Gradient of each polynomial Y_k w.r.t. (x, y, z), contracted with w_k:
@@ -282,23 +307,13 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
-    // every load first, so one memory latency covers the parameters and the
-    // colour coefficients (the scheduler would otherwise sink the colour loads
-    // below the activation arithmetic, serialising two latencies); the colour
-    // coefficients, 192 of the 236 bytes, are read once per pass: non-temporal
-    float f[K][3];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-            f[k][ch] = __builtin_nontemporal_load(a.sh + ((int64_t)k * 3 + ch) * n + i);
     const Raw raw = load_raw(a, i);
-    __builtin_amdgcn_sched_barrier(0);
     float mu[3];
     Activated g;
     activate_light(raw, mu, g);
     activate_rot(raw, g);
 
+    u32 vis = 0;   // views that bin this Gaussian (bit v)
     for (int v = 0; v < a.V; ++v) {
         const gs_camera c = a.cams[v];
         const gs_view_info vi = a.views[v];
@@ -353,30 +368,12 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
                 const u32 tx0 = (u32)x0, tx1 = (u32)x1;
                 const u32 ty0 = (u32)y0, ty1 = (u32)y1;
                 rc = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-                // colour for the direction from the camera centre C = -R^T t
-                const float cx = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
-                const float cy = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
-                const float cz = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
-                float dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
-                const float idist = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-                dx *= idist; dy *= idist; dz *= idist;
-                float Y[16];
-                sh_eval<DEG>(dx, dy, dz, Y);
-                float rgb[3];
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    float acc = 0.5f;
-#pragma unroll
-                    for (int k = 0; k < K; ++k) acc = fmaf(Y[k], f[k][ch], acc);
-                    rgb[ch] = acc > 0.f ? acc : 0.f;
-                }
                 const float uh = (float)u, wh = (float)w;
                 const float ul = (float)(u - (double)uh), wl = (float)(w - (double)wh);
                 const float4 s0 = make_float4(uh, wh, ul, wl);
                 const float4 s1 = make_float4(p.chol[0], p.chol[1], p.chol[2], g.o);
                 a.splat[3 * e + 0] = s0;
                 a.splat[3 * e + 1] = s1;
-                a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
                 if (SIGMA3) {
                     tt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
                 } else {
@@ -391,10 +388,40 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
         a.tiles_touched[e] = tt;
         if (tt) {
             a.rect[e] = rc;
+            vis |= 1u << v;
             // the adjoint of this step accumulates into these
 #pragma unroll
             for (int k = 0; k < 9; ++k) a.splat_grad[9 * e + k] = 0.f;
         }
+    }
+    // colour, for the views that bin the Gaussian: the colour coefficients (192
+    // of the 236 bytes of a Gaussian) are read only by lanes that need them, and
+    // not at all by a wave with no such lane (whole waves of Gaussians outside
+    // every view, when the Gaussians are in spatial order)
+    if (__ballot(vis != 0) == 0) return;
+    float f[K][3];
+    if (vis) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                f[k][ch] = __builtin_nontemporal_load(a.sh + ((int64_t)k * 3 + ch) * n + i);
+    }
+    for (u32 m = vis; m; m &= m - 1) {
+        const int v = __builtin_ctz(m);
+        const gs_camera c = a.cams[v];
+        const int64_t e = (int64_t)v * n + i;
+        float Y[16], dir[3], idist;
+        view_basis<DEG>(c, mu, Y, dir, idist);
+        float rgb[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc = fmaf(Y[k], f[k][ch], acc);
+            rgb[ch] = acc > 0.f ? acc : 0.f;
+        }
+        a.splat[3 * e + 2] = make_float4(rgb[0], rgb[1], rgb[2], 0.f);
     }
 }
 
@@ -418,10 +445,28 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
-    // Every lane takes the same path (a Gaussian no view rendered just gets
-    // zeros): with visibility scattered over the index order every 128-byte
-    // line of the SoA arrays is fetched anyway, and a divergent early exit
-    // would split each store into partial-line writes.
+    // the views that rendered this Gaussian (bit v)
+    u32 rend = 0;
+    for (int v = 0; v < a.V; ++v) rend |= (b.tiles_touched[(int64_t)v * n + i] != 0 ? 1u : 0u) << v;
+    // A wave of Gaussians no view rendered reads nothing more and writes zero
+    // gradients (whole waves of them, when the Gaussians are in spatial order).
+    if (__ballot(rend != 0) == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            __builtin_nontemporal_store(0.f, b.d_means + k * n + i);
+            __builtin_nontemporal_store(0.f, b.d_log_scales + k * n + i);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(0.f, b.d_quats + k * n + i);
+        __builtin_nontemporal_store(0.f, b.d_logits + i);
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) __builtin_nontemporal_store(0.f, b.d_sh + (int64_t)k * n + i);
+        return;
+    }
+    // Otherwise every lane of the wave takes the same path (a Gaussian no view
+    // rendered just gets zeros): when the rendered Gaussians are scattered over
+    // the index order every 128-byte line of the SoA arrays is fetched anyway,
+    // and a divergent early exit would split each store into partial-line writes.
     // every load first, so one memory latency covers the parameters and the
     // colour coefficients (the scheduler would otherwise sink the colour loads
     // below the activation arithmetic, serialising two latencies); the colour
@@ -447,12 +492,14 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
 #pragma unroll
     for (int k = 0; k < K; ++k) dsh[k][0] = dsh[k][1] = dsh[k][2] = 0.f;
     float st_acc = 0.f, st_den = 0.f;
-    // gradient w.r.t. Sigma (symmetric, 6 entries), summed over views
-    float GSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // G R (3x3) and diag(R^T G R) (3) summed over views, G = dL/dSigma; kept
+    // instead of G itself (see the per-view update below)
+    float GRs[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float RGR[3] = {0.f, 0.f, 0.f};
 
     for (int v = 0; v < a.V; ++v) {
         const int64_t e = (int64_t)v * n + i;
-        if (b.tiles_touched[e] == 0) continue;
+        if (!((rend >> v) & 1u)) continue;
         const gs_camera c = a.cams[v];
         const gs_view_info vi = a.views[v];
         ViewProj p;
@@ -473,15 +520,9 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
 
         // colour = max(0, sum_k Y_k f_k + 1/2), direction from the camera centre
         {
-            const float cx = -(c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
-            const float cy = -(c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
-            const float cz = -(c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
-            float dx = mu[0] - cx, dy = mu[1] - cy, dz = mu[2] - cz;
-            const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
-            const float idist = 1.0f / dist;
-            dx *= idist; dy *= idist; dz *= idist;
-            float Y[16];
-            sh_eval<DEG>(dx, dy, dz, Y);
+            float Y[16], dir[3], idist;
+            view_basis<DEG>(c, mu, Y, dir, idist);
+            const float dx = dir[0], dy = dir[1], dz = dir[2];
             float wk[16];
 #pragma unroll
             for (int k = 0; k < K; ++k) wk[k] = 0.f;
@@ -515,23 +556,28 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
         const float S00 = -(P00 * qa + P01 * qb);
         const float S01 = -0.5f * ((P00 * qb + P01 * qc) + (P10 * qa + P11 * qb));
         const float S11 = -(P10 * qb + P11 * qc);
-        // Sigma' = T Sigma T^T + 0.3 I: G_Sigma += T^T S T, G_T = 2 S T Sigma
+        // Sigma' = T Sigma T^T + 0.3 I: G_Sigma = T^T S T, G_T = 2 S T Sigma.
+        // The scale and rotation gradients only need G R and diag(R^T G R),
+        // taken here through the Gaussian's axes projected to the screen,
+        // v_k = T R_k, and u_k = Q v_k:  S v_k = -Q (G_Q u_k), so
+        // G R_k = T^T S v_k and R_k^T G R_k = -u_k . (G_Q u_k).  Neither G nor
+        // S is contracted with an axis directly: G has a null direction (the
+        // ray; T is 2x3), and S = -Q G_Q Q applied to an axis along the long
+        // side of the ellipse (near Q's small eigenvector) cancels by the square
+        // of Sigma's eigenvalue ratio, leaving FP32 rounding far above the result.
         const float* T = p.T;
         {
-            // U = S T (2x3)
-            float U[6];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                U[k] = S00 * T[k] + S01 * T[3 + k];
-                U[3 + k] = S01 * T[k] + S11 * T[3 + k];
+                const float v0 = T[0] * g.R[k] + T[1] * g.R[3 + k] + T[2] * g.R[6 + k];
+                const float v1 = T[3] * g.R[k] + T[4] * g.R[3 + k] + T[5] * g.R[6 + k];
+                const float u0 = qa * v0 + qb * v1, u1 = qb * v0 + qc * v1;
+                const float z0 = ga * u0 + gb * u1, z1 = gb * u0 + gc * u1;
+                RGR[k] -= u0 * z0 + u1 * z1;
+                const float w0 = -(qa * z0 + qb * z1), w1 = -(qb * z0 + qc * z1);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) GRs[3 * r + k] += T[r] * w0 + T[3 + r] * w1;
             }
-            // T^T U (3x3 symmetric)
-            GSig[0] += T[0] * U[0] + T[3] * U[3];
-            GSig[1] += T[0] * U[1] + T[3] * U[4];
-            GSig[2] += T[0] * U[2] + T[3] * U[5];
-            GSig[3] += T[1] * U[1] + T[4] * U[4];
-            GSig[4] += T[1] * U[2] + T[4] * U[5];
-            GSig[5] += T[2] * U[2] + T[5] * U[5];
         }
         float GT[6];
         {
@@ -574,38 +620,39 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
         dmu[2] += W[2] * gt0 + W[5] * gt1 + W[8] * gt2;
     }
 
-    // Sigma = M M^T, M = R diag(s):  G_M = 2 G_Sigma M, then scales and rotation
+    // Sigma = M M^T, M = R diag(s):  G_M = 2 G M, so dL/dR = G_M diag(s) =
+    // 2 (G R) diag(s^2) and dL/dlog s_k = s_k (R^T G_M)_kk = 2 s_k^2 R_k^T G R_k
     {
-        const float G[9] = {GSig[0], GSig[1], GSig[2], GSig[1], GSig[3], GSig[4],
-                            GSig[2], GSig[4], GSig[5]};
         float GR[9];
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            const float s2 = 2.f * g.s[k] * g.s[k];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float Mk0 = g.R[k] * g.s[k];          // M[0][k]
-                const float Mk1 = g.R[3 + k] * g.s[k];      // M[1][k]
-                const float Mk2 = g.R[6 + k] * g.s[k];      // M[2][k]
-                const float GM = 2.f * (G[3 * r] * Mk0 + G[3 * r + 1] * Mk1 + G[3 * r + 2] * Mk2);
-                GR[3 * r + k] = GM * g.s[k];
-                dls[k] += GM * g.R[3 * r + k];              // dL/ds_k, scaled below
-            }
+            for (int r = 0; r < 3; ++r) GR[3 * r + k] = GRs[3 * r + k] * s2;
+            dls[k] = RGR[k] * s2;
+        }
+        // dL/dR -> unit quaternion -> raw quaternion (the tangent projection
+        // (I - q q^T) / |q|), in FP64 from the raw quaternion: the projection
+        // cancels the radial part, which can be most of the unit-quaternion
+        // gradient
+        const double q0 = raw.q[0], q1 = raw.q[1], q2 = raw.q[2], q3 = raw.q[3];
+        const double iq = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        const double w = q0 * iq, x = q1 * iq, y = q2 * iq, z = q3 * iq;
+        double G[9];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) dls[k] *= g.s[k];
-        const float w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
-        const float gw = 2.f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
-        const float gx = 2.f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.f * x * GR[4] - w * GR[5] +
-                                z * GR[6] + w * GR[7] - 2.f * x * GR[8]);
-        const float gy = 2.f * (-2.f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] -
-                                w * GR[6] + z * GR[7] - 2.f * y * GR[8]);
-        const float gz = 2.f * (-2.f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] -
-                                2.f * z * GR[4] + y * GR[5] + x * GR[6] + y * GR[7]);
-        const float dot = w * gw + x * gx + y * gy + z * gz;
-        const float iq = 1.0f / g.qnorm;
-        dq[0] = (gw - w * dot) * iq;
-        dq[1] = (gx - x * dot) * iq;
-        dq[2] = (gy - y * dot) * iq;
-        dq[3] = (gz - z * dot) * iq;
+        for (int k = 0; k < 9; ++k) G[k] = GR[k];
+        const double gw = 2.0 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+        const double gx = 2.0 * (y * G[1] + z * G[2] + y * G[3] - 2.0 * x * G[4] - w * G[5] +
+                                 z * G[6] + w * G[7] - 2.0 * x * G[8]);
+        const double gy = 2.0 * (-2.0 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] -
+                                 w * G[6] + z * G[7] - 2.0 * y * G[8]);
+        const double gz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] -
+                                 2.0 * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
+        const double dot = w * gw + x * gx + y * gy + z * gz;
+        dq[0] = (float)((gw - w * dot) * iq);
+        dq[1] = (float)((gx - x * dot) * iq);
+        dq[2] = (float)((gy - y * dot) * iq);
+        dq[3] = (float)((gz - z * dot) * iq);
     }
 
     // Gradients and colour coefficients stream through once: non-temporal

@@ -226,13 +226,16 @@ gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_hos
 }
 
 gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
-                        int bits, void* scratch, int* slot, hipStream_t s) {
+                        int bits, void* scratch, int* slot, hipStream_t s, bool balanced) {
     const unsigned G = sort_blocks(capacity);
     u32* counts = (u32*)scratch;
     u32* part = counts + 256 * (uint64_t)G;
     int cur = 0;
-    for (int shift = 0; shift < bits; shift += 8) {
-        const int b = (bits - shift) < 8 ? (bits - shift) : 8;
+    // the same number of passes either way; balanced digits split the bits evenly
+    const int passes = (bits + 7) / 8;
+    const int width = balanced ? (bits + passes - 1) / passes : 8;
+    for (int shift = 0; shift < bits; shift += width) {
+        const int b = (bits - shift) < width ? (bits - shift) : width;
         sort_count_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], n_dev, n_host, shift, b, counts);
         GS_TRY(gs_check_launch("sort_count"));
         sort_rowscan_kernel<<<256, GS_BLOCK, 0, s>>>(counts, G, part);

@@ -33,6 +33,8 @@ ATTR_COPY, ATTR_MEAN, ATTR_LOGSCALE, ATTR_ZERO_NEW, ATTR_ZERO, ATTR_SPLIT_COUNT,
 DENSIFY_SPLIT_LARGE, DENSIFY_ADAPTIVE, DENSIFY_SPLIT_ONLY, DENSIFY_CLONE_ONLY = range(4)
 RASTER_COUNT_COMPOSITED = 1
 RASTER_FOOTPRINT_3SIGMA = 2
+RASTER_DEPTH_PRESORT = 4
+RASTER_BALANCED_DIGITS = 8
 
 
 class GsError(RuntimeError):
@@ -94,6 +96,8 @@ _SIGS = {
     "gs_frame_status": [_P, _P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)],
     "gs_project": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts), _P],
     "gs_render": [_P, ctypes.POINTER(RasterOpts), _P, _P],
+    "gs_bin": [_P, ctypes.POINTER(RasterOpts), _P],
+    "gs_composite": [_P, ctypes.POINTER(RasterOpts), _P, _P],
     "gs_render_backward": [_P, ctypes.POINTER(RasterOpts), _P, _P],
     "gs_project_backward": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts),
                             ctypes.POINTER(GaussianGrads), _P, _P, _P],
@@ -106,6 +110,8 @@ _SIGS = {
     "gs_densify_apply": [_P, _P, _I64, _I64, ctypes.POINTER(Attr), _I32, _P, _P, _P, _U64, _U64,
                          _P],
     "gs_split_normals": [_P, _P, _I64, _U64, _U64, _P, _P, _P],
+    "gs_spatial_order_workspace_size": [_I64, ctypes.POINTER(_U64)],
+    "gs_spatial_order": [_P, _I64, _P, _P, _P, _U64, _P],
     "gs_ssim_workspace_size": [_I32, _I32, _I32, ctypes.POINTER(_U64)],
     "gs_ssim_loss_grad": [_P, _P, _I32, _I32, _I32, ctypes.c_float, _P, _P, _P, _U64, _P],
     "gs_adam_step": [ctypes.POINTER(AdamParam), _I32, _I64, _P, _I32, ctypes.c_float,
@@ -201,17 +207,22 @@ def cameras_to_device(cams, device="cuda") -> torch.Tensor:
 
 
 def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0,
-                count_composited=False, footprint_3sigma=False):
+                count_composited=False, footprint_3sigma=False, depth_presort=False,
+                balanced_digits=False):
     """footprint_3sigma: bin by 3-sigma squares as the original 3DGS
     rasterizer does (images then depend on the tile grid) instead of by the
-    opacity-aware ellipse (GS_RASTER_FOOTPRINT_3SIGMA)."""
+    opacity-aware ellipse (GS_RASTER_FOOTPRINT_3SIGMA).  depth_presort: order
+    the visible entries by depth before emission instead of sorting each tile's
+    list (GS_RASTER_DEPTH_PRESORT; same lists, different cost)."""
     o = RasterOpts()
     o.bg[:] = [float(x) for x in bg]
     o.near_plane = float(np.float32(near_plane))
     o.raster_batch = int(raster_batch)
     o.persistent_blocks = int(persistent_blocks)
     o.flags = ((RASTER_COUNT_COMPOSITED if count_composited else 0) |
-               (RASTER_FOOTPRINT_3SIGMA if footprint_3sigma else 0))
+               (RASTER_FOOTPRINT_3SIGMA if footprint_3sigma else 0) |
+               (RASTER_DEPTH_PRESORT if depth_presort else 0) |
+               (RASTER_BALANCED_DIGITS if balanced_digits else 0))
     return o
 
 
@@ -289,6 +300,24 @@ class Frame:
             images = torch.empty(self.image_numel(), dtype=torch.float32, device=self.device)
         _check(lib().gs_render(self.handle, ctypes.byref(opts), _ptr(images), _stream(stream)))
         return images
+
+    def bin(self, opts, stream=None):
+        _check(lib().gs_bin(self.handle, ctypes.byref(opts), _stream(stream)))
+
+    def composite(self, opts, images=None, stream=None):
+        if images is None:
+            images = torch.empty(self.image_numel(), dtype=torch.float32, device=self.device)
+        _check(lib().gs_composite(self.handle, ctypes.byref(opts), _ptr(images), _stream(stream)))
+        return images
+
+    def overflowed(self, clear=False):
+        """Whether any binning of this frame overflowed its instance capacity
+        since the flag was last cleared (reads a device word: synchronises)."""
+        c = self.buffer(BUF_COUNTERS)
+        flag = int(c[6].item())
+        if clear:
+            c[6:7].zero_()
+        return flag != 0
 
     def render_backward(self, opts, dL_dimages, stream=None):
         _check(lib().gs_render_backward(self.handle, ctypes.byref(opts), _ptr(dL_dimages),
@@ -402,6 +431,29 @@ def densify_apply(src, kind, n_in, attrs, parent_means, parent_log_scales, paren
     return outs
 
 
+def spatial_order(means, stream=None):
+    """(src, kind): the Morton-order permutation of the Gaussians as a map for
+    densify_apply (every row KEEP)."""
+    n = means.shape[-1]
+    nb = ctypes.c_uint64()
+    _check(lib().gs_spatial_order_workspace_size(n, ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=means.device)
+    src = torch.empty(max(n, 1), dtype=torch.int32, device=means.device)
+    kind = torch.empty(max(n, 1), dtype=torch.uint8, device=means.device)
+    _check(lib().gs_spatial_order(_ptr(means), n, _ptr(src), _ptr(kind), _ptr(ws), int(nb.value),
+                                  _stream(stream)))
+    return src[:n], kind[:n]
+
+
+def reorder(tensors, src, kind, stream=None):
+    """Apply a spatial order (or any all-KEEP map) to [rows, n] / [n] tensors:
+    one gather launch for all of them.  Returns the new tensors."""
+    n = src.numel()
+    attrs = [(t.reshape(-1, n), t.numel() // n, ATTR_COPY) for t in tensors]
+    outs = densify_apply(src, kind, n, attrs, None, None, None, 0, 0, stream=stream)
+    return [o.view(t.shape) for o, t in zip(outs, tensors)]
+
+
 def split_normals(parents, children, seed, step, stream=None):
     m = parents.numel()
     words = torch.empty((m, 4), dtype=torch.int32, device=parents.device)
@@ -423,6 +475,12 @@ def adaptive_prune_threshold(logits, p=0.03, tau_u=0.05, stream=None):
     _check(lib().gs_adaptive_prune_threshold(_ptr(logits), n, k, upper, _ptr(thr), _ptr(ws),
                                              int(nb.value), _stream(stream)))
     return thr, k
+
+
+def ssim_workspace_bytes(channels, height, width):
+    nb = ctypes.c_uint64()
+    _check(lib().gs_ssim_workspace_size(int(channels), int(height), int(width), ctypes.byref(nb)))
+    return int(nb.value)
 
 
 def ssim_loss_grad(image, target, lam=0.2, loss=None, grad=None, workspace=None, stream=None):

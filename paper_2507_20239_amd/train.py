@@ -35,7 +35,8 @@ LINEAGE_POLICY = {"origin": gsmi.ATTR_COPY, "splits": gsmi.ATTR_SPLIT_COUNT,
 class Trainer:
     def __init__(self, params: dict, sh_degree: int, cameras, targets, policy, extent: float,
                  lrs=None, lam: float = 0.2, seed: int = 0, device="cuda", capacity=None,
-                 lineage: bool = False, footprint_3sigma: bool = False):
+                 lineage: bool = False, footprint_3sigma: bool = False,
+                 spatial_order: bool = True):
         self.dev = torch.device(device)
         self.p = {k: params[k].to(self.dev).contiguous().clone() for k in PARAMS}
         self.sh_degree = sh_degree
@@ -51,6 +52,10 @@ class Trainer:
         self.seed = seed
         self.capacity = capacity
         self.opts = gsmi.raster_opts(footprint_3sigma=footprint_3sigma)
+        # keep the Gaussians in spatial (Morton) order after every densification:
+        # the projection, its adjoint and sparse Adam then skip whole waves of
+        # Gaussians the view does not render
+        self.spatial_order = spatial_order
         self._reset_state()
         # original position [3][n], split count [1][n], clone count [1][n] (FP32)
         self.lineage = None
@@ -159,6 +164,15 @@ class Trainer:
                 self.lineage[k] = o.contiguous()
             else:
                 getattr(self, st)[k] = o.reshape(*shapes[k], n_out).contiguous()
+        if self.spatial_order:
+            osrc, okind = gsmi.spatial_order(self.p["means"])
+            keys = [(st, k) for st in ("p", "m", "v") for k in PARAMS]
+            tensors = [getattr(self, st)[k] for st, k in keys]
+            if self.lineage is not None:
+                keys += [("lineage", k) for k in LINEAGE_POLICY]
+                tensors += [self.lineage[k] for k in LINEAGE_POLICY]
+            for (st, k), o in zip(keys, gsmi.reorder(tensors, osrc, okind)):
+                (self.lineage if st == "lineage" else getattr(self, st))[k] = o.contiguous()
         self.accum = torch.zeros(n_out, device=self.dev)
         self.denom = torch.zeros(n_out, device=self.dev)
         self.grads = {k: torch.empty_like(v) for k, v in self.p.items()}

@@ -38,8 +38,8 @@ def test_frame_workspace_size_and_validation():
     P = ctypes.c_void_p
     assert L.gs_frame_workspace_size(1_000_000, 1, W.ctypes.data_as(P), H.ctypes.data_as(P),
                                      1 << 24, ctypes.byref(nb)) == gsmi.GS_OK
-    # 108 B per entry + 16 B per instance + 12 B per pixel, plus small tables
-    base = 108e6 + 16 * (1 << 24) + 12 * 1_664_000
+    # 120 B per entry + 16 B per instance + 12 B per pixel, plus small tables
+    base = 120e6 + 16 * (1 << 24) + 12 * 1_664_000
     assert base < nb.value < base + 4e6
     assert L.gs_frame_workspace_size(-1, 1, W.ctypes.data_as(P), H.ctypes.data_as(P), 10,
                                      ctypes.byref(nb)) == gsmi.GS_ERR_INVALID

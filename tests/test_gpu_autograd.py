@@ -14,7 +14,7 @@ import torch
 import oracle
 from paper_2507_20239_amd import gsmi, synth
 from paper_2507_20239_amd.autograd import GaussianRasterizer
-from parity_util import MARGIN, assert_close_scaled, dev, raw_grad_scale
+from parity_util import MARGIN, _report, assert_close_scaled, dev, raw_grad_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -306,28 +306,39 @@ class FiniteDifferences:
 
 
 GROUPS = ((0, 3), (3, 6), (6, 10), (10, 11), (11, 59))
+FD_RTOL = 1e-4
 
 
-def check_fd(gg, fdiff, gid):
-    """GPU gradient (FP32) against central differences, per parameter group:
-    within 1e-3 of the group's largest derivative plus 1e-3 relative.  A
-    component that fails is differenced again with a 4x larger step: if the
-    two differences disagree the loss is not smooth there (the depth key is
-    the FP32 rounding of the depth, a step function, so moving a mean can swap
-    two splats of equal key) and the component is counted as skipped.
-    Returns the number skipped."""
+def check_fd(gg, want, fdiff, gid):
+    """GPU gradient (FP32) against central differences of the FP64 oracle, per
+    parameter group: within 1e-4 of the group's largest derivative plus 1e-4
+    relative.  Where a component misses that bar and the oracle's own analytic
+    gradient (FP64) misses it too, the differences are what is off: the loss is
+    not smooth within the step there (the depth key is the FP32 rounding of
+    the depth, a step function, so moving a mean can swap two splats of equal
+    key; a pixel's alpha can cross the 1/255 cut-off).  Such a component
+    counts as FD-limited if the GPU still agrees with the analytic gradient
+    to 1e-4 of the group scale.  Returns (number FD-limited, largest GPU-vs-FD
+    ratio per group)."""
     fd = np.array([fdiff(k) for k in range(gg.size)])
-    skipped = 0
+    limited = 0
+    ratios = []
     for a, b in GROUPS:
         big = np.abs(fd[a:b]).max()
+        r = float(np.abs(gg[a:b] - fd[a:b]).max() / big) if big > 0 else 0.0
+        ra = float(np.abs(want[a:b] - fd[a:b]).max() / big) if big > 0 else 0.0
+        _report("FD group %d..%d of Gaussian %d" % (a, b, gid), n=b - a, group_ratio=r,
+                oracle_group_ratio=ra)
+        ratios.append(r)
         for k in range(a, b):
-            tol = 1e-3 * big + 1e-3 * abs(fd[k]) + 1e-11
+            tol = FD_RTOL * big + FD_RTOL * abs(fd[k]) + 1e-11
             if abs(gg[k] - fd[k]) <= tol:
                 continue
-            fd4 = fdiff(k, rel_step=4e-6)
-            assert abs(fd4 - fd[k]) > 1e-2 * (abs(fd[k]) + big), (gid, k, gg[k], fd[k], fd4)
-            skipped += 1
-    return skipped
+            assert abs(want[k] - fd[k]) > tol, (gid, k, gg[k], want[k], fd[k])
+            assert abs(gg[k] - want[k]) <= FD_RTOL * max(big, abs(want[k])) + 1e-11, \
+                (gid, k, gg[k], want[k], fd[k])
+            limited += 1
+    return limited, ratios
 
 
 @pytest.fixture(scope="module")
@@ -356,24 +367,38 @@ def slice_grads(scene_6m_1920x1080, tmp_path_factory):
     return slice_ids, Ws, support, got
 
 
-def test_6m_slice_gradients_match_oracle_adjoint(scene_6m_1920x1080, slice_grads):
+@pytest.fixture(scope="module")
+def slice_oracle(scene_6m_1920x1080, slice_grads):
     sc, cams, projs = scene_6m_1920x1080
-    slice_ids, Ws, support, got = slice_grads
-    want, scale = oracle_slice_grads(sc, cams, projs, Ws, support, slice_ids)
+    slice_ids, Ws, support, _ = slice_grads
+    return oracle_slice_grads(sc, cams, projs, Ws, support, slice_ids)
+
+
+def test_6m_slice_gradients_match_oracle_adjoint(slice_grads, slice_oracle):
+    got = slice_grads[3]
+    want, scale = slice_oracle
     for k in gsmi.PARAM_NAMES:
         assert_close_scaled(got[k], want[k], scale[k], what="6M-Gaussian slice " + k)
 
 
 @pytest.mark.parametrize("part", range(4))
-def test_6m_slice_gradients_match_finite_differences(scene_6m_1920x1080, slice_grads, part):
+def test_6m_slice_gradients_match_finite_differences(scene_6m_1920x1080, slice_grads,
+                                                     slice_oracle, part):
     """Central differences on all 64 Gaussians of the slice (16 per part), all
-    59 raw parameters each."""
+    59 raw parameters each, at 1e-4 of the group scale."""
     sc, cams, projs = scene_6m_1920x1080
     slice_ids, Ws, support, got = slice_grads
-    skipped = 0
+    want = slice_oracle[0]
+    limited = 0
+    worst = np.zeros(len(GROUPS))
     for j in range(16 * part, 16 * part + 16):
         gid = slice_ids[j]
         fdiff = FiniteDifferences(sc, cams, projs, Ws, support, gid)
         gg = np.concatenate([got[k][..., j].reshape(-1) for k in gsmi.PARAM_NAMES])
-        skipped += check_fd(gg, fdiff, gid)
-    assert skipped <= 0.02 * 16 * 59
+        ww = np.concatenate([want[k][..., j].reshape(-1) for k in gsmi.PARAM_NAMES])
+        n_lim, ratios = check_fd(gg, ww, fdiff, gid)
+        limited += n_lim
+        worst = np.maximum(worst, ratios)
+    print("FD part %d: largest GPU-vs-FD ratio per group %s, FD-limited components %d"
+          % (part, np.array2string(worst, precision=2), limited), flush=True)
+    assert limited <= 0.02 * 16 * 59

@@ -107,7 +107,10 @@ def test_1m_1600x1040_backward_from_sampled_pixels(view_1m_1600x1040):
     # chain rule (FP64) of the oracle's splat gradients, over every Gaussian
     # whose binning is not within rounding distance of a tile decision
     racc, rden = np.zeros(sc.n), np.zeros(sc.n)
-    gref = oracle.project_backward(sc, cam, p["visible"], gproj, stats=(racc, rden))
+    # rendered = binned to a tile (a thin ellipse at the border can have a non-empty
+    # footprint rectangle and no tile)
+    rend_o = (p["tiles_touched"] > 0).astype(np.int32)
+    gref = oracle.project_backward(sc, cam, rend_o, gproj, stats=(racc, rden))
     scales = raw_grad_scale(sc, cam, p, gabs)
     ok = p["flags"] == 0
     assert ok.mean() > 0.99
@@ -164,8 +167,8 @@ def test_batched_8_views_500k_sampled(batch, persistent):
         gproj, gabs = oracle.render_backward_pixels(p, pb, g.astype(np.float64))
         assert np.all(gabs[~tt[v]] == 0)
         assert_close_scaled(sg[v][tt[v]], gproj[tt[v]], gabs[tt[v]], what="view %d grads" % v)
-        gref = oracle.project_backward(sc, cams[v], p["visible"], gproj, grads=gref,
-                                       stats=(racc, rden))
+        gref = oracle.project_backward(sc, cams[v], (p["tiles_touched"] > 0).astype(np.int32),
+                                       gproj, grads=gref, stats=(racc, rden))
         gn += np.hypot(gabs[:, 0] * cams[v].width / 2, gabs[:, 1] * cams[v].height / 2)
         sv = raw_grad_scale(sc, cams[v], p, gabs)
         scales = sv if scales is None else {k: scales[k] + sv[k] for k in sv}

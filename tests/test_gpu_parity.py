@@ -72,11 +72,14 @@ def test_project_matches_oracle(name):
     np.testing.assert_allclose(sp[m, 8:11], p["rgb"][m], rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("presort", [False, True])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_binning_lists_match_oracle_exactly(name):
+def test_binning_lists_match_oracle_exactly(name, presort):
     sc = SCENES[name]
     cam = sc.cameras[0]
-    frame, *_ = gpu_forward(sc, [cam])
+    opts = gsmi.raster_opts(bg=tuple(float(x) for x in sc.bg), count_composited=True,
+                            depth_presort=presort)
+    frame, *_ = gpu_forward(sc, [cam], opts)
     p = oracle.project(sc, cam)
     tiles, gids, ranges = oracle.tile_lists(p)
     nv, ni, ovf = frame.status()
@@ -401,3 +404,78 @@ def test_persistent_backward_after_plain_render_is_rejected_on_the_host():
     tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).view(-1) > 0
     ga, gb = a.view(-1, 9)[tt], b.view(-1, 9)[tt]
     assert torch.allclose(ga, gb, rtol=1e-4, atol=1e-6 * float(ga.abs().max()))
+
+
+def test_bin_then_composite_is_render():
+    """gs_bin followed by gs_composite gives gs_render's image and per-pixel
+    state bit for bit (plain and persistent); a persistent composite after a
+    plain binning is refused on the host."""
+    sc = SCENES["ragged_300_37x29_sh3"]
+    cam = sc.cameras[0]
+    for pb in (0, 5):
+        o = gsmi.raster_opts(bg=tuple(sc.bg), persistent_blocks=pb, count_composited=True)
+        frame, a, params, cams_dev, _ = gpu_forward(sc, [cam], o)
+        bufs = [frame.buffer(b).clone() for b in (gsmi.BUF_T_FINAL, gsmi.BUF_N_CONTRIB,
+                                                  gsmi.BUF_N_COMPOSITED)]
+        a = a.clone()
+        frame.project(params, sc.sh_degree, cams_dev, o)
+        frame.bin(o)
+        b = frame.composite(o)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        for x, b2 in zip(bufs, (gsmi.BUF_T_FINAL, gsmi.BUF_N_CONTRIB, gsmi.BUF_N_COMPOSITED)):
+            assert torch.equal(x, frame.buffer(b2))
+    plain = gsmi.raster_opts(bg=tuple(sc.bg))
+    frame.bin(plain)
+    with pytest.raises(gsmi.GsError, match="heavy-first"):
+        frame.composite(gsmi.raster_opts(bg=tuple(sc.bg), persistent_blocks=5))
+
+
+def test_sticky_overflow_flag():
+    """The sticky flag records an overflowing binning until the caller clears
+    it, while the per-render flag follows the last binning."""
+    sc = SCENES["sh1_500_70x45"]
+    cam = sc.cameras[0]
+    o = gsmi.raster_opts(bg=tuple(sc.bg))
+    frame, _, params, cams_dev, _ = gpu_forward(sc, [cam], o, cap=1 << 20)
+    assert not frame.overflowed()
+    small = gsmi.Frame(sc.n, [(cam.width, cam.height)], 64, dev())
+    small.project(params, sc.sh_degree, cams_dev, o)
+    small.render(o)
+    assert small.status(raise_on_overflow=False)[2] == 1
+    assert small.overflowed()
+    assert small.overflowed(clear=True) and not small.overflowed()
+    # the flag stays clear across renders that fit
+    empty = synth.random_scene(3, 4, cam.width, cam.height, sh_degree=1)
+    small2 = gsmi.Frame(empty.n, [(cam.width, cam.height)], 64, dev())
+    small2.project(params_of(empty), empty.sh_degree, cams_dev, o)
+    small2.render(o)
+    assert not small2.overflowed()
+
+
+@pytest.mark.parametrize("name", ["sh1_500_70x45", "long_lists_3000_96x64"])
+def test_depth_presort_gives_the_same_lists_images_and_gradients(name):
+    """Ordering the visible entries by depth before emission (the presort
+    path) leaves the per-tile lists, images, per-pixel state and splat
+    gradients bit-identical to sorting each tile's list afterwards."""
+    sc = SCENES[name] if name in SCENES else synth.random_scene(9, 3000, 96, 64, sh_degree=1,
+                                                                 log_scale=(-1.8, 0.4))
+    cam = sc.cameras[0]
+    out = []
+    for presort in (False, True):
+        o = gsmi.raster_opts(bg=tuple(sc.bg), count_composited=True, depth_presort=presort)
+        frame, img, *_ = gpu_forward(sc, [cam], o)
+        nv, ni, ovf = frame.status()
+        dL = torch.linspace(-1e-3, 1e-3, img.numel(), device=img.device)
+        frame.render_backward(o, dL)
+        torch.cuda.synchronize()
+        bufs = [frame.buffer(b).clone() for b in (gsmi.BUF_RANGES, gsmi.BUF_T_FINAL,
+                                                  gsmi.BUF_N_CONTRIB, gsmi.BUF_N_COMPOSITED)]
+        lists = [frame.buffer(b)[:ni].clone() for b in (gsmi.BUF_INST_TILE, gsmi.BUF_INST_ENTRY)]
+        out.append([img.clone()] + bufs + lists +
+                   [frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).clone()])
+    for a, b in zip(out[0][:-1], out[1][:-1]):
+        assert torch.equal(a, b)
+    # the splat gradients are sums of hardware atomics (order not fixed)
+    ga, gb = out[0][-1], out[1][-1]
+    assert torch.allclose(ga, gb, rtol=1e-5, atol=1e-6 * float(ga.abs().max()))

@@ -722,3 +722,23 @@ def test_adjoint_sums_do_not_depend_on_the_thread_count():
     oracle.set_threads(os.cpu_count() or 1)
     for a, b in zip(out[0], out[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_spatial_order_codes_and_permutation():
+    """Morton codes by hand (unit steps along each axis, the corners of the
+    grid) and the order they give: a tiny point set whose Z-order is known,
+    a non-finite mean last, equal cells by index."""
+    assert oracle.morton_code(0, 0, 0) == 0
+    assert oracle.morton_code(1, 0, 0) == 1 and oracle.morton_code(0, 1, 0) == 2
+    assert oracle.morton_code(0, 0, 1) == 4 and oracle.morton_code(1, 1, 1) == 7
+    assert oracle.morton_code(2, 0, 0) == 8 and oracle.morton_code(0, 0, 2) == 32
+    assert oracle.morton_code(1023, 1023, 1023) == (1 << 30) - 1
+    # cube [0, 4]^3: cell width 4/1024; points placed in known cells
+    pts = np.array([[4.0, 0.0, 0.0, 0.0, 0.0, 0.005, np.nan, 0.005],
+                    [4.0, 0.0, 0.0, 0.005, 0.0, 0.0, 0.0, 0.0],
+                    [4.0, 0.0, 0.005, 0.0, 0.0, 0.0, 0.0, 0.0]], np.float32)
+    src, codes = oracle.spatial_order(pts)
+    # cells: p0 (1023, 1023, 1023), p1 (0,0,0), p2 (0,0,1), p3 (0,1,0), p4 (0,0,0),
+    # p5 (1,0,0), p6 non-finite, p7 (1,0,0)
+    assert codes.tolist() == [(1 << 30) - 1, 0, 4, 2, 0, 1, 0x3FFFFFFF, 1]
+    assert src.tolist() == [1, 4, 5, 7, 3, 2, 0, 6]
