@@ -93,11 +93,15 @@ def parse():
                     help="skip the loss, Adam, densification and 6M training timings")
     ap.add_argument("--c5-steps", type=int, default=200,
                     help="training steps of the 6M-Gaussian workload (timed: steps 11..)")
-    ap.add_argument("--profile-workload", choices=("batched_8_views", "step_6m_4_views"),
+    ap.add_argument("--profile-workload",
+                    choices=("batched_8_views", "step_6m_4_views", "plain_128x128"),
                     help="for a profiler: time only this workload with the launch shape given by "
-                         "--raster-batch / --persistent and print one JSON line")
+                         "--raster-batch / --persistent / --presort / --balanced and print one "
+                         "JSON line")
     ap.add_argument("--raster-batch", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--presort", action="store_true")
+    ap.add_argument("--balanced", action="store_true")
     return ap.parse_args()
 
 
@@ -259,11 +263,12 @@ def timed(torch, fn, steps, warmup):
 # ---------------------------------------------------------------------------------------
 # GPU legs
 # ---------------------------------------------------------------------------------------
-def metric_leg(torch, gsmi, sc, params, dev, K, W, label):
+def metric_leg(torch, gsmi, sc, params, dev, K, W, label, rendered_only=False):
     """The 1M-Gaussian 1600x1040 step: graph and eager timing, per-stage
     breakdown, the adjoint's roofline, and the HBM-bound stages' algorithmic
-    bytes over their live times."""
-    opts = gsmi.raster_opts()
+    bytes over their live times.  rendered_only: the projection adjoint writes
+    the gradient rows of rendered Gaussians only (what sparse Adam reads)."""
+    opts = gsmi.raster_opts(grad_rendered_only=rendered_only)
     st = Step(sc, sc.cameras, params, opts, 16 << 20, torch, gsmi, dev)
     st.eager()
     nvis, ninst = st.checked()
@@ -619,10 +624,11 @@ def profile_workload(args):
     from paper_2507_20239_amd import gsmi, synth
     dev = torch.device("cuda:0")
     K, W = args.steps, args.warmup
-    shape = {"raster_batch": args.raster_batch, "persistent_blocks": args.persistent}
-    if args.profile_workload == "batched_8_views":
-        sb = synth.batched_c2f()
-        pb = to_dev(sb, dev, torch, gsmi)
+    shape = {"raster_batch": args.raster_batch, "persistent_blocks": args.persistent,
+             "depth_presort": args.presort, "balanced_digits": args.balanced}
+    if args.profile_workload in ("batched_8_views", "plain_128x128"):
+        sb = synth.batched_c2f() if args.profile_workload == "batched_8_views" else synth.tiny_scene()
+        pb, _ = spatially_ordered(torch, gsmi, to_dev(sb, dev, torch, gsmi), reps=1)
         st = Step(sb, sb.cameras, pb, gsmi.raster_opts(**shape), 32 << 20, torch, gsmi, dev)
         st.eager()
         st.checked()
@@ -879,13 +885,20 @@ def main():
     sc = synth.single_view_1m()
     params0 = to_dev(sc, dev, torch, gsmi)
     # the generator's order (uniform random positions: the Gaussians a view renders are
-    # scattered over the index range)
-    leg0, st0 = metric_leg(torch, gsmi, sc, params0, dev, K, W, "generator order")
+    # scattered over the index range); a profiling run times the value's configuration only
+    leg0 = leg1 = {"hbm": []}
+    if not args.profile:
+        leg0, st0 = metric_leg(torch, gsmi, sc, params0, dev, K, W, "generator order")
+        del st0
     # the spatial order the trainer keeps (applied at every densification): the same
     # Gaussians permuted by gs_spatial_order + gs_densify_apply; its cost is reported
     params, reorder = spatially_ordered(torch, gsmi, params0)
-    del st0
-    leg, st = metric_leg(torch, gsmi, sc, params, dev, K, W, "spatial order")
+    if not args.profile:
+        leg1, st1 = metric_leg(torch, gsmi, sc, params, dev, K, W, "spatial order, dense gradients")
+        del st1
+    # the trainer's configuration: spatial order, gradient rows of rendered Gaussians
+    leg, st = metric_leg(torch, gsmi, sc, params, dev, K, W, "spatial order, rendered rows",
+                         rendered_only=True)
     ms, parts, roofline, hbm = leg["ms"], leg["breakdown_ms"], leg["roofline"], leg["hbm"]
     nvis, ninst = leg["visible"], leg["instances"]
     ms_graph, ms_eager = leg["graph_ms"], leg["eager_ms"]
@@ -910,12 +923,15 @@ def main():
                                "fwd+bwd+densify statistic",
                    "launch": "hipGraph" if ms_graph <= ms_eager else "eager",
                    "gaussian_order": "spatial (Morton) order, as the trainer keeps it",
+                   "gradients": "rows of the Gaussians the view rendered (sparse Adam's input; the "
+                                "others are zero and not written)",
                    "gaussians": sc.n, "width": 1600, "height": 1040, "sh_degree": 3,
                    "visible": nvis, "instances": ninst},
         "graph_ms": round(ms_graph, 4), "eager_ms": round(ms_eager, 4),
         "breakdown_ms": {k: round(v, 4) for k, v in parts.items()},
         "roofline": roofline,
         "generator_order": {k: v for k, v in leg0.items() if k not in ("hbm",)},
+        "spatial_order_dense_gradients": {k: v for k, v in leg1.items() if k not in ("hbm",)},
         "spatial_reorder": reorder,
     }
     scenes = {"c2": sc, "c3": None, "c5": None, "c5_cams": None}

@@ -137,6 +137,12 @@ typedef struct {
  * digits and a narrower last one (8 + 5).  Same passes, same result; a tuning
  * knob. */
 #define GS_RASTER_BALANCED_DIGITS 8
+/* gs_raster_opts.flags: gs_project_backward writes the gradient rows of the
+ * Gaussians some view rendered and leaves every other row as it was (their
+ * gradient is zero), for callers whose optimiser reads rendered rows only
+ * (gs_adam_step with the frame's tiles_touched).  Without the flag every row is
+ * written. */
+#define GS_RASTER_GRAD_RENDERED_ONLY 16
 
 /* ------------------------------------------------------------------------ */
 /* Frame: the device state of one rendering step for a fixed set of view     */

@@ -36,7 +36,8 @@ class GaussianRasterizer:
 
     def __init__(self, n, cameras, sh_degree, device="cuda", bg=(0.0, 0.0, 0.0),
                  raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2,
-                 footprint_3sigma=False, autotune=False, lazy_overflow=False):
+                 footprint_3sigma=False, autotune=False, lazy_overflow=False,
+                 depth_presort=False, balanced_digits=False):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.device = torch.device(device)
@@ -46,6 +47,7 @@ class GaussianRasterizer:
         self.lazy_overflow = bool(lazy_overflow)
         self._opt_args = dict(bg=bg, near_plane=near_plane, footprint_3sigma=footprint_3sigma)
         self.opts = gsmi.raster_opts(raster_batch=raster_batch, persistent_blocks=persistent_blocks,
+                                     depth_presort=depth_presort, balanced_digits=balanced_digits,
                                      **self._opt_args)
         self.autotune = bool(autotune)
         self.tuned = None

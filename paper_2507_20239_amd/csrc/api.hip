@@ -139,7 +139,7 @@ gs_status check_opts(const gs_raster_opts* o) {
     if (o->persistent_blocks < 0 || o->persistent_blocks > 65536)
         return gs_fail(GS_ERR_INVALID, "persistent_blocks must be in [0, 65536]");
     if (o->flags & ~(GS_RASTER_COUNT_COMPOSITED | GS_RASTER_FOOTPRINT_3SIGMA | GS_RASTER_DEPTH_PRESORT |
-                     GS_RASTER_BALANCED_DIGITS))
+                     GS_RASTER_BALANCED_DIGITS | GS_RASTER_GRAD_RENDERED_ONLY))
         return gs_fail(GS_ERR_INVALID, "unknown bits in raster flags");
     if (!(o->near_plane > 0.f)) return gs_fail(GS_ERR_INVALID, "near_plane must be > 0");
     return GS_OK;
@@ -336,6 +336,7 @@ gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camer
     if ((accum == nullptr) != (denom == nullptr))
         return gs_fail(GS_ERR_INVALID, "accum and denom must both be set or both be null");
     return gs_launch_project_bwd(f, g, cameras, opts->near_plane, grads, accum, denom,
+                                 (opts->flags & GS_RASTER_GRAD_RENDERED_ONLY) != 0,
                                  (hipStream_t)stream);
 }
 

@@ -530,6 +530,27 @@ struct PresortEpi {
     __device__ void finish(u32) const {}
 };
 
+// First pass of the depth-order offsets scan: gathers the tile counts through
+// the sorted entry list once (a random read per entry) into a contiguous array
+// the second pass reads in order, and sums each partition.
+__global__ void __launch_bounds__(GS_BLOCK) presort_gather_reduce_kernel(const u32* tt,
+                                                                         const u32* sorted,
+                                                                         const u32* n_dev,
+                                                                         u32* tt_sorted, u32* part) {
+    __shared__ u32 lds4[4];
+    u32 beg, end;
+    chunk_of(*n_dev, GS_SCAN_PARTS, blockIdx.x, beg, end);
+    u32 s = 0;
+    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) {
+        const u32 v = tt[sorted[i]];
+        tt_sorted[i] = v;
+        s += v;
+    }
+    u32 total;
+    block_exclusive_scan(s, lds4, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
 // heavy-first order key: longer lists first (lists of 65535 instances or
 // more tie), ties by tile id (stable sort); 16 bits, two radix passes
 constexpr int TILE_WEIGHT_BITS = 16;
@@ -570,11 +591,15 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first, bool preso
             int slot = 0;
             GS_TRY(gs_radix_sort(k, v, cnt + 0, 0, E, 32, f->sort_scratch, &slot, s));
             if (slot != 0) return gs_fail(GS_ERR_HIP, "depth presort ended in the wrong buffer");
+            // the depth keys are consumed: their first buffer holds the gathered counts
             u32* sp = f->scan_part;
-            GS_TRY(gs_scan_reduce(f->tiles_touched, f->visible, cnt + 0, 0, sp, s));
+            u32* tt_sorted = f->dkeys[0];
+            presort_gather_reduce_kernel<<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(
+                f->tiles_touched, f->visible, cnt + 0, tt_sorted, sp);
+            GS_TRY(gs_check_launch("presort_gather"));
             const PresortEpi pe{f->inst_off, f->chunk_start, (u32)f->cap};
             scan_down_kernel<PresortEpi><<<GS_SCAN_PARTS, GS_BLOCK, 0, s>>>(
-                f->tiles_touched, f->visible, cnt + 0, 0, sp, pe);
+                tt_sorted, nullptr, cnt + 0, 0, sp, pe);
             GS_TRY(gs_check_launch("presort_offsets"));
         }
         if (f->sigma3)

@@ -291,12 +291,25 @@ __global__ void __launch_bounds__(GS_BLOCK) box_kernel(const float* __restrict__
             hi[a] = max(hi[a], (u32)__shfl_xor((int)hi[a], off, 64));
         }
     }
+    // the workgroup's four waves through LDS, then one atomic per bound and
+    // workgroup (the grid is a few hundred workgroups: six addresses take every
+    // atomic, so their number is what costs)
+    __shared__ u32 s_box[GS_BLOCK / 64][6];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            atomicMin(&box[a], lo[a]);
-            atomicMax(&box[3 + a], hi[a]);
+            s_box[w][a] = lo[a];
+            s_box[w][3 + a] = hi[a];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        u32 v = s_box[0][a];
+        for (int j = 1; j < GS_BLOCK / 64; ++j) v = a < 3 ? min(v, s_box[j][a]) : max(v, s_box[j][a]);
+        if (a < 3) atomicMin(&box[a], v);
+        else atomicMax(&box[a], v);
     }
 }
 
@@ -643,7 +656,7 @@ gs_status gs_spatial_order(const float* means, int64_t n, int32_t* src, uint8_t*
     box_init_kernel<<<1, 64, 0, s>>>(box);
     GS_TRY(gs_check_launch("spatial_box_init"));
     int64_t blocks = blocks_for(n);
-    box_kernel<<<(unsigned)(blocks > 2048 ? 2048 : blocks), GS_BLOCK, 0, s>>>(means, n, box);
+    box_kernel<<<(unsigned)(blocks > 512 ? 512 : blocks), GS_BLOCK, 0, s>>>(means, n, box);
     GS_TRY(gs_check_launch("spatial_box"));
     morton_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(means, n, box, k0, (u32*)src);
     GS_TRY(gs_check_launch("morton_codes"));

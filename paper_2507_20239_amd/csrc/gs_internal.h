@@ -234,7 +234,7 @@ gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float
                                hipStream_t s);
 gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                                 float near_plane, const gs_gaussian_grads* gr, float* accum,
-                                float* denom, hipStream_t s);
+                                float* denom, bool rendered_only, hipStream_t s);
 
 // ------------------------------------------------------------------------
 // Device helpers

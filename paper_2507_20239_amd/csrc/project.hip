@@ -436,6 +436,7 @@ struct ProjBwdArgs {
     float* d_sh;
     float* accum;
     float* denom;
+    int rendered_only;     // rows of Gaussians no view rendered are not written
 };
 
 template <int DEG>
@@ -449,8 +450,10 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     u32 rend = 0;
     for (int v = 0; v < a.V; ++v) rend |= (b.tiles_touched[(int64_t)v * n + i] != 0 ? 1u : 0u) << v;
     // A wave of Gaussians no view rendered reads nothing more and writes zero
-    // gradients (whole waves of them, when the Gaussians are in spatial order).
+    // gradients, or nothing when only rendered rows are wanted (whole waves of
+    // them, when the Gaussians are in spatial order).
     if (__ballot(rend != 0) == 0) {
+        if (b.rendered_only) return;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             __builtin_nontemporal_store(0.f, b.d_means + k * n + i);
@@ -722,7 +725,7 @@ gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera*
 
 gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                                 float near_plane, const gs_gaussian_grads* gr, float* accum,
-                                float* denom, hipStream_t s) {
+                                float* denom, bool rendered_only, hipStream_t s) {
     if (f->n == 0) return GS_OK;
     ProjBwdArgs b;
     b.p = make_args(f, g, cams, near_plane);
@@ -735,6 +738,7 @@ gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_cam
     b.d_sh = gr->sh;
     b.accum = accum;
     b.denom = denom;
+    b.rendered_only = rendered_only ? 1 : 0;
     const unsigned blocks = (unsigned)((f->n + GS_BLOCK - 1) / GS_BLOCK);
     switch (g->sh_degree) {
         case 0: project_bwd_kernel<0><<<blocks, GS_BLOCK, 0, s>>>(b); break;

@@ -35,6 +35,7 @@ RASTER_COUNT_COMPOSITED = 1
 RASTER_FOOTPRINT_3SIGMA = 2
 RASTER_DEPTH_PRESORT = 4
 RASTER_BALANCED_DIGITS = 8
+RASTER_GRAD_RENDERED_ONLY = 16
 
 
 class GsError(RuntimeError):
@@ -208,7 +209,7 @@ def cameras_to_device(cams, device="cuda") -> torch.Tensor:
 
 def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0,
                 count_composited=False, footprint_3sigma=False, depth_presort=False,
-                balanced_digits=False):
+                balanced_digits=False, grad_rendered_only=False):
     """footprint_3sigma: bin by 3-sigma squares as the original 3DGS
     rasterizer does (images then depend on the tile grid) instead of by the
     opacity-aware ellipse (GS_RASTER_FOOTPRINT_3SIGMA).  depth_presort: order
@@ -222,7 +223,8 @@ def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_b
     o.flags = ((RASTER_COUNT_COMPOSITED if count_composited else 0) |
                (RASTER_FOOTPRINT_3SIGMA if footprint_3sigma else 0) |
                (RASTER_DEPTH_PRESORT if depth_presort else 0) |
-               (RASTER_BALANCED_DIGITS if balanced_digits else 0))
+               (RASTER_BALANCED_DIGITS if balanced_digits else 0) |
+               (RASTER_GRAD_RENDERED_ONLY if grad_rendered_only else 0))
     return o
 
 

@@ -51,7 +51,8 @@ class Trainer:
         self.rng = np.random.default_rng(seed)
         self.seed = seed
         self.capacity = capacity
-        self.opts = gsmi.raster_opts(footprint_3sigma=footprint_3sigma)
+        # sparse Adam reads the gradient rows of rendered Gaussians only
+        self.opts = gsmi.raster_opts(footprint_3sigma=footprint_3sigma, grad_rendered_only=True)
         # keep the Gaussians in spatial (Morton) order after every densification:
         # the projection, its adjoint and sparse Adam then skip whole waves of
         # Gaussians the view does not render

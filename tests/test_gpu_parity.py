@@ -72,13 +72,13 @@ def test_project_matches_oracle(name):
     np.testing.assert_allclose(sp[m, 8:11], p["rgb"][m], rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("presort", [False, True])
+@pytest.mark.parametrize("presort,balanced", [(False, False), (True, False), (False, True)])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_binning_lists_match_oracle_exactly(name, presort):
+def test_binning_lists_match_oracle_exactly(name, presort, balanced):
     sc = SCENES[name]
     cam = sc.cameras[0]
     opts = gsmi.raster_opts(bg=tuple(float(x) for x in sc.bg), count_composited=True,
-                            depth_presort=presort)
+                            depth_presort=presort, balanced_digits=balanced)
     frame, *_ = gpu_forward(sc, [cam], opts)
     p = oracle.project(sc, cam)
     tiles, gids, ranges = oracle.tile_lists(p)
@@ -479,3 +479,39 @@ def test_depth_presort_gives_the_same_lists_images_and_gradients(name):
     # the splat gradients are sums of hardware atomics (order not fixed)
     ga, gb = out[0][-1], out[1][-1]
     assert torch.allclose(ga, gb, rtol=1e-5, atol=1e-6 * float(ga.abs().max()))
+
+
+def test_gradients_of_rendered_rows_only():
+    """With GS_RASTER_GRAD_RENDERED_ONLY the projection adjoint writes the rows
+    of rendered Gaussians (bit-identical to the dense call's rows) and leaves
+    the others as they were; waves with no rendered Gaussian are skipped."""
+    sc = synth.random_scene(43, 6000, 96, 64, sh_degree=3, spread=2.5)
+    cam = sc.cameras[0]
+    params = params_of(sc)
+    src, kind = gsmi.spatial_order(params["means"])
+    params = dict(zip(gsmi.PARAM_NAMES, gsmi.reorder([params[k] for k in gsmi.PARAM_NAMES], src,
+                                                     kind)))
+    cams = gsmi.cameras_to_device([cam], dev())
+    dense = gsmi.raster_opts(bg=tuple(sc.bg))
+    sparse = gsmi.raster_opts(bg=tuple(sc.bg), grad_rendered_only=True)
+    frame = gsmi.Frame(sc.n, [(cam.width, cam.height)], 1 << 22, dev())
+    frame.project(params, sc.sh_degree, cams, dense)
+    img = frame.render(dense)
+    frame.render_backward(dense, torch.linspace(-1e-3, 1e-3, img.numel(), device=dev()))
+    out = []
+    for o in (dense, sparse):
+        grads = {k: torch.full_like(v, 7.0) for k, v in params.items()}
+        frame.project_backward(params, sc.sh_degree, cams, o, grads)
+        torch.cuda.synchronize()
+        out.append(grads)
+    rend = frame.buffer(gsmi.BUF_TILES_TOUCHED).view(-1) > 0
+    # waves (64 consecutive Gaussians) with a rendered one are written whole
+    pad = torch.zeros((sc.n + 63) // 64 * 64, dtype=torch.bool, device=dev())
+    pad[: sc.n] = rend
+    written = pad.view(-1, 64).any(1).repeat_interleave(64)[: sc.n]
+    assert (~written).any() and written.any()
+    for k in gsmi.PARAM_NAMES:
+        d, s = out[0][k], out[1][k]
+        assert torch.equal(d[..., written], s[..., written]), k
+        assert bool((s[..., ~written] == 7.0).all()), k
+        assert bool((d[..., ~rend] == 0).all()), k
