@@ -185,6 +185,21 @@ def time_loop(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def paired_loops(torch, fa, fb, steps, warmup, rounds=4):
+    """Two launch forms of one step timed in alternating blocks of `steps`
+    steps (a b b a a b b a ...), each block bracketed by synchronisations, so
+    neither takes the clock ramp or drift of its position; the median block of
+    each."""
+    for _ in range(warmup):
+        fa()
+        fb()
+    ta, tb = [], []
+    for r in range(rounds):
+        for which in ((0, 1) if r % 2 == 0 else (1, 0)):
+            (ta if which == 0 else tb).append(time_loop(torch, (fa, fb)[which], steps, 0))
+    return statistics.median(ta), statistics.median(tb)
+
+
 def median_events(torch, fn, reps, setup=None):
     """Median over reps of fn's duration between two events on the current
     stream (setup, if given, runs before each rep outside the timed pair)."""
@@ -274,8 +289,7 @@ def metric_leg(torch, gsmi, sc, params, dev, K, W, label, rendered_only=False):
     nvis, ninst = st.checked()
     log("%s: visible %d instances %d" % (label, nvis, ninst))
     st.capture()
-    ms_graph = time_loop(torch, st.launch, K, W)
-    ms_eager = time_loop(torch, st.eager, K, W)
+    ms_graph, ms_eager = paired_loops(torch, st.launch, st.eager, K, W)
     st.checked()
     log("%s: 1M-Gaussian 1600x1040 step: graph %.3f ms eager %.3f ms" % (label, ms_graph, ms_eager))
     parts = breakdown(torch, st, max(5, K))
@@ -364,8 +378,7 @@ def plain_128(torch, gsmi, synth, dev, K, W):
     nv, ni = st.checked()
     st.capture()
     reps = max(K, 100)
-    g = time_loop(torch, st.launch, reps, W)
-    e = time_loop(torch, st.eager, reps, W)
+    g, e = paired_loops(torch, st.launch, st.eager, reps, W)
     return {"workload": "single view 128x128, 2,000 Gaussians, SH degree 0, fwd+bwd+statistic",
             "graph_ms": round(g, 4), "eager_ms": round(e, 4), "ms_per_step": round(min(g, e), 4),
             "visible": nv, "instances": ni, "steps": reps}, sc
@@ -383,8 +396,7 @@ def batched_leg(torch, gsmi, synth, dev, K, W):
     bst.eager()
     nv, ni = bst.checked()
     bst.capture()
-    ms_b = time_loop(torch, bst.launch, K, W)
-    ms_b_eager = time_loop(torch, bst.eager, K, W)
+    ms_b, ms_b_eager = paired_loops(torch, bst.launch, bst.eager, K, W)
     bst.checked()
     plain = []
     popts = gsmi.raster_opts()
@@ -406,8 +418,7 @@ def batched_leg(torch, gsmi, synth, dev, K, W):
         for s1 in plain:
             s1.eager()
 
-    ms_p = time_loop(torch, plain_graph, K, W)
-    ms_p_eager = time_loop(torch, plain_eager, K, W)
+    ms_p, ms_p_eager = paired_loops(torch, plain_graph, plain_eager, K, W)
     for s1 in plain:
         s1.checked()
     best_plain = min(ms_p, ms_p_eager)
@@ -529,13 +540,18 @@ def extras(torch, gsmi, synth, st, params, sc, dev, reps=20):
     return out, hbm, d
 
 
-def c5_training(torch, gsmi, synth, dev, steps, first_timed=11):
+def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
     """The large training workload as configured: 6,000,000 Gaussians on
     spheres and planes, SH3, 64 ring cameras at 1920x1080, four random views
     per step through the torch.autograd.Function; targets are renders of the
     unperturbed scene, training starts from a perturbed copy (means +
     N(0, 0.01^2), DC + N(0, 0.1^2)); Eq. 3 loss (lambda 0.2), sparse Adam.
-    Returns mean ms over steps first_timed..steps and the first/last loss."""
+    Run twice from the same start and view sequence: eagerly, and as one
+    captured graph of the whole step (rasterize, loss, backward, Adam)
+    replayed from step warm + 1 on (the rasterizer checks its capacity
+    lazily, takes its cameras from a device table, and Adam counts its steps
+    on the device).  Returns mean ms over steps first_timed..steps and the
+    first/last loss of each."""
     import numpy as np
     from paper_2507_20239_amd.autograd import GaussianRasterizer, photometric_loss
     log("generating the 6M-Gaussian procedural scene (64 cameras, 4 x 1920x1080 per step)")
@@ -547,71 +563,110 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11):
                            lazy_overflow=True)
     table = gsmi.cameras_to_device(cams, dev).view(len(cams), -1)
     log("rendering the 64 target views")
-    targets = []
+    targets = torch.empty(len(cams), 3, 1080, 1920, device=dev)
     with torch.no_grad():
         # the first call autotunes the launch shape and sizes the capacity
         for j in range(0, len(cams), 4):
             r.use_device_cameras(table[j:j + 4].reshape(-1))
-            targets += [im.clone() for im in r(*[P0[k] for k in names])]
+            for i, im in enumerate(r(*[P0[k] for k in names])):
+                targets[j + i].copy_(im)
         assert not r.overflowed()
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(6)
-    P = {k: P0[k].clone() for k in names}
-    P["means"] += 0.01 * torch.randn(P["means"].shape, device=dev, generator=gen)
-    P["sh"][0] += 0.1 * torch.randn(P["sh"][0].shape, device=dev, generator=gen)
-    del P0
-    for t in P.values():
-        t.requires_grad_()
-    mom = {k: (torch.zeros_like(P[k]), torch.zeros_like(P[k])) for k in names}
     extent = 1.1 * 6.0
     lrs = {"means": 1.6e-4 * extent, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2,
            "sh": 2.5e-3}
     rng = np.random.default_rng(7)
-    picks_host = np.stack([rng.choice(len(cams), 4, replace=False) for _ in range(steps)])
-    # camera rows gathered on the device: no host-to-device copy inside the loop
-    picks = torch.from_numpy(picks_host).to(dev)
+    picks = torch.from_numpy(np.stack([rng.choice(len(cams), 4, replace=False)
+                                       for _ in range(steps)])).to(dev)
     nb = gsmi.ssim_workspace_bytes(3, 1080, 1920)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-    losses = torch.zeros(steps, device=dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+    # the step's inputs that change from step to step, at fixed addresses
+    pick = picks[0].clone()
+    cam_static = table.index_select(0, pick).reshape(-1).clone()
+    r.use_device_cameras(cam_static)
 
-    def run():
+    def start():
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(6)
+        P = {k: P0[k].clone() for k in names}
+        P["means"] += 0.01 * torch.randn(P["means"].shape, device=dev, generator=gen)
+        P["sh"][0] += 0.1 * torch.randn(P["sh"][0].shape, device=dev, generator=gen)
+        for t in P.values():
+            t.requires_grad_()
+        mom = {k: (torch.zeros_like(P[k]), torch.zeros_like(P[k])) for k in names}
+        return P, mom, gsmi.adam_counter(dev)
+
+    def step(P, mom, counter):
+        cam_static.copy_(table.index_select(0, pick).reshape(-1))
+        imgs = r(*[P[k] for k in names])
+        tg = targets.index_select(0, pick)
+        loss = sum(photometric_loss(im, tg[i], 0.2, ws) for i, im in enumerate(imgs)) / 4
+        loss.backward()
+        gsmi.adam_step([(P[k].data, P[k].grad, mom[k][0], mom[k][1], lrs[k]) for k in names],
+                       sc.n, counter, tiles_touched=r.frame.buffer(gsmi.BUF_TILES_TOUCHED),
+                       n_views=4)
+        return loss.detach()
+
+    def run(mode):
+        P, mom, counter = start()
+        losses = torch.zeros(steps, device=dev)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        graph = loss_static = None
+        torch.cuda.synchronize()
         for s in range(steps):
+            if mode == "graph" and s == warm:
+                # capture after `warm` eager steps (run on a side stream, as capture wants)
+                torch.cuda.synchronize()
+                for t in P.values():
+                    t.grad = None
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph):
+                    loss_static = step(P, mom, counter)
             ev[s][0].record()
-            r.use_device_cameras(table.index_select(0, picks[s]).reshape(-1))
-            imgs = r(*[P[k] for k in names])
-            loss = sum(photometric_loss(im, targets[int(j)], 0.2, ws)
-                       for im, j in zip(imgs, picks_host[s])) / 4
-            loss.backward()
-            losses[s] = loss.detach()
-            tt = r.frame.buffer(gsmi.BUF_TILES_TOUCHED)
-            gsmi.adam_step([(P[k].data, P[k].grad, mom[k][0], mom[k][1], lrs[k]) for k in names],
-                           sc.n, s + 1, tiles_touched=tt, n_views=4)
-            for t in P.values():
-                t.grad = None
+            pick.copy_(picks[s])
+            if graph is not None:
+                graph.replay()
+                losses[s].copy_(loss_static)
+            else:
+                for t in P.values():
+                    t.grad = None
+                if mode == "graph":
+                    side = torch.cuda.Stream()
+                    side.wait_stream(torch.cuda.current_stream())
+                    with torch.cuda.stream(side):
+                        losses[s] = step(P, mom, counter)
+                    torch.cuda.current_stream().wait_stream(side)
+                else:
+                    losses[s] = step(P, mom, counter)
             ev[s][1].record()
+        torch.cuda.synchronize()
+        if r.overflowed():
+            raise RuntimeError("instance capacity overflowed during the 6M training run (%s)" % mode)
+        if int(counter[0]) != steps:
+            raise RuntimeError("Adam counted %d steps of %d" % (int(counter[0]), steps))
+        ms = [a.elapsed_time(b) for a, b in ev][first_timed - 1:]
+        ls = losses.cpu().numpy()
+        del graph, P, mom
+        return {"mean_ms_per_step": round(float(np.mean(ms)), 4),
+                "median_ms_per_step": round(float(np.median(ms)), 4),
+                "first_loss": round(float(ls[0]), 6), "last_loss": round(float(ls[-1]), 6),
+                "mean_loss_first_10": round(float(ls[:10].mean()), 6),
+                "mean_loss_last_10": round(float(ls[-10:].mean()), 6)}
 
-    run()
-    torch.cuda.synchronize()
-    if r.overflowed():
-        raise RuntimeError("instance capacity overflowed during the 6M training run")
-    ms = [a.elapsed_time(b) for a, b in ev]
-    timed = ms[first_timed - 1:]
-    ls = losses.cpu().numpy()
+    eager = run("eager")
+    log("6M training, eager: %.3f ms/step" % eager["mean_ms_per_step"])
+    captured = run("graph")
+    log("6M training, captured step: %.3f ms/step" % captured["mean_ms_per_step"])
     nv, ni, _ = r.frame.status()
     out = {"workload": "6,000,000 Gaussians (64 spheres, 16 planes), SH3, 64 ring cameras at "
                        "1920x1080, 4 random views per step, autograd fwd+bwd + Eq. 3 loss "
                        "(L1 + 0.2 D-SSIM) + sparse Adam, from a perturbed copy",
-           "steps": steps, "timed_steps": "%d..%d" % (first_timed, steps),
-           "mean_ms_per_step": round(float(np.mean(timed)), 4),
-           "median_ms_per_step": round(float(np.median(timed)), 4),
-           "first_loss": round(float(ls[0]), 6), "last_loss": round(float(ls[-1]), 6),
-           "mean_loss_first_10": round(float(ls[:10].mean()), 6),
-           "mean_loss_last_10": round(float(ls[-10:].mean()), 6),
-           "visible_entries_last_step": nv, "instances_last_step": ni,
-           "capacity": r.frame.cap, "tuned": r.tuned}
-    del r, P, mom, targets
+           "steps": steps, "timed_steps": "%d..%d" % (first_timed, steps)}
+    out.update(eager)
+    out["captured"] = dict(captured, replayed_from_step=warm + 1)
+    out.update({"visible_entries_last_step": nv, "instances_last_step": ni,
+                "capacity": r.frame.cap, "tuned": r.tuned})
+    del r, targets
     torch.cuda.empty_cache()
     return out, sc, cams
 

@@ -436,6 +436,26 @@ gs_status gs_adam_step(const gs_adam_param* params, int32_t n_params, int64_t n,
                        const uint32_t* tiles_touched, int32_t n_views, float beta1, float beta2,
                        float eps, int64_t step, void* stream);
 
+/* The step count of gs_adam_step_counted, kept in device memory (8-byte
+ * aligned, zeroed by the caller before the first call; each call adds one to
+ * step and stores the two bias-correction factors it used). */
+typedef struct {
+    int64_t step;
+    float c1;   /* 1 / (1 - beta1^step), FP64 rounded once */
+    float c2;   /* 1 / (1 - beta2^step) */
+} gs_adam_counter;
+
+/* gs_adam_step with the step count read from and advanced in device memory
+ * instead of passed from the host: the same update as gs_adam_step with step
+ * = counter->step + 1 (bit for bit), so a caller can capture the whole
+ * training step in a graph and replay it step after step (callers whose step
+ * count cannot come from the host: graph capture).  counter: device pointer;
+ * calls that share it must be ordered (one stream).  The counter advances on
+ * every successful call, also when n or n_params is 0. */
+gs_status gs_adam_step_counted(const gs_adam_param* params, int32_t n_params, int64_t n,
+                               const uint32_t* tiles_touched, int32_t n_views, float beta1,
+                               float beta2, float eps, gs_adam_counter* counter, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Primitives exposed for testing                                            */
 /* ------------------------------------------------------------------------ */

@@ -39,12 +39,28 @@ __device__ __forceinline__ void adam_one(bool upd, float g, float& m, float& v, 
     }
 }
 
+// The step count of a counted call: one thread advances the device counter
+// and writes the two bias-correction factors next to it, as the host computes
+// them for an uncounted call (FP64, rounded once).
+__global__ void adam_count_kernel(gs_adam_counter* c, double b1, double b2) {
+    if (threadIdx.x != 0) return;
+    const int64_t t = c->step + 1;
+    c->step = t;
+    c->c1 = (float)(1.0 / (1.0 - pow(b1, (double)t)));
+    c->c2 = (float)(1.0 / (1.0 - pow(b2, (double)t)));
+}
+
 __global__ void __launch_bounds__(GS_BLOCK) adam_kernel(AdamTable t, int64_t n,
                                                         const u32* __restrict__ tiles_touched,
                                                         int n_views, float b1, float b2,
-                                                        float eps, float c1, float c2) {
+                                                        float eps, float c1, float c2,
+                                                        const gs_adam_counter* counter) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= n) return;
+    if (counter) {
+        c1 = counter->c1;
+        c2 = counter->c2;
+    }
     bool upd = true;
     if (tiles_touched) {
         u32 any = 0;
@@ -91,29 +107,62 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + GS_BLOCK - 1) / GS_BLOCK
 
 }  // namespace
 
-extern "C" gs_status gs_adam_step(const gs_adam_param* params, int32_t n_params, int64_t n,
-                                  const uint32_t* tiles_touched, int32_t n_views, float beta1,
-                                  float beta2, float eps, int64_t step, void* stream) {
+namespace {
+
+gs_status adam_launch(const gs_adam_param* params, int32_t n_params, int64_t n,
+                      const uint32_t* tiles_touched, int32_t n_views, float beta1, float beta2,
+                      float eps, int64_t step, gs_adam_counter* counter, hipStream_t s) {
     if (n < 0 || n_params < 0 || n_params > ADAM_MAX_PARAMS)
         return gs_fail(GS_ERR_INVALID, "n_params must be in [0, %d] and n >= 0", ADAM_MAX_PARAMS);
-    if (step < 1) return gs_fail(GS_ERR_INVALID, "step counts from 1");
+    if (!counter && step < 1) return gs_fail(GS_ERR_INVALID, "step counts from 1");
     if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
         return gs_fail(GS_ERR_INVALID, "need 0 <= beta < 1 and eps > 0");
     if (tiles_touched && (n_views < 1 || n_views > GS_MAX_VIEWS))
         return gs_fail(GS_ERR_INVALID, "n_views must be in [1, %d]", GS_MAX_VIEWS);
-    if (n == 0 || n_params == 0) return GS_OK;
-    if (!params) return gs_fail(GS_ERR_INVALID, "params is null");
+    const bool work = n > 0 && n_params > 0;
     AdamTable t;
     t.count = n_params;
-    for (int a = 0; a < n_params; ++a) {
-        const gs_adam_param& q = params[a];
-        if (!q.param || !q.grad || !q.m || !q.v || q.rows <= 0)
-            return gs_fail(GS_ERR_INVALID, "parameter %d: null pointer or rows <= 0", a);
-        t.p[a] = q;
+    if (work) {
+        if (!params) return gs_fail(GS_ERR_INVALID, "params is null");
+        for (int a = 0; a < n_params; ++a) {
+            const gs_adam_param& q = params[a];
+            if (!q.param || !q.grad || !q.m || !q.v || q.rows <= 0)
+                return gs_fail(GS_ERR_INVALID, "parameter %d: null pointer or rows <= 0", a);
+            t.p[a] = q;
+        }
     }
-    const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
-    const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
-    adam_kernel<<<blocks_for(n), GS_BLOCK, 0, (hipStream_t)stream>>>(t, n, tiles_touched, n_views,
-                                                                     beta1, beta2, eps, c1, c2);
+    // a counted call advances its counter even when there is nothing to update,
+    // so the count always equals the number of calls
+    if (counter) {
+        adam_count_kernel<<<1, 64, 0, s>>>(counter, (double)beta1, (double)beta2);
+        GS_TRY(gs_check_launch("adam_count"));
+    }
+    if (!work) return GS_OK;
+    float c1 = 1.f, c2 = 1.f;
+    if (!counter) {
+        c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+        c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+    }
+    adam_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(t, n, tiles_touched, n_views, beta1, beta2, eps,
+                                                   c1, c2, counter);
     return gs_check_launch("adam_step");
+}
+
+}  // namespace
+
+extern "C" gs_status gs_adam_step(const gs_adam_param* params, int32_t n_params, int64_t n,
+                                  const uint32_t* tiles_touched, int32_t n_views, float beta1,
+                                  float beta2, float eps, int64_t step, void* stream) {
+    return adam_launch(params, n_params, n, tiles_touched, n_views, beta1, beta2, eps, step,
+                       nullptr, (hipStream_t)stream);
+}
+
+extern "C" gs_status gs_adam_step_counted(const gs_adam_param* params, int32_t n_params, int64_t n,
+                                          const uint32_t* tiles_touched, int32_t n_views,
+                                          float beta1, float beta2, float eps,
+                                          gs_adam_counter* counter, void* stream) {
+    if (!counter) return gs_fail(GS_ERR_INVALID, "counter is null");
+    if (((uintptr_t)counter & 7) != 0) return gs_fail(GS_ERR_INVALID, "counter must be 8-byte aligned");
+    return adam_launch(params, n_params, n, tiles_touched, n_views, beta1, beta2, eps, 0, counter,
+                       (hipStream_t)stream);
 }

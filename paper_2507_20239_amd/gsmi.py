@@ -117,6 +117,8 @@ _SIGS = {
     "gs_ssim_loss_grad": [_P, _P, _I32, _I32, _I32, ctypes.c_float, _P, _P, _P, _U64, _P],
     "gs_adam_step": [ctypes.POINTER(AdamParam), _I32, _I64, _P, _I32, ctypes.c_float,
                      ctypes.c_float, ctypes.c_float, _I64, _P],
+    "gs_adam_step_counted": [ctypes.POINTER(AdamParam), _I32, _I64, _P, _I32, ctypes.c_float,
+                             ctypes.c_float, ctypes.c_float, _P, _P],
     "gs_radix_select_workspace_size": [_I64, ctypes.POINTER(_U64)],
     "gs_adaptive_prune_threshold": [_P, _I64, _I64, _F, _P, _P, _U64, _P],
     "gs_sort_workspace_size": [_I64, ctypes.POINTER(_U64)],
@@ -501,11 +503,19 @@ def ssim_loss_grad(image, target, lam=0.2, loss=None, grad=None, workspace=None,
     return loss, grad
 
 
+def adam_counter(device):
+    """A zeroed gs_adam_counter on the device (int64 [2]: the step count, then
+    the two FP32 bias-correction factors of the last counted step)."""
+    return torch.zeros(2, dtype=torch.int64, device=device)
+
+
 def adam_step(entries, n, step, tiles_touched=None, n_views=1, beta1=0.9, beta2=0.999, eps=1e-15,
               stream=None):
     """Sparse Adam step.  entries: list of (param, grad, m, v, lr), tensors of
     shape [rows, n] (or [n]); tiles_touched: a frame's BUF_TILES_TOUCHED (only
-    Gaussians rendered in some view are updated) or None (all of them)."""
+    Gaussians rendered in some view are updated) or None (all of them).
+    step: the global step count (from 1), or a device counter of adam_counter,
+    which the call advances on the device (gs_adam_step_counted)."""
     arr = (AdamParam * len(entries))()
     for i, (p, g, m, v, lr) in enumerate(entries):
         rows = p.numel() // n if n else 0
@@ -516,6 +526,13 @@ def adam_step(entries, n, step, tiles_touched=None, n_views=1, beta1=0.9, beta2=
                                                          v.data_ptr())
         arr[i].rows = rows
         arr[i].lr = float(lr)
+    if isinstance(step, torch.Tensor):
+        if step.dtype != torch.int64 or step.numel() != 2 or not step.is_contiguous():
+            raise ValueError("step counter must be adam_counter's int64 [2] tensor")
+        _check(lib().gs_adam_step_counted(arr, len(entries), int(n), _ptr(tiles_touched),
+                                          int(n_views), float(beta1), float(beta2), float(eps),
+                                          _ptr(step), _stream(stream)))
+        return
     _check(lib().gs_adam_step(arr, len(entries), int(n), _ptr(tiles_touched), int(n_views),
                               float(beta1), float(beta2), float(eps), int(step), _stream(stream)))
 

@@ -402,3 +402,96 @@ def test_6m_slice_gradients_match_finite_differences(scene_6m_1920x1080, slice_g
     print("FD part %d: largest GPU-vs-FD ratio per group %s, FD-limited components %d"
           % (part, np.array2string(worst, precision=2), limited), flush=True)
     assert limited <= 0.02 * 16 * 59
+
+
+def test_captured_training_step_replays_match_eager():
+    """The whole training step (rasterize, Eq. 3 loss, backward, sparse Adam)
+    captured once in a graph and replayed step after step with new views: the
+    rasterizer checks its capacity lazily, takes its cameras from a device
+    table row copy, and Adam counts its steps on the device.  Each replay is
+    checked against the same step run eagerly from the same parameters and
+    moments on a second rasterizer: the loss and the gradients (FP32 atomics,
+    so to 1e-5 of their scale), and the new parameters and moments bit for bit
+    against the host-counted Adam applied to the replay's own gradients."""
+    from paper_2507_20239_amd.autograd import photometric_loss
+    sc = synth.random_scene(61, 3000, 96, 80, sh_degree=3, n_views=4, log_scale=(-2.4, 0.5))
+    cams = list(sc.cameras)
+    table = gsmi.cameras_to_device(cams, dev()).view(len(cams), -1)
+    pick = torch.tensor([0, 1], dtype=torch.int64, device=dev())
+    cam_static = table.index_select(0, pick).reshape(-1).clone()
+    r = GaussianRasterizer(sc.n, cams[:2], sc.sh_degree, device=dev(), lazy_overflow=True)
+    r.use_device_cameras(cam_static)
+    g = torch.Generator(device=dev())
+    g.manual_seed(4)
+    targets = torch.rand(len(cams), 3, 80, 96, device=dev(), generator=g)
+    ws = torch.empty(gsmi.ssim_workspace_bytes(3, 80, 96), dtype=torch.uint8, device=dev())
+    names = gsmi.PARAM_NAMES
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    P = _leaf_params(sc)
+    mom = {k: (torch.zeros_like(P[k]), torch.zeros_like(P[k])) for k in names}
+    counter = gsmi.adam_counter(dev())
+
+    def step(rast, params, moments, count, cam_rows):
+        if cam_rows is not None:
+            cam_static.copy_(cam_rows)
+        imgs = rast(*[params[k] for k in names])
+        tg = targets.index_select(0, pick)
+        loss = sum(photometric_loss(im, tg[i], 0.2, ws) for i, im in enumerate(imgs)) / 2
+        loss.backward()
+        gsmi.adam_step([(params[k].data, params[k].grad, moments[k][0], moments[k][1], lrs[k])
+                        for k in names], sc.n, count,
+                       tiles_touched=rast.frame.buffer(gsmi.BUF_TILES_TOUCHED), n_views=2)
+        return loss.detach()
+
+    # warm-up steps on a side stream, then the capture (which runs nothing)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            for t in P.values():
+                t.grad = None
+            step(r, P, mom, counter, table.index_select(0, pick).reshape(-1))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for t in P.values():
+        t.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        loss_static = step(r, P, mom, counter, table.index_select(0, pick).reshape(-1))
+    assert int(counter[0]) == 3
+
+    r2 = GaussianRasterizer(sc.n, cams[:2], sc.sh_degree, device=dev())
+    rng = np.random.default_rng(8)
+    for replay in range(4):
+        pick.copy_(torch.from_numpy(rng.choice(len(cams), 2, replace=False)))
+        before = {k: P[k].detach().clone() for k in names}
+        mom_before = {k: (m.clone(), v.clone()) for k, (m, v) in mom.items()}
+        count_before = int(counter[0])
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(counter[0]) == count_before + 1
+        assert not r.overflowed()
+        # the eager step from the same state, on its own rasterizer
+        P2 = {k: before[k].clone().requires_grad_() for k in names}
+        mom2 = {k: (m.clone(), v.clone()) for k, (m, v) in mom_before.items()}
+        r2.use_device_cameras(table.index_select(0, pick).reshape(-1))
+        loss2 = step(r2, P2, mom2, count_before + 1, None)
+        torch.cuda.synchronize()
+        _close = lambda a, b, what: np.testing.assert_allclose(  # noqa: E731
+            a.detach().cpu().double().numpy(), b.detach().cpu().double().numpy(), rtol=1e-5,
+            atol=1e-5 * max(float(b.detach().abs().max()), 1e-30), err_msg="%s %d" % (what, replay))
+        _close(loss_static, loss2, "loss")
+        for k in names:
+            _close(P[k].grad, P2[k].grad, k)
+        # Adam of the replay's own gradients, counted on the host
+        p3 = {k: before[k].clone() for k in names}
+        m3 = {k: (m.clone(), v.clone()) for k, (m, v) in mom_before.items()}
+        gsmi.adam_step([(p3[k], P[k].grad, m3[k][0], m3[k][1], lrs[k]) for k in names], sc.n,
+                       count_before + 1, tiles_touched=r.frame.buffer(gsmi.BUF_TILES_TOUCHED),
+                       n_views=2)
+        torch.cuda.synchronize()
+        for k in names:
+            assert torch.equal(P[k].detach(), p3[k]), (k, replay)
+            assert torch.equal(mom[k][0], m3[k][0]) and torch.equal(mom[k][1], m3[k][1]), k
+        moved = sum(int((P[k].detach() != before[k]).sum()) for k in names)
+        assert moved > 0, replay

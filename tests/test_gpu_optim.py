@@ -68,3 +68,31 @@ def test_dense_adam_updates_every_gaussian():
     torch.cuda.synchronize()
     # first step: m_hat = g, v_hat = g^2, so p = -lr g / (|g| + eps)
     assert torch.allclose(p, torch.full_like(p, -0.1))
+
+
+def test_counted_adam_equals_host_counted_adam():
+    """gs_adam_step_counted (step count on the device) against gs_adam_step with
+    the same count from the host, bit for bit, over several steps; the counter
+    advances on every call, also one with no Gaussians."""
+    n = 50_001
+    rng = np.random.default_rng(5)
+    p = torch.from_numpy(rng.standard_normal((3, n)).astype(np.float32)).to(dev())
+    a = [p.clone(), torch.zeros_like(p), torch.zeros_like(p)]
+    b = [p.clone(), torch.zeros_like(p), torch.zeros_like(p)]
+    counter = gsmi.adam_counter(dev())
+    tt = torch.from_numpy((rng.random((2, n)) < 0.5).astype(np.int32)).to(dev())
+    for step in range(1, 7):
+        g = torch.from_numpy(rng.standard_normal((3, n)).astype(np.float32)).to(dev())
+        gsmi.adam_step([(a[0], g, a[1], a[2], 1e-2)], n, step, tiles_touched=tt, n_views=2)
+        gsmi.adam_step([(b[0], g, b[1], b[2], 1e-2)], n, counter, tiles_touched=tt, n_views=2)
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert torch.equal(x, y), step
+    assert int(counter[0]) == 6
+    c = counter[1:].view(torch.float32).cpu().numpy()
+    # the FP32 hyper-parameters, widened: what the host path takes the powers of
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    assert c[0] == np.float32(1.0 / (1.0 - b1 ** 6)) and c[1] == np.float32(1.0 / (1.0 - b2 ** 6))
+    gsmi.adam_step([(b[0], g, b[1], b[2], 1e-2)], 0, counter)
+    torch.cuda.synchronize()
+    assert int(counter[0]) == 7
