@@ -559,6 +559,9 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
     cams = synth.procedural_cameras()
     names = gsmi.PARAM_NAMES
     P0 = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(dev) for k in names}
+    # the generator draws each Gaussian's primitive at random; the trainer keeps the
+    # Gaussians in spatial order (gs_spatial_order at every densification)
+    P0, reorder = spatially_ordered(torch, gsmi, P0, reps=1)
     r = GaussianRasterizer(sc.n, cams[:4], sc.sh_degree, device=dev, autotune=True,
                            lazy_overflow=True)
     table = gsmi.cameras_to_device(cams, dev).view(len(cams), -1)
@@ -661,6 +664,8 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
     out = {"workload": "6,000,000 Gaussians (64 spheres, 16 planes), SH3, 64 ring cameras at "
                        "1920x1080, 4 random views per step, autograd fwd+bwd + Eq. 3 loss "
                        "(L1 + 0.2 D-SSIM) + sparse Adam, from a perturbed copy",
+           "gaussian_order": "spatial (Morton) order, as the trainer keeps it",
+           "spatial_reorder": reorder,
            "steps": steps, "timed_steps": "%d..%d" % (first_timed, steps)}
     out.update(eager)
     out["captured"] = dict(captured, replayed_from_step=warm + 1)
@@ -693,8 +698,11 @@ def profile_workload(args):
         from paper_2507_20239_amd.autograd import GaussianRasterizer
         sc = synth.procedural_scene()
         cams = synth.procedural_cameras()[:4]
-        P = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(dev).requires_grad_()
+        P = {k: torch.from_numpy(np.ascontiguousarray(getattr(sc, k))).to(dev)
              for k in gsmi.PARAM_NAMES}
+        P, _ = spatially_ordered(torch, gsmi, P, reps=1)
+        for t in P.values():
+            t.requires_grad_()
         r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev, **shape)
         g = torch.Generator(device=dev)
         g.manual_seed(5)

@@ -237,14 +237,59 @@ struct ViewProj {
     float chol[3];         // Cholesky factor of kappa * conic: l11, l21, l22
 };
 
-__device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_info& vi,
-                                             float near_plane, const float mu[3],
-                                             const Activated& g, ViewProj& p) {
+// Camera-space position; false behind the near plane (or not finite).
+__device__ __forceinline__ bool view_position(const gs_camera& c, float near_plane,
+                                              const float mu[3], ViewProj& p) {
     const double x = mu[0], y = mu[1], z = mu[2];
     p.tx = fma((double)c.R[0], x, fma((double)c.R[1], y, fma((double)c.R[2], z, (double)c.t[0])));
     p.ty = fma((double)c.R[3], x, fma((double)c.R[4], y, fma((double)c.R[5], z, (double)c.t[1])));
     p.tz = fma((double)c.R[6], x, fma((double)c.R[7], y, fma((double)c.R[8], z, (double)c.t[2])));
-    if (!(p.tz > (double)near_plane) || !isfinite(p.tx) || !isfinite(p.ty)) return false;
+    return p.tz > (double)near_plane && isfinite(p.tx) && isfinite(p.ty);
+}
+
+// True only when the footprint box { o G >= 1/255 } of the projection below
+// certainly holds no pixel centre of the view: its half-widths are bounded
+// from above without the screen-space covariance, by
+// Sigma'_xx <= |row 0 of J W|^2 lambda_max(Sigma) + dilation, lambda_max(Sigma)
+// being the largest squared scale.  Evaluated in FP32 with a relative slack of
+// 2^-8, two pixels and 2^-16 of the centre's coordinate, far above the
+// rounding of either path (a NaN or an overflow leaves the Gaussian to the
+// exact path).  Gaussians that are in front of the camera but off screen then
+// skip the FP64 covariance; the outputs do not change, as the exact path
+// finds their box empty too.
+__device__ __forceinline__ bool surely_off_screen(const gs_camera& c, const gs_view_info& vi,
+                                                  const ViewProj& p, const Activated& g) {
+    const float tx = (float)p.tx, ty = (float)p.ty, iz = 1.0f / (float)p.tz;
+    const float limx = GS_FOV_CLAMP * (0.5f * vi.width / c.fx);
+    const float limy = GS_FOV_CLAMP * (0.5f * vi.height / c.fy);
+    const float xr = fminf(fmaxf(tx * iz, -limx), limx);
+    const float yr = fminf(fmaxf(ty * iz, -limy), limy);
+    const float J00 = c.fx * iz, J02 = -c.fx * xr * iz;
+    const float J11 = c.fy * iz, J12 = -c.fy * yr * iz;
+    float n0 = 0.f, n1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float t0 = fmaf(J00, c.R[b], J02 * c.R[6 + b]);
+        const float t1 = fmaf(J11, c.R[3 + b], J12 * c.R[6 + b]);
+        n0 = fmaf(t0, t0, n0);
+        n1 = fmaf(t1, t1, n1);
+    }
+    const float lam = fmaxf(fmaxf(g.s[0] * g.s[0], g.s[1] * g.s[1]), g.s[2] * g.s[2]);
+    const float slack = 1.0f + 1.0f / 256.0f;
+    const float L = 2.0f * logf(255.0f * g.o) * slack;
+    const float k = (float)GS_FOOTPRINT_INFLATE * slack;
+    const float u = fmaf(c.fx, tx * iz, c.cx), w = fmaf(c.fy, ty * iz, c.cy);
+    // (the rounding of u and w grows with their magnitude: 2^-16 of it more)
+    const float ex = sqrtf(L * fmaf(n0 * lam, slack, GS_DILATION)) * k + 2.0f + fabsf(u) * 0x1p-16f;
+    const float ey = sqrtf(L * fmaf(n1 * lam, slack, GS_DILATION)) * k + 2.0f + fabsf(w) * 0x1p-16f;
+    return u + ex < 0.5f || u - ex > (float)vi.width - 0.5f || w + ey < 0.5f ||
+           w - ey > (float)vi.height - 0.5f;
+}
+
+// The rest of the projection of a Gaussian in front of the camera: J, the
+// screen-space covariance, its conic and Cholesky factor.
+__device__ __forceinline__ void view_shape(const gs_camera& c, const gs_view_info& vi,
+                                           const Activated& g, ViewProj& p) {
     p.t[0] = (float)p.tx;
     p.t[1] = (float)p.ty;
     p.t[2] = (float)p.tz;
@@ -298,6 +343,13 @@ __device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_i
     p.chol[0] = (float)l11;
     p.chol[1] = (float)(-kappa * c1 * idet / l11);
     p.chol[2] = (float)sqrt(kappa / c2);
+}
+
+__device__ __forceinline__ bool view_project(const gs_camera& c, const gs_view_info& vi,
+                                             float near_plane, const float mu[3],
+                                             const Activated& g, ViewProj& p) {
+    if (!view_position(c, near_plane, mu, p)) return false;
+    view_shape(c, vi, g, p);
     return true;
 }
 
@@ -319,11 +371,12 @@ __global__ void __launch_bounds__(GS_BLOCK) project_fwd_kernel(ProjArgs a) {
         const gs_view_info vi = a.views[v];
         const int64_t e = (int64_t)v * n + i;
         ViewProj p;
-        const bool ok = view_project(c, vi, a.near_plane, mu, g, p);
+        const bool ok = view_position(c, a.near_plane, mu, p);
         a.depth_key[e] = __float_as_uint((float)p.tz);
         u32 tt = 0;
         uint2 rc = make_uint2(0u, 0u);
-        if (ok && (SIGMA3 || g.o >= GS_ALPHA_MIN)) {
+        if (ok && (SIGMA3 || (g.o >= GS_ALPHA_MIN && !surely_off_screen(c, vi, p, g)))) {
+            view_shape(c, vi, g, p);
             const double u = (double)c.fx * p.tx / p.tz + (double)c.cx;
             const double w = (double)c.fy * p.ty / p.tz + (double)c.cy;
             double x0, x1, y0, y1;   // tile columns and rows, inclusive

@@ -72,6 +72,61 @@ def test_project_matches_oracle(name):
     np.testing.assert_allclose(sp[m, 8:11], p["rgb"][m], rtol=1e-5, atol=1e-6)
 
 
+def _border_scene(seed=31, n=20000, W=96, H=72):
+    """Gaussians whose centres fall around the image border (up to 300 pixels
+    outside it) and far off axis, at depths from just past the near plane,
+    many of them large or elongated and some barely above the opacity cutoff:
+    the cases the projection's off-screen test must leave to the exact path."""
+    rng = np.random.default_rng(seed)
+    base = synth.random_scene(seed, 8, W, H, sh_degree=1)
+    cam = base.cameras[0]
+    side = rng.integers(0, 4, n)
+    d = rng.exponential(40.0, n)
+    along = rng.uniform(-300, 300 + max(W, H), n)
+    u = np.where(side == 0, -d, np.where(side == 1, W + d, along))
+    w = np.where(side == 2, -d, np.where(side == 3, H + d, along))
+    u = np.where(side >= 2, np.clip(u, -300, W + 300), u)
+    w = np.where(side < 2, np.clip(w, -300, H + 300), w)
+    far = rng.random(n) < 0.05   # beyond the field-of-view clamp
+    u[far] *= 40.0
+    z = np.where(rng.random(n) < 0.1, rng.uniform(0.21, 0.5, n), rng.uniform(0.5, 6.0, n))
+    xc = (u - cam.cx) * z / cam.fx
+    yc = (w - cam.cy) * z / cam.fy
+    camp = np.stack([xc, yc, z])
+    means = cam.R.T @ (camp - cam.t[:, None])
+    log_scales = rng.uniform(-5.0, 0.0, (3, n))
+    flat = rng.random(n) < 0.3
+    log_scales[0, flat] -= 4.0
+    logits = np.where(rng.random(n) < 0.2, rng.uniform(-5.6, -5.3, n), rng.normal(0.0, 2.0, n))
+    quats = rng.standard_normal((4, n))
+    sh = rng.normal(0.0, 0.3, (4, 3, n))
+    f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)  # noqa: E731
+    return synth.Scene(f32(means), f32(log_scales), f32(quats), f32(logits), f32(sh), 1, [cam],
+                       [np.zeros((3, H, W), np.float32)], np.zeros(3, np.float32))
+
+
+def test_off_screen_gaussians_project_exactly():
+    """Tile counts, rectangles and depth keys of Gaussians around the image
+    border against the oracle (which has no off-screen shortcut), bit for bit."""
+    sc = _border_scene()
+    cam = sc.cameras[0]
+    frame, *_ = gpu_forward(sc, [cam])
+    p = oracle.project(sc, cam)
+    tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy().view(np.uint32).astype(np.int64)
+    key = frame.buffer(gsmi.BUF_DEPTH_KEY).cpu().numpy().view(np.uint32)
+    rect = frame.buffer(gsmi.BUF_RECT).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    ok = p["flags"] == 0
+    vis = p["tiles_touched"] > 0
+    # most are off screen; a good share reach into the image from outside it
+    assert 0.05 < vis.mean() < 0.7 and ok.mean() > 0.99
+    np.testing.assert_array_equal(key, p["depth_key"])
+    np.testing.assert_array_equal(tt[ok], p["tiles_touched"][ok])
+    gx0, gx1 = rect[:, 0] & 0xFFFF, rect[:, 0] >> 16
+    gy0, gy1 = rect[:, 1] & 0xFFFF, rect[:, 1] >> 16
+    m = ok & vis
+    np.testing.assert_array_equal(np.stack([gx0, gx1, gy0, gy1], 1)[m], p["rect"][m])
+
+
 @pytest.mark.parametrize("presort,balanced", [(False, False), (True, False), (False, True)])
 @pytest.mark.parametrize("name", list(SCENES))
 def test_binning_lists_match_oracle_exactly(name, presort, balanced):
