@@ -55,17 +55,17 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_count_kernel(const u32* __restr
     u32 beg, end;
     chunk_of(dev_len(n_dev, n_host), gridDim.x, blockIdx.x, beg, end);
     const u32 mask = (1u << bits) - 1u;
-    // four keys per thread loaded before their digits are counted, so their
-    // loads are in flight together
-    for (u32 base = beg; base < end; base += 4 * GS_BLOCK) {
-        u32 k[4];
+    // eight keys per thread loaded before their digits are counted, so their
+    // loads are in flight together (the loop is bound by load latency)
+    for (u32 base = beg; base < end; base += 8 * GS_BLOCK) {
+        u32 k[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 8; ++j) {
             const u32 i = base + j * GS_BLOCK + threadIdx.x;
             k[j] = i < end ? keys[i] : 0u;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 8; ++j) {
             const bool valid = base + j * GS_BLOCK + threadIdx.x < end;
             const u32 d = valid ? (k[j] >> shift) & mask : 0u;
             // one LDS add per group of equal digits in the wave
@@ -83,24 +83,24 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_count_kernel(const u32* __restr
 }
 
 // One workgroup per digit: exclusive scan of the digit's row of workgroup
-// counts (counts[d][0..G), G <= 1024, in place) and the digit's total.  The
+// counts (counts[d][0..G), G <= 2048, in place) and the digit's total.  The
 // scatter adds the digit bases (an exclusive scan of the 256 totals, which
 // every scatter workgroup computes for itself), so a pass is three launches.
 __global__ void __launch_bounds__(GS_BLOCK) sort_rowscan_kernel(u32* counts, u32 G, u32* dtot) {
     __shared__ u32 lds4[4];
     u32* row = counts + (u64)blockIdx.x * G;
-    const u32 i0 = threadIdx.x * 4;
-    u32 v[4];
+    const u32 i0 = threadIdx.x * 8;
+    u32 v[8];
     u32 sum = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
         v[j] = i0 + j < G ? row[i0 + j] : 0u;
         sum += v[j];
     }
     u32 total;
     u32 ex = block_exclusive_scan(sum, lds4, total);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
         if (i0 + j < G) row[i0 + j] = ex;
         ex += v[j];
     }
@@ -188,10 +188,15 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
     }
 }
 
+// One workgroup per 4096 slots of capacity, at most 7 per CU (the scatter's
+// LDS allows seven per CU; its loop is bound by load latency, so a full CU
+// hides more of it): 1792 on 256 CUs.
+constexpr int64_t SORT_MAX_BLOCKS = 1792;
+
 unsigned sort_blocks(int64_t capacity) {
     int64_t g = (capacity + 4095) / 4096;
     if (g < 1) g = 1;
-    if (g > 1024) g = 1024;
+    if (g > SORT_MAX_BLOCKS) g = SORT_MAX_BLOCKS;
     return (unsigned)g;
 }
 
