@@ -263,16 +263,35 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
 // and i, or the two ends) closes the previous tile, writes the tiles strictly
 // between the two keys and opens the next.  Keys >= T (never produced) count
 // as T.
+// Four boundaries per thread and pass, their key loads issued together (a
+// pass over tens of millions of keys is otherwise bound by one load latency
+// per boundary).
+constexpr int RANGES_UNROLL = 4;
+
 __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, u32 T) {
     const u32 n = *n_ptr;
-    const u32 stride = gridDim.x * blockDim.x;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
-        const int64_t prev = i == 0 ? -1 : (int64_t)(keys[i - 1] < T ? keys[i - 1] : T);
-        const int64_t cur = i == n ? (int64_t)T : (int64_t)(keys[i] < T ? keys[i] : T);
-        if (cur == prev) continue;
-        if (prev >= 0 && prev < (int64_t)T) ranges[prev].y = i;
-        for (int64_t t = prev + 1; t < cur && t < (int64_t)T; ++t) ranges[t] = make_uint2(i, i);
-        if (cur < (int64_t)T) ranges[cur].x = i;
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 base = (u64)blockIdx.x * blockDim.x + threadIdx.x; base <= n;
+         base += RANGES_UNROLL * stride) {
+        u32 kp[RANGES_UNROLL], kc[RANGES_UNROLL];
+#pragma unroll
+        for (int j = 0; j < RANGES_UNROLL; ++j) {
+            const u64 i = base + j * stride;
+            kp[j] = i >= 1 && i <= n ? keys[i - 1] : 0u;
+            kc[j] = i < n ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < RANGES_UNROLL; ++j) {
+            const u64 iw = base + j * stride;
+            if (iw > n) break;
+            const u32 i = (u32)iw;
+            const int64_t prev = i == 0 ? -1 : (int64_t)(kp[j] < T ? kp[j] : T);
+            const int64_t cur = i == n ? (int64_t)T : (int64_t)(kc[j] < T ? kc[j] : T);
+            if (cur == prev) continue;
+            if (prev >= 0 && prev < (int64_t)T) ranges[prev].y = i;
+            for (int64_t t = prev + 1; t < cur && t < (int64_t)T; ++t) ranges[t] = make_uint2(i, i);
+            if (cur < (int64_t)T) ranges[cur].x = i;
+        }
     }
 }
 
