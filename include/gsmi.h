@@ -143,6 +143,18 @@ typedef struct {
  * (gs_adam_step with the frame's tiles_touched).  Without the flag every row is
  * written. */
 #define GS_RASTER_GRAD_RENDERED_ONLY 16
+/* gs_raster_opts.flags: lane layout of the compositing kernels (Eq. 2 and its
+ * adjoint).  A frame of fewer than 2048 tiles rendered on the plain grid gives
+ * each lane one pixel (four waves per 16x16 tile, each owning an 8x8
+ * quarter): such frames have at most two tiles per SIMD (1024 SIMDs), and one
+ * wave per tile would run each splat step at a single wave's latency.  Larger frames, and every persistent
+ * launch, give each lane a 2x2 quad (one wave per tile).  LANE_PIXELS forces
+ * one pixel per lane (not with persistent_blocks > 0), LANE_QUADS forces
+ * quads; setting both is an error.  Images, transmittance and walk lengths are
+ * bit-identical in both layouts; the adjoint's per-splat sums are added in a
+ * different order. */
+#define GS_RASTER_LANE_PIXELS 32
+#define GS_RASTER_LANE_QUADS 64
 
 /* ------------------------------------------------------------------------ */
 /* Frame: the device state of one rendering step for a fixed set of view     */

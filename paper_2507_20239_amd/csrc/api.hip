@@ -139,8 +139,13 @@ gs_status check_opts(const gs_raster_opts* o) {
     if (o->persistent_blocks < 0 || o->persistent_blocks > 65536)
         return gs_fail(GS_ERR_INVALID, "persistent_blocks must be in [0, 65536]");
     if (o->flags & ~(GS_RASTER_COUNT_COMPOSITED | GS_RASTER_FOOTPRINT_3SIGMA | GS_RASTER_DEPTH_PRESORT |
-                     GS_RASTER_BALANCED_DIGITS | GS_RASTER_GRAD_RENDERED_ONLY))
+                     GS_RASTER_BALANCED_DIGITS | GS_RASTER_GRAD_RENDERED_ONLY |
+                     GS_RASTER_LANE_PIXELS | GS_RASTER_LANE_QUADS))
         return gs_fail(GS_ERR_INVALID, "unknown bits in raster flags");
+    if ((o->flags & GS_RASTER_LANE_PIXELS) && (o->flags & GS_RASTER_LANE_QUADS))
+        return gs_fail(GS_ERR_INVALID, "GS_RASTER_LANE_PIXELS and GS_RASTER_LANE_QUADS exclude each other");
+    if ((o->flags & GS_RASTER_LANE_PIXELS) && o->persistent_blocks > 0)
+        return gs_fail(GS_ERR_INVALID, "one pixel per lane runs on the plain grid (persistent_blocks = 0)");
     if (!(o->near_plane > 0.f)) return gs_fail(GS_ERR_INVALID, "near_plane must be > 0");
     return GS_OK;
 }

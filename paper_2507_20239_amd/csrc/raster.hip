@@ -22,11 +22,21 @@
 // persistent > 0 a fixed grid of waves takes items from an atomic queue in
 // heaviest-list-first order (coarse-to-fine batches mix tiny and full-size
 // views, so the tail is what limits a plain launch).
+//
+// A small frame (a coarse level of the coarse-to-fine schedule, or a tiny
+// view) has at most a couple of tiles per SIMD, and one wave per tile then
+// runs every splat step at a single wave's dependent latency.  Such frames
+// take one pixel per lane instead: four waves per tile, each owning an 8x8
+// quarter and walking the tile's whole list.  Each pixel's arithmetic is the
+// same in both layouts (the single-pixel path repeats the quad's operations
+// for its pixel), so images, transmittance and walk lengths are bit-identical;
+// the adjoint then adds four partial sums per (splat, tile) instead of one.
 #include "gs_internal.h"
 
 namespace {
 
-constexpr int PIX = 4;   // pixels per lane (2x2 quad)
+// Frames with fewer tiles than this take one pixel per lane (plain grid).
+constexpr int PIXEL_LANE_MAX_TILES = 2048;
 
 struct RasterArgs {
     const float4* splat;       // [E][3]
@@ -56,8 +66,8 @@ __device__ __forceinline__ int find_view(const gs_view_info* views, int V, u32 t
 }
 
 // Next work item of this wave: the block index, or a queue ticket.
-__device__ __forceinline__ u32 next_item(const RasterArgs& a, u32 item, bool first) {
-    if (!a.queue) return first ? blockIdx.x : (u32)a.T;
+__device__ __forceinline__ u32 next_item(const RasterArgs& a, u32 n_items, bool first) {
+    if (!a.queue) return first ? blockIdx.x : n_items;
     u32 t = 0;
     if (threadIdx.x == 0) t = atomicAdd(a.queue, 1u);
     return __builtin_amdgcn_readfirstlane(t);
@@ -73,24 +83,84 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane layout.  PIXQ = 4: lane l owns the 2x2 quad whose top-left pixel is
+// (16 tx + 2 (l % 8), 16 ty + 2 (l / 8)).  PIXQ = 1: work item 4 t + q is
+// quarter q of tile t, the 8x8 pixels at (16 tx + 8 (q % 2), 16 ty + 8 (q / 2)),
+// and lane l owns pixel (l % 8, l / 8) of it.  Either way a lane's pixels lie
+// in one quad with top-left pixel (qx, qy); its pixel i is (qx + i % 2,
+// qy + i / 2), for i < 4 (quads) or i = pi (one pixel).
 struct TileCoords {
     gs_view_info vi;
     uint2 rg;
-    int px0, py0;   // top-left pixel of this lane's quad
+    int qx, qy;     // top-left pixel of the lane's quad
+    int pi;         // one pixel per lane: the lane's pixel within its quad
 };
 
-__device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t) {
+template <int PIXQ>
+__device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t, u32 quarter) {
     TileCoords c;
     const int v = find_view(a.views, a.V, t);
     c.vi = a.views[v];
     const int lt = (int)t - c.vi.tile_base;
     const int tx = lt % c.vi.tiles_x, ty = lt / c.vi.tiles_x;
     const int lane = threadIdx.x;
-    c.px0 = tx * GS_TILE + 2 * (lane & 7);
-    c.py0 = ty * GS_TILE + 2 * (lane >> 3);
+    if (PIXQ == 4) {
+        c.qx = tx * GS_TILE + 2 * (lane & 7);
+        c.qy = ty * GS_TILE + 2 * (lane >> 3);
+        c.pi = 0;
+    } else {
+        const int px = tx * GS_TILE + 8 * (int)(quarter & 1u) + (lane & 7);
+        const int py = ty * GS_TILE + 8 * (int)(quarter >> 1) + (lane >> 3);
+        c.qx = px & ~1;
+        c.qy = py & ~1;
+        c.pi = (px & 1) | ((py & 1) << 1);
+    }
     c.rg = a.ranges[t];
     return c;
 }
+
+// Pixel i of the lane, as an index into its quad.
+template <int PIXQ>
+__device__ __forceinline__ int quad_pixel(const TileCoords& c, int i) {
+    return PIXQ == 4 ? i : c.pi;
+}
+
+// A splat's Gaussian at the lane's pixels.  The quad form evaluates all four
+// pixels of the quad; the single-pixel form repeats the quad's operations for
+// the lane's one pixel (same operands, same order), so both give bit-identical
+// values.
+template <int PIXQ>
+struct LaneGeom;
+
+template <>
+struct LaneGeom<4> {
+    Quad q;
+    __device__ __forceinline__ void setup(float4 p0, float4 p1, float qxc, float qyc, int) {
+        quad_setup(p0, p1, qxc, qyc, q);
+    }
+    __device__ __forceinline__ float G(int i) const { return quad_G(q, i); }
+};
+
+template <>
+struct LaneGeom<1> {
+    float dx, dy, u, vv;
+    __device__ __forceinline__ void setup(float4 p0, float4 p1, float qxc, float qyc, int pi) {
+        const bool ox = (pi & 1) != 0, oy = (pi & 2) != 0;
+        const float dx0 = (qxc - p0.x) - p0.z;
+        const float dy0 = (qyc - p0.y) - p0.w;
+        dx = ox ? dx0 + 1.f : dx0;
+        dy = oy ? dy0 + 1.f : dy0;
+        const float u0 = fmaf(p1.x, dx0, p1.y * dy0);
+        const float ux = ox ? u0 + p1.x : u0;
+        u = oy ? ux + p1.y : ux;
+        const float v0 = p1.z * dy0;
+        const float v = oy ? v0 + p1.z : v0;
+        vv = v * v;
+    }
+    __device__ __forceinline__ float G(int) const {
+        return __builtin_amdgcn_exp2f(-fmaf(u, u, vv));
+    }
+};
 
 // Stage splats [b0, b0 + cnt) of the sorted instance list in LDS; the fourth
 // component of the colour record (unused in HBM) carries the entry id.
@@ -108,39 +178,47 @@ __device__ __forceinline__ void load_batch(const RasterArgs& a, u32 b0, u32 cnt,
     }
 }
 
-// Some pixel of the quad still composites (T > 0).  Signed-integer order of
+// Some pixel of the lane still composites (T > 0).  Signed-integer order of
 // the bit patterns agrees with the float order on the sign and on positive
 // values, so one integer max decides it.
+template <int PIXQ>
 __device__ __forceinline__ bool any_live(const float* T) {
-    const int m = max(max(__float_as_int(T[0]), __float_as_int(T[1])),
-                      max(__float_as_int(T[2]), __float_as_int(T[3])));
-    return m > 0;
+    if constexpr (PIXQ == 1) {
+        return __float_as_int(T[0]) > 0;
+    } else {
+        const int m = max(max(__float_as_int(T[0]), __float_as_int(T[1])),
+                          max(__float_as_int(T[2]), __float_as_int(T[3])));
+        return m > 0;
+    }
 }
 
-template <int BATCH, bool COUNT>
+template <int BATCH, bool COUNT, int PIXQ>
 __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
-    for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
-        const u32 t = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
+    const u32 n_items = PIXQ == 4 ? (u32)a.T : 4u * (u32)a.T;
+    for (u32 item = next_item(a, n_items, true); item < n_items;
+         item = next_item(a, n_items, false)) {
+        const u32 it = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
+        const u32 t = PIXQ == 4 ? it : it >> 2;
         if (t >= (u32)a.T) continue;   // never taken for an order the binning built
-        const TileCoords tc = tile_coords(a, t);
+        const TileCoords tc = tile_coords<PIXQ>(a, t, it & 3u);
+        const float qxc = (float)tc.qx + 0.5f, qyc = (float)tc.qy + 0.5f;
         // T < 0 marks a finished pixel, with |T| its final transmittance
         // (pixels outside the image start finished); the sign replaces a
         // per-pixel flag and keeps the state update at two selects.
-        float pxc[PIX], pyc[PIX], T[PIX], C0[PIX], C1[PIX], C2[PIX];
-        u32 last[PIX], ncomp[PIX];
+        float T[PIXQ], C0[PIXQ], C1[PIXQ], C2[PIXQ];
+        u32 last[PIXQ], ncomp[PIXQ];
 #pragma unroll
-        for (int i = 0; i < PIX; ++i) {
-            const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
-            pxc[i] = (float)px + 0.5f;
-            pyc[i] = (float)py + 0.5f;
+        for (int i = 0; i < PIXQ; ++i) {
+            const int qp = quad_pixel<PIXQ>(tc, i);
+            const int px = tc.qx + (qp & 1), py = tc.qy + (qp >> 1);
             T[i] = (px < tc.vi.width && py < tc.vi.height) ? 1.f : -1.f;
             C0[i] = C1[i] = C2[i] = 0.f;
             last[i] = 0;
             ncomp[i] = 0;
         }
         for (u32 b0 = tc.rg.x; b0 < tc.rg.y; b0 += BATCH) {
-            if (__ballot(any_live(T)) == 0) break;
+            if (__ballot(any_live<PIXQ>(T)) == 0) break;
             const u32 cnt = min((u32)BATCH, tc.rg.y - b0);
             __syncthreads();
             load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2);
@@ -148,11 +226,11 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
             for (u32 k = 0; k < cnt; ++k) {
                 const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
                 const u32 idx = b0 - tc.rg.x + k + 1;
-                Quad q;
-                quad_setup(p0, p1, pxc[0], pyc[0], q);
+                LaneGeom<PIXQ> g;
+                g.setup(p0, p1, qxc, qyc, tc.pi);
 #pragma unroll
-                for (int i = 0; i < PIX; ++i) {
-                    const float alpha = fminf(p1.w * quad_G(q, i), GS_ALPHA_MAX);
+                for (int i = 0; i < PIXQ; ++i) {
+                    const float alpha = fminf(p1.w * g.G(i), GS_ALPHA_MAX);
                     const bool hit = alpha >= GS_ALPHA_MIN;
                     // T (1 - alpha) with one rounding; a finished pixel has T < 0,
                     // so Tn < 0 and it never takes
@@ -169,13 +247,14 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
                     last[i] = take ? idx : last[i];
                     if (COUNT) ncomp[i] += take ? 1u : 0u;
                 }
-                if (__ballot(any_live(T)) == 0) break;
+                if (__ballot(any_live<PIXQ>(T)) == 0) break;
             }
         }
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
 #pragma unroll
-        for (int i = 0; i < PIX; ++i) {
-            const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
+        for (int i = 0; i < PIXQ; ++i) {
+            const int qp = quad_pixel<PIXQ>(tc, i);
+            const int px = tc.qx + (qp & 1), py = tc.qy + (qp >> 1);
             if (px < tc.vi.width && py < tc.vi.height) {
                 const int64_t off = (int64_t)py * tc.vi.width + px;
                 float* img = a.images + 3 * tc.vi.pix_base + off;
@@ -191,7 +270,7 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
     }
 }
 
-template <int BATCH>
+template <int BATCH, int PIXQ>
 __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
     __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
     // transpose buffer of the per-splat reduction: value j of lane l at red[j][l]
@@ -202,19 +281,22 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
     const int rj = lane >> 2;
     const float fa = rj < 2 ? 1.f / GS_KAPPA : (rj == 2 || rj == 4) ? -0.5f : rj == 3 ? -1.f : 0.f;
     const float fb = (rj >= 5 && rj < 9) ? 1.f : 0.f;
-    for (u32 item = next_item(a, 0, true); item < (u32)a.T; item = next_item(a, item, false)) {
-        const u32 t = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
+    const u32 n_items = PIXQ == 4 ? (u32)a.T : 4u * (u32)a.T;
+    for (u32 item = next_item(a, n_items, true); item < n_items;
+         item = next_item(a, n_items, false)) {
+        const u32 it = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
+        const u32 t = PIXQ == 4 ? it : it >> 2;
         if (t >= (u32)a.T) continue;   // never taken for an order the binning built
-        const TileCoords tc = tile_coords(a, t);
+        const TileCoords tc = tile_coords<PIXQ>(a, t, it & 3u);
+        const float qxc = (float)tc.qx + 0.5f, qyc = (float)tc.qy + 0.5f;
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
-        float pxc[PIX], pyc[PIX], T[PIX], g0[PIX], g1[PIX], g2[PIX], sd[PIX];
-        u32 last[PIX];
+        float T[PIXQ], g0[PIXQ], g1[PIXQ], g2[PIXQ], sd[PIXQ];
+        u32 last[PIXQ];
         u32 mlast = 0;
 #pragma unroll
-        for (int i = 0; i < PIX; ++i) {
-            const int px = tc.px0 + (i & 1), py = tc.py0 + (i >> 1);
-            pxc[i] = (float)px + 0.5f;
-            pyc[i] = (float)py + 0.5f;
+        for (int i = 0; i < PIXQ; ++i) {
+            const int qp = quad_pixel<PIXQ>(tc, i);
+            const int px = tc.qx + (qp & 1), py = tc.qy + (qp >> 1);
             T[i] = g0[i] = g1[i] = g2[i] = 0.f;
             last[i] = 0;
             if (px < tc.vi.width && py < tc.vi.height) {
@@ -243,16 +325,16 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
             for (int k = (int)cnt - 1; k >= 0; --k) {
                 const u32 rel = (u32)bi * BATCH + (u32)k;
                 const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
-                Quad q;
-                quad_setup(p0, p1, pxc[0], pyc[0], q);
+                LaneGeom<PIXQ> g;
+                g.setup(p0, p1, qxc, qyc, tc.pi);
                 // per pixel: go = dL/dalpha * G (zero where the splat did not
                 // contribute or alpha was clamped); per lane: colour gradient sums
-                float go[PIX];
+                float go[PIXQ];
                 float gr0 = 0.f, gr1 = 0.f, gr2 = 0.f;
                 bool contrib = false;
 #pragma unroll
-                for (int i = 0; i < PIX; ++i) {
-                    const float G = quad_G(q, i);
+                for (int i = 0; i < PIXQ; ++i) {
+                    const float G = g.G(i);
                     const float raw = p1.w * G;
                     const float alpha = fminf(raw, GS_ALPHA_MAX);
                     const bool use = rel < last[i] && alpha >= GS_ALPHA_MIN;
@@ -280,21 +362,33 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
                     go[i] = (use && raw <= GS_ALPHA_MAX) ? dalpha * G : 0.f;
                 }
                 if (__ballot(contrib) == 0) continue;
-                // lane moments of go over the quad: sums of go (1, dx, dy, dx^2, dx dy,
-                // dy^2), factored by column (pixels 0, 2 | 1, 3) and row (0, 1 | 2, 3).
-                // Every term keeps its own offsets: an expansion around one pixel
-                // would cancel when the others sit next to the splat's centre.
-                const float A0 = go[0] + go[2], A1 = go[1] + go[3];
-                const float B0 = go[0] + go[1], B1 = go[2] + go[3];
-                const float gop = A0 + A1;
-                const float X0 = q.dx[0] * A0, X1 = q.dx[1] * A1;
-                const float Y0 = q.dy[0] * B0, Y1 = q.dy[1] * B1;
-                const float sx = X0 + X1;
-                const float sy = Y0 + Y1;
-                const float sxx = fmaf(q.dx[0], X0, q.dx[1] * X1);
-                const float syy = fmaf(q.dy[0], Y0, q.dy[1] * Y1);
-                const float sxy = fmaf(q.dx[0], fmaf(go[0], q.dy[0], go[2] * q.dy[1]),
-                                       q.dx[1] * fmaf(go[1], q.dy[0], go[3] * q.dy[1]));
+                // lane moments of go over its pixels: sums of go (1, dx, dy, dx^2,
+                // dx dy, dy^2), each pixel with its own offsets (an expansion
+                // around one pixel would cancel when the others sit next to the
+                // splat's centre)
+                float gop, sx, sy, sxx, syy, sxy;
+                if constexpr (PIXQ == 4) {
+                    // factored by column (pixels 0, 2 | 1, 3) and row (0, 1 | 2, 3)
+                    const Quad& q = g.q;
+                    const float A0 = go[0] + go[2], A1 = go[1] + go[3];
+                    const float B0 = go[0] + go[1], B1 = go[2] + go[3];
+                    gop = A0 + A1;
+                    const float X0 = q.dx[0] * A0, X1 = q.dx[1] * A1;
+                    const float Y0 = q.dy[0] * B0, Y1 = q.dy[1] * B1;
+                    sx = X0 + X1;
+                    sy = Y0 + Y1;
+                    sxx = fmaf(q.dx[0], X0, q.dx[1] * X1);
+                    syy = fmaf(q.dy[0], Y0, q.dy[1] * Y1);
+                    sxy = fmaf(q.dx[0], fmaf(go[0], q.dy[0], go[2] * q.dy[1]),
+                               q.dx[1] * fmaf(go[1], q.dy[0], go[3] * q.dy[1]));
+                } else {
+                    gop = go[0];
+                    sx = g.dx * gop;
+                    sy = g.dy * gop;
+                    sxx = g.dx * sx;
+                    syy = g.dy * sy;
+                    sxy = g.dx * sy;
+                }
                 // With w = dL/dalpha o G:  dL/dmean = sum w Q d,
                 // dL/d(a, b, c) = -sum w (dx^2/2, dx dy, dy^2/2), dL/do = sum dL/dalpha G;
                 // Q = L L^T / kappa from the stored Cholesky factor.  Q is applied
@@ -359,9 +453,19 @@ RasterArgs make_args(gs_frame* f, const gs_raster_opts* o) {
     return a;
 }
 
+// One pixel per lane: forced by GS_RASTER_LANE_PIXELS, else chosen for a small
+// frame on the plain grid unless GS_RASTER_LANE_QUADS asks for quads.
+bool pixel_lanes(const gs_frame* f, const gs_raster_opts* o) {
+    if (o->flags & GS_RASTER_LANE_PIXELS) return true;
+    if (o->flags & GS_RASTER_LANE_QUADS) return false;
+    return o->persistent_blocks == 0 && f->T < PIXEL_LANE_MAX_TILES;
+}
+
 gs_status grid_for(gs_frame* f, const gs_raster_opts* o, RasterArgs& a, int queue_slot,
-                   hipStream_t s, unsigned& grid) {
-    if (o->persistent_blocks > 0) {
+                   hipStream_t s, bool pixels, unsigned& grid) {
+    if (pixels) {
+        grid = 4u * (unsigned)f->T;   // four quarter-tile waves per tile (plain grid)
+    } else if (o->persistent_blocks > 0) {
         GS_TRY(gs_fill_u32(f->counters + queue_slot, 0u, 1, s));
         a.queue = f->counters + queue_slot;
         a.order = f->tvals[f->tsorted];
@@ -372,6 +476,30 @@ gs_status grid_for(gs_frame* f, const gs_raster_opts* o, RasterArgs& a, int queu
     return GS_OK;
 }
 
+template <int BATCH, int PIXQ>
+void launch_fwd(const RasterArgs& a, bool count, unsigned grid, hipStream_t s) {
+    if (count) raster_fwd_kernel<BATCH, true, PIXQ><<<grid, 64, 0, s>>>(a);
+    else raster_fwd_kernel<BATCH, false, PIXQ><<<grid, 64, 0, s>>>(a);
+}
+
+template <int PIXQ>
+void launch_fwd_batch(const RasterArgs& a, int batch, bool count, unsigned grid, hipStream_t s) {
+    switch (batch) {
+        case 128: launch_fwd<128, PIXQ>(a, count, grid, s); break;
+        case 256: launch_fwd<256, PIXQ>(a, count, grid, s); break;
+        default: launch_fwd<64, PIXQ>(a, count, grid, s); break;
+    }
+}
+
+template <int PIXQ>
+void launch_bwd_batch(const RasterArgs& a, int batch, unsigned grid, hipStream_t s) {
+    switch (batch) {
+        case 128: raster_bwd_kernel<128, PIXQ><<<grid, 64, 0, s>>>(a); break;
+        case 256: raster_bwd_kernel<256, PIXQ><<<grid, 64, 0, s>>>(a); break;
+        default: raster_bwd_kernel<64, PIXQ><<<grid, 64, 0, s>>>(a); break;
+    }
+}
+
 }  // namespace
 
 gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* images,
@@ -379,23 +507,12 @@ gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* imag
     if (f->T == 0) return GS_OK;
     RasterArgs a = make_args(f, o);
     a.images = images;
+    const bool pixels = pixel_lanes(f, o);
     unsigned grid;
-    GS_TRY(grid_for(f, o, a, 3, s, grid));
+    GS_TRY(grid_for(f, o, a, 3, s, pixels, grid));
     const bool count = (o->flags & GS_RASTER_COUNT_COMPOSITED) != 0;
-    switch (o->raster_batch) {
-        case 128:
-            if (count) raster_fwd_kernel<128, true><<<grid, 64, 0, s>>>(a);
-            else raster_fwd_kernel<128, false><<<grid, 64, 0, s>>>(a);
-            break;
-        case 256:
-            if (count) raster_fwd_kernel<256, true><<<grid, 64, 0, s>>>(a);
-            else raster_fwd_kernel<256, false><<<grid, 64, 0, s>>>(a);
-            break;
-        default:
-            if (count) raster_fwd_kernel<64, true><<<grid, 64, 0, s>>>(a);
-            else raster_fwd_kernel<64, false><<<grid, 64, 0, s>>>(a);
-            break;
-    }
+    if (pixels) launch_fwd_batch<1>(a, o->raster_batch, count, grid, s);
+    else launch_fwd_batch<4>(a, o->raster_batch, count, grid, s);
     return gs_check_launch("raster_fwd");
 }
 
@@ -404,12 +521,10 @@ gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float
     if (f->T == 0) return GS_OK;
     RasterArgs a = make_args(f, o);
     a.dL = dL;
+    const bool pixels = pixel_lanes(f, o);
     unsigned grid;
-    GS_TRY(grid_for(f, o, a, 4, s, grid));
-    switch (o->raster_batch) {
-        case 128: raster_bwd_kernel<128><<<grid, 64, 0, s>>>(a); break;
-        case 256: raster_bwd_kernel<256><<<grid, 64, 0, s>>>(a); break;
-        default: raster_bwd_kernel<64><<<grid, 64, 0, s>>>(a); break;
-    }
+    GS_TRY(grid_for(f, o, a, 4, s, pixels, grid));
+    if (pixels) launch_bwd_batch<1>(a, o->raster_batch, grid, s);
+    else launch_bwd_batch<4>(a, o->raster_batch, grid, s);
     return gs_check_launch("raster_bwd");
 }

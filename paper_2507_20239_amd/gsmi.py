@@ -36,6 +36,8 @@ RASTER_FOOTPRINT_3SIGMA = 2
 RASTER_DEPTH_PRESORT = 4
 RASTER_BALANCED_DIGITS = 8
 RASTER_GRAD_RENDERED_ONLY = 16
+RASTER_LANE_PIXELS = 32
+RASTER_LANE_QUADS = 64
 
 
 class GsError(RuntimeError):
@@ -211,12 +213,16 @@ def cameras_to_device(cams, device="cuda") -> torch.Tensor:
 
 def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_blocks=0,
                 count_composited=False, footprint_3sigma=False, depth_presort=False,
-                balanced_digits=False, grad_rendered_only=False):
+                balanced_digits=False, grad_rendered_only=False, lanes=None):
     """footprint_3sigma: bin by 3-sigma squares as the original 3DGS
     rasterizer does (images then depend on the tile grid) instead of by the
     opacity-aware ellipse (GS_RASTER_FOOTPRINT_3SIGMA).  depth_presort: order
     the visible entries by depth before emission instead of sorting each tile's
-    list (GS_RASTER_DEPTH_PRESORT; same lists, different cost)."""
+    list (GS_RASTER_DEPTH_PRESORT; same lists, different cost).  lanes: None
+    (one pixel per lane for frames of fewer than 2048 tiles on the plain grid,
+    a 2x2 quad otherwise), "pixels" or "quads" to force one layout."""
+    if lanes not in (None, "pixels", "quads"):
+        raise ValueError("lanes must be None, 'pixels' or 'quads'")
     o = RasterOpts()
     o.bg[:] = [float(x) for x in bg]
     o.near_plane = float(np.float32(near_plane))
@@ -226,7 +232,9 @@ def raster_opts(bg=(0.0, 0.0, 0.0), near_plane=0.2, raster_batch=0, persistent_b
                (RASTER_FOOTPRINT_3SIGMA if footprint_3sigma else 0) |
                (RASTER_DEPTH_PRESORT if depth_presort else 0) |
                (RASTER_BALANCED_DIGITS if balanced_digits else 0) |
-               (RASTER_GRAD_RENDERED_ONLY if grad_rendered_only else 0))
+               (RASTER_GRAD_RENDERED_ONLY if grad_rendered_only else 0) |
+               (RASTER_LANE_PIXELS if lanes == "pixels" else 0) |
+               (RASTER_LANE_QUADS if lanes == "quads" else 0))
     return o
 
 

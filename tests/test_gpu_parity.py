@@ -161,11 +161,17 @@ def test_scenes_cover_every_list_sort_path():
         assert ((lens > lo) & (lens <= hi)).any(), (lo, hi)
 
 
+def _lane_opts(sc, lanes):
+    return gsmi.raster_opts(bg=tuple(float(x) for x in sc.bg), count_composited=True, lanes=lanes)
+
+
+# both compositing layouts: one pixel per lane (the small frames' default) and 2x2 quads
+@pytest.mark.parametrize("lanes", ["pixels", "quads"])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_render_matches_oracle(name):
+def test_render_matches_oracle(name, lanes):
     sc = SCENES[name]
     cam = sc.cameras[0]
-    frame, flat, *_ = gpu_forward(sc, [cam])
+    frame, flat, *_ = gpu_forward(sc, [cam], _lane_opts(sc, lanes))
     p = oracle.project(sc, cam)
     ref, Tref, nref, margin = oracle.render_image(p, sc.bg)
     img = flat.view(3, cam.height, cam.width).cpu().numpy()
@@ -180,11 +186,12 @@ def test_render_matches_oracle(name):
     np.testing.assert_array_equal(nc[good], nref[good])
 
 
+@pytest.mark.parametrize("lanes", ["pixels", "quads"])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_backward_matches_oracle(name):
+def test_backward_matches_oracle(name, lanes):
     sc = SCENES[name]
     cam = sc.cameras[0]
-    frame, flat, params, cams_dev, opts = gpu_forward(sc, [cam])
+    frame, flat, params, cams_dev, opts = gpu_forward(sc, [cam], _lane_opts(sc, lanes))
     p = oracle.project(sc, cam)
     _, _, _, margin = oracle.render_image(p, sc.bg)
     rng = np.random.default_rng(5)
@@ -459,6 +466,54 @@ def test_persistent_backward_after_plain_render_is_rejected_on_the_host():
     tt = frame.buffer(gsmi.BUF_TILES_TOUCHED).view(-1) > 0
     ga, gb = a.view(-1, 9)[tt], b.view(-1, 9)[tt]
     assert torch.allclose(ga, gb, rtol=1e-4, atol=1e-6 * float(ga.abs().max()))
+
+
+def test_lane_layouts_agree():
+    """One pixel per lane and 2x2 quads per lane: images, final transmittance,
+    walk lengths and composited counts bit-identical (each pixel's arithmetic
+    is the same) and equal to the default layout's, splat gradients equal to
+    FP32 summation order, on a two-view frame with ragged edges.  Host validation refuses both layouts at once and
+    one pixel per lane on a persistent grid."""
+    sc = synth.random_scene(27, 3000, 150, 100, sh_degree=2, n_views=2, log_scale=(-2.5, 0.5))
+    cams = [sc.cameras[0], synth.Camera(sc.cameras[1].R, sc.cameras[1].t, 90.0, 90.0, 45.3,
+                                        30.8, 91, 61)]
+    out = {}
+    rng = np.random.default_rng(9)
+    dL = None
+    for lanes in ("pixels", "quads", None):
+        opts = _lane_opts(sc, lanes)
+        frame, flat, *_ = gpu_forward(sc, cams, opts)
+        if dL is None:
+            dL = torch.from_numpy(rng.standard_normal(flat.numel()).astype(np.float32) * 1e-3)
+            dL = dL.to(dev())
+        frame.render_backward(opts, dL)
+        torch.cuda.synchronize()
+        out[lanes] = dict(img=flat.clone(),
+                          T=frame.buffer(gsmi.BUF_T_FINAL, torch.float32).clone(),
+                          n=frame.buffer(gsmi.BUF_N_CONTRIB).clone(),
+                          nc=frame.buffer(gsmi.BUF_N_COMPOSITED).clone(),
+                          g=frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).view(-1, 9).clone(),
+                          tt=frame.buffer(gsmi.BUF_TILES_TOUCHED).clone())
+    a, b, c = out["pixels"], out["quads"], out[None]
+    for k in ("img", "T", "n", "nc", "tt"):
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(a[k], c[k]), k
+    r = a["tt"] > 0
+    ga, gb = a["g"][r].double(), b["g"][r].double()
+    scale = gb.abs().max(dim=0).values.clamp_min(1e-30)
+    assert ((ga - gb).abs() <= 1e-5 * scale + 1e-5 * gb.abs()).all()
+    gc = c["g"][r].double()
+    assert ((gc - ga).abs() <= 1e-5 * scale + 1e-5 * ga.abs()).all()
+    L = gsmi.lib()
+    frame, flat, *_ = gpu_forward(sc, cams, _lane_opts(sc, None))
+    for flags, pb in ((gsmi.RASTER_LANE_PIXELS | gsmi.RASTER_LANE_QUADS, 0),
+                      (gsmi.RASTER_LANE_PIXELS, 16)):
+        o = _lane_opts(sc, None)
+        o.flags |= flags
+        o.persistent_blocks = pb
+        st = L.gs_composite(frame.handle, ctypes.byref(o), gsmi._ptr(flat), gsmi._stream())
+        assert st == gsmi.GS_ERR_INVALID, flags
+        assert b"pixel" in L.gs_last_error().lower() or b"lane" in L.gs_last_error().lower()
 
 
 def test_bin_then_composite_is_render():
