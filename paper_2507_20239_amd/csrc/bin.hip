@@ -140,10 +140,9 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n
         u64 s = 0;
         const u32 i0 = base + threadIdx.x * 4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            t[j] = i0 + j < end ? tt[i0 + j] : 0u;
-            s += vis_pack(t[j]);
-        }
+        for (int j = 0; j < 4; ++j) t[j] = load_or_zero(tt, i0 + j, end);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s += vis_pack(t[j]);
         u64 total;
         u64 ex = block_exclusive_scan(s, lds4, total) + carry;
 #pragma unroll
@@ -273,12 +272,15 @@ __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, 
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 base = (u64)blockIdx.x * blockDim.x + threadIdx.x; base <= n;
          base += RANGES_UNROLL * stride) {
-        u32 kp[RANGES_UNROLL], kc[RANGES_UNROLL];
+        u32 kp[RANGES_UNROLL] = {}, kc[RANGES_UNROLL] = {};
+        if (n > 0) {
 #pragma unroll
-        for (int j = 0; j < RANGES_UNROLL; ++j) {
-            const u64 i = base + j * stride;
-            kp[j] = i >= 1 && i <= n ? keys[i - 1] : 0u;
-            kc[j] = i < n ? keys[i] : 0u;
+            for (int j = 0; j < RANGES_UNROLL; ++j) {
+                const u64 i = base + j * stride;
+                const u32 ic = i < n ? (u32)i : n;   // position i, clamped to n
+                kp[j] = load_or_zero(keys, ic - 1u + (ic == 0u ? 1u : 0u), n);
+                kc[j] = load_or_zero(keys, ic, n);
+            }
         }
 #pragma unroll
         for (int j = 0; j < RANGES_UNROLL; ++j) {
@@ -305,11 +307,6 @@ __global__ void ranges_kernel(const u32* keys, const u32* n_ptr, uint2* ranges, 
 constexpr u32 SORT_WAVE_MAX = 512;
 constexpr int SORT_LDS = 2048;
 constexpr int SORT_THREADS = 256;
-
-__device__ __forceinline__ u64 list_key(const u32* depth_key, u32 e, u32 E) {
-    if (e >= E) e = E - 1;   // only for slots an overflowing frame left unwritten
-    return ((u64)depth_key[e] << 32) | e;
-}
 
 // value of lane ^ m (m a power of two below 64): quad permutations and a row
 // rotation by 8 on the VALU, swizzles inside 32-lane halves, a lane
@@ -382,15 +379,25 @@ __device__ __forceinline__ void bitonic_merges(u64 (&x)[R], u32 t, u64* lds) {
     if constexpr (K < NT * R) bitonic_merges<R, NT, 2 * K>(x, t, lds);
 }
 
-// keys of elements [0, L) of a list (L <= NT R), padded with the largest key
+// keys of elements [0, L) of a list (1 <= L <= NT R), padded with the largest
+// key.  The R entry loads are issued together (at clamped positions), then the
+// R depth loads, so a thread waits twice instead of twice per key.
 template <int R, int NT>
 __device__ __forceinline__ void load_list_keys(u64 (&x)[R], const u32* ent, u32 L,
                                                const u32* depth_key, u32 E, u32 t) {
+    u32 e[R], d[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const u32 i = t * R + r;
-        x[r] = i < L ? list_key(depth_key, ent[i], E) : ~0ull;
+        e[r] = ent[i < L ? i : L - 1];
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        e[r] = e[r] < E ? e[r] : E - 1;   // only for slots an overflowing frame left unwritten
+        d[r] = depth_key[e[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = t * R + r < L ? ((u64)d[r] << 32) | e[r] : ~0ull;
 }
 
 // sort one list of L <= NT R instances in place
@@ -560,10 +567,15 @@ __global__ void __launch_bounds__(GS_BLOCK) presort_gather_reduce_kernel(const u
     u32 beg, end;
     chunk_of(*n_dev, GS_SCAN_PARTS, blockIdx.x, beg, end);
     u32 s = 0;
-    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) {
-        const u32 v = tt[sorted[i]];
-        tt_sorted[i] = v;
-        s += v;
+    // four gathers per thread in flight per step
+    for (u32 i = beg + threadIdx.x; i < end; i += 4 * GS_BLOCK) {
+        u32 v[4];
+        scan_in_n<4>(tt, sorted, i, GS_BLOCK, end, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i + j * GS_BLOCK < end) tt_sorted[i + j * GS_BLOCK] = v[j];
+            s += v[j];
+        }
     }
     u32 total;
     block_exclusive_scan(s, lds4, total);

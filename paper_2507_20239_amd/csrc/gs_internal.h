@@ -151,6 +151,35 @@ __device__ __forceinline__ u32 scan_in(const u32* in, const u32* gather, u32 i) 
     return gather ? in[gather[i]] : in[i];
 }
 
+// p[i] for i < end, else 0 (end > 0).  The load is issued whatever i is (at a
+// clamped index), so the loads of an unrolled loop stay in flight together;
+// a conditional load would sit in a branch of its own that waits for it.
+__device__ __forceinline__ u32 load_or_zero(const u32* p, u32 i, u32 end) {
+    const u32 v = p[i < end ? i : end - 1];
+    return i < end ? v : 0u;
+}
+
+// N values scan_in(in, gather, i0 + j * stride) (0 at or beyond end > 0), their
+// loads issued together: the gather indices first, then the values
+template <int N>
+__device__ __forceinline__ void scan_in_n(const u32* in, const u32* gather, u32 i0, u32 stride,
+                                          u32 end, u32 (&v)[N]) {
+    u32 idx[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const u32 i = i0 + j * stride;
+        idx[j] = i < end ? i : end - 1;
+    }
+    if (gather) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) idx[j] = gather[idx[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = in[idx[j]];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = i0 + j * stride < end ? v[j] : 0u;
+}
+
 struct ScanStore {
     u32* out;
     u32* total;
@@ -174,11 +203,9 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, cons
         u32 v[4];
         u32 s = 0;
         const u32 i0 = base + threadIdx.x * 4;
+        scan_in_n<4>(in, gather, i0, 1u, end, v);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = (i0 + j < end) ? scan_in(in, gather, i0 + j) : 0u;
-            s += v[j];
-        }
+        for (int j = 0; j < 4; ++j) s += v[j];
         u32 total;
         u32 ex = block_exclusive_scan(s, lds4, total) + carry;
 #pragma unroll

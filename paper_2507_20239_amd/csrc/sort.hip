@@ -30,7 +30,13 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_reduce_kernel(const u32* in, co
     u32 beg, end;
     chunk_of(dev_len(n_dev, n_host), GS_SCAN_PARTS, blockIdx.x, beg, end);
     u32 s = 0;
-    for (u32 i = beg + threadIdx.x; i < end; i += GS_BLOCK) s += scan_in(in, gather, i);
+    // four values per thread in flight per step
+    for (u32 i = beg + threadIdx.x; i < end; i += 4 * GS_BLOCK) {
+        u32 v[4];
+        scan_in_n<4>(in, gather, i, GS_BLOCK, end, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s += v[j];
+    }
     u32 total;
     block_exclusive_scan(s, lds4, total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
@@ -130,12 +136,18 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
         for (int j = lane; j < 256; j += 64) whist[w][j] = 0;
         __syncthreads();
         u32 k[RADIX_ITEMS], v[RADIX_ITEMS], d[RADIX_ITEMS], r[RADIX_ITEMS];
+        // every item's key and value loaded before any is ranked: sixteen loads in
+        // flight per thread instead of one round trip per item
+#pragma unroll
+        for (int i = 0; i < RADIX_ITEMS; ++i) {
+            const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
+            k[i] = load_or_zero(kin, idx, end);
+            v[i] = load_or_zero(vin, idx, end);
+        }
 #pragma unroll
         for (int i = 0; i < RADIX_ITEMS; ++i) {
             const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
             const bool valid = idx < end;
-            k[i] = valid ? kin[idx] : 0u;
-            v[i] = valid ? vin[idx] : 0u;
             d[i] = (k[i] >> shift) & mask;
             u64 peers = __ballot(valid);
             for (int b = 0; b < bits; ++b) {
