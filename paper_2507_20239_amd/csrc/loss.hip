@@ -34,8 +34,29 @@ __device__ __forceinline__ float rcp_refined(float x) {
     return fmaf(fmaf(-x, r, 1.f), r, r);
 }
 
-__device__ __forceinline__ float patch_at(const float* img, int H, int W, int y, int x) {
-    return (y >= 0 && y < H && x >= 0 && x < W) ? img[(int64_t)y * W + x] : 0.f;
+constexpr int PATCH = PH * PW;
+constexpr int PATCH_STEPS = (PATCH + 255) / 256;   // patch elements per thread (5)
+
+// Element k of this thread's share of the patch at (y0, x0): where it sits in
+// the patch (r, q) and its offset in a plane, clamped into the image (so the
+// load is always issued; `in` says whether the value is used or taken as 0).
+struct PatchSlot {
+    int r, q;
+    int64_t o;
+    bool in, valid;
+};
+
+__device__ __forceinline__ PatchSlot patch_slot(int t, int k, int H, int W, int y0, int x0) {
+    PatchSlot p;
+    const int i0 = t + 256 * k;
+    p.valid = i0 < PATCH;
+    const int i = p.valid ? i0 : PATCH - 1;
+    p.r = i / PW;
+    p.q = i % PW;
+    const int y = y0 + p.r, x = x0 + p.q;
+    p.in = y >= 0 && y < H && x >= 0 && x < W;
+    p.o = (int64_t)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
+    return p;
 }
 
 __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__ img,
@@ -51,10 +72,25 @@ __global__ void __launch_bounds__(256) ssim_fwd_kernel(const float* __restrict__
     const float* Y = tgt + c * plane;
     const int x0 = blockIdx.x * TW - SR, y0 = blockIdx.y * TH - SR;
     const int t = threadIdx.x;
-    for (int i = t; i < PH * PW; i += 256) {
-        const int r = i / PW, q = i % PW;
-        sx[r][q] = patch_at(X, H, W, y0 + r, x0 + q);
-        sy[r][q] = patch_at(Y, H, W, y0 + r, x0 + q);
+    {
+        // every patch load of the thread in flight before any is stored (zero
+        // padding outside the image)
+        float vx[PATCH_STEPS], vy[PATCH_STEPS];
+#pragma unroll
+        for (int k = 0; k < PATCH_STEPS; ++k) {
+            const PatchSlot p = patch_slot(t, k, H, W, y0, x0);
+            const float a = X[p.o], b = Y[p.o];
+            vx[k] = p.in ? a : 0.f;
+            vy[k] = p.in ? b : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < PATCH_STEPS; ++k) {
+            const PatchSlot p = patch_slot(t, k, H, W, y0, x0);
+            if (p.valid) {
+                sx[p.r][p.q] = vx[k];
+                sy[p.r][p.q] = vy[k];
+            }
+        }
     }
     __syncthreads();
     for (int i = t; i < PH * TW; i += 256) {
@@ -158,11 +194,25 @@ __global__ void __launch_bounds__(256) ssim_bwd_kernel(const float* __restrict__
     const int64_t plane = (int64_t)H * W;
     const int x0 = blockIdx.x * TW - SR, y0 = blockIdx.y * TH - SR;
     const int t = threadIdx.x;
-    for (int i = t; i < PH * PW; i += 256) {
-        const int r = i / PW, q = i % PW;
+    {
+        float v[3][PATCH_STEPS];
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-            sa[m][r][q] = patch_at(abc + ((int64_t)m * gridDim.z + c) * plane, H, W, y0 + r, x0 + q);
+        for (int k = 0; k < PATCH_STEPS; ++k) {
+            const PatchSlot p = patch_slot(t, k, H, W, y0, x0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const float a = abc[((int64_t)m * gridDim.z + c) * plane + p.o];
+                v[m][k] = p.in ? a : 0.f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PATCH_STEPS; ++k) {
+            const PatchSlot p = patch_slot(t, k, H, W, y0, x0);
+            if (p.valid) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) sa[m][p.r][p.q] = v[m][k];
+            }
+        }
     }
     __syncthreads();
     for (int i = t; i < PH * TW; i += 256) {
