@@ -90,22 +90,26 @@ __global__ void plan_count_kernel(const uint8_t* split, const uint8_t* clone, co
                                   int64_t n, u32* cnt) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
     if (i >= n) return;
-    cnt[i] = prune[i] ? 0u : ((split[i] || clone[i]) ? 2u : 1u);
+    // the three mask loads issued together (no short-circuit chain of waits)
+    const uint8_t p = prune[i], sp = split[i], cl = clone[i];
+    cnt[i] = p ? 0u : ((sp | cl) ? 2u : 1u);
 }
 
 __global__ void plan_write_kernel(const uint8_t* split, const uint8_t* clone, const uint8_t* prune,
                                   const u32* offs, int64_t n, int32_t* src, uint8_t* kind,
                                   int64_t cap) {
     const int64_t i = (int64_t)blockIdx.x * GS_BLOCK + threadIdx.x;
-    if (i >= n || prune[i]) return;
+    if (i >= n) return;
+    const uint8_t p = prune[i], sp = split[i], cl = clone[i];
     const int64_t o = offs[i];
+    if (p) return;
     uint8_t k0 = GS_KIND_KEEP, k1 = GS_KIND_KEEP;
     int rows = 1;
-    if (split[i]) {
+    if (sp) {
         k0 = GS_KIND_SPLIT0;
         k1 = GS_KIND_SPLIT1;
         rows = 2;
-    } else if (clone[i]) {
+    } else if (cl) {
         k1 = GS_KIND_CLONE;
         rows = 2;
     }
