@@ -128,8 +128,7 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_reduce_kernel(const u32* tt, u32
 __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n, const u64* part,
                                                             VisEpi epi) {
     __shared__ u64 lds4[4];
-    u64 carry = 0;
-    for (u32 i = threadIdx.x; i < blockIdx.x; i += GS_BLOCK) carry += part[i];
+    u64 carry = partition_prefix(part, blockIdx.x);
     u64 before;
     block_exclusive_scan(carry, lds4, before);
     carry = before;
@@ -153,8 +152,7 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n
         carry += total;
     }
     if (blockIdx.x == gridDim.x - 1) {
-        u64 tiles = 0;
-        for (u32 i = threadIdx.x; i < GS_SCAN_PARTS; i += GS_BLOCK) tiles += part[GS_SCAN_PARTS + i];
+        u64 tiles = partition_prefix(part + GS_SCAN_PARTS, GS_SCAN_PARTS);
         u64 all;
         __syncthreads();
         block_exclusive_scan(tiles, lds4, all);

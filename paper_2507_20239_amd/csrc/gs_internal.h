@@ -151,6 +151,24 @@ __device__ __forceinline__ u32 scan_in(const u32* in, const u32* gather, u32 i) 
     return gather ? in[gather[i]] : in[i];
 }
 
+// This thread's share of the sum of the partition totals before partition b
+// (b < GS_SCAN_PARTS): its GS_SCAN_PARTS / GS_BLOCK loads issued together.
+template <class T>
+__device__ __forceinline__ T partition_prefix(const T* part, u32 b) {
+    static_assert(GS_SCAN_PARTS % GS_BLOCK == 0, "partitions split evenly over the threads");
+    constexpr int N = GS_SCAN_PARTS / GS_BLOCK;
+    T v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const u32 i = threadIdx.x + j * GS_BLOCK;
+        v[j] = part[i < GS_SCAN_PARTS ? i : 0];
+    }
+    T s = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += threadIdx.x + j * GS_BLOCK < b ? v[j] : (T)0;
+    return s;
+}
+
 // p[i] for i < end, else 0 (end > 0).  The load is issued whatever i is (at a
 // clamped index), so the loads of an unrolled loop stay in flight together;
 // a conditional load would sit in a branch of its own that waits for it.
@@ -192,8 +210,7 @@ __global__ void __launch_bounds__(GS_BLOCK) scan_down_kernel(const u32* in, cons
                                                              const u32* n_dev, u32 n_host,
                                                              const u32* part, Epi epi) {
     __shared__ u32 lds4[4];
-    u32 carry = 0;
-    for (u32 i = threadIdx.x; i < blockIdx.x; i += GS_BLOCK) carry += part[i];
+    u32 carry = partition_prefix(part, blockIdx.x);
     u32 before;
     block_exclusive_scan(carry, lds4, before);
     carry = before;

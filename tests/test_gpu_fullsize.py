@@ -216,3 +216,55 @@ def test_largest_view_16384x16384():
     Tgot = Tg[torch.from_numpy(pix[:, 1]).long().to(Tg.device),
               torch.from_numpy(pix[:, 0]).long().to(Tg.device)].cpu().numpy()
     assert_close_scaled(Tgot[good], T[good], np.abs(T[good]), what="T_final")
+
+
+def test_1m_coarse_level_200x130_both_lane_layouts():
+    """The 1M-Gaussian view at 1/8 resolution, a coarse level of the
+    coarse-to-fine schedule: 117 tiles whose lists hold thousands of splats,
+    which the default launch renders with one pixel per lane.  Against the
+    2x2-quad layout: images, final transmittance, walk lengths and composited
+    counts bit-identical.  Against the oracle, in both layouts: a sample of
+    pixels and the splat gradients of a loss on a sample of pixels (long
+    back-to-front walks)."""
+    sc = synth.single_view_1m(with_targets=False)
+    cam = sc.cameras[0].scaled(8)
+    p = oracle.project(sc, cam)
+    rng = np.random.default_rng(31)
+    pix = _sample_pixels(rng, cam.width, cam.height, 300)
+    C, T, nc, margin = oracle.render_pixels(p, pix)
+    good = margin > MARGIN
+    assert good.mean() > 0.95
+    bpix = pix[good][:150]
+    g = rng.standard_normal((bpix.shape[0], 3)).astype(np.float32)
+    dL = np.zeros((3, cam.height, cam.width), np.float32)
+    dL[:, bpix[:, 1], bpix[:, 0]] = g.T
+    gproj, gabs = oracle.render_backward_pixels(p, bpix, g.astype(np.float64))
+    state = {}
+    for lanes in ("pixels", "quads"):
+        opts = gsmi.raster_opts(count_composited=True, lanes=lanes)
+        frame, flat, *_ = gpu_forward(sc, [cam], opts=opts, cap=16 << 20)
+        img = flat.view(3, cam.height, cam.width).cpu().numpy()
+        got = img[:, pix[:, 1], pix[:, 0]].T
+        assert_close_scaled(got[good], C[good], np.abs(C[good]), what="pixels (%s)" % lanes)
+        Tg = frame.buffer(gsmi.BUF_T_FINAL, torch.float32).cpu().numpy().reshape(cam.height, cam.width)
+        assert_close_scaled(Tg[pix[good, 1], pix[good, 0]], T[good], np.abs(T[good]),
+                            what="T_final (%s)" % lanes)
+        ncg = frame.buffer(gsmi.BUF_N_COMPOSITED).cpu().numpy().view(np.uint32)
+        ncg = ncg.reshape(cam.height, cam.width)
+        np.testing.assert_array_equal(ncg[pix[good, 1], pix[good, 0]], nc[good])
+        frame.render_backward(opts, torch.from_numpy(dL).to(dev()).reshape(-1))
+        torch.cuda.synchronize()
+        sg = frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).view(-1, 9).cpu().numpy()
+        rendered = frame.buffer(gsmi.BUF_TILES_TOUCHED).cpu().numpy() > 0
+        assert np.all(gabs[~rendered] == 0)
+        assert (gabs > 0).any(1).sum() > 1000
+        assert_close_scaled(sg[rendered], gproj[rendered], gabs[rendered],
+                            what="splat gradients (%s)" % lanes)
+        state[lanes] = [flat.cpu().clone(),
+                        frame.buffer(gsmi.BUF_T_FINAL, torch.float32).cpu().clone(),
+                        frame.buffer(gsmi.BUF_N_CONTRIB).cpu().clone(), ncg.copy()]
+        del frame
+    a, b = state["pixels"], state["quads"]
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
+    np.testing.assert_array_equal(a[3], b[3])
