@@ -96,12 +96,14 @@ def parse():
     ap.add_argument("--profile-workload",
                     choices=("batched_8_views", "step_6m_4_views", "plain_128x128"),
                     help="for a profiler: time only this workload with the launch shape given by "
-                         "--raster-batch / --persistent / --presort / --balanced and print one "
-                         "JSON line")
+                         "--raster-batch / --persistent / --presort / --balanced / --lanes and "
+                         "print one JSON line")
     ap.add_argument("--raster-batch", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--presort", action="store_true")
     ap.add_argument("--balanced", action="store_true")
+    ap.add_argument("--lanes", choices=("pixels", "quads"), default=None,
+                    help="lane layout of the compositing kernels (default: by frame size)")
     return ap.parse_args()
 
 
@@ -696,7 +698,7 @@ def profile_workload(args):
     dev = torch.device("cuda:0")
     K, W = args.steps, args.warmup
     shape = {"raster_batch": args.raster_batch, "persistent_blocks": args.persistent,
-             "depth_presort": args.presort, "balanced_digits": args.balanced}
+             "depth_presort": args.presort, "balanced_digits": args.balanced, "lanes": args.lanes}
     if args.profile_workload in ("batched_8_views", "plain_128x128"):
         sb = synth.batched_c2f() if args.profile_workload == "batched_8_views" else synth.tiny_scene()
         pb, _ = spatially_ordered(torch, gsmi, to_dev(sb, dev, torch, gsmi), reps=1)

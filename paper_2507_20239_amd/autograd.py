@@ -27,17 +27,18 @@ class GaussianRasterizer:
     cameras: list of objects with R (3x3), t (3), fx, fy, cx, cy, width, height
     (see synth.Camera); their sizes fix the frame.  The instance capacity
     grows (and the step re-runs) when a render overflows it.  footprint_3sigma
-    bins by the original 3DGS 3-sigma squares (gsmi.raster_opts).  With
-    autotune=True the first call times the launch shapes of the autotuner
-    (LDS batch, plain grid or heavy-first persistent grid) on these views and
-    parameters and keeps the fastest, instead of raster_batch and
-    persistent_blocks.
+    bins by the original 3DGS 3-sigma squares (gsmi.raster_opts).
+    raster_batch, persistent_blocks, depth_presort, balanced_digits and lanes
+    set the launch shape (gsmi.raster_opts).  With autotune=True the first
+    call times the autotuner's launch shapes (LDS batch, lane layout or
+    heavy-first persistent grid, sort form, digit split) on these views and
+    parameters and keeps the fastest instead.
     """
 
     def __init__(self, n, cameras, sh_degree, device="cuda", bg=(0.0, 0.0, 0.0),
                  raster_batch=0, persistent_blocks=0, capacity=None, near_plane=0.2,
                  footprint_3sigma=False, autotune=False, lazy_overflow=False,
-                 depth_presort=False, balanced_digits=False):
+                 depth_presort=False, balanced_digits=False, lanes=None):
         self.n = int(n)
         self.sh_degree = int(sh_degree)
         self.device = torch.device(device)
@@ -48,7 +49,7 @@ class GaussianRasterizer:
         self._opt_args = dict(bg=bg, near_plane=near_plane, footprint_3sigma=footprint_3sigma)
         self.opts = gsmi.raster_opts(raster_batch=raster_batch, persistent_blocks=persistent_blocks,
                                      depth_presort=depth_presort, balanced_digits=balanced_digits,
-                                     **self._opt_args)
+                                     lanes=lanes, **self._opt_args)
         self.autotune = bool(autotune)
         self.tuned = None
         self.set_cameras(cameras)

@@ -1,11 +1,12 @@
 """Autotuner for the rasterizer launch shape.
 
 Searches the LDS batch size (splats staged per batch: 64, 128, 256), the
-work distribution (one wave64 workgroup per (view, tile), or a persistent grid
-of 2048 / 4096 / 8192 waves pulling tiles heaviest-first from a queue), how the
-per-tile lists are put in depth order (a sort per tile, or a depth presort of
-the visible entries) and the digit split of the radix sort by tile (48
-candidates), by timing the captured training step of the given views, and
+work distribution (one workgroup per (view, tile) with one wave and a 2x2
+quad per lane or four waves and one pixel per lane, or a persistent grid of
+2048 / 4096 / 8192 single waves pulling tiles heaviest-first from a queue),
+how the per-tile lists are put in depth order (a sort per tile, or a depth
+presort of the visible entries) and the digit split of the radix sort by tile
+(60 candidates), by timing the captured training step of the given views, and
 caches the winner per (device, workload signature) in a JSON file
 ($GSMI_AUTOTUNE_CACHE, default ~/.cache/gsmi_autotune.json).
 """
@@ -25,7 +26,15 @@ PERSISTENT = (0, 2048, 4096, 8192)
 # radix sort by tile (8-bit digits, or digits of equal width)
 PRESORT = (False, True)
 BALANCED = (False, True)
-SHAPE_KEYS = ("raster_batch", "persistent_blocks", "depth_presort", "balanced_digits")
+# lanes of the compositing kernels on the plain grid: one pixel (four waves per
+# tile) or a 2x2 quad (one wave per tile); persistent grids take quads
+LANES = ("pixels", "quads")
+SHAPE_KEYS = ("raster_batch", "persistent_blocks", "depth_presort", "balanced_digits", "lanes")
+
+
+def n_candidates():
+    per_sort = len(PRESORT) * len(BALANCED)
+    return len(BATCHES) * per_sort * (len(LANES) + len(PERSISTENT) - 1)
 
 
 def opts_of(best, **other):
@@ -44,7 +53,9 @@ def _signature(n, cams, sh_degree, opts=None):
     extra = ""
     if opts and opts.get("footprint_3sigma"):
         extra = "|3sigma"
-    return "%s|n=%d|sh=%d|%s%s" % (dev, n, sh_degree, sizes, extra)
+    # the candidate set is part of the signature: a cache written for another set
+    # is not reused
+    return "%s|n=%d|sh=%d|%s%s|%d candidates" % (dev, n, sh_degree, sizes, extra, n_candidates())
 
 
 def _load():
@@ -106,12 +117,13 @@ def tune_batched(scene, cams, params, device, cap=32 << 20, use_cache=True, opts
         for pb in PERSISTENT:
             for ps in PRESORT:
                 for bd in BALANCED:
-                    shape = {"raster_batch": b, "persistent_blocks": pb, "depth_presort": ps,
-                             "balanced_digits": bd}
-                    o = opts_of(shape, **opts)
-                    ms = _time_step(frame, params, scene.sh_degree, cams_dev, o, images, targets,
-                                    scale, loss, dL, grads)
-                    results.append(dict(shape, ms=round(ms, 4)))
+                    for ln in (LANES if pb == 0 else ("quads",)):
+                        shape = {"raster_batch": b, "persistent_blocks": pb, "depth_presort": ps,
+                                 "balanced_digits": bd, "lanes": ln}
+                        o = opts_of(shape, **opts)
+                        ms = _time_step(frame, params, scene.sh_degree, cams_dev, o, images,
+                                        targets, scale, loss, dL, grads)
+                        results.append(dict(shape, ms=round(ms, 4)))
     best = dict(min(results, key=lambda r: r["ms"]))
     best["candidates"] = len(results)
     cache[sig] = best
