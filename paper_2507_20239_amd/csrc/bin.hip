@@ -1,14 +1,15 @@
 // Tile binning: per-tile, depth-ordered splat lists.
 //
 // The order inside a tile's list is (FP32 depth bits, entry id).  Instances
-// are grouped by tile with a stable radix sort on the tile id alone, and each
-// tile's list is then put in depth order by one wave that owns it:
+// are grouped by tile with a radix sort on the tile id alone, and each tile's
+// list is then put in depth order by one wave that owns it:
 //
 //   one exclusive scan of (tiles_touched > 0, tiles_touched) -> compacted
 //   visible entries and their instance offsets (entry order)
 //   emit (tile, entry) for every tile each footprint meets (or, with the
 //   3-sigma footprint, every tile of its rectangle), row-major
-//   radix sort on the tile id (stable)
+//   radix sort on the tile id (its first pass need not be stable: the
+//   per-tile sort fixes the order inside each list)
 //   tile ranges from adjacent keys;  optional heavy-first tile order
 //   per tile: sort the list by (depth bits, entry) in registers (one wave up
 //   to 512, the workgroup up to 2048), or for longer lists as register-sorted
@@ -642,8 +643,11 @@ gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first, bool preso
                                                          f->chunk_start, f->ikeys[0], f->ivals[0],
                                                          E, (u32)f->T);
         GS_TRY(gs_check_launch("emit"));
+        // the per-tile sort orders each list by (depth bits, entry) afterwards, so
+        // the first pass need not keep equal digits in order; after the depth
+        // presort the tile sort must be stable throughout
         GS_TRY(gs_radix_sort(f->ikeys, f->ivals, cnt + 5, 0, f->cap, f->tile_bits, f->sort_scratch,
-                             &f->isorted, s, balanced));
+                             &f->isorted, s, balanced, !presort));
     } else {
         GS_TRY(gs_fill_u32(cnt, 0u, 6, s));
     }

@@ -259,8 +259,13 @@ gs_status gs_scan_reduce(const u32* in, const u32* gather, const u32* n_dev, u32
 // `capacity` (< 2^30).  `scratch` needs gs_radix_scratch_bytes(capacity, bits).
 // balanced: digits of equal width (ceil(bits / passes)) instead of 8 bits and a
 // narrower last digit; the pass count, and so the result slot, is the same.
+// unstable_first: the first pass may place equal digits in any order (cheaper
+// ranking); the result is then ordered by key, but pairs with equal keys are
+// not in input order, so only a caller that orders them itself afterwards
+// may ask for it.
 gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
-                        int bits, void* scratch, int* slot, hipStream_t s, bool balanced = false);
+                        int bits, void* scratch, int* slot, hipStream_t s, bool balanced = false,
+                        bool unstable_first = false);
 uint64_t gs_radix_scratch_bytes(int64_t capacity, int bits);
 
 // sigma3: bin by 3-sigma squares (GS_RASTER_FOOTPRINT_3SIGMA) instead of the

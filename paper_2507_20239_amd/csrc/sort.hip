@@ -7,10 +7,11 @@
 //
 // Radix sort: 8-bit digits; per pass, per-workgroup digit counts, an
 // exclusive scan of the count matrix and a stable scatter.  Keys are ranked
-// inside a workgroup with a wave-level multi-split: eight ballots
-// give each lane the mask of lanes holding the same digit, the popcount below
+// inside a workgroup with a wave-level multi-split: one ballot per digit bit
+// gives each lane the mask of lanes holding the same digit, the popcount below
 // the lane is its rank within the item, per-wave running counters in LDS
-// order successive items, and a 4-wave exclusive scan orders the waves.
+// order successive items, and a 4-wave exclusive scan orders the waves.  A
+// pass that may reorder equal digits ranks each key with one LDS add instead.
 #include "gs_internal.h"
 
 namespace {
@@ -61,27 +62,30 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_count_kernel(const u32* __restr
     u32 beg, end;
     chunk_of(dev_len(n_dev, n_host), gridDim.x, blockIdx.x, beg, end);
     const u32 mask = (1u << bits) - 1u;
-    // eight keys per thread loaded before their digits are counted, so their
-    // loads are in flight together (the loop is bound by load latency)
+    const u32 lane = threadIdx.x & 63u;
+    const u64 above = lane < 63 ? ~0ull << (lane + 1) : 0ull;   // lanes above this one
+    // Counting needs no order among equal digits: one LDS add per run of equal
+    // digits in consecutive lanes, by the run's first lane (key streams here
+    // are locally coherent: a footprint's tiles, a tile group's high digit),
+    // and the LDS serialises only the equal digits that remain in a wave.
     for (u32 base = beg; base < end; base += 8 * GS_BLOCK) {
         u32 k[8];
+        // eight keys per thread loaded together (the loop is bound by load latency)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) k[j] = load_or_zero(keys, base + j * GS_BLOCK + threadIdx.x, end);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const u32 i = base + j * GS_BLOCK + threadIdx.x;
-            k[j] = i < end ? keys[i] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const bool valid = base + j * GS_BLOCK + threadIdx.x < end;
-            const u32 d = valid ? (k[j] >> shift) & mask : 0u;
-            // one LDS add per group of equal digits in the wave
-            u64 peers = __ballot(valid);
-            for (int b = 0; b < bits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const u64 bal = __ballot(bit);
-                peers &= bit ? bal : ~bal;
+            const bool valid = base + j * GS_BLOCK + threadIdx.x < end;   // a prefix of the wave
+            const u32 d = valid ? (k[j] >> shift) & mask : 0xffffffffu;
+            const u32 prev = (u32)__shfl_up((int)d, 1, 64);
+            const bool head = valid && (lane == 0 || d != prev);
+            // a run ends where the next one starts or the valid lanes end
+            const u64 stops = __ballot(head) | ~__ballot(valid);
+            if (head) {
+                const u64 nxt = stops & above;
+                const u32 len = (nxt ? (u32)__builtin_ctzll(nxt) : 64u) - lane;
+                atomicAdd(&h[d], len);
             }
-            if (valid && popc_below(peers) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
         }
     }
     __syncthreads();
@@ -116,7 +120,7 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_rowscan_kernel(u32* counts, u32
 __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
     const u32* __restrict__ kin, const u32* __restrict__ vin, u32* __restrict__ kout,
     u32* __restrict__ vout, const u32* n_dev, u32 n_host, int shift, int bits,
-    const u32* __restrict__ offs, const u32* __restrict__ dtot) {
+    const u32* __restrict__ offs, const u32* __restrict__ dtot, int unstable) {
     __shared__ u32 whist[4][256];
     __shared__ u32 s_base[256];    // global start of each digit's run for the next sub-batch
     __shared__ u32 s_local[256];   // start of each digit inside the sub-batch
@@ -135,7 +139,7 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
     for (u32 sub = beg; sub < end; sub += RADIX_SUB) {
         for (int j = lane; j < 256; j += 64) whist[w][j] = 0;
         __syncthreads();
-        u32 k[RADIX_ITEMS], v[RADIX_ITEMS], d[RADIX_ITEMS], r[RADIX_ITEMS];
+        u32 k[RADIX_ITEMS], v[RADIX_ITEMS], r[RADIX_ITEMS];
         // every item's key and value loaded before any is ranked: sixteen loads in
         // flight per thread instead of one round trip per item
 #pragma unroll
@@ -147,21 +151,26 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
 #pragma unroll
         for (int i = 0; i < RADIX_ITEMS; ++i) {
             const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
-            const bool valid = idx < end;
-            d[i] = (k[i] >> shift) & mask;
+            const bool valid = idx < end;   // a prefix of the wave
+            const u32 d = (k[i] >> shift) & mask;
+            if (unstable) {
+                // any order among equal digits: one LDS add per key takes its place
+                r[i] = valid ? atomicAdd(&whist[w][d], 1u) : 0u;
+                continue;
+            }
             u64 peers = __ballot(valid);
             for (int b = 0; b < bits; ++b) {
-                const bool bit = (d[i] >> b) & 1u;
+                const bool bit = (d >> b) & 1u;
                 const u64 bal = __ballot(bit);
                 peers &= bit ? bal : ~bal;
             }
             const u32 lo = popc_below(peers);
             const u32 cnt = (u32)__popcll(peers);
             u32 prior = 0;
-            if (valid) prior = whist[w][d[i]];
+            if (valid) prior = whist[w][d];
             r[i] = prior + lo;
             // the highest lane of each digit group advances the wave counter
-            if (valid && lo == cnt - 1u) whist[w][d[i]] = prior + cnt;
+            if (valid && lo == cnt - 1u) whist[w][d] = prior + cnt;
         }
         __syncthreads();
         const u32 c0 = whist[0][tid], c1 = whist[1][tid], c2 = whist[2][tid], c3 = whist[3][tid];
@@ -174,12 +183,12 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
         whist[2][tid] = loc + c0 + c1;
         whist[3][tid] = loc + c0 + c1 + c2;
         __syncthreads();
-        // place the sub-batch in LDS in (digit, original order) order
+        // place the sub-batch in LDS in (digit, rank) order
 #pragma unroll
         for (int i = 0; i < RADIX_ITEMS; ++i) {
             const u32 idx = sub + (u32)(w * 64 * RADIX_ITEMS + i * 64 + lane);
             if (idx < end) {
-                const u32 pos = whist[w][d[i]] + r[i];
+                const u32 pos = whist[w][(k[i] >> shift) & mask] + r[i];
                 s_key[pos] = k[i];
                 s_val[pos] = v[i];
             }
@@ -243,7 +252,8 @@ gs_status gs_scan_exclusive(const u32* in, u32* out, const u32* n_dev, u32 n_hos
 }
 
 gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int64_t capacity,
-                        int bits, void* scratch, int* slot, hipStream_t s, bool balanced) {
+                        int bits, void* scratch, int* slot, hipStream_t s, bool balanced,
+                        bool unstable_first) {
     const unsigned G = sort_blocks(capacity);
     u32* counts = (u32*)scratch;
     u32* part = counts + 256 * (uint64_t)G;
@@ -258,7 +268,8 @@ gs_status gs_radix_sort(u32* k[2], u32* v[2], const u32* n_dev, u32 n_host, int6
         sort_rowscan_kernel<<<256, GS_BLOCK, 0, s>>>(counts, G, part);
         GS_TRY(gs_check_launch("sort_rowscan"));
         sort_scatter_kernel<<<G, GS_BLOCK, 0, s>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n_dev,
-                                                   n_host, shift, b, counts, part);
+                                                   n_host, shift, b, counts, part,
+                                                   unstable_first && shift == 0 ? 1 : 0);
         GS_TRY(gs_check_launch("sort_scatter"));
         cur ^= 1;
     }
