@@ -158,12 +158,14 @@ __global__ void __launch_bounds__(GS_BLOCK) sort_scatter_kernel(
                 r[i] = valid ? atomicAdd(&whist[w][d], 1u) : 0u;
                 continue;
             }
-            u64 peers = __ballot(valid);
+            // lanes whose digit differs in some bit: a lane with bit b set
+            // differs from the lanes without it (~ballot), else from those with it
+            u64 differ = ~__ballot(valid);
             for (int b = 0; b < bits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const u64 bal = __ballot(bit);
-                peers &= bit ? bal : ~bal;
+                const u32 sb = (u32)((int)(d << (31 - b)) >> 31);   // bit b as 0 or all ones
+                differ |= __ballot(sb != 0u) ^ (((u64)sb << 32) | sb);
             }
+            const u64 peers = ~differ;
             const u32 lo = popc_below(peers);
             const u32 cnt = (u32)__popcll(peers);
             u32 prior = 0;
