@@ -392,9 +392,12 @@ __device__ __forceinline__ FootprintRows footprint_rows(float4 p0, float4 p1) {
     return f;
 }
 
-__device__ __forceinline__ bool footprint_row(const FootprintRows& f, int ty, int& c0, int& c1) {
-    float dya = ((float)(GS_TILE * ty) - f.hy) - f.ly;
-    float dyb = dya + (float)GS_TILE;
+// Columns [c0, c1] (of width w, 1 / w = iw) whose squares the ellipse meets
+// inside the row band y0 <= y <= y0 + h; false if it misses the band.
+__device__ __forceinline__ bool footprint_band(const FootprintRows& f, float y0, float h, float iw,
+                                               int& c0, int& c1) {
+    float dya = (y0 - f.hy) - f.ly;
+    float dyb = dya + h;
     if (dya > f.ry || dyb < -f.ry) return false;
     dya = fmaxf(dya, -f.ry);
     dyb = fminf(dyb, f.ry);
@@ -403,9 +406,31 @@ __device__ __forceinline__ bool footprint_row(const FootprintRows& f, int ty, in
     const float vl = f.l22 * dl, vr = f.l22 * dr;
     const float xl = (-__builtin_amdgcn_sqrtf(fmaxf(fmaf(-vl, vl, f.r2), 0.f)) - f.l21 * dl) * f.il11;
     const float xr = (__builtin_amdgcn_sqrtf(fmaxf(fmaf(-vr, vr, f.r2), 0.f)) - f.l21 * dr) * f.il11;
-    c0 = (int)ceilf((f.mx + xl) * (1.0f / GS_TILE)) - 1;   // 16 tx + 16 >= x_left
-    c1 = (int)floorf((f.mx + xr) * (1.0f / GS_TILE));      // 16 tx <= x_right
+    c0 = (int)ceilf((f.mx + xl) * iw) - 1;   // w c + w >= x_left
+    c1 = (int)floorf((f.mx + xr) * iw);      // w c <= x_right
     return true;
+}
+
+__device__ __forceinline__ bool footprint_row(const FootprintRows& f, int ty, int& c0, int& c1) {
+    return footprint_band(f, (float)(GS_TILE * ty), (float)GS_TILE, 1.0f / GS_TILE, c0, c1);
+}
+
+// The 8x8 quadrants of tile (tx, ty) that the footprint ellipse meets: bit
+// (q & 1) + 2 (q >> 1) for the quadrant at (8 (q & 1), 8 (q >> 1)), from the
+// row test at half resolution.  Every pixel whose alpha reaches 1/255 lies in
+// a quadrant of the mask.
+__device__ __forceinline__ u32 quadrant_mask(const FootprintRows& f, int tx, int ty) {
+    u32 m = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        int c0, c1;
+        if (footprint_band(f, (float)(GS_TILE * ty + 8 * h), 8.0f, 0.125f, c0, c1)) {
+            const int cl = 2 * tx;
+            if (c0 <= cl && cl <= c1) m |= 1u << (2 * h);
+            if (c0 <= cl + 1 && cl + 1 <= c1) m |= 2u << (2 * h);
+        }
+    }
+    return m;
 }
 
 // Number of tiles of row ty inside the rectangle columns [x0, x1]; the first

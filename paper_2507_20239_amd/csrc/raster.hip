@@ -92,6 +92,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 struct TileCoords {
     gs_view_info vi;
     uint2 rg;
+    int tx, ty;     // tile of the view
+    int q;          // one pixel per lane: the wave's quadrant
     int qx, qy;     // top-left pixel of the lane's quad
     int pi;         // one pixel per lane: the lane's pixel within its quad
 };
@@ -102,15 +104,18 @@ __device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t, u3
     const int v = find_view(a.views, a.V, t);
     c.vi = a.views[v];
     const int lt = (int)t - c.vi.tile_base;
-    const int tx = lt % c.vi.tiles_x, ty = lt / c.vi.tiles_x;
+    c.tx = lt % c.vi.tiles_x;
+    c.ty = lt / c.vi.tiles_x;
     const int lane = threadIdx.x;
     if (PIXQ == 4) {
-        c.qx = tx * GS_TILE + 2 * (lane & 7);
-        c.qy = ty * GS_TILE + 2 * (lane >> 3);
+        c.q = 0;
+        c.qx = c.tx * GS_TILE + 2 * (lane & 7);
+        c.qy = c.ty * GS_TILE + 2 * (lane >> 3);
         c.pi = 0;
     } else {
-        const int px = tx * GS_TILE + 8 * (int)(quarter & 1u) + (lane & 7);
-        const int py = ty * GS_TILE + 8 * (int)(quarter >> 1) + (lane >> 3);
+        c.q = (int)quarter;
+        const int px = c.tx * GS_TILE + 8 * (int)(quarter & 1u) + (lane & 7);
+        const int py = c.ty * GS_TILE + 8 * (int)(quarter >> 1) + (lane >> 3);
         c.qx = px & ~1;
         c.qy = py & ~1;
         c.pi = (px & 1) | ((py & 1) << 1);
@@ -162,20 +167,50 @@ struct LaneGeom<1> {
     }
 };
 
-// Stage splats [b0, b0 + cnt) of the sorted instance list in LDS; the fourth
-// component of the colour record (unused in HBM) carries the entry id.
-template <int BATCH>
-__device__ __forceinline__ void load_batch(const RasterArgs& a, u32 b0, u32 cnt, float4* sp0,
-                                           float4* sp1, float4* sp2) {
-    for (u32 j = threadIdx.x; j < cnt; j += 64) {
-        u32 e = a.inst_entry[b0 + j];
-        if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
-        sp0[j] = a.splat[3 * (u64)e + 0];
-        sp1[j] = a.splat[3 * (u64)e + 1];
-        float4 c = a.splat[3 * (u64)e + 2];
-        c.w = __uint_as_float(e);
-        sp2[j] = c;
+// One batch of a tile's list in LDS: the splat records (the fourth component
+// of the colour record, unused in HBM, carries the entry id) and, for a wave
+// that owns one quadrant (one pixel per lane), the batch indices of the
+// splats whose footprint meets its quadrant, in list order (one slot more:
+// the walk reads the index after the last one ahead of its use).
+template <int BATCH, int PIXQ>
+struct Stage {
+    float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
+    unsigned short sub[PIXQ == 1 ? BATCH + 1 : 1];
+};
+
+// Stage splats [b0, b0 + cnt) of the sorted instance list; returns the
+// number of splat steps.  Quads: every splat of the batch.  One pixel per
+// lane: only the splats whose footprint meets the wave's quadrant (the tile
+// culling's ellipse test at half resolution), listed in S.sub in list order;
+// a pixel outside every quadrant a splat meets has alpha < 1/255 for it, so
+// walking only those splats leaves every pixel's compositing unchanged.
+template <int BATCH, int PIXQ>
+__device__ __forceinline__ u32 stage_batch(const RasterArgs& a, u32 b0, u32 cnt,
+                                           const TileCoords& tc, Stage<BATCH, PIXQ>& S) {
+    const u32 lane = threadIdx.x;
+    u32 n = 0;
+    for (u32 r = 0; r < cnt; r += 64) {
+        const u32 j = r + lane;
+        bool in = false;
+        if (j < cnt) {
+            u32 e = a.inst_entry[b0 + j];
+            if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
+            const float4 p0 = a.splat[3 * (u64)e + 0];
+            const float4 p1 = a.splat[3 * (u64)e + 1];
+            float4 c = a.splat[3 * (u64)e + 2];
+            c.w = __uint_as_float(e);
+            S.sp0[j] = p0;
+            S.sp1[j] = p1;
+            S.sp2[j] = c;
+            if (PIXQ == 1) in = (quadrant_mask(footprint_rows(p0, p1), tc.tx, tc.ty) >> tc.q) & 1u;
+        }
+        if (PIXQ == 1) {
+            const u64 m = __ballot(in);
+            if (in) S.sub[n + popc_below(m)] = (unsigned short)j;
+            n += (u32)__popcll(m);
+        }
     }
+    return PIXQ == 4 ? cnt : n;
 }
 
 // Some pixel of the lane still composites (T > 0).  Signed-integer order of
@@ -194,7 +229,7 @@ __device__ __forceinline__ bool any_live(const float* T) {
 
 template <int BATCH, bool COUNT, int PIXQ>
 __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
-    __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
+    __shared__ Stage<BATCH, PIXQ> S;
     const u32 n_items = PIXQ == 4 ? (u32)a.T : 4u * (u32)a.T;
     for (u32 item = next_item(a, n_items, true); item < n_items;
          item = next_item(a, n_items, false)) {
@@ -221,11 +256,17 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
             if (__ballot(any_live<PIXQ>(T)) == 0) break;
             const u32 cnt = min((u32)BATCH, tc.rg.y - b0);
             __syncthreads();
-            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2);
+            const u32 n = stage_batch<BATCH, PIXQ>(a, b0, cnt, tc, S);
             __syncthreads();
-            for (u32 k = 0; k < cnt; ++k) {
-                const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
-                const u32 idx = b0 - tc.rg.x + k + 1;
+            // idx: the list position + 1
+            const u32 base = b0 - tc.rg.x + 1;
+            u32 kn = PIXQ == 4 ? 0u : S.sub[0];
+            for (u32 s = 0; s < n; ++s) {
+                // the splat: step s of the batch (quads) or of the quadrant's list
+                const u32 k = PIXQ == 4 ? s : kn;
+                if (PIXQ == 1) kn = S.sub[s + 1];
+                const float4 p0 = S.sp0[k], p1 = S.sp1[k], c = S.sp2[k];
+                const u32 idx = base + k;
                 LaneGeom<PIXQ> g;
                 g.setup(p0, p1, qxc, qyc, tc.pi);
 #pragma unroll
@@ -272,7 +313,7 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
 
 template <int BATCH, int PIXQ>
 __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
-    __shared__ float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
+    __shared__ Stage<BATCH, PIXQ> S;
     // transpose buffer of the per-splat reduction: value j of lane l at red[j][l]
     // (rows padded by 16 bytes to spread the 16-byte reads over the banks)
     __shared__ float red[9][RED_STRIDE];
@@ -320,11 +361,15 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
             const u32 b0 = tc.rg.x + (u32)bi * BATCH;
             const u32 cnt = min((u32)BATCH, mlast - (u32)bi * BATCH);
             __syncthreads();
-            load_batch<BATCH>(a, b0, cnt, sp0, sp1, sp2);
+            const u32 n = stage_batch<BATCH, PIXQ>(a, b0, cnt, tc, S);
             __syncthreads();
-            for (int k = (int)cnt - 1; k >= 0; --k) {
-                const u32 rel = (u32)bi * BATCH + (u32)k;
-                const float4 p0 = sp0[k], p1 = sp1[k], c = sp2[k];
+            // back to front over the batch (quads) or the quadrant's list
+            u32 kn = PIXQ == 4 ? 0u : S.sub[n > 0 ? n - 1 : 0];
+            for (int s = (int)n - 1; s >= 0; --s) {
+                const u32 k = PIXQ == 4 ? (u32)s : kn;
+                if (PIXQ == 1) kn = S.sub[s > 0 ? s - 1 : 0];
+                const u32 rel = (u32)bi * BATCH + k;
+                const float4 p0 = S.sp0[k], p1 = S.sp1[k], c = S.sp2[k];
                 LaneGeom<PIXQ> g;
                 g.setup(p0, p1, qxc, qyc, tc.pi);
                 // per pixel: go = dL/dalpha * G (zero where the splat did not
