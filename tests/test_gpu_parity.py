@@ -468,6 +468,66 @@ def test_persistent_backward_after_plain_render_is_rejected_on_the_host():
     assert torch.allclose(ga, gb, rtol=1e-4, atol=1e-6 * float(ga.abs().max()))
 
 
+def _quadrant_edge_scene(seed=41, n=6000, W=160, H=112):
+    """Small and elongated Gaussians centred on and next to the 8-pixel
+    quadrant lines and the 16-pixel tile lines, with opacities from just above
+    the 1/255 cutoff to 1: the splats whose quadrant masks decide the most
+    (pixel lanes walk only the splats meeting their quadrant)."""
+    rng = np.random.default_rng(seed)
+    base = synth.random_scene(seed, 8, W, H, sh_degree=1)
+    cam = base.cameras[0]
+    u = 8.0 * rng.integers(0, W // 8 + 1, n) + rng.choice([0.0, 0.5, -0.5, 1e-3, -1e-3, 2.0], n)
+    w = 8.0 * rng.integers(0, H // 8 + 1, n) + rng.choice([0.0, 0.5, -0.5, 1e-3, -1e-3, 2.0], n)
+    z = rng.uniform(1.0, 4.0, n)
+    camp = np.stack([(u - cam.cx) * z / cam.fx, (w - cam.cy) * z / cam.fy, z])
+    means = cam.R.T @ (camp - cam.t[:, None])
+    log_scales = rng.uniform(-5.5, -2.5, (3, n))
+    thin = rng.random(n) < 0.4
+    log_scales[0, thin] -= 3.0
+    logits = np.where(rng.random(n) < 0.3, rng.uniform(-5.6, -5.0, n), rng.normal(0.0, 2.0, n))
+    f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)  # noqa: E731
+    return synth.Scene(f32(means), f32(log_scales), f32(rng.standard_normal((4, n))), f32(logits),
+                       f32(rng.normal(0.0, 0.3, (4, 3, n))), 1, [cam],
+                       [np.zeros((3, H, W), np.float32)], np.zeros(3, np.float32))
+
+
+@pytest.mark.parametrize("sigma3", [False, True])
+def test_quadrant_walk_is_exact(sigma3):
+    """Pixel lanes walk only the splats whose footprint meets their 8x8
+    quadrant; quads walk every splat of the list.  On splats sitting on the
+    quadrant and tile lines both give bit-identical images, transmittance,
+    walk lengths and composited counts (a splat skipped wrongly would change
+    them), and the same gradients up to FP32 summation order; under the
+    3-sigma footprint the lists hold splats the ellipse test excludes."""
+    sc = _quadrant_edge_scene()
+    cams = sc.cameras
+    out = {}
+    dL = None
+    for lanes in ("pixels", "quads"):
+        opts = gsmi.raster_opts(bg=(0.1, 0.2, 0.3), count_composited=True, lanes=lanes,
+                                footprint_3sigma=sigma3)
+        frame, flat, *_ = gpu_forward(sc, cams, opts)
+        if dL is None:
+            rng = np.random.default_rng(3)
+            dL = torch.from_numpy(rng.standard_normal(flat.numel()).astype(np.float32)).to(dev())
+        frame.render_backward(opts, dL)
+        torch.cuda.synchronize()
+        out[lanes] = dict(img=flat.clone(),
+                          T=frame.buffer(gsmi.BUF_T_FINAL, torch.float32).clone(),
+                          n=frame.buffer(gsmi.BUF_N_CONTRIB).clone(),
+                          nc=frame.buffer(gsmi.BUF_N_COMPOSITED).clone(),
+                          g=frame.buffer(gsmi.BUF_SPLAT_GRAD, torch.float32).view(-1, 9).clone(),
+                          tt=frame.buffer(gsmi.BUF_TILES_TOUCHED).clone())
+    a, b = out["pixels"], out["quads"]
+    assert int((a["nc"] > 0).sum()) > 1000
+    for k in ("img", "T", "n", "nc", "tt"):
+        assert torch.equal(a[k], b[k]), k
+    r = a["tt"] > 0
+    ga, gb = a["g"][r].double(), b["g"][r].double()
+    scale = gb.abs().max(dim=0).values.clamp_min(1e-30)
+    assert ((ga - gb).abs() <= 1e-5 * scale + 1e-5 * gb.abs()).all()
+
+
 def test_lane_layouts_agree():
     """One pixel per lane and 2x2 quads per lane: images, final transmittance,
     walk lengths and composited counts bit-identical (each pixel's arithmetic
