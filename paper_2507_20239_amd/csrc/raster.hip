@@ -84,21 +84,23 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Lane layout.  PIXQ = 4: lane l owns the 2x2 quad whose top-left pixel is
-// (16 tx + 2 (l % 8), 16 ty + 2 (l / 8)).  PIXQ = 1: work item 4 t + q is
-// quarter q of tile t, the 8x8 pixels at (16 tx + 8 (q % 2), 16 ty + 8 (q / 2)),
-// and lane l owns pixel (l % 8, l / 8) of it.  Either way a lane's pixels lie
-// in one quad with top-left pixel (qx, qy); its pixel i is (qx + i % 2,
-// qy + i / 2), for i < 4 (quads) or i = pi (one pixel).
+// (16 tx + 2 (l % 8), 16 ty + 2 (l / 8)); grouped by quadrant (the forward),
+// lanes 16 q .. 16 q + 15 own quadrant q, the 8x8 pixels at (16 tx + 8 (q % 2),
+// 16 ty + 8 (q / 2)), lane 16 q + j the quad at (2 (j % 4), 2 (j / 4)) of it.
+// PIXQ = 1: work item 4 t + q is quarter (quadrant) q of tile t, and lane l
+// owns pixel (l % 8, l / 8) of it.  Either way a lane's pixels lie in one quad
+// with top-left pixel (qx, qy); its pixel i is (qx + i % 2, qy + i / 2), for
+// i < 4 (quads) or i = pi (one pixel).
 struct TileCoords {
     gs_view_info vi;
     uint2 rg;
     int tx, ty;     // tile of the view
-    int q;          // one pixel per lane: the wave's quadrant
+    int q;          // the quadrant of the lane's pixels (grouped quads, one pixel per lane)
     int qx, qy;     // top-left pixel of the lane's quad
     int pi;         // one pixel per lane: the lane's pixel within its quad
 };
 
-template <int PIXQ>
+template <int PIXQ, bool GROUPED>
 __device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t, u32 quarter) {
     TileCoords c;
     const int v = find_view(a.views, a.V, t);
@@ -107,7 +109,13 @@ __device__ __forceinline__ TileCoords tile_coords(const RasterArgs& a, u32 t, u3
     c.tx = lt % c.vi.tiles_x;
     c.ty = lt / c.vi.tiles_x;
     const int lane = threadIdx.x;
-    if (PIXQ == 4) {
+    if (PIXQ == 4 && GROUPED) {
+        c.q = lane >> 4;
+        const int j = lane & 15;
+        c.qx = c.tx * GS_TILE + 8 * (c.q & 1) + 2 * (j & 3);
+        c.qy = c.ty * GS_TILE + 8 * (c.q >> 1) + 2 * (j >> 2);
+        c.pi = 0;
+    } else if (PIXQ == 4) {
         c.q = 0;
         c.qx = c.tx * GS_TILE + 2 * (lane & 7);
         c.qy = c.ty * GS_TILE + 2 * (lane >> 3);
@@ -168,30 +176,46 @@ struct LaneGeom<1> {
 };
 
 // One batch of a tile's list in LDS: the splat records (the fourth component
-// of the colour record, unused in HBM, carries the entry id) and, for a wave
-// that owns one quadrant (one pixel per lane), the batch indices of the
-// splats whose footprint meets its quadrant, in list order (one slot more:
-// the walk reads the index after the last one ahead of its use).
-template <int BATCH, int PIXQ>
+// of the colour record, unused in HBM, carries the entry id; record BATCH is
+// all zeros, so alpha is 0 at every pixel and a step on it changes nothing)
+// and NQ quadrant lists: per quadrant, the batch indices of the splats whose
+// footprint meets it, in list order, padded with BATCH to the longest (one
+// slot more: the walk reads the next index ahead of its use).  NQ = 4: the
+// grouped quads of the forward; NQ = 1: a quarter's wave (one pixel per
+// lane); NQ = 0: the whole batch in order.
+template <int BATCH, int NQ>
 struct Stage {
-    float4 sp0[BATCH], sp1[BATCH], sp2[BATCH];
-    unsigned short sub[PIXQ == 1 ? BATCH + 1 : 1];
+    float4 sp0[BATCH + 1], sp1[BATCH + 1], sp2[BATCH + 1];
+    unsigned short sub[NQ > 0 ? NQ : 1][NQ > 0 ? BATCH + 2 : 1];
 };
 
-// Stage splats [b0, b0 + cnt) of the sorted instance list; returns the
-// number of splat steps.  Quads: every splat of the batch.  One pixel per
-// lane: only the splats whose footprint meets the wave's quadrant (the tile
-// culling's ellipse test at half resolution), listed in S.sub in list order;
-// a pixel outside every quadrant a splat meets has alpha < 1/255 for it, so
-// walking only those splats leaves every pixel's compositing unchanged.
-template <int BATCH, int PIXQ>
-__device__ __forceinline__ u32 stage_batch(const RasterArgs& a, u32 b0, u32 cnt,
-                                           const TileCoords& tc, Stage<BATCH, PIXQ>& S) {
+template <int BATCH, int NQ>
+__device__ __forceinline__ void zero_record(Stage<BATCH, NQ>& S) {
+    if (threadIdx.x == 0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        S.sp0[BATCH] = z;
+        S.sp1[BATCH] = z;
+        S.sp2[BATCH] = z;
+    }
+}
+
+// Stage splats [b0, b0 + cnt) of the sorted instance list and build the
+// quadrant lists (list q: the splats j < lim[q] whose footprint meets
+// quadrant q, or the wave's quadrant tc.q when NQ = 1), from the tile
+// culling's ellipse test at half resolution.  A pixel outside every quadrant
+// a splat meets has alpha < 1/255 for it, so walking only its quadrant's list
+// leaves every pixel's compositing unchanged.  Returns the number of steps:
+// the longest list, or cnt when NQ = 0.
+template <int BATCH, int NQ>
+__device__ __forceinline__ u32 stage_batch(const RasterArgs& a, u32 b0, u32 cnt, const u32* lim,
+                                           const TileCoords& tc, Stage<BATCH, NQ>& S) {
     const u32 lane = threadIdx.x;
-    u32 n = 0;
+    u32 n[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) n[q] = 0;
     for (u32 r = 0; r < cnt; r += 64) {
         const u32 j = r + lane;
-        bool in = false;
+        u32 m = 0;
         if (j < cnt) {
             u32 e = a.inst_entry[b0 + j];
             if (e >= a.E) e = a.E - 1;   // never taken for a consistent frame
@@ -202,15 +226,25 @@ __device__ __forceinline__ u32 stage_batch(const RasterArgs& a, u32 b0, u32 cnt,
             S.sp0[j] = p0;
             S.sp1[j] = p1;
             S.sp2[j] = c;
-            if (PIXQ == 1) in = (quadrant_mask(footprint_rows(p0, p1), tc.tx, tc.ty) >> tc.q) & 1u;
+            if (NQ > 0) m = quadrant_mask(footprint_rows(p0, p1), tc.tx, tc.ty);
+            if (NQ == 1) m >>= tc.q;
         }
-        if (PIXQ == 1) {
-            const u64 m = __ballot(in);
-            if (in) S.sub[n + popc_below(m)] = (unsigned short)j;
-            n += (u32)__popcll(m);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const bool in = ((m >> q) & 1u) != 0 && j < lim[q];
+            const u64 bal = __ballot(in);
+            if (in) S.sub[q][n[q] + popc_below(bal)] = (unsigned short)j;
+            n[q] += (u32)__popcll(bal);
         }
     }
-    return PIXQ == 4 ? cnt : n;
+    if (NQ == 0) return cnt;
+    u32 nmax = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) nmax = max(nmax, n[q]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        for (u32 s = n[q] + lane; s <= nmax; s += 64) S.sub[q][s] = (unsigned short)BATCH;
+    return nmax;
 }
 
 // Some pixel of the lane still composites (T > 0).  Signed-integer order of
@@ -229,14 +263,16 @@ __device__ __forceinline__ bool any_live(const float* T) {
 
 template <int BATCH, bool COUNT, int PIXQ>
 __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
-    __shared__ Stage<BATCH, PIXQ> S;
+    constexpr int NQ = PIXQ == 4 ? 4 : 1;
+    __shared__ Stage<BATCH, NQ> S;
+    zero_record(S);
     const u32 n_items = PIXQ == 4 ? (u32)a.T : 4u * (u32)a.T;
     for (u32 item = next_item(a, n_items, true); item < n_items;
          item = next_item(a, n_items, false)) {
         const u32 it = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
         const u32 t = PIXQ == 4 ? it : it >> 2;
         if (t >= (u32)a.T) continue;   // never taken for an order the binning built
-        const TileCoords tc = tile_coords<PIXQ>(a, t, it & 3u);
+        const TileCoords tc = tile_coords<PIXQ, true>(a, t, it & 3u);
         const float qxc = (float)tc.qx + 0.5f, qyc = (float)tc.qy + 0.5f;
         // T < 0 marks a finished pixel, with |T| its final transmittance
         // (pixels outside the image start finished); the sign replaces a
@@ -252,19 +288,27 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
             last[i] = 0;
             ncomp[i] = 0;
         }
+        // each lane walks the list of its quadrant (the four 16-lane groups of a
+        // quad wave walk four lists side by side, as many steps as the longest)
+        const unsigned short* my = S.sub[PIXQ == 4 ? tc.q : 0];
         for (u32 b0 = tc.rg.x; b0 < tc.rg.y; b0 += BATCH) {
-            if (__ballot(any_live<PIXQ>(T)) == 0) break;
+            const u64 live = __ballot(any_live<PIXQ>(T));
+            if (live == 0) break;
             const u32 cnt = min((u32)BATCH, tc.rg.y - b0);
+            // a quadrant whose pixels have all finished needs no list
+            u32 lim[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                lim[q] = PIXQ == 1 || ((live >> (16 * q)) & 0xffffull) != 0 ? cnt : 0u;
             __syncthreads();
-            const u32 n = stage_batch<BATCH, PIXQ>(a, b0, cnt, tc, S);
+            const u32 n = stage_batch<BATCH, NQ>(a, b0, cnt, lim, tc, S);
             __syncthreads();
             // idx: the list position + 1
             const u32 base = b0 - tc.rg.x + 1;
-            u32 kn = PIXQ == 4 ? 0u : S.sub[0];
+            u32 kn = my[0];
             for (u32 s = 0; s < n; ++s) {
-                // the splat: step s of the batch (quads) or of the quadrant's list
-                const u32 k = PIXQ == 4 ? s : kn;
-                if (PIXQ == 1) kn = S.sub[s + 1];
+                const u32 k = kn;
+                kn = my[s + 1];
                 const float4 p0 = S.sp0[k], p1 = S.sp1[k], c = S.sp2[k];
                 const u32 idx = base + k;
                 LaneGeom<PIXQ> g;
@@ -313,7 +357,8 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
 
 template <int BATCH, int PIXQ>
 __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
-    __shared__ Stage<BATCH, PIXQ> S;
+    constexpr int NQ = PIXQ == 4 ? 0 : 1;
+    __shared__ Stage<BATCH, NQ> S;
     // transpose buffer of the per-splat reduction: value j of lane l at red[j][l]
     // (rows padded by 16 bytes to spread the 16-byte reads over the banks)
     __shared__ float red[9][RED_STRIDE];
@@ -328,7 +373,7 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
         const u32 it = __builtin_amdgcn_readfirstlane(a.order ? a.order[item] : item);
         const u32 t = PIXQ == 4 ? it : it >> 2;
         if (t >= (u32)a.T) continue;   // never taken for an order the binning built
-        const TileCoords tc = tile_coords<PIXQ>(a, t, it & 3u);
+        const TileCoords tc = tile_coords<PIXQ, false>(a, t, it & 3u);
         const float qxc = (float)tc.qx + 0.5f, qyc = (float)tc.qy + 0.5f;
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
         float T[PIXQ], g0[PIXQ], g1[PIXQ], g2[PIXQ], sd[PIXQ];
@@ -360,14 +405,19 @@ __global__ void __launch_bounds__(64) raster_bwd_kernel(RasterArgs a) {
         for (int bi = (int)((mlast + BATCH - 1) / BATCH) - 1; bi >= 0; --bi) {
             const u32 b0 = tc.rg.x + (u32)bi * BATCH;
             const u32 cnt = min((u32)BATCH, mlast - (u32)bi * BATCH);
+            const u32 lim[1] = {cnt};
             __syncthreads();
-            const u32 n = stage_batch<BATCH, PIXQ>(a, b0, cnt, tc, S);
+            const u32 n = stage_batch<BATCH, NQ>(a, b0, cnt, lim, tc, S);
             __syncthreads();
             // back to front over the batch (quads) or the quadrant's list
-            u32 kn = PIXQ == 4 ? 0u : S.sub[n > 0 ? n - 1 : 0];
+            u32 kn = 0;
+            if constexpr (NQ == 1) kn = S.sub[0][n > 0 ? n - 1 : 0];
             for (int s = (int)n - 1; s >= 0; --s) {
-                const u32 k = PIXQ == 4 ? (u32)s : kn;
-                if (PIXQ == 1) kn = S.sub[s > 0 ? s - 1 : 0];
+                u32 k = (u32)s;
+                if constexpr (NQ == 1) {
+                    k = kn;
+                    kn = S.sub[0][s > 0 ? s - 1 : 0];
+                }
                 const u32 rel = (u32)bi * BATCH + k;
                 const float4 p0 = S.sp0[k], p1 = S.sp1[k], c = S.sp2[k];
                 LaneGeom<PIXQ> g;
