@@ -26,13 +26,19 @@ namespace {
 // Instance emission, balanced per 256 instances.  Pass 1 records, for every
 // chunk of 256 consecutive instance slots, the visible entry whose tiles
 // start the chunk.  Pass 2 gives each workgroup whole chunks: it stages the
-// (at most 256) entries a chunk can touch in LDS, and each thread finds the
-// entry of its slot by binary search over their offsets (strictly
-// increasing: every visible entry has at least one tile), then writes
-// (tile, entry) for the k-th tile of the rectangle, row-major.  Balancing on
-// instances rather than on entries keeps the workgroups even when a few
-// footprints cover many tiles.
+// (at most 256) entries a chunk can touch in LDS.  With the rectangle test,
+// and with the ellipse test when the chunk holds many entries (small
+// footprints), each thread finds the entry of its slot by binary search over
+// their offsets (strictly increasing: every visible entry has at least one
+// tile) and the k-th tile of that entry, walking its rows; when the chunk
+// holds few entries (footprints of many rows, whose every instance would walk
+// them again) the threads first count the tiles of the entries' rows, one
+// row each, and each slot then searches the rows.  Balancing on instances
+// rather than on entries keeps the workgroups even when a few footprints
+// cover many tiles.
 constexpr u32 EMIT_CHUNK = 256;
+// Chunks of at most this many entries count their rows in passes.
+constexpr int EMIT_PASS_MAX_ENTRIES = 48;
 
 // Visible entries and their instance offsets in one scan: each entry adds
 // (1 << 32 | tiles) if it has tiles, so the exclusive prefix holds its slot in
@@ -161,6 +167,21 @@ __global__ void __launch_bounds__(GS_BLOCK) vis_down_kernel(const u32* tt, u32 n
     }
 }
 
+// The footprint row constants of staged entry j.
+__device__ __forceinline__ FootprintRows staged_rows(const float (&s)[9][EMIT_CHUNK], int j) {
+    FootprintRows f;
+    f.l21 = s[0][j];
+    f.l22 = s[1][j];
+    f.r2 = s[2][j];
+    f.ry = s[3][j];
+    f.ds = s[4][j];
+    f.il11 = s[5][j];
+    f.mx = s[6][j];
+    f.hy = s[7][j];
+    f.ly = s[8][j];
+    return f;
+}
+
 template <bool SIGMA3>
 __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, const u32* offs,
                                                         const uint2* rect, const float4* splat,
@@ -168,10 +189,17 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
                                                         const u32* n_vis, const u32* n_kept,
                                                         const u32* chunk_start, u32* tile_keys,
                                                         u32* entries, int64_t E, u32 T) {
+    // per staged entry: its instance offset, entry, columns x0 | x1 << 16 and
+    // rows y0 | y1 << 16, first tile of its view and the view's tiles per row
     __shared__ u32 s_off[EMIT_CHUNK], s_e[EMIT_CHUNK], s_rx[EMIT_CHUNK], s_ry[EMIT_CHUNK];
     __shared__ u32 s_tb[EMIT_CHUNK], s_tw[EMIT_CHUNK];
     // the footprint row constants of each staged entry, computed once per entry
     __shared__ float s_fr[9][EMIT_CHUNK];
+    // row passes: the first row slot of each staged entry; per row slot of a
+    // pass its first instance, its first tile and its staged entry
+    __shared__ u32 s_rs[EMIT_CHUNK], s_roff[EMIT_CHUNK], s_rtile[EMIT_CHUNK];
+    __shared__ unsigned char s_rlo[EMIT_CHUNK];
+    __shared__ u32 lds4[4];
     const int t = threadIdx.x;
     const u32 nv = *n_vis, kept = *n_kept;
     const u32 chunks = (kept + EMIT_CHUNK - 1) / EMIT_CHUNK;
@@ -182,6 +210,11 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
         const u32 j1 = c + 1 < chunks ? chunk_start[c + 1] : nv - 1;
         const u32 span = j1 - j0 + 1;
         const int m = span < EMIT_CHUNK ? (int)span : (int)EMIT_CHUNK;
+        // with few entries per chunk (footprints of many tiles) the rows are
+        // counted once each, in passes; with many (small footprints) every
+        // instance walks its entry's rows itself
+        const bool passes = !SIGMA3 && m <= EMIT_PASS_MAX_ENTRIES;
+        u32 rows = 0;
         __syncthreads();
         if (t < m) {
             u32 e = visible[j0 + t];
@@ -195,6 +228,8 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
             s_ry[t] = r.y;
             s_tb[t] = (u32)views[v].tile_base;
             s_tw[t] = (u32)views[v].tiles_x;
+            const int y0 = (int)(r.y & 0xffffu), y1 = (int)(r.y >> 16);
+            rows = y1 >= y0 ? (u32)(y1 - y0 + 1) : 0u;
             if (!SIGMA3) {
                 const FootprintRows fr = footprint_rows(splat[3 * (u64)e], splat[3 * (u64)e + 1]);
                 s_fr[0][t] = fr.l21;
@@ -208,49 +243,96 @@ __global__ void __launch_bounds__(GS_BLOCK) emit_kernel(const u32* visible, cons
                 s_fr[8][t] = fr.ly;
             }
         }
-        __syncthreads();
         const u32 o = c * EMIT_CHUNK + (u32)t;
-        if (o < kept) {
-            int lo = 0, hi = m - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= o) lo = mid;
-                else hi = mid - 1;
-            }
-            // the k-th tile of the entry, rows top to bottom, columns left to right,
-            // counted exactly as the projection counted them
-            u32 k = o - s_off[lo];
-            const u32 rx = s_rx[lo], ry = s_ry[lo];
-            const int x0 = (int)(rx & 0xffffu), x1 = (int)(rx >> 16);
-            const int y0 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
-            u32 tile = T;   // not reached: the rows hold exactly the counted tiles
-            if (SIGMA3) {
-                // every tile of the rectangle
-                const u32 w = (u32)(x1 - x0 + 1);
-                tile = s_tb[lo] + ((u32)y0 + k / w) * s_tw[lo] + (u32)x0 + k % w;
-            } else {
-                FootprintRows fr;
-                fr.l21 = s_fr[0][lo];
-                fr.l22 = s_fr[1][lo];
-                fr.r2 = s_fr[2][lo];
-                fr.ry = s_fr[3][lo];
-                fr.ds = s_fr[4][lo];
-                fr.il11 = s_fr[5][lo];
-                fr.mx = s_fr[6][lo];
-                fr.hy = s_fr[7][lo];
-                fr.ly = s_fr[8][lo];
-                for (int ty = y0; ty <= y1; ++ty) {
-                    int first = 0;
-                    const u32 cnt = footprint_row_count(fr, ty, x0, x1, &first);
-                    if (k < cnt) {
-                        tile = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first + k;
-                        break;
-                    }
-                    k -= cnt;
+        if (!passes) {
+            __syncthreads();
+            if (o < kept) {
+                int lo = 0, hi = m - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= o) lo = mid;
+                    else hi = mid - 1;
                 }
+                // the k-th tile of the entry, rows top to bottom, columns left to
+                // right, counted exactly as the projection counted them
+                u32 k = o - s_off[lo];
+                const u32 rx = s_rx[lo], ry = s_ry[lo];
+                const int x0 = (int)(rx & 0xffffu), x1 = (int)(rx >> 16);
+                const int y0 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
+                u32 tile = T;   // not reached: the rows hold exactly the counted tiles
+                if (SIGMA3) {
+                    // every tile of the rectangle
+                    const u32 w = (u32)(x1 - x0 + 1);
+                    tile = s_tb[lo] + ((u32)y0 + k / w) * s_tw[lo] + (u32)x0 + k % w;
+                } else {
+                    const FootprintRows fr = staged_rows(s_fr, lo);
+                    for (int ty = y0; ty <= y1; ++ty) {
+                        int first = 0;
+                        const u32 cnt = footprint_row_count(fr, ty, x0, x1, &first);
+                        if (k < cnt) {
+                            tile = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first + k;
+                            break;
+                        }
+                        k -= cnt;
+                    }
+                }
+                tile_keys[o] = tile;
+                entries[o] = s_e[lo];
             }
-            tile_keys[o] = tile;
-            entries[o] = s_e[lo];
+            continue;
+        }
+        // Row passes: the rows of the staged entries in order, a workgroup's
+        // width at a time.  Each thread counts the tiles of one row with the
+        // projection's row test, a scan of the counts places the rows'
+        // instances (the first staged entry's instances start at its offset,
+        // and every entry's rows hold exactly the tiles the projection
+        // counted), and each instance of the chunk finds its row by binary
+        // search.  Passes stop once they reach the end of the chunk.
+        u32 nr;
+        const u32 rs = block_exclusive_scan(rows, lds4, nr);
+        if (t < m) s_rs[t] = rs;
+        const u32 end = min(kept, c * EMIT_CHUNK + EMIT_CHUNK);
+        u32 base = s_off[0];   // uniform, like every pass total below
+        for (u32 p0 = 0; p0 < nr && base < end; p0 += EMIT_CHUNK) {
+            __syncthreads();
+            const u32 r = p0 + (u32)t;
+            u32 cnt = 0, tile0 = 0;
+            int lo = 0;
+            if (r < nr) {
+                // the staged entry that owns row slot r
+                int hi = m - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_rs[mid] <= r) lo = mid;
+                    else hi = mid - 1;
+                }
+                const FootprintRows fr = staged_rows(s_fr, lo);
+                const u32 rx = s_rx[lo];
+                const int ty = (int)(s_ry[lo] & 0xffffu) + (int)(r - s_rs[lo]);
+                int first = 0;
+                cnt = footprint_row_count(fr, ty, (int)(rx & 0xffffu), (int)(rx >> 16), &first);
+                tile0 = s_tb[lo] + (u32)ty * s_tw[lo] + (u32)first;
+            }
+            u32 tot;
+            // rows past the last hold no tiles and start at the pass's end,
+            // after every instance of the pass
+            s_roff[t] = base + block_exclusive_scan(cnt, lds4, tot);
+            s_rtile[t] = tile0;
+            s_rlo[t] = (unsigned char)lo;
+            __syncthreads();
+            if (o < end && o >= base && o - base < tot) {
+                // the last row that starts at or before o: rows without tiles
+                // start where the next row does, so this is the row holding o
+                int lr = 0, hr = EMIT_CHUNK - 1;
+                while (lr < hr) {
+                    const int mid = (lr + hr + 1) >> 1;
+                    if (s_roff[mid] <= o) lr = mid;
+                    else hr = mid - 1;
+                }
+                tile_keys[o] = s_rtile[lr] + (o - s_roff[lr]);
+                entries[o] = s_e[s_rlo[lr]];
+            }
+            base += tot;
         }
     }
 }

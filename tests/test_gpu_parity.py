@@ -491,6 +491,60 @@ def _quadrant_edge_scene(seed=41, n=6000, W=160, H=112):
                        [np.zeros((3, H, W), np.float32)], np.zeros(3, np.float32))
 
 
+def _tall_scene(seed=43, n_small=3000, n_tall=40, W=512, H=8192):
+    """A tall view (32 x 512 tiles) with small Gaussians and a few long
+    axis-aligned ones whose footprints span up to all 512 tile rows, so the
+    emission's row counting needs several passes for one chunk of instances
+    and starts chunks in the middle of a footprint."""
+    rng = np.random.default_rng(seed)
+    cam = synth.random_scene(seed, 8, W, H, sh_degree=1).cameras[0]
+    n = n_small + n_tall
+    u = rng.uniform(-20.0, W + 20.0, n)
+    w = rng.uniform(-20.0, H + 20.0, n)
+    z = rng.uniform(1.5, 4.0, n)
+    camp = np.stack([(u - cam.cx) * z / cam.fx, (w - cam.cy) * z / cam.fy, z])
+    means = cam.R.T @ (camp - cam.t[:, None])
+    log_scales = rng.uniform(-4.0, -1.5, (3, n))
+    quats = rng.standard_normal((4, n))
+    t = slice(n_small, n)
+    log_scales[0, t] = rng.uniform(-3.0, -1.5, n_tall)
+    log_scales[1, t] = rng.uniform(0.5, 2.0, n_tall)
+    log_scales[2, t] = -3.0
+    quats[:, t] = np.array([1.0, 0.0, 0.0, 0.0])[:, None]
+    logits = rng.normal(1.0, 1.5, n)
+    f32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)  # noqa: E731
+    return synth.Scene(f32(means), f32(log_scales), f32(quats), f32(logits),
+                       f32(rng.normal(0.0, 0.3, (4, 3, n))), 1, [cam],
+                       [np.zeros((3, H, W), np.float32)], np.zeros(3, np.float32))
+
+
+@pytest.mark.parametrize("presort", [False, True])
+def test_emission_of_footprints_spanning_hundreds_of_rows(presort):
+    """Footprints of up to 512 tile rows, next to small ones: the per-tile
+    lists bit-exact against the oracle whichever way the emission places a
+    chunk's instances (row counts in several passes for chunks of few large
+    footprints, each instance walking its footprint's rows for chunks of many
+    small ones), in entry and in depth order."""
+    sc = _tall_scene()
+    cam = sc.cameras[0]
+    p = oracle.project(sc, cam)
+    rect = p["rect"][p["tiles_touched"] > 0]
+    assert (rect[:, 3] - rect[:, 2] + 1).max() > 256   # one footprint outgrows a pass
+    opts = gsmi.raster_opts(count_composited=True, depth_presort=presort)
+    frame, *_ = gpu_forward(sc, [cam], opts, cap=1 << 20)
+    tiles, gids, ranges = oracle.tile_lists(p)
+    nv, ni, ovf = frame.status()
+    assert ovf == 0
+    gt = frame.buffer(gsmi.BUF_INST_TILE).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    ge = frame.buffer(gsmi.BUF_INST_ENTRY).cpu().numpy()[:ni].view(np.uint32).astype(np.int64)
+    gr = frame.buffer(gsmi.BUF_RANGES).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    nflag = _compare_lists(p, gt, ge, tiles, gids)
+    _check_ranges_partition(gr, gt)
+    if nflag == 0:
+        assert ni == tiles.size
+        np.testing.assert_array_equal(_norm_ranges(gr), _norm_ranges(ranges))
+
+
 @pytest.mark.parametrize("sigma3", [False, True])
 def test_quadrant_walk_is_exact(sigma3):
     """Pixel lanes walk only the splats whose footprint meets their 8x8
