@@ -61,6 +61,19 @@ class GaussianRasterizer:
         self.accum = torch.zeros(self.n, device=self.device)
         self.denom = torch.zeros(self.n, device=self.device)
         self.generation = 0
+        self.sh_adam = None
+
+    def fuse_sh_adam(self, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15):
+        """Fuse the colour coefficients' sparse Adam step into the backward
+        (gs_project_backward_sh_adam): the backward updates the sh tensor the
+        forward was given in place, with moments m and v, and returns no
+        gradient for it; the caller's optimiser step then covers the other
+        four parameters (with the same step counter, a device counter of
+        gsmi.adam_counter that the fused step reads and does not advance).
+        Same bits as a separate gsmi.adam_step over all five.  None (m=None)
+        switches fusion off."""
+        self.sh_adam = None if m is None else dict(m=m, v=v, lr=lr, step=step, beta1=beta1,
+                                                   beta2=beta2, eps=eps)
 
     def set_cameras(self, cameras):
         """New poses / intrinsics for views of the same sizes."""
@@ -145,6 +158,9 @@ class _Rasterize(torch.autograd.Function):
         ctx.generation = r.generation
         ctx.params = params
         ctx.cams_dev = r.cams_dev
+        ctx.sh_adam = r.sh_adam
+        if r.sh_adam is not None and params["sh"].data_ptr() != sh.data_ptr():
+            raise ValueError("a fused Adam step updates sh in place: it must be contiguous")
         return images
 
     @staticmethod
@@ -154,9 +170,13 @@ class _Rasterize(torch.autograd.Function):
             raise RuntimeError("the rasterizer rendered again before this backward; its frame no "
                                "longer holds this forward's state")
         r.frame.render_backward(r.opts, dL_dimages.contiguous())
-        grads = gsmi.empty_grads(ctx.params)
+        if ctx.sh_adam is None:
+            grads = gsmi.empty_grads(ctx.params)
+        else:
+            grads = {k: torch.empty_like(ctx.params[k]) for k in gsmi.PARAM_NAMES if k != "sh"}
+            grads["sh"] = None
         r.frame.project_backward(ctx.params, r.sh_degree, ctx.cams_dev, r.opts, grads, r.accum,
-                                 r.denom)
+                                 r.denom, sh_adam=ctx.sh_adam)
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"],
                 grads["sh"], None)
 

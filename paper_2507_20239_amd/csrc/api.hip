@@ -341,7 +341,34 @@ gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camer
     if ((accum == nullptr) != (denom == nullptr))
         return gs_fail(GS_ERR_INVALID, "accum and denom must both be set or both be null");
     return gs_launch_project_bwd(f, g, cameras, opts->near_plane, grads, accum, denom,
-                                 (opts->flags & GS_RASTER_GRAD_RENDERED_ONLY) != 0,
+                                 (opts->flags & GS_RASTER_GRAD_RENDERED_ONLY) != 0, nullptr,
+                                 (hipStream_t)stream);
+}
+
+gs_status gs_project_backward_sh_adam(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,
+                                      const gs_raster_opts* opts, const gs_gaussian_grads* grads,
+                                      float* accum, float* denom, const gs_sh_adam* adam,
+                                      void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_gaussians(f, g));
+    GS_TRY(check_opts(opts));
+    if (!cameras || !grads || !adam) return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (f->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits))
+        return gs_fail(GS_ERR_INVALID, "a gradient pointer is null");
+    if ((accum == nullptr) != (denom == nullptr))
+        return gs_fail(GS_ERR_INVALID, "accum and denom must both be set or both be null");
+    if (f->n > 0 && (!adam->sh || !adam->m || !adam->v))
+        return gs_fail(GS_ERR_INVALID, "adam: sh, m and v must be set");
+    if (f->n > 0 && adam->sh != g->sh)
+        return gs_fail(GS_ERR_INVALID, "adam->sh must be the Gaussians' sh (updated in place)");
+    if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f &&
+          adam->eps > 0.f))
+        return gs_fail(GS_ERR_INVALID, "adam: need 0 <= beta < 1 and eps > 0");
+    if (!adam->counter && adam->step < 1) return gs_fail(GS_ERR_INVALID, "adam: step counts from 1");
+    if (adam->counter && ((uintptr_t)adam->counter & 7) != 0)
+        return gs_fail(GS_ERR_INVALID, "adam: counter must be 8-byte aligned");
+    return gs_launch_project_bwd(f, g, cameras, opts->near_plane, grads, accum, denom,
+                                 (opts->flags & GS_RASTER_GRAD_RENDERED_ONLY) != 0, adam,
                                  (hipStream_t)stream);
 }
 

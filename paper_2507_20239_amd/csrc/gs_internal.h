@@ -281,14 +281,39 @@ gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* imag
                                hipStream_t s);
 gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float* dL,
                                hipStream_t s);
+// adam (may be NULL): the colour coefficients take their sparse Adam step
+// instead of having their gradient written (gs_project_backward_sh_adam)
 gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                                 float near_plane, const gs_gaussian_grads* gr, float* accum,
-                                float* denom, bool rendered_only, hipStream_t s);
+                                float* denom, bool rendered_only, const gs_sh_adam* adam,
+                                hipStream_t s);
 
 // ------------------------------------------------------------------------
 // Device helpers
 // ------------------------------------------------------------------------
 #ifdef __HIPCC__
+// One element of the sparse Adam step: the update when upd, else the values
+// as read.  m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m c1) / (sqrt(v c2) + eps), c1, c2 the bias-correction factors.
+// Shared by the optimiser kernel and the projection adjoint's fused step, so
+// both give the same bits.
+__device__ __forceinline__ void adam_element(bool upd, float g, float& m, float& v, float& p,
+                                             float lr, float b1, float b2, float eps, float c1,
+                                             float c2) {
+    const float mn = fmaf(b1, m, (1.f - b1) * g);
+    const float vn = fmaf(b2, v, (1.f - b2) * g * g);
+    if (upd) {
+        m = mn;
+        v = vn;
+        p -= lr * (mn * c1) / (sqrtf(vn * c2) + eps);
+    }
+}
+
+// The bias-correction factors 1 / (1 - b^t) of step t, in FP64 rounded once.
+__host__ __device__ __forceinline__ float adam_bias_factor(float b, int64_t t) {
+    return (float)(1.0 / (1.0 - pow((double)b, (double)t)));
+}
+
 __device__ __forceinline__ int lane_id() {
     return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }

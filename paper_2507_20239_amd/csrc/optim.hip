@@ -27,27 +27,15 @@ struct AdamTable {
     int count;
 };
 
-// One element: the Adam update when upd, else the values as read.
-__device__ __forceinline__ void adam_one(bool upd, float g, float& m, float& v, float& p, float lr,
-                                         float b1, float b2, float eps, float c1, float c2) {
-    const float mn = fmaf(b1, m, (1.f - b1) * g);
-    const float vn = fmaf(b2, v, (1.f - b2) * g * g);
-    if (upd) {
-        m = mn;
-        v = vn;
-        p -= lr * (mn * c1) / (sqrtf(vn * c2) + eps);
-    }
-}
-
 // The step count of a counted call: one thread advances the device counter
 // and writes the two bias-correction factors next to it, as the host computes
 // them for an uncounted call (FP64, rounded once).
-__global__ void adam_count_kernel(gs_adam_counter* c, double b1, double b2) {
+__global__ void adam_count_kernel(gs_adam_counter* c, float b1, float b2) {
     if (threadIdx.x != 0) return;
     const int64_t t = c->step + 1;
     c->step = t;
-    c->c1 = (float)(1.0 / (1.0 - pow(b1, (double)t)));
-    c->c2 = (float)(1.0 / (1.0 - pow(b2, (double)t)));
+    c->c1 = adam_bias_factor(b1, t);
+    c->c2 = adam_bias_factor(b2, t);
 }
 
 __global__ void __launch_bounds__(GS_BLOCK) adam_kernel(AdamTable t, int64_t n,
@@ -86,7 +74,7 @@ __global__ void __launch_bounds__(GS_BLOCK) adam_kernel(AdamTable t, int64_t n,
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t k = (int64_t)(r + j) * n + i;
-                adam_one(upd, g[j], m[j], v[j], p[j], q.lr, b1, b2, eps, c1, c2);
+                adam_element(upd, g[j], m[j], v[j], p[j], q.lr, b1, b2, eps, c1, c2);
                 q.m[k] = m[j];
                 q.v[k] = v[j];
                 q.param[k] = p[j];
@@ -95,7 +83,7 @@ __global__ void __launch_bounds__(GS_BLOCK) adam_kernel(AdamTable t, int64_t n,
         for (; r < q.rows; ++r) {
             const int64_t k = (int64_t)r * n + i;
             float m = q.m[k], v = q.v[k], p = q.param[k];
-            adam_one(upd, upd ? q.grad[k] : 0.f, m, v, p, q.lr, b1, b2, eps, c1, c2);
+            adam_element(upd, upd ? q.grad[k] : 0.f, m, v, p, q.lr, b1, b2, eps, c1, c2);
             q.m[k] = m;
             q.v[k] = v;
             q.param[k] = p;
@@ -134,14 +122,14 @@ gs_status adam_launch(const gs_adam_param* params, int32_t n_params, int64_t n,
     // a counted call advances its counter even when there is nothing to update,
     // so the count always equals the number of calls
     if (counter) {
-        adam_count_kernel<<<1, 64, 0, s>>>(counter, (double)beta1, (double)beta2);
+        adam_count_kernel<<<1, 64, 0, s>>>(counter, beta1, beta2);
         GS_TRY(gs_check_launch("adam_count"));
     }
     if (!work) return GS_OK;
     float c1 = 1.f, c2 = 1.f;
     if (!counter) {
-        c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
-        c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+        c1 = adam_bias_factor(beta1, step);
+        c2 = adam_bias_factor(beta2, step);
     }
     adam_kernel<<<blocks_for(n), GS_BLOCK, 0, s>>>(t, n, tiles_touched, n_views, beta1, beta2, eps,
                                                    c1, c2, counter);

@@ -490,6 +490,14 @@ struct ProjBwdArgs {
     float* accum;
     float* denom;
     int rendered_only;     // rows of Gaussians no view rendered are not written
+    // fused sparse Adam of the colour coefficients (sh_m == nullptr: off):
+    // coefficients and moments, step size, decay rates, eps, and the
+    // bias-correction factors (from the device counter when it is set)
+    float* sh_param;
+    float* sh_m;
+    float* sh_v;
+    float lr, b1, b2, eps, c1, c2;
+    const gs_adam_counter* counter;
 };
 
 template <int DEG>
@@ -506,6 +514,8 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     // gradients, or nothing when only rendered rows are wanted (whole waves of
     // them, when the Gaussians are in spatial order).
     if (__ballot(rend != 0) == 0) {
+        // (the fused Adam step leaves such Gaussians as they are, like the
+        // optimiser kernel, and writes no colour-coefficient gradient)
         if (b.rendered_only) return;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -515,8 +525,9 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(0.f, b.d_quats + k * n + i);
         __builtin_nontemporal_store(0.f, b.d_logits + i);
+        if (!b.sh_m)
 #pragma unroll
-        for (int k = 0; k < 3 * K; ++k) __builtin_nontemporal_store(0.f, b.d_sh + (int64_t)k * n + i);
+            for (int k = 0; k < 3 * K; ++k) __builtin_nontemporal_store(0.f, b.d_sh + (int64_t)k * n + i);
         return;
     }
     // Otherwise every lane of the wave takes the same path (a Gaussian no view
@@ -722,11 +733,43 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(dq[k], b.d_quats + k * n + i);
     __builtin_nontemporal_store(dlogit, b.d_logits + i);
+    if (b.sh_m) {
+        // the colour coefficients' sparse Adam step with their summed gradient
+        // (the optimiser kernel's update; a Gaussian no view rendered stores
+        // back what it read, as there)
+        float c1 = b.c1, c2 = b.c2;
+        if (b.counter) {
+            const int64_t t = b.counter->step + 1;
+            c1 = adam_bias_factor(b.b1, t);
+            c2 = adam_bias_factor(b.b2, t);
+        }
+        const bool upd = rend != 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+            float m[3], v[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-            __builtin_nontemporal_store(dsh[k][ch], b.d_sh + ((int64_t)k * 3 + ch) * n + i);
+            for (int ch = 0; ch < 3; ++ch) {
+                const int64_t j = ((int64_t)k * 3 + ch) * n + i;
+                m[ch] = __builtin_nontemporal_load(b.sh_m + j);
+                v[ch] = __builtin_nontemporal_load(b.sh_v + j);
+            }
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const int64_t j = ((int64_t)k * 3 + ch) * n + i;
+                float p = f[k][ch];
+                adam_element(upd, dsh[k][ch], m[ch], v[ch], p, b.lr, b.b1, b.b2, b.eps, c1, c2);
+                __builtin_nontemporal_store(m[ch], b.sh_m + j);
+                __builtin_nontemporal_store(v[ch], b.sh_v + j);
+                __builtin_nontemporal_store(p, b.sh_param + j);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                __builtin_nontemporal_store(dsh[k][ch], b.d_sh + ((int64_t)k * 3 + ch) * n + i);
+    }
     if (b.accum) {
         b.accum[i] += st_acc;
         b.denom[i] += st_den;
@@ -778,7 +821,8 @@ gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera*
 
 gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                                 float near_plane, const gs_gaussian_grads* gr, float* accum,
-                                float* denom, bool rendered_only, hipStream_t s) {
+                                float* denom, bool rendered_only, const gs_sh_adam* adam,
+                                hipStream_t s) {
     if (f->n == 0) return GS_OK;
     ProjBwdArgs b;
     b.p = make_args(f, g, cams, near_plane);
@@ -792,6 +836,25 @@ gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_cam
     b.accum = accum;
     b.denom = denom;
     b.rendered_only = rendered_only ? 1 : 0;
+    b.sh_param = b.sh_m = b.sh_v = nullptr;
+    b.lr = b.b1 = b.b2 = b.eps = 0.f;
+    b.c1 = b.c2 = 1.f;
+    b.counter = nullptr;
+    if (adam) {
+        b.d_sh = nullptr;
+        b.sh_param = adam->sh;
+        b.sh_m = adam->m;
+        b.sh_v = adam->v;
+        b.lr = adam->lr;
+        b.b1 = adam->beta1;
+        b.b2 = adam->beta2;
+        b.eps = adam->eps;
+        b.counter = adam->counter;
+        if (!adam->counter) {
+            b.c1 = adam_bias_factor(adam->beta1, adam->step);
+            b.c2 = adam_bias_factor(adam->beta2, adam->step);
+        }
+    }
     const unsigned blocks = (unsigned)((f->n + GS_BLOCK - 1) / GS_BLOCK);
     switch (g->sh_degree) {
         case 0: project_bwd_kernel<0><<<blocks, GS_BLOCK, 0, s>>>(b); break;

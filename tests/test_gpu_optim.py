@@ -96,3 +96,90 @@ def test_counted_adam_equals_host_counted_adam():
     gsmi.adam_step([(b[0], g, b[1], b[2], 1e-2)], 0, counter)
     torch.cuda.synchronize()
     assert int(counter[0]) == 7
+
+
+@pytest.mark.parametrize("sh_degree,counted,rendered_only",
+                         [(3, True, True), (3, False, False), (1, True, False), (0, False, True)])
+def test_fused_sh_adam_equals_projection_adjoint_then_adam(sh_degree, counted, rendered_only):
+    """gs_project_backward_sh_adam against gs_project_backward followed by
+    gs_adam_step on the colour coefficients, from the same per-splat gradients
+    and nonzero moments over two views, part of the Gaussians behind the
+    cameras: coefficients and moments bit for bit (unrendered ones untouched),
+    the other four gradients and the densification statistic bit for bit, no
+    colour-coefficient gradient written, a device counter read and not
+    advanced; host validation of the Adam arguments."""
+    from parity_util import params_of
+    from paper_2507_20239_amd import synth
+    sc = synth.random_scene(71, 3000, 96, 80, sh_degree=sh_degree, n_views=2,
+                            log_scale=(-2.4, 0.5))
+    sc.means[2, ::7] = -1.0   # behind both cameras: never rendered
+    cams = list(sc.cameras)
+    n = sc.n
+    P = params_of(sc)
+    cams_dev = gsmi.cameras_to_device(cams, dev())
+    opts = gsmi.raster_opts(grad_rendered_only=rendered_only)
+    frame = gsmi.Frame(n, [(c.width, c.height) for c in cams], 1 << 20, dev())
+    frame.project(P, sh_degree, cams_dev, opts)
+    flat = frame.render(opts)
+    g = torch.Generator(device=dev())
+    g.manual_seed(5)
+    frame.render_backward(opts, torch.randn(flat.numel(), device=dev(), generator=g))
+    tt = frame.buffer(gsmi.BUF_TILES_TOUCHED)
+    rendered = (tt.view(2, n) != 0).any(0).cpu().numpy()
+    assert 0 < rendered.sum() < n
+    m0 = 0.01 * torch.randn(P["sh"].shape, device=dev(), generator=g)
+    v0 = 1e-4 * torch.rand(P["sh"].shape, device=dev(), generator=g)
+    lr, done = 2.5e-3, 4
+
+    def step_arg():
+        if not counted:
+            return done + 1
+        c = gsmi.adam_counter(dev())
+        c[0] = done
+        return c
+
+    # separate: the adjoint's gradients, then Adam on the colour coefficients
+    sa, ma, va = P["sh"].clone(), m0.clone(), v0.clone()
+    grads_a = gsmi.empty_grads(P)
+    acc_a, den_a = torch.zeros(n, device=dev()), torch.zeros(n, device=dev())
+    frame.project_backward(P, sh_degree, cams_dev, opts, grads_a, acc_a, den_a)
+    cnt_a = step_arg()
+    gsmi.adam_step([(sa, grads_a["sh"], ma, va, lr)], n, cnt_a, tiles_touched=tt, n_views=2)
+    # fused
+    Pb = {k: t.clone() for k, t in P.items()}
+    mb, vb = m0.clone(), v0.clone()
+    grads_b = {k: torch.full_like(P[k], 7.0) for k in gsmi.PARAM_NAMES if k != "sh"}
+    grads_b["sh"] = None
+    acc_b, den_b = torch.zeros(n, device=dev()), torch.zeros(n, device=dev())
+    cnt_b = step_arg()
+    frame.project_backward(Pb, sh_degree, cams_dev, opts, grads_b, acc_b, den_b,
+                           sh_adam=dict(m=mb, v=vb, lr=lr, step=cnt_b))
+    torch.cuda.synchronize()
+    assert torch.equal(Pb["sh"], sa) and torch.equal(mb, ma) and torch.equal(vb, va)
+    un = torch.from_numpy(~rendered).to(dev())
+    assert torch.equal(Pb["sh"][..., un], P["sh"][..., un]) and torch.equal(mb[..., un], m0[..., un])
+    assert not torch.equal(Pb["sh"], P["sh"])
+    rows = torch.from_numpy(rendered).to(dev()) if rendered_only else torch.ones(n, dtype=torch.bool,
+                                                                                   device=dev())
+    for k in ("means", "log_scales", "quats", "opacity_logits"):
+        assert torch.equal(grads_b[k][..., rows], grads_a[k][..., rows]), k
+    assert torch.equal(acc_b, acc_a) and torch.equal(den_b, den_a)
+    if counted:
+        assert int(cnt_b[0]) == done and int(cnt_a[0]) == done + 1
+    # host validation: the in-place array, the decay rates, the step count
+    for bad in (dict(m=mb, v=vb, lr=lr, step=1, beta1=1.0), dict(m=mb, v=vb, lr=lr, step=0)):
+        with pytest.raises(gsmi.GsError):
+            frame.project_backward(Pb, sh_degree, cams_dev, opts, grads_b, sh_adam=bad)
+    L = gsmi.lib()
+    gs = gsmi.gaussians_struct(Pb, sh_degree)
+    gr = gsmi.GaussianGrads(*(grads_b[k].data_ptr() if grads_b[k] is not None else None
+                              for k in gsmi.PARAM_NAMES))
+    other = torch.empty_like(P["sh"])
+    a = gsmi.ShAdam(other.data_ptr(), mb.data_ptr(), vb.data_ptr(), lr, 0.9, 0.999, 1e-15, None, 1)
+    import ctypes
+    st = L.gs_project_backward_sh_adam(frame.handle, ctypes.byref(gs), gsmi._ptr(cams_dev),
+                                       ctypes.byref(opts), ctypes.byref(gr), None, None,
+                                       ctypes.byref(a), gsmi._stream())
+    assert st == gsmi.GS_ERR_INVALID and b"in place" in L.gs_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(mb, ma)
