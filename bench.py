@@ -606,9 +606,9 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
         tg = targets.index_select(0, pick)
         loss = sum(photometric_loss(im, tg[i], 0.2, ws) for i, im in enumerate(imgs)) / 4
         loss.backward()
-        # with the colour coefficients' Adam step fused into the backward, the
-        # optimiser step covers the other four parameter arrays
-        opt = [k for k in names if not (fused and k == "sh")]
+        # with the Adam step fused into the backward, the optimiser launch only
+        # advances the step counter
+        opt = [] if fused else names
         gsmi.adam_step([(P[k].data, P[k].grad, mom[k][0], mom[k][1], lrs[k]) for k in opt],
                        sc.n, counter, tiles_touched=r.frame.buffer(gsmi.BUF_TILES_TOUCHED),
                        n_views=4)
@@ -616,10 +616,7 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
 
     def run(mode, fused=True):
         P, mom, counter = start()
-        if fused:
-            r.fuse_sh_adam(mom["sh"][0], mom["sh"][1], lrs["sh"], counter)
-        else:
-            r.fuse_sh_adam(None, None, 0.0, None)
+        r.fuse_adam(gsmi.FusedAdamStep(mom, lrs, counter) if fused else None)
         losses = torch.zeros(steps, device=dev)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
@@ -670,9 +667,8 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
     captured = run("graph")
     log("6M training, captured step: %.3f ms/step" % captured["mean_ms_per_step"])
     separate = run("eager", fused=False)
-    log("6M training, eager, colour-coefficient Adam as a separate launch: %.3f ms/step"
-        % separate["mean_ms_per_step"])
-    r.fuse_sh_adam(None, None, 0.0, None)
+    log("6M training, eager, Adam as a separate launch: %.3f ms/step" % separate["mean_ms_per_step"])
+    r.fuse_adam(None)
     nv, ni, _ = r.frame.status()
     out = {"workload": "6,000,000 Gaussians (64 spheres, 16 planes), SH3, 64 ring cameras at "
                        "1920x1080, 4 random views per step, autograd fwd+bwd + Eq. 3 loss "
@@ -681,11 +677,10 @@ def c5_training(torch, gsmi, synth, dev, steps, first_timed=11, warm=3):
            "spatial_reorder": reorder,
            "steps": steps, "timed_steps": "%d..%d" % (first_timed, steps)}
     out.update(eager)
-    out["optimizer"] = ("sparse Adam; the colour coefficients' step fused into the projection "
-                        "adjoint (gs_project_backward_sh_adam), the other parameters in one "
-                        "gs_adam_step_counted launch")
+    out["optimizer"] = ("sparse Adam fused into the projection adjoint (gs_project_backward_adam); "
+                        "a gs_adam_step_counted launch with no arrays advances the step count")
     out["captured"] = dict(captured, replayed_from_step=warm + 1)
-    out["separate_colour_adam"] = separate
+    out["separate_adam"] = separate
     out.update({"visible_entries_last_step": nv, "instances_last_step": ni,
                 "capacity": r.frame.cap, "tuned": r.tuned})
     del r, targets

@@ -468,37 +468,38 @@ gs_status gs_adam_step_counted(const gs_adam_param* params, int32_t n_params, in
                                const uint32_t* tiles_touched, int32_t n_views, float beta1,
                                float beta2, float eps, gs_adam_counter* counter, void* stream);
 
-/* The sparse Adam step of the colour coefficients for
- * gs_project_backward_sh_adam.  sh: the coefficients, device FP32 [K][3][n],
- * updated in place (it must be the gs_gaussians' sh); m, v: their moments,
- * same layout.  The step count t comes from counter (device; t =
- * counter->step + 1, the count the next gs_adam_step_counted call with that
- * counter takes) or, when counter is NULL, from step (>= 1). */
+/* The sparse Adam step fused into gs_project_backward_adam, for each of the
+ * five parameter arrays k = 0..4 (means, log_scales, quats, opacity_logits,
+ * sh): param[k], the gs_gaussians' array, updated in place; m[k], v[k] its
+ * moments (device FP32, same layout); lr[k] its step size.  param[k] = NULL
+ * leaves array k out: its gradient goes to grads as in gs_project_backward.
+ * The step count t comes from counter (device; t = counter->step + 1, the
+ * count the next gs_adam_step_counted call with it takes; this call does not
+ * advance it) or, when counter is NULL, from step (>= 1). */
 typedef struct {
-    float* sh;
-    float* m;
-    float* v;
-    float lr;
+    float* param[5];
+    float* m[5];
+    float* v[5];
+    float lr[5];
     float beta1, beta2, eps;
     const gs_adam_counter* counter;
     int64_t step;
-} gs_sh_adam;
+} gs_fused_adam;
 
-/* gs_project_backward with the sparse Adam step of the colour coefficients
- * fused in: the summed colour-coefficient gradient of each Gaussian goes from
- * registers into the Adam update of gs_adam_step (same arithmetic, bit for
- * bit, with the frame's tiles_touched deciding which Gaussians move) instead
- * of to grads->sh, which is neither written nor read (may be NULL); every
- * other output is gs_project_backward's.  The colour coefficients are ~80 %
- * of an SH3 Gaussian's parameters, and their gradient never reaches memory:
- * a training step then runs gs_adam_step(_counted) on the other four
- * parameter arrays only (with a counter: after this call, which does not
- * advance it).  For the optimiser step of the accelerated 3DGS training the
- * paper builds on (Experiments, implementation details). */
-gs_status gs_project_backward_sh_adam(gs_frame* frame, const gs_gaussians* g,
-                                      const gs_camera* cameras, const gs_raster_opts* opts,
-                                      const gs_gaussian_grads* grads, float* accum, float* denom,
-                                      const gs_sh_adam* adam, void* stream);
+/* gs_project_backward with the sparse Adam step of gs_adam_step fused in
+ * for the arrays adam selects: each Gaussian's gradient, summed over the
+ * views in registers, goes straight into the update (same arithmetic, bit
+ * for bit, with the frame's tiles_touched deciding which Gaussians move)
+ * instead of to grads, whose pointers for those arrays are neither written
+ * nor read (may be NULL); every other output is gs_project_backward's.  A
+ * training step that fuses all five arrays then only advances its counter
+ * (gs_adam_step_counted with no arrays).  For the optimiser step of the
+ * accelerated 3DGS training the paper builds on (Experiments, implementation
+ * details). */
+gs_status gs_project_backward_adam(gs_frame* frame, const gs_gaussians* g, const gs_camera* cameras,
+                                   const gs_raster_opts* opts, const gs_gaussian_grads* grads,
+                                   float* accum, float* denom, const gs_fused_adam* adam,
+                                   void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Primitives exposed for testing                                            */

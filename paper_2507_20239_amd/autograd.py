@@ -61,19 +61,17 @@ class GaussianRasterizer:
         self.accum = torch.zeros(self.n, device=self.device)
         self.denom = torch.zeros(self.n, device=self.device)
         self.generation = 0
-        self.sh_adam = None
+        self.adam = None
 
-    def fuse_sh_adam(self, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15):
-        """Fuse the colour coefficients' sparse Adam step into the backward
-        (gs_project_backward_sh_adam): the backward updates the sh tensor the
-        forward was given in place, with moments m and v, and returns no
-        gradient for it; the caller's optimiser step then covers the other
-        four parameters (with the same step counter, a device counter of
-        gsmi.adam_counter that the fused step reads and does not advance).
-        Same bits as a separate gsmi.adam_step over all five.  None (m=None)
-        switches fusion off."""
-        self.sh_adam = None if m is None else dict(m=m, v=v, lr=lr, step=step, beta1=beta1,
-                                                   beta2=beta2, eps=eps)
+    def fuse_adam(self, adam):
+        """Fuse a sparse Adam step into the backward (a gsmi.FusedAdamStep, or
+        None to switch fusion off; gs_project_backward_adam): the backward
+        updates the parameter tensors it names in place, with their moments,
+        and returns no gradient for them.  The caller's optimiser step covers
+        the others, and with a device step counter advances it (a counted
+        gsmi.adam_step with the remaining arrays, or none).  Same bits as a
+        separate gsmi.adam_step."""
+        self.adam = adam
 
     def set_cameras(self, cameras):
         """New poses / intrinsics for views of the same sizes."""
@@ -158,9 +156,14 @@ class _Rasterize(torch.autograd.Function):
         ctx.generation = r.generation
         ctx.params = params
         ctx.cams_dev = r.cams_dev
-        ctx.sh_adam = r.sh_adam
-        if r.sh_adam is not None and params["sh"].data_ptr() != sh.data_ptr():
-            raise ValueError("a fused Adam step updates sh in place: it must be contiguous")
+        ctx.adam = r.adam
+        if r.adam is not None:
+            given = dict(means=means, log_scales=log_scales, quats=quats,
+                         opacity_logits=opacity_logits, sh=sh)
+            for k in r.adam.names():
+                if params[k].data_ptr() != given[k].data_ptr():
+                    raise ValueError("a fused Adam step updates %s in place: it must be "
+                                     "contiguous" % k)
         return images
 
     @staticmethod
@@ -170,13 +173,11 @@ class _Rasterize(torch.autograd.Function):
             raise RuntimeError("the rasterizer rendered again before this backward; its frame no "
                                "longer holds this forward's state")
         r.frame.render_backward(r.opts, dL_dimages.contiguous())
-        if ctx.sh_adam is None:
-            grads = gsmi.empty_grads(ctx.params)
-        else:
-            grads = {k: torch.empty_like(ctx.params[k]) for k in gsmi.PARAM_NAMES if k != "sh"}
-            grads["sh"] = None
+        fused = ctx.adam.names() if ctx.adam is not None else []
+        grads = {k: None if k in fused else torch.empty_like(ctx.params[k])
+                 for k in gsmi.PARAM_NAMES}
         r.frame.project_backward(ctx.params, r.sh_degree, ctx.cams_dev, r.opts, grads, r.accum,
-                                 r.denom, sh_adam=ctx.sh_adam)
+                                 r.denom, adam=ctx.adam)
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"],
                 grads["sh"], None)
 

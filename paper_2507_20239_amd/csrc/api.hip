@@ -345,22 +345,30 @@ gs_status gs_project_backward(gs_frame* f, const gs_gaussians* g, const gs_camer
                                  (hipStream_t)stream);
 }
 
-gs_status gs_project_backward_sh_adam(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,
-                                      const gs_raster_opts* opts, const gs_gaussian_grads* grads,
-                                      float* accum, float* denom, const gs_sh_adam* adam,
-                                      void* stream) {
+gs_status gs_project_backward_adam(gs_frame* f, const gs_gaussians* g, const gs_camera* cameras,
+                                   const gs_raster_opts* opts, const gs_gaussian_grads* grads,
+                                   float* accum, float* denom, const gs_fused_adam* adam,
+                                   void* stream) {
     GS_TRY(check_frame(f));
     GS_TRY(check_gaussians(f, g));
     GS_TRY(check_opts(opts));
     if (!cameras || !grads || !adam) return gs_fail(GS_ERR_INVALID, "null pointer");
-    if (f->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits))
-        return gs_fail(GS_ERR_INVALID, "a gradient pointer is null");
     if ((accum == nullptr) != (denom == nullptr))
         return gs_fail(GS_ERR_INVALID, "accum and denom must both be set or both be null");
-    if (f->n > 0 && (!adam->sh || !adam->m || !adam->v))
-        return gs_fail(GS_ERR_INVALID, "adam: sh, m and v must be set");
-    if (f->n > 0 && adam->sh != g->sh)
-        return gs_fail(GS_ERR_INVALID, "adam->sh must be the Gaussians' sh (updated in place)");
+    const float* own[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->sh};
+    float* const grad[5] = {grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
+                            grads->sh};
+    for (int k = 0; k < 5; ++k) {
+        if (f->n == 0) break;
+        if (!adam->param[k]) {
+            if (!grad[k]) return gs_fail(GS_ERR_INVALID, "gradient %d is null and not fused", k);
+            continue;
+        }
+        if (adam->param[k] != own[k])
+            return gs_fail(GS_ERR_INVALID, "adam param %d must be the Gaussians' array (updated in place)", k);
+        if (!adam->m[k] || !adam->v[k])
+            return gs_fail(GS_ERR_INVALID, "adam param %d: null moment", k);
+    }
     if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f &&
           adam->eps > 0.f))
         return gs_fail(GS_ERR_INVALID, "adam: need 0 <= beta < 1 and eps > 0");

@@ -281,11 +281,11 @@ gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* imag
                                hipStream_t s);
 gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float* dL,
                                hipStream_t s);
-// adam (may be NULL): the colour coefficients take their sparse Adam step
-// instead of having their gradient written (gs_project_backward_sh_adam)
+// adam (may be NULL): the arrays it selects take their sparse Adam step
+// instead of having their gradient written (gs_project_backward_adam)
 gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                                 float near_plane, const gs_gaussian_grads* gr, float* accum,
-                                float* denom, bool rendered_only, const gs_sh_adam* adam,
+                                float* denom, bool rendered_only, const gs_fused_adam* adam,
                                 hipStream_t s);
 
 // ------------------------------------------------------------------------

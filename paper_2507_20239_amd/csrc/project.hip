@@ -490,15 +490,44 @@ struct ProjBwdArgs {
     float* accum;
     float* denom;
     int rendered_only;     // rows of Gaussians no view rendered are not written
-    // fused sparse Adam of the colour coefficients (sh_m == nullptr: off):
-    // coefficients and moments, step size, decay rates, eps, and the
-    // bias-correction factors (from the device counter when it is set)
-    float* sh_param;
-    float* sh_m;
-    float* sh_v;
-    float lr, b1, b2, eps, c1, c2;
+    // fused sparse Adam (gs_project_backward_adam) of parameter array k
+    // (means, log_scales, quats, logits, sh; ap[k] == nullptr: its gradient is
+    // written instead): the parameters and moments, step sizes, decay rates,
+    // eps and the bias-correction factors (from the device counter when set)
+    float* ap[5];
+    float* am[5];
+    float* av[5];
+    float alr[5];
+    float b1, b2, eps, c1, c2;
     const gs_adam_counter* counter;
 };
+
+// R rows of the fused sparse Adam step: elements j0 + r n of parameter array
+// k, with summed gradients g[r], take the optimiser kernel's update (a
+// Gaussian no view rendered stores back what it read, as there); p: their
+// values when the caller holds them, else they are read again.  Every load is
+// issued before the first update.
+template <int R>
+__device__ __forceinline__ void fused_adam_rows(const ProjBwdArgs& b, int k, int64_t j0, int64_t n,
+                                                bool upd, const float* g, const float* p,
+                                                float c1, float c2) {
+    float m[R], v[R], q[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = j0 + r * n;
+        m[r] = __builtin_nontemporal_load(b.am[k] + j);
+        v[r] = __builtin_nontemporal_load(b.av[k] + j);
+        q[r] = p ? p[r] : b.ap[k][j];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = j0 + r * n;
+        adam_element(upd, g[r], m[r], v[r], q[r], b.alr[k], b.b1, b.b2, b.eps, c1, c2);
+        __builtin_nontemporal_store(m[r], b.am[k] + j);
+        __builtin_nontemporal_store(v[r], b.av[k] + j);
+        __builtin_nontemporal_store(q[r], b.ap[k] + j);
+    }
+}
 
 template <int DEG>
 __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
@@ -515,17 +544,18 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     // them, when the Gaussians are in spatial order).
     if (__ballot(rend != 0) == 0) {
         // (the fused Adam step leaves such Gaussians as they are, like the
-        // optimiser kernel, and writes no colour-coefficient gradient)
+        // optimiser kernel, and writes no gradient for the arrays it covers)
         if (b.rendered_only) return;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            __builtin_nontemporal_store(0.f, b.d_means + k * n + i);
-            __builtin_nontemporal_store(0.f, b.d_log_scales + k * n + i);
+            if (!b.ap[0]) __builtin_nontemporal_store(0.f, b.d_means + k * n + i);
+            if (!b.ap[1]) __builtin_nontemporal_store(0.f, b.d_log_scales + k * n + i);
         }
+        if (!b.ap[2])
 #pragma unroll
-        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(0.f, b.d_quats + k * n + i);
-        __builtin_nontemporal_store(0.f, b.d_logits + i);
-        if (!b.sh_m)
+            for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(0.f, b.d_quats + k * n + i);
+        if (!b.ap[3]) __builtin_nontemporal_store(0.f, b.d_logits + i);
+        if (!b.ap[4])
 #pragma unroll
             for (int k = 0; k < 3 * K; ++k) __builtin_nontemporal_store(0.f, b.d_sh + (int64_t)k * n + i);
         return;
@@ -725,44 +755,42 @@ __global__ void __launch_bounds__(GS_BLOCK) project_bwd_kernel(ProjBwdArgs b) {
     // Gradients and colour coefficients stream through once: non-temporal
     // stores and loads keep them from evicting the step's reused data and leave
     // no dirty lines for the next kernel to write back.
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        __builtin_nontemporal_store(dmu[k], b.d_means + k * n + i);
-        __builtin_nontemporal_store(dls[k], b.d_log_scales + k * n + i);
+    // Each array's summed gradient goes to HBM, or straight into its fused
+    // sparse Adam step (the parameter itself reread: its line is in the cache,
+    // and keeping it live across the view loop would cost registers; the
+    // colour coefficients are still held).
+    float c1 = b.c1, c2 = b.c2;
+    if (b.counter) {
+        const int64_t t = b.counter->step + 1;
+        c1 = adam_bias_factor(b.b1, t);
+        c2 = adam_bias_factor(b.b2, t);
     }
+    const bool upd = rend != 0;
+    if (b.ap[0]) {
+        fused_adam_rows<3>(b, 0, i, n, upd, dmu, nullptr, c1, c2);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(dq[k], b.d_quats + k * n + i);
-    __builtin_nontemporal_store(dlogit, b.d_logits + i);
-    if (b.sh_m) {
-        // the colour coefficients' sparse Adam step with their summed gradient
-        // (the optimiser kernel's update; a Gaussian no view rendered stores
-        // back what it read, as there)
-        float c1 = b.c1, c2 = b.c2;
-        if (b.counter) {
-            const int64_t t = b.counter->step + 1;
-            c1 = adam_bias_factor(b.b1, t);
-            c2 = adam_bias_factor(b.b2, t);
-        }
-        const bool upd = rend != 0;
+        for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(dmu[k], b.d_means + k * n + i);
+    }
+    if (b.ap[1]) {
+        fused_adam_rows<3>(b, 1, i, n, upd, dls, nullptr, c1, c2);
+    } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            float m[3], v[3];
+        for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(dls[k], b.d_log_scales + k * n + i);
+    }
+    if (b.ap[2]) {
+        fused_adam_rows<4>(b, 2, i, n, upd, dq, nullptr, c1, c2);
+    } else {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const int64_t j = ((int64_t)k * 3 + ch) * n + i;
-                m[ch] = __builtin_nontemporal_load(b.sh_m + j);
-                v[ch] = __builtin_nontemporal_load(b.sh_v + j);
-            }
+        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(dq[k], b.d_quats + k * n + i);
+    }
+    if (b.ap[3]) fused_adam_rows<1>(b, 3, i, n, upd, &dlogit, nullptr, c1, c2);
+    else __builtin_nontemporal_store(dlogit, b.d_logits + i);
+    if (b.ap[4]) {
+        // a coefficient's three channels at a time (their values are held)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const int64_t j = ((int64_t)k * 3 + ch) * n + i;
-                float p = f[k][ch];
-                adam_element(upd, dsh[k][ch], m[ch], v[ch], p, b.lr, b.b1, b.b2, b.eps, c1, c2);
-                __builtin_nontemporal_store(m[ch], b.sh_m + j);
-                __builtin_nontemporal_store(v[ch], b.sh_v + j);
-                __builtin_nontemporal_store(p, b.sh_param + j);
-            }
-        }
+        for (int k = 0; k < K; ++k) fused_adam_rows<3>(b, 4, (int64_t)k * 3 * n + i, n, upd, dsh[k],
+                                                       f[k], c1, c2);
     } else {
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -821,7 +849,7 @@ gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera*
 
 gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_camera* cams,
                                 float near_plane, const gs_gaussian_grads* gr, float* accum,
-                                float* denom, bool rendered_only, const gs_sh_adam* adam,
+                                float* denom, bool rendered_only, const gs_fused_adam* adam,
                                 hipStream_t s) {
     if (f->n == 0) return GS_OK;
     ProjBwdArgs b;
@@ -836,16 +864,16 @@ gs_status gs_launch_project_bwd(gs_frame* f, const gs_gaussians* g, const gs_cam
     b.accum = accum;
     b.denom = denom;
     b.rendered_only = rendered_only ? 1 : 0;
-    b.sh_param = b.sh_m = b.sh_v = nullptr;
-    b.lr = b.b1 = b.b2 = b.eps = 0.f;
+    b.b1 = b.b2 = b.eps = 0.f;
     b.c1 = b.c2 = 1.f;
     b.counter = nullptr;
+    for (int k = 0; k < 5; ++k) {
+        b.ap[k] = adam ? adam->param[k] : nullptr;
+        b.am[k] = adam ? adam->m[k] : nullptr;
+        b.av[k] = adam ? adam->v[k] : nullptr;
+        b.alr[k] = adam ? adam->lr[k] : 0.f;
+    }
     if (adam) {
-        b.d_sh = nullptr;
-        b.sh_param = adam->sh;
-        b.sh_m = adam->m;
-        b.sh_v = adam->v;
-        b.lr = adam->lr;
         b.b1 = adam->beta1;
         b.b2 = adam->beta2;
         b.eps = adam->eps;

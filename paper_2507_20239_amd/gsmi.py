@@ -81,10 +81,11 @@ class AdamParam(ctypes.Structure):
                 ("v", ctypes.c_void_p), ("rows", ctypes.c_int32), ("lr", ctypes.c_float)]
 
 
-class ShAdam(ctypes.Structure):
-    _fields_ = [("sh", ctypes.c_void_p), ("m", ctypes.c_void_p), ("v", ctypes.c_void_p),
-                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("counter", ctypes.c_void_p), ("step", ctypes.c_int64)]
+class FusedAdam(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p * 5), ("m", ctypes.c_void_p * 5),
+                ("v", ctypes.c_void_p * 5), ("lr", ctypes.c_float * 5), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("counter", ctypes.c_void_p),
+                ("step", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -110,9 +111,9 @@ _SIGS = {
     "gs_render_backward": [_P, ctypes.POINTER(RasterOpts), _P, _P],
     "gs_project_backward": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts),
                             ctypes.POINTER(GaussianGrads), _P, _P, _P],
-    "gs_project_backward_sh_adam": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts),
-                                    ctypes.POINTER(GaussianGrads), _P, _P,
-                                    ctypes.POINTER(ShAdam), _P],
+    "gs_project_backward_adam": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts),
+                                 ctypes.POINTER(GaussianGrads), _P, _P,
+                                 ctypes.POINTER(FusedAdam), _P],
     "gs_l1_loss_grad": [_P, _P, _I64, _F, _P, _P, _P],
     "gs_accumulate_densify_stats": [_P, _P, _P, _I32, _I64, _P, _P, _P],
     "gs_densify_select": [_P, _P, _P, _P, _I64, _F, _F, _F, _I32, _P, _P, _P, _P],
@@ -345,37 +346,64 @@ class Frame:
                                         _stream(stream)))
 
     def project_backward(self, params, sh_degree, cams_dev, opts, grads, accum=None, denom=None,
-                         stream=None, sh_adam=None):
-        """sh_adam: None, or the colour coefficients' sparse Adam step to fuse
-        in (gs_project_backward_sh_adam): a dict with m, v (moments shaped like
-        params["sh"], which is updated in place), lr, step (a device counter
-        of adam_counter, not advanced here, or the step count from 1) and
-        optionally beta1, beta2, eps; grads["sh"] is then not written."""
+                         stream=None, adam=None):
+        """adam: None, or the sparse Adam step to fuse in
+        (gs_project_backward_adam; see FusedAdamStep): the parameter arrays it
+        names are updated in place and get no gradient (grads may omit them
+        or hold None)."""
         g = gaussians_struct(params, sh_degree)
-        if sh_adam is None:
-            gr = grads_struct(grads)
+        gr = GaussianGrads(*(grads[k].data_ptr() if grads.get(k) is not None else None
+                             for k in PARAM_NAMES))
+        if adam is None:
             _check(lib().gs_project_backward(self.handle, ctypes.byref(g), _ptr(cams_dev),
                                              ctypes.byref(opts), ctypes.byref(gr), _ptr(accum),
                                              _ptr(denom), _stream(stream)))
             return
-        gr = GaussianGrads(*(grads[k].data_ptr() if grads.get(k) is not None else None
-                             for k in PARAM_NAMES))
-        sh = params["sh"]
-        for t in (sh_adam["m"], sh_adam["v"]):
-            if t.numel() != sh.numel() or not t.is_contiguous() or t.dtype != torch.float32:
-                raise ValueError("the moments must be contiguous float32 shaped like sh")
-        step = sh_adam["step"]
-        counted = isinstance(step, torch.Tensor)
-        if counted and (step.dtype != torch.int64 or step.numel() != 2 or not step.is_contiguous()):
+        a = adam.struct(params)
+        _check(lib().gs_project_backward_adam(self.handle, ctypes.byref(g), _ptr(cams_dev),
+                                              ctypes.byref(opts), ctypes.byref(gr), _ptr(accum),
+                                              _ptr(denom), ctypes.byref(a), _stream(stream)))
+
+
+class FusedAdamStep:
+    """The sparse Adam step a projection adjoint applies itself
+    (gs_project_backward_adam).  moments: {name: (m, v)} for the parameter
+    arrays to update (names of PARAM_NAMES), lrs: {name: step size}, step: a
+    device counter of adam_counter (read, not advanced: a gs_adam_step_counted
+    call, with the other arrays or none, advances it) or the step count from 1."""
+
+    def __init__(self, moments, lrs, step, beta1=0.9, beta2=0.999, eps=1e-15):
+        for k in moments:
+            if k not in PARAM_NAMES:
+                raise ValueError("unknown parameter array %r" % k)
+        if isinstance(step, torch.Tensor) and (step.dtype != torch.int64 or step.numel() != 2 or
+                                               not step.is_contiguous()):
             raise ValueError("step counter must be adam_counter's int64 [2] tensor")
-        a = ShAdam(sh.data_ptr(), sh_adam["m"].data_ptr(), sh_adam["v"].data_ptr(),
-                   float(sh_adam["lr"]), float(sh_adam.get("beta1", 0.9)),
-                   float(sh_adam.get("beta2", 0.999)), float(sh_adam.get("eps", 1e-15)),
-                   step.data_ptr() if counted else None, 0 if counted else int(step))
-        _check(lib().gs_project_backward_sh_adam(self.handle, ctypes.byref(g), _ptr(cams_dev),
-                                                 ctypes.byref(opts), ctypes.byref(gr),
-                                                 _ptr(accum), _ptr(denom), ctypes.byref(a),
-                                                 _stream(stream)))
+        self.moments = dict(moments)
+        self.lrs = {k: float(lrs[k]) for k in moments}
+        self.step = step
+        self.beta1, self.beta2, self.eps = float(beta1), float(beta2), float(eps)
+
+    def names(self):
+        return list(self.moments)
+
+    def struct(self, params) -> FusedAdam:
+        a = FusedAdam()
+        for i, k in enumerate(PARAM_NAMES):
+            if k not in self.moments:
+                continue
+            m, v = self.moments[k]
+            p = params[k]
+            for t in (m, v):
+                if t.numel() != p.numel() or not t.is_contiguous() or t.dtype != torch.float32:
+                    raise ValueError("the moments of %s must be contiguous float32 like it" % k)
+            a.param[i], a.m[i], a.v[i] = p.data_ptr(), m.data_ptr(), v.data_ptr()
+            a.lr[i] = self.lrs[k]
+        a.beta1, a.beta2, a.eps = self.beta1, self.beta2, self.eps
+        counted = isinstance(self.step, torch.Tensor)
+        a.counter = self.step.data_ptr() if counted else None
+        a.step = 0 if counted else int(self.step)
+        return a
 
 
 def empty_grads(params: dict) -> dict:

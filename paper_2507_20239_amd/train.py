@@ -78,7 +78,6 @@ class Trainer:
         self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
         self.accum = torch.zeros(self.n, device=self.dev)
         self.denom = torch.zeros(self.n, device=self.dev)
-        self.grads = {k: torch.empty_like(v) for k, v in self.p.items() if k != "sh"}
         self.t = 0
 
     def _frame(self, cam):
@@ -119,14 +118,11 @@ class Trainer:
         frame.render_backward(self.opts, dL.reshape(-1))
         self.t += 1
         lrs = dict(self.lrs, means=self.policy.position_lr(it, self.extent))
-        # the colour coefficients take their Adam step inside the projection
-        # adjoint (their gradient never reaches memory); one launch for the rest
-        frame.project_backward(self.p, self.sh_degree, cams_dev, self.opts, self.grads, self.accum,
-                               self.denom, sh_adam=dict(m=self.m["sh"], v=self.v["sh"],
-                                                        lr=lrs["sh"], step=self.t))
-        gsmi.adam_step([(self.p[k], self.grads[k], self.m[k], self.v[k], lrs[k])
-                        for k in PARAMS if k != "sh"],
-                       self.n, self.t, tiles_touched=frame.buffer(gsmi.BUF_TILES_TOUCHED))
+        # sparse Adam inside the projection adjoint: each Gaussian's summed
+        # gradients go from registers into the update, none reaches memory
+        adam = gsmi.FusedAdamStep({k: (self.m[k], self.v[k]) for k in PARAMS}, lrs, self.t)
+        frame.project_backward(self.p, self.sh_degree, cams_dev, self.opts, {}, self.accum,
+                               self.denom, adam=adam)
         value = float(loss)
         self.history.append((it, value, self.n, r))
         if self.policy.densify_now(it):
@@ -180,7 +176,6 @@ class Trainer:
                 (self.lineage if st == "lineage" else getattr(self, st))[k] = o.contiguous()
         self.accum = torch.zeros(n_out, device=self.dev)
         self.denom = torch.zeros(n_out, device=self.dev)
-        self.grads = {k: torch.empty_like(v) for k, v in self.p.items() if k != "sh"}
         kinds = torch.bincount(kind.to(torch.int64), minlength=4).tolist()
         self.densify_log.append((it, n_in, n_out, kinds[gsmi.KIND_CLONE], kinds[gsmi.KIND_SPLIT0],
                                  int(prune.sum()), mode))

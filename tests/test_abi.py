@@ -59,8 +59,8 @@ def test_entry_points_reject_bad_arguments_without_launching():
     assert L.gs_render(None, None, None, None) == gsmi.GS_ERR_INVALID
     assert L.gs_project_backward(None, None, None, None, None, None, None,
                                  None) == gsmi.GS_ERR_INVALID
-    assert L.gs_project_backward_sh_adam(None, None, None, None, None, None, None, None,
-                                         None) == gsmi.GS_ERR_INVALID
+    assert L.gs_project_backward_adam(None, None, None, None, None, None, None, None,
+                                      None) == gsmi.GS_ERR_INVALID
     assert L.gs_densify_select(None, None, None, None, -1, 0, 0, 0, 1, None, None, None,
                                None) == gsmi.GS_ERR_INVALID
     assert L.gs_densify_plan(None, None, None, 1 << 31, None, None, 0, None, None, 0,

@@ -404,46 +404,51 @@ def test_6m_slice_gradients_match_finite_differences(scene_6m_1920x1080, slice_g
     assert limited <= 0.02 * 16 * 59
 
 
-def test_fused_colour_adam_in_the_backward():
-    """fuse_sh_adam: the backward updates the sh leaf in place and gives it no
-    gradient; the result equals the separate projection adjoint followed by
-    sparse Adam on the same frame state, bit for bit; the other four
-    gradients are the usual ones; the device counter is read, not advanced."""
+def test_fused_adam_in_the_backward():
+    """fuse_adam: the backward updates the parameter leaves in place and gives
+    them no gradient; the result equals the separate projection adjoint
+    followed by sparse Adam on the same frame state, bit for bit, for all five
+    arrays and for the colour coefficients alone (the other four then get
+    their usual gradients); the device counter is read, not advanced."""
     sc = synth.random_scene(62, 2000, 96, 80, sh_degree=3, n_views=2, log_scale=(-2.4, 0.5))
     cams = list(sc.cameras)
     names = gsmi.PARAM_NAMES
-    P = _leaf_params(sc)
-    r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev())
-    m, v = torch.zeros_like(P["sh"]), torch.zeros_like(P["sh"])
-    counter = gsmi.adam_counter(dev())
-    counter[0] = 2
-    r.fuse_sh_adam(m, v, 2.5e-3, counter)
-    sh0 = P["sh"].detach().clone()
-    g = torch.Generator(device=dev())
-    g.manual_seed(11)
-    imgs = _call(r, P)
-    loss = sum((im * torch.rand(im.shape, device=dev(), generator=g)).sum() for im in imgs)
-    loss.backward()
-    torch.cuda.synchronize()
-    assert P["sh"].grad is None and int(counter[0]) == 2
-    assert not torch.equal(P["sh"].detach(), sh0)
-    params0 = {k: P[k].detach().clone() for k in names}
-    params0["sh"] = sh0
-    grads = gsmi.empty_grads(params0)
-    r.frame.project_backward(params0, sc.sh_degree, r.cams_dev, r.opts, grads)
-    ref_sh, ref_m, ref_v = sh0.clone(), torch.zeros_like(sh0), torch.zeros_like(sh0)
-    c2 = gsmi.adam_counter(dev())
-    c2[0] = 2
-    gsmi.adam_step([(ref_sh, grads["sh"], ref_m, ref_v, 2.5e-3)], sc.n, c2,
-                   tiles_touched=r.frame.buffer(gsmi.BUF_TILES_TOUCHED), n_views=2)
-    torch.cuda.synchronize()
-    assert torch.equal(P["sh"].detach(), ref_sh)
-    assert torch.equal(m, ref_m) and torch.equal(v, ref_v)
-    for k in names:
-        if k != "sh":
-            assert torch.equal(P[k].grad, grads[k]), k
-    r.fuse_sh_adam(None, None, 0.0, None)
-    assert r.sh_adam is None
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    for fused in (names, ("sh",)):
+        P = _leaf_params(sc)
+        r = GaussianRasterizer(sc.n, cams, sc.sh_degree, device=dev())
+        mom = {k: (torch.zeros_like(P[k]), torch.zeros_like(P[k])) for k in fused}
+        counter = gsmi.adam_counter(dev())
+        counter[0] = 2
+        r.fuse_adam(gsmi.FusedAdamStep(mom, lrs, counter))
+        start = {k: P[k].detach().clone() for k in names}
+        g = torch.Generator(device=dev())
+        g.manual_seed(11)
+        imgs = _call(r, P)
+        loss = sum((im * torch.rand(im.shape, device=dev(), generator=g)).sum() for im in imgs)
+        loss.backward()
+        torch.cuda.synchronize()
+        assert int(counter[0]) == 2
+        grads = gsmi.empty_grads(start)
+        r.frame.project_backward(start, sc.sh_degree, r.cams_dev, r.opts, grads)
+        ref = {k: (start[k].clone(), torch.zeros_like(start[k]), torch.zeros_like(start[k]))
+               for k in fused}
+        c2 = gsmi.adam_counter(dev())
+        c2[0] = 2
+        gsmi.adam_step([(ref[k][0], grads[k], ref[k][1], ref[k][2], lrs[k]) for k in fused], sc.n,
+                       c2, tiles_touched=r.frame.buffer(gsmi.BUF_TILES_TOUCHED), n_views=2)
+        torch.cuda.synchronize()
+        for k in names:
+            if k in fused:
+                assert P[k].grad is None, k
+                assert not torch.equal(P[k].detach(), start[k]), k
+                assert torch.equal(P[k].detach(), ref[k][0]), k
+                assert torch.equal(mom[k][0], ref[k][1]) and torch.equal(mom[k][1], ref[k][2]), k
+            else:
+                assert torch.equal(P[k].detach(), start[k]), k
+                assert torch.equal(P[k].grad, grads[k]), k
+        r.fuse_adam(None)
+        assert r.adam is None
 
 
 def test_captured_training_step_replays_match_eager():

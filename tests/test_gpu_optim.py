@@ -98,16 +98,22 @@ def test_counted_adam_equals_host_counted_adam():
     assert int(counter[0]) == 7
 
 
-@pytest.mark.parametrize("sh_degree,counted,rendered_only",
-                         [(3, True, True), (3, False, False), (1, True, False), (0, False, True)])
-def test_fused_sh_adam_equals_projection_adjoint_then_adam(sh_degree, counted, rendered_only):
-    """gs_project_backward_sh_adam against gs_project_backward followed by
-    gs_adam_step on the colour coefficients, from the same per-splat gradients
-    and nonzero moments over two views, part of the Gaussians behind the
-    cameras: coefficients and moments bit for bit (unrendered ones untouched),
-    the other four gradients and the densification statistic bit for bit, no
-    colour-coefficient gradient written, a device counter read and not
+ALL = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.mark.parametrize("sh_degree,counted,rendered_only,fused",
+                         [(3, True, True, ALL), (3, False, False, ("sh",)),
+                          (1, True, False, ("means", "quats", "sh")),
+                          (0, False, True, ("log_scales", "opacity_logits"))])
+def test_fused_adam_equals_projection_adjoint_then_adam(sh_degree, counted, rendered_only, fused):
+    """gs_project_backward_adam against gs_project_backward followed by
+    gs_adam_step on the same arrays, from the same per-splat gradients and
+    nonzero moments over two views, part of the Gaussians behind the cameras:
+    the fused arrays' parameters and moments bit for bit (unrendered Gaussians
+    untouched), the other gradients and the densification statistic bit for
+    bit, no gradient written for a fused array, a device counter read and not
     advanced; host validation of the Adam arguments."""
+    import ctypes
     from parity_util import params_of
     from paper_2507_20239_amd import synth
     sc = synth.random_scene(71, 3000, 96, 80, sh_degree=sh_degree, n_views=2,
@@ -115,6 +121,7 @@ def test_fused_sh_adam_equals_projection_adjoint_then_adam(sh_degree, counted, r
     sc.means[2, ::7] = -1.0   # behind both cameras: never rendered
     cams = list(sc.cameras)
     n = sc.n
+    names = gsmi.PARAM_NAMES
     P = params_of(sc)
     cams_dev = gsmi.cameras_to_device(cams, dev())
     opts = gsmi.raster_opts(grad_rendered_only=rendered_only)
@@ -127,9 +134,10 @@ def test_fused_sh_adam_equals_projection_adjoint_then_adam(sh_degree, counted, r
     tt = frame.buffer(gsmi.BUF_TILES_TOUCHED)
     rendered = (tt.view(2, n) != 0).any(0).cpu().numpy()
     assert 0 < rendered.sum() < n
-    m0 = 0.01 * torch.randn(P["sh"].shape, device=dev(), generator=g)
-    v0 = 1e-4 * torch.rand(P["sh"].shape, device=dev(), generator=g)
-    lr, done = 2.5e-3, 4
+    mom0 = {k: (0.01 * torch.randn(P[k].shape, device=dev(), generator=g),
+                1e-4 * torch.rand(P[k].shape, device=dev(), generator=g)) for k in fused}
+    lrs = {"means": 1e-3, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+    done = 4
 
     def step_arg():
         if not counted:
@@ -138,48 +146,66 @@ def test_fused_sh_adam_equals_projection_adjoint_then_adam(sh_degree, counted, r
         c[0] = done
         return c
 
-    # separate: the adjoint's gradients, then Adam on the colour coefficients
-    sa, ma, va = P["sh"].clone(), m0.clone(), v0.clone()
+    # separate: the adjoint's gradients, then Adam on the same arrays
+    Pa = {k: t.clone() for k, t in P.items()}
+    mom_a = {k: (m.clone(), v.clone()) for k, (m, v) in mom0.items()}
     grads_a = gsmi.empty_grads(P)
     acc_a, den_a = torch.zeros(n, device=dev()), torch.zeros(n, device=dev())
     frame.project_backward(P, sh_degree, cams_dev, opts, grads_a, acc_a, den_a)
     cnt_a = step_arg()
-    gsmi.adam_step([(sa, grads_a["sh"], ma, va, lr)], n, cnt_a, tiles_touched=tt, n_views=2)
+    gsmi.adam_step([(Pa[k], grads_a[k], mom_a[k][0], mom_a[k][1], lrs[k]) for k in fused], n,
+                   cnt_a, tiles_touched=tt, n_views=2)
     # fused
     Pb = {k: t.clone() for k, t in P.items()}
-    mb, vb = m0.clone(), v0.clone()
-    grads_b = {k: torch.full_like(P[k], 7.0) for k in gsmi.PARAM_NAMES if k != "sh"}
-    grads_b["sh"] = None
+    mom_b = {k: (m.clone(), v.clone()) for k, (m, v) in mom0.items()}
+    grads_b = {k: None if k in fused else torch.full_like(P[k], 7.0) for k in names}
     acc_b, den_b = torch.zeros(n, device=dev()), torch.zeros(n, device=dev())
     cnt_b = step_arg()
     frame.project_backward(Pb, sh_degree, cams_dev, opts, grads_b, acc_b, den_b,
-                           sh_adam=dict(m=mb, v=vb, lr=lr, step=cnt_b))
+                           adam=gsmi.FusedAdamStep(mom_b, lrs, cnt_b))
     torch.cuda.synchronize()
-    assert torch.equal(Pb["sh"], sa) and torch.equal(mb, ma) and torch.equal(vb, va)
     un = torch.from_numpy(~rendered).to(dev())
-    assert torch.equal(Pb["sh"][..., un], P["sh"][..., un]) and torch.equal(mb[..., un], m0[..., un])
-    assert not torch.equal(Pb["sh"], P["sh"])
     rows = torch.from_numpy(rendered).to(dev()) if rendered_only else torch.ones(n, dtype=torch.bool,
                                                                                    device=dev())
-    for k in ("means", "log_scales", "quats", "opacity_logits"):
-        assert torch.equal(grads_b[k][..., rows], grads_a[k][..., rows]), k
+    for k in names:
+        if k in fused:
+            assert torch.equal(Pb[k], Pa[k]), k
+            assert torch.equal(mom_b[k][0], mom_a[k][0]) and torch.equal(mom_b[k][1], mom_a[k][1]), k
+            assert torch.equal(Pb[k][..., un], P[k][..., un]), k
+            assert not torch.equal(Pb[k], P[k]), k
+        else:
+            assert torch.equal(Pb[k], P[k]), k
+            assert torch.equal(grads_b[k][..., rows], grads_a[k][..., rows]), k
     assert torch.equal(acc_b, acc_a) and torch.equal(den_b, den_a)
     if counted:
         assert int(cnt_b[0]) == done and int(cnt_a[0]) == done + 1
-    # host validation: the in-place array, the decay rates, the step count
-    for bad in (dict(m=mb, v=vb, lr=lr, step=1, beta1=1.0), dict(m=mb, v=vb, lr=lr, step=0)):
+    # host validation: the decay rates, the step count, the in-place arrays, a
+    # missing gradient of an array not fused
+    for bad in (dict(beta1=1.0), dict(eps=0.0)):
         with pytest.raises(gsmi.GsError):
-            frame.project_backward(Pb, sh_degree, cams_dev, opts, grads_b, sh_adam=bad)
+            frame.project_backward(Pb, sh_degree, cams_dev, opts, grads_b,
+                                   adam=gsmi.FusedAdamStep(mom_b, lrs, 1, **bad))
+    with pytest.raises(gsmi.GsError):
+        frame.project_backward(Pb, sh_degree, cams_dev, opts, grads_b,
+                               adam=gsmi.FusedAdamStep(mom_b, lrs, 0))
     L = gsmi.lib()
     gs = gsmi.gaussians_struct(Pb, sh_degree)
     gr = gsmi.GaussianGrads(*(grads_b[k].data_ptr() if grads_b[k] is not None else None
-                              for k in gsmi.PARAM_NAMES))
-    other = torch.empty_like(P["sh"])
-    a = gsmi.ShAdam(other.data_ptr(), mb.data_ptr(), vb.data_ptr(), lr, 0.9, 0.999, 1e-15, None, 1)
-    import ctypes
-    st = L.gs_project_backward_sh_adam(frame.handle, ctypes.byref(gs), gsmi._ptr(cams_dev),
-                                       ctypes.byref(opts), ctypes.byref(gr), None, None,
-                                       ctypes.byref(a), gsmi._stream())
+                              for k in names))
+    a = gsmi.FusedAdamStep(mom_b, lrs, 1).struct(Pb)
+    other = torch.empty_like(P[fused[0]])
+    a.param[names.index(fused[0])] = other.data_ptr()
+    st = L.gs_project_backward_adam(frame.handle, ctypes.byref(gs), gsmi._ptr(cams_dev),
+                                    ctypes.byref(opts), ctypes.byref(gr), None, None,
+                                    ctypes.byref(a), gsmi._stream())
     assert st == gsmi.GS_ERR_INVALID and b"in place" in L.gs_last_error()
+    if len(fused) < len(names):
+        a = gsmi.FusedAdamStep(mom_b, lrs, 1).struct(Pb)
+        gr0 = gsmi.GaussianGrads(None, None, None, None, None)
+        st = L.gs_project_backward_adam(frame.handle, ctypes.byref(gs), gsmi._ptr(cams_dev),
+                                        ctypes.byref(opts), ctypes.byref(gr0), None, None,
+                                        ctypes.byref(a), gsmi._stream())
+        assert st == gsmi.GS_ERR_INVALID and b"not fused" in L.gs_last_error()
     torch.cuda.synchronize()
-    assert torch.equal(mb, ma)
+    for k in fused:
+        assert torch.equal(mom_b[k][0], mom_a[k][0]), k
