@@ -115,7 +115,8 @@ def to_dev(sc, dev, torch, gsmi):
     return {k: torch.from_numpy(getattr(sc, k)).to(dev).contiguous() for k in gsmi.PARAM_NAMES}
 
 
-STAGES = ["project", "bin", "composite", "l1", "render_backward", "project_backward"]
+# composite_l1: compositing with the L1 term of Eq. 3 fused into its pixel writes
+STAGES = ["project", "bin", "composite_l1", "render_backward", "project_backward"]
 
 
 class Step:
@@ -147,16 +148,14 @@ class Step:
         if ev: ev[1].record()
         f.bin(self.opts)
         if ev: ev[2].record()
-        f.composite(self.opts, self.images)
-        if ev: ev[3].record()
         self.loss.zero_()
-        g.l1_loss_grad(self.images, self.targets, self.l1_scale, self.loss, self.dL)
-        if ev: ev[4].record()
+        f.composite_l1(self.opts, self.images, self.targets, self.l1_scale, self.loss, self.dL)
+        if ev: ev[3].record()
         f.render_backward(self.opts, self.dL)
-        if ev: ev[5].record()
+        if ev: ev[4].record()
         f.project_backward(self.params, self.sc.sh_degree, self.cams_dev, self.opts, self.grads,
                            self.acc, self.den)
-        if ev: ev[6].record()
+        if ev: ev[5].record()
 
     def capture(self):
         self.graph = self.gsmi.StepGraph(self.frame, self.params, self.sc.sh_degree, self.cams_dev,

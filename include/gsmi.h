@@ -238,6 +238,16 @@ gs_status gs_render(gs_frame* frame, const gs_raster_opts* opts, float* images, 
 gs_status gs_bin(gs_frame* frame, const gs_raster_opts* opts, void* stream);
 gs_status gs_composite(gs_frame* frame, const gs_raster_opts* opts, float* images, void* stream);
 
+/* gs_composite with the L1 term of Eq. 3 computed as each pixel is written:
+ * loss[0] += l1_scale * sum |image - target| and dL_dimages = l1_scale *
+ * sign(image - target) (sign(0) = 0): gs_composite followed by
+ * gs_l1_loss_grad, with the same image, the same gradient bit for bit and the
+ * loss summed in another order.  targets, dL_dimages: the images' layout;
+ * loss: one device float the caller has set (the call adds to it). */
+gs_status gs_composite_l1(gs_frame* frame, const gs_raster_opts* opts, float* images,
+                          const float* targets, float l1_scale, float* loss, float* dL_dimages,
+                          void* stream);
+
 /* Adjoint of gs_render: from dL/dimages (same layout as images) to the
  * per-splat gradients GS_BUF_SPLAT_GRAD, which gs_project cleared; call it
  * once per gs_project/gs_render.  Walks each pixel's list back to front,
@@ -516,8 +526,9 @@ gs_status gs_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int32_t key_b
 /* ------------------------------------------------------------------------ */
 typedef struct gs_graph gs_graph;
 
-/* Capture project -> render -> L1 loss/gradient -> render backward -> project
- * backward (+ statistics) for the frame's views into a hipGraph.  The graph
+/* Capture project -> bin -> composite with the L1 loss/gradient
+ * (gs_composite_l1) -> render backward -> project backward (+ statistics)
+ * for the frame's views into a hipGraph.  The graph
  * keeps every pointer given here; the caller must keep those buffers alive and
  * unchanged in size until gs_graph_destroy.  Camera contents (device) may be
  * rewritten between launches.  loss: device float, zeroed by the graph.

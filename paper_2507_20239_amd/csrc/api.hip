@@ -306,7 +306,22 @@ gs_status gs_composite(gs_frame* f, const gs_raster_opts* opts, float* images, v
         return gs_fail(GS_ERR_INVALID,
                        "persistent_blocks > 0 needs the heavy-first tile order, which the last "
                        "binning did not build (it ran with persistent_blocks = 0)");
-    return gs_launch_raster_fwd(f, opts, images, (hipStream_t)stream);
+    return gs_launch_raster_fwd(f, opts, images, nullptr, 0.f, nullptr, nullptr,
+                                (hipStream_t)stream);
+}
+
+gs_status gs_composite_l1(gs_frame* f, const gs_raster_opts* opts, float* images,
+                          const float* targets, float l1_scale, float* loss, float* dL_dimages,
+                          void* stream) {
+    GS_TRY(check_frame(f));
+    GS_TRY(check_opts(opts));
+    if (!images || !targets || !loss || !dL_dimages) return gs_fail(GS_ERR_INVALID, "null pointer");
+    if (opts->persistent_blocks > 0 && !f->heavy_built)
+        return gs_fail(GS_ERR_INVALID,
+                       "persistent_blocks > 0 needs the heavy-first tile order, which the last "
+                       "binning did not build (it ran with persistent_blocks = 0)");
+    return gs_launch_raster_fwd(f, opts, images, targets, l1_scale, loss, dL_dimages,
+                                (hipStream_t)stream);
 }
 
 gs_status gs_render(gs_frame* f, const gs_raster_opts* opts, float* images, void* stream) {
@@ -430,9 +445,9 @@ gs_status gs_step_graph_create(gs_frame* f, const gs_gaussians* g, const gs_came
     }
     const int64_t numel = 3 * f->P;
     st = gs_project(f, g, cameras, opts, cs);
-    if (st == GS_OK) st = gs_render(f, opts, images, cs);
     if (st == GS_OK) st = gs_fill_u32((u32*)loss, 0u, 1, cs);
-    if (st == GS_OK) st = gs_l1_loss_grad(images, targets, numel, l1_scale, loss, dL_dimages, cs);
+    if (st == GS_OK) st = gs_bin(f, opts, cs);
+    if (st == GS_OK) st = gs_composite_l1(f, opts, images, targets, l1_scale, loss, dL_dimages, cs);
     if (st == GS_OK) st = gs_render_backward(f, opts, dL_dimages, cs);
     if (st == GS_OK) st = gs_project_backward(f, g, cameras, opts, grads, accum, denom, cs);
     e = hipStreamEndCapture(cs, &graph);

@@ -277,7 +277,9 @@ gs_status gs_launch_project(gs_frame* f, const gs_gaussians* g, const gs_camera*
 // sorting each tile's list afterwards (GS_RASTER_DEPTH_PRESORT)
 // balanced: balanced digit widths in the radix sort by tile (GS_RASTER_BALANCED_DIGITS)
 gs_status gs_launch_bin(gs_frame* f, hipStream_t s, bool heavy_first, bool presort, bool balanced);
+// targets (may be NULL): the L1 term of Eq. 3 fused in (gs_composite_l1)
 gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* images,
+                               const float* targets, float l1_scale, float* loss, float* dL,
                                hipStream_t s);
 gs_status gs_launch_raster_bwd(gs_frame* f, const gs_raster_opts* o, const float* dL,
                                hipStream_t s);

@@ -51,6 +51,10 @@ struct RasterArgs {
     float bg0, bg1, bg2;
     // forward
     float* images;
+    const float* l1_target;    // with the L1 term of Eq. 3 fused: targets, or null
+    float* l1_grad;
+    float* l1_loss;
+    float l1_scale;
     float* T_final;
     u32* n_contrib;
     u32* n_comp;
@@ -336,6 +340,7 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
             }
         }
         const int64_t hw = (int64_t)tc.vi.width * tc.vi.height;
+        float l1 = 0.f;   // this lane's share of sum |I - T| (the fused L1 term)
 #pragma unroll
         for (int i = 0; i < PIXQ; ++i) {
             const int qp = quad_pixel<PIXQ>(tc, i);
@@ -344,13 +349,30 @@ __global__ void __launch_bounds__(64) raster_fwd_kernel(RasterArgs a) {
                 const int64_t off = (int64_t)py * tc.vi.width + px;
                 float* img = a.images + 3 * tc.vi.pix_base + off;
                 const float Tf = fabsf(T[i]);
-                img[0] = fmaf(Tf, a.bg0, C0[i]);
-                img[hw] = fmaf(Tf, a.bg1, C1[i]);
-                img[2 * hw] = fmaf(Tf, a.bg2, C2[i]);
+                const float c[3] = {fmaf(Tf, a.bg0, C0[i]), fmaf(Tf, a.bg1, C1[i]),
+                                    fmaf(Tf, a.bg2, C2[i])};
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) img[ch * hw] = c[ch];
+                if (a.l1_target) {
+                    // the L1 term: |I - T| summed, scale * sign(I - T) as the gradient
+                    const float* tg = a.l1_target + 3 * tc.vi.pix_base + off;
+                    float* gd = a.l1_grad + 3 * tc.vi.pix_base + off;
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const float d = c[ch] - tg[ch * hw];
+                        gd[ch * hw] = d > 0.f ? a.l1_scale : (d < 0.f ? -a.l1_scale : 0.f);
+                        l1 += fabsf(d);
+                    }
+                }
                 a.T_final[tc.vi.pix_base + off] = Tf;
                 a.n_contrib[tc.vi.pix_base + off] = last[i];
                 if (COUNT) a.n_comp[tc.vi.pix_base + off] = ncomp[i];
             }
+        }
+        if (a.l1_target) {
+            // one atomic per work item
+            l1 = wave_sum_lane63(l1);
+            if (threadIdx.x == 63) unsafeAtomicAdd(a.l1_loss, l1 * a.l1_scale);
         }
     }
 }
@@ -540,6 +562,10 @@ RasterArgs make_args(gs_frame* f, const gs_raster_opts* o) {
     a.bg1 = o->bg[1];
     a.bg2 = o->bg[2];
     a.images = nullptr;
+    a.l1_target = nullptr;
+    a.l1_grad = nullptr;
+    a.l1_loss = nullptr;
+    a.l1_scale = 0.f;
     a.T_final = f->T_final;
     a.n_contrib = f->n_contrib;
     a.n_comp = f->n_comp;
@@ -598,10 +624,15 @@ void launch_bwd_batch(const RasterArgs& a, int batch, unsigned grid, hipStream_t
 }  // namespace
 
 gs_status gs_launch_raster_fwd(gs_frame* f, const gs_raster_opts* o, float* images,
+                               const float* targets, float l1_scale, float* loss, float* dL,
                                hipStream_t s) {
     if (f->T == 0) return GS_OK;
     RasterArgs a = make_args(f, o);
     a.images = images;
+    a.l1_target = targets;
+    a.l1_grad = dL;
+    a.l1_loss = loss;
+    a.l1_scale = l1_scale;
     const bool pixels = pixel_lanes(f, o);
     unsigned grid;
     GS_TRY(grid_for(f, o, a, 3, s, pixels, grid));

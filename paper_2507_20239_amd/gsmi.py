@@ -108,6 +108,7 @@ _SIGS = {
     "gs_render": [_P, ctypes.POINTER(RasterOpts), _P, _P],
     "gs_bin": [_P, ctypes.POINTER(RasterOpts), _P],
     "gs_composite": [_P, ctypes.POINTER(RasterOpts), _P, _P],
+    "gs_composite_l1": [_P, ctypes.POINTER(RasterOpts), _P, _P, _F, _P, _P, _P],
     "gs_render_backward": [_P, ctypes.POINTER(RasterOpts), _P, _P],
     "gs_project_backward": [_P, ctypes.POINTER(Gaussians), _P, ctypes.POINTER(RasterOpts),
                             ctypes.POINTER(GaussianGrads), _P, _P, _P],
@@ -330,6 +331,17 @@ class Frame:
         if images is None:
             images = torch.empty(self.image_numel(), dtype=torch.float32, device=self.device)
         _check(lib().gs_composite(self.handle, ctypes.byref(opts), _ptr(images), _stream(stream)))
+        return images
+
+    def composite_l1(self, opts, images, targets, scale, loss, grad, stream=None):
+        """composite with the L1 term fused (gs_composite_l1): writes images,
+        adds scale * sum |images - targets| to loss[0] and writes
+        grad = scale * sign(images - targets)."""
+        for t in (images, targets, grad):
+            if t.numel() != self.image_numel() or not t.is_contiguous():
+                raise ValueError("images, targets and grad must hold the frame's images")
+        _check(lib().gs_composite_l1(self.handle, ctypes.byref(opts), _ptr(images), _ptr(targets),
+                                     float(scale), _ptr(loss), _ptr(grad), _stream(stream)))
         return images
 
     def overflowed(self, clear=False):
@@ -621,7 +633,8 @@ def sort_pairs(keys, vals, key_bits=32, stream=None):
 # Captured step
 # ----------------------------------------------------------------------------
 class StepGraph:
-    """hipGraph of project -> render -> L1 -> render backward -> project backward."""
+    """hipGraph of project -> bin -> composite with the L1 term -> render
+    backward -> project backward."""
 
     def __init__(self, frame: Frame, params, sh_degree, cams_dev, opts, images, targets, l1_scale,
                  loss, dL, grads, accum=None, denom=None, stream=None):

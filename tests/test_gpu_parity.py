@@ -429,6 +429,41 @@ def test_l1_loss_grad():
     np.testing.assert_array_equal(g.cpu().numpy(), ref_g.astype(np.float32))
 
 
+@pytest.mark.parametrize("lanes,persistent", [("pixels", 0), ("quads", 0), (None, 7)])
+def test_composite_l1_equals_composite_then_l1(lanes, persistent):
+    """gs_composite_l1 (the L1 term of Eq. 3 computed as the compositing writes
+    each pixel) against gs_composite followed by gs_l1_loss_grad on a two-view
+    frame with ragged edges and pixels equal to their target: images, final
+    transmittance, walk lengths and dL/dimage bit for bit, the loss to FP32
+    summation order; the loss is added to what the caller set."""
+    sc = synth.random_scene(27, 3000, 150, 100, sh_degree=2, n_views=2, log_scale=(-2.5, 0.5))
+    cams = [sc.cameras[0], synth.Camera(sc.cameras[1].R, sc.cameras[1].t, 90.0, 90.0, 45.3,
+                                        30.8, 91, 61)]
+    opts = gsmi.raster_opts(bg=(0.1, 0.2, 0.3), lanes=lanes, persistent_blocks=persistent)
+    frame, flat, *_ = gpu_forward(sc, cams, opts)
+    torch.cuda.synchronize()
+    ref_img = flat.clone()
+    ref_T = frame.buffer(gsmi.BUF_T_FINAL, torch.float32).clone()
+    ref_n = frame.buffer(gsmi.BUF_N_CONTRIB).clone()
+    g = torch.Generator(device=dev())
+    g.manual_seed(13)
+    targets = torch.rand(flat.numel(), device=dev(), generator=g)
+    targets[::97] = ref_img[::97]   # sign(0) = 0
+    scale = 1.0 / flat.numel()
+    ref_loss, ref_dL = gsmi.l1_loss_grad(ref_img, targets, scale)
+    img = torch.empty_like(flat)
+    dL = torch.empty_like(flat)
+    loss = torch.full((1,), 0.25, device=dev())
+    frame.composite_l1(opts, img, targets, scale, loss, dL)
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_img)
+    assert torch.equal(frame.buffer(gsmi.BUF_T_FINAL, torch.float32), ref_T)
+    assert torch.equal(frame.buffer(gsmi.BUF_N_CONTRIB), ref_n)
+    assert torch.equal(dL, ref_dL)
+    assert int((dL == 0).sum()) >= flat.numel() // 97
+    assert float(loss) - 0.25 == pytest.approx(float(ref_loss), rel=1e-5)
+
+
 def test_render_twice_after_one_projection_is_identical():
     """Rendering reads the projection's outputs without modifying them, so a
     second render of the same projection repeats the first exactly."""
