@@ -161,17 +161,19 @@ struct LaneGeom<4> {
 template <>
 struct LaneGeom<1> {
     float dx, dy, u, vv;
+    // The quad's steps for pixel pi: each "+ step" of the quad is taken as
+    // fma(o, step, x) with o = 1 or 0 the lane's (constant) pixel offset,
+    // which rounds like x + step for o = 1 and returns x for o = 0, one
+    // instruction instead of an add and a select.
     __device__ __forceinline__ void setup(float4 p0, float4 p1, float qxc, float qyc, int pi) {
-        const bool ox = (pi & 1) != 0, oy = (pi & 2) != 0;
+        const float ox = (pi & 1) ? 1.f : 0.f, oy = (pi & 2) ? 1.f : 0.f;
         const float dx0 = (qxc - p0.x) - p0.z;
         const float dy0 = (qyc - p0.y) - p0.w;
-        dx = ox ? dx0 + 1.f : dx0;
-        dy = oy ? dy0 + 1.f : dy0;
+        dx = dx0 + ox;
+        dy = dy0 + oy;
         const float u0 = fmaf(p1.x, dx0, p1.y * dy0);
-        const float ux = ox ? u0 + p1.x : u0;
-        u = oy ? ux + p1.y : ux;
-        const float v0 = p1.z * dy0;
-        const float v = oy ? v0 + p1.z : v0;
+        u = fmaf(oy, p1.y, fmaf(ox, p1.x, u0));
+        const float v = fmaf(oy, p1.z, p1.z * dy0);
         vv = v * v;
     }
     __device__ __forceinline__ float G(int) const {
