@@ -243,7 +243,8 @@ gs_status gs_composite(gs_frame* frame, const gs_raster_opts* opts, float* image
  * sign(image - target) (sign(0) = 0): gs_composite followed by
  * gs_l1_loss_grad, with the same image, the same gradient bit for bit and the
  * loss summed in another order.  targets, dL_dimages: the images' layout;
- * loss: one device float the caller has set (the call adds to it). */
+ * loss: one device float the caller has set (the call adds to it).  Errors as
+ * gs_composite, and GS_ERR_INVALID for a null targets, loss or dL_dimages. */
 gs_status gs_composite_l1(gs_frame* frame, const gs_raster_opts* opts, float* images,
                           const float* targets, float l1_scale, float* loss, float* dL_dimages,
                           void* stream);
@@ -503,9 +504,14 @@ typedef struct {
  * instead of to grads, whose pointers for those arrays are neither written
  * nor read (may be NULL); every other output is gs_project_backward's.  A
  * training step that fuses all five arrays then only advances its counter
- * (gs_adam_step_counted with no arrays).  For the optimiser step of the
- * accelerated 3DGS training the paper builds on (Experiments, implementation
- * details). */
+ * (gs_adam_step_counted with no arrays).  The parameters, moments and the
+ * frame's state are read and written on the stream in order; no other work
+ * may touch them meanwhile.  GS_ERR_INVALID before any launch for the errors
+ * of gs_project_backward, a null adam, a param[k] other than the Gaussians'
+ * array k, a null moment of a selected array, a null gradient of an array not
+ * selected, beta outside [0, 1), eps <= 0, step < 1 without a counter or a
+ * counter not 8-byte aligned.  For the optimiser step of the accelerated 3DGS
+ * training the paper builds on (Experiments, implementation details). */
 gs_status gs_project_backward_adam(gs_frame* frame, const gs_gaussians* g, const gs_camera* cameras,
                                    const gs_raster_opts* opts, const gs_gaussian_grads* grads,
                                    float* accum, float* denom, const gs_fused_adam* adam,
