@@ -312,6 +312,22 @@ def test_empty_and_culled_scene_renders_background():
     frame.project_backward(params, 0, cams_dev, opts, grads)
     for k in gsmi.PARAM_NAMES:
         assert torch.count_nonzero(grads[k]).item() == 0
+    # the fused forms: the L1 term of the background alone, and an optimiser
+    # step that moves nothing (no Gaussian was rendered)
+    loss = torch.zeros(1, device=dev())
+    img2, g2 = torch.empty_like(flat), torch.empty_like(flat)
+    frame.composite_l1(opts, img2, torch.zeros_like(flat), 0.5, loss, g2)
+    torch.cuda.synchronize()
+    assert torch.equal(img2, flat) and bool((g2 == 0.5).all())
+    assert float(loss) == pytest.approx(0.5 * 17 * 33 * float(sc.bg.sum()), rel=1e-6)
+    before = {k: t.clone() for k, t in params.items()}
+    mom = {k: (torch.full_like(t, 0.1), torch.full_like(t, 0.2)) for k, t in params.items()}
+    lrs = {k: 1e-3 for k in gsmi.PARAM_NAMES}
+    frame.project_backward(params, 0, cams_dev, opts, {}, adam=gsmi.FusedAdamStep(mom, lrs, 1))
+    torch.cuda.synchronize()
+    for k in gsmi.PARAM_NAMES:
+        assert torch.equal(params[k], before[k]), k
+        assert bool((mom[k][0] == 0.1).all()) and bool((mom[k][1] == 0.2).all()), k
 
 
 def test_nonfinite_gaussians_are_culled():
